@@ -1,0 +1,187 @@
+/*
+ * ms.h -- C ABI of the MI355X plane-wave multiple-scattering transport library.
+ *
+ * Method: Li, Chu, Zhang, Cheng, "Electron transport in graphene/graphene
+ * side-contact junction by plane-wave multiple scattering method"
+ * (arXiv:1504.01462).  Local-potential form: -nabla^2 psi + V psi = E psi
+ * (Rydberg units, hbar^2/2m = 1, lengths in bohr), V periodic in the
+ * transverse plane and z-independent inside each slice, constant in the two
+ * leads.  The non-local projector terms (C, H^a, H^b, h^a, h^b) are zero.
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved {re, im}; c128 = two doubles.  Matrices
+ *     are row-major and contiguous (leading dimension = number of columns).
+ *   - Every array argument is DEVICE memory of the context's device, except
+ *     the small host arrays named `bvec`, `kpar` and `energies`.
+ *   - The caller allocates and owns every input and output buffer.  The
+ *     context owns only its workspace (grown on demand, freed at destroy).
+ *   - Calls enqueue work on the context's stream and return at once.
+ *     Argument errors are returned synchronously and enqueue nothing.
+ *     Numerical problems found on the device (zero pivot, non-finite data)
+ *     are recorded in the context's device status word and returned by
+ *     ms_ctx_sync; ms_transmission_batch also writes one status per point.
+ *   - Output values are unspecified for points whose status is not MS_OK.
+ *   - A context is used by one host thread at a time.
+ *
+ * Notation (paper, Sec. II.A and App. A): slices p = 1..N between the left
+ * lead (p = 0) and the right lead (p = N+1); slice p ends at its reference
+ * plane z_p; its modes are the eigenpairs (E^p_n, U^p[:,n]) of the
+ * transverse Hamiltonian (Eq. loc); k^p_n = sqrt(E - E^p_n) with Im k >= 0.
+ * S(p,p+1) maps [A^p; B^{p+1}] to [A^{p+1}; B^p] (Eq. smm2); its blocks
+ * S11, S12, S21, S22 are called t, rp, r, tp here.
+ */
+#ifndef MS_H
+#define MS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MS_OK = 0,
+  MS_ERR_ARG = 1,          /* bad size, null pointer, inconsistent arguments            */
+  MS_ERR_ALLOC = 2,        /* device workspace allocation failed                         */
+  MS_ERR_HIP = 3,          /* a HIP runtime call failed                                  */
+  MS_ERR_SINGULAR = 4,     /* exact zero pivot in an LU factorisation (X, I - S12 S21,   */
+                           /* or the fused interface matrix)                             */
+  MS_ERR_THRESHOLD = 5,    /* |E - lead channel energy| < 1e-10: k = 0 in a lead          */
+  MS_ERR_NONFINITE = 6,    /* NaN or Inf met in inputs or results                        */
+  MS_ERR_UNSUPPORTED = 7,  /* size or mode this build does not handle                    */
+  MS_ERR_NOCONV = 8        /* slice eigensolver did not reach its tolerance              */
+} ms_status;
+
+typedef enum {
+  MS_PREC_FP64 = 0,        /* every step in FP64 (complex128)                            */
+  MS_PREC_FP32_MFMA = 1    /* star-product GEMMs on FP32 MFMA (complex64, FP32           */
+                           /* accumulation); factorisation, solves and scalings in FP64  */
+} ms_prec;
+
+typedef struct ms_ctx_s* ms_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  Fails with MS_ERR_HIP
+ * when the device cannot be selected. */
+ms_status ms_ctx_create(int device, void* hip_stream, ms_ctx* out);
+
+/* Wait for the context's stream, free its workspace and the context. */
+ms_status ms_ctx_destroy(ms_ctx ctx);
+
+/* Wait for all work on the context's stream; return the first numerical
+ * status recorded on the device since the last sync (then clear it). */
+ms_status ms_ctx_sync(ms_ctx ctx);
+
+/* Static, NUL-terminated name of a status code. */
+const char* ms_status_str(ms_status s);
+
+/* Copy the last error message of `ctx` (or of the most recent failed
+ * ms_ctx_create when ctx is NULL) into buf (NUL-terminated, at most len). */
+ms_status ms_ctx_last_error(ms_ctx ctx, char* buf, int64_t len);
+
+/* One scattering matrix: four n x n c128 blocks in device memory.
+ * t = S11, rp = S12, r = S21, tp = S22 (Eq. smm2 and Eq. scatter). */
+typedef struct {
+  int64_t n;
+  void* t;
+  void* rp;
+  void* r;
+  void* tp;
+} ms_smat;
+
+/* E-independent slice data of one k_par (filled by ms_slices_prepare).
+ *   dz   [n_slices]                 slice thicknesses (bohr); slice p+1 is dz[p]
+ *   eps  [n_slices+2][n_g] f64      E^p_n ascending; row 0 = left lead,
+ *                                   row n_slices+1 = right lead (|k+G|^2 + V_lead)
+ *   ovl  [n_slices+1][n_g][n_g] c128  O^p = U^p^dagger U^{p+1}, p = 0..n_slices
+ *                                   (the overlap sum of App. A, Eq. app), with
+ *                                   U^0 = U^{n_slices+1} = I
+ *   evec [n_slices][n_g][n_g] c128  optional (may be NULL): U^p of slice p+1 as
+ *                                   columns (unit norm), matching eps rows 1..n_slices */
+typedef struct {
+  int64_t n_g;
+  int64_t n_slices;
+  const double* dz;
+  double* eps;
+  void* ovl;
+  void* evec;
+} ms_slices;
+
+/* a1-a3: slice Hamiltonians, their eigenpairs and the interface overlaps.
+ *   H^p_ij = |k_par + G_i|^2 delta_ij + V^p(G_i - G_j)        (Sec. II.A, Eq. loc)
+ * with G_i = g_mn[i][0] b1 + g_mn[i][1] b2.
+ *   g_mn     [n_g][2] int32 (device)  Miller indices of the basis
+ *   bvec     [4] f64 (host)           b1x, b1y, b2x, b2y (bohr^-1)
+ *   kpar     [2] f64 (host)           k_par (bohr^-1)
+ *   vlead_left, vlead_right           constant lead potentials (Ry)
+ *   q_of_ij  [n_g][n_g] int32 (device) index into vq's second axis of G_i - G_j
+ *   vq       [n_slices][n_q] c128 (device)  V^p(Q); must be Hermitian:
+ *            vq[p][q_of_ij[j][i]] = conj(vq[p][q_of_ij[i][j]])
+ *   inout    n_g, n_slices, dz, eps, ovl set by the caller (evec optional)
+ * Errors: MS_ERR_ARG (sizes, nulls), MS_ERR_UNSUPPORTED (n_g > 4096),
+ * MS_ERR_NOCONV / MS_ERR_NONFINITE via ms_ctx_sync. */
+ms_status ms_slices_prepare(ms_ctx ctx, int64_t n_g, const int32_t* g_mn, const double* bvec,
+                            const double* kpar, double vlead_left, double vlead_right,
+                            int64_t n_slices, int64_t n_q, const int32_t* q_of_ij,
+                            const void* vq, ms_slices* inout);
+
+/* a4: S(p,p+1) for p = p0 .. p1-1 at energy E (App. A, Eqs. app, bpp,
+ * transfer and scatter), in the form with the growing factor cancelled:
+ *   X_nj = O_nj (k^p_n + k^{p+1}_j) / (2 k^p_n),  Y_nj = O_nj (k^p_n - k^{p+1}_j) / (2 k^p_n),
+ *   P = diag exp(i k^{p+1} dz_{p+1})  (dz of the right lead = 0),
+ *   S11 = P X^-1,  S12 = -P X^-1 Y P,  S21 = Y X^-1,  S22 = (X - Y X^-1 Y) P.
+ * out[i] receives S(p0+i, p0+i+1); out[i].n must equal slices->n_g.
+ * Errors: MS_ERR_ARG; MS_ERR_SINGULAR via ms_ctx_sync when X has a zero pivot. */
+ms_status ms_slice_smatrix(ms_ctx ctx, const ms_slices* slices, double energy, int64_t p0,
+                           int64_t p1, const ms_smat* out);
+
+/* a5: whole = s[0] * s[1] * ... * s[n-1], the star (layer-doubling) product of
+ * Sec. II.A, Eq. recurrence1 (App. A, Eq. recurrence) for a = S(m,n), b = S(n,k):
+ *   F = I - S12(a) S21(b)
+ *   S11 = S11(b) F^-1 S11(a)             S12 = S12(b) + S11(b) F^-1 S12(a) S22(b)
+ *   S21 = S21(a) + S22(a) S21(b) F^-1 S11(a)
+ *   S22 = S22(a) S22(b) + S22(a) S21(b) F^-1 S12(a) S22(b)
+ * The inputs are not modified; `whole` must not alias them.  prec must be
+ * MS_PREC_FP64 (others return MS_ERR_UNSUPPORTED).
+ * Errors: MS_ERR_ARG; MS_ERR_SINGULAR via ms_ctx_sync when F has a zero pivot. */
+ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n, ms_prec prec, ms_smat* whole);
+
+/* a6: T, R and the open-channel count of the whole junction for waves
+ * incident from the left (App. C: A^0 = I, B^{N+1} = 0, so t = S11 and
+ * r = S21), flux-normalised over the open channels O = {n : eps_n < E}:
+ *   T = sum_{i in O_right, j in O_left} (k_i / k_j) |t_ij|^2,
+ *   R = sum_{i, j in O_left} (k_i / k_j) |r_ij|^2.
+ *   eps_left, eps_right [n] f64 (device)  lead channel energies
+ *   T, R [1] f64, n_open [1] int64 (device outputs)
+ * Errors: MS_ERR_ARG; MS_ERR_THRESHOLD via ms_ctx_sync. */
+ms_status ms_transmission(ms_ctx ctx, const ms_smat* whole, double energy, const double* eps_left,
+                          const double* eps_right, double* T, double* R, int64_t* n_open);
+
+/* a4+a5+a6 fused, batched over energies that share the slice data: the
+ * interfaces are folded from the right lead to the left one; each step is
+ * the star product of S(p,p+1) with the accumulated right part, written so
+ * that one LU factorisation per interface and energy serves both the
+ * slice matrix X and F = I - S12 S21 (exactly equal up to rounding).  No
+ * S(p,p+1) is stored.
+ *   energies   [n_e] f64 (host)
+ *   T, R       [n_e] f64 (device outputs)
+ *   n_open     [n_e] int64 (device output)
+ *   point_status [n_e] int32 (device output; ms_status per point)
+ * Errors: MS_ERR_ARG, MS_ERR_UNSUPPORTED (n_g > 4096), MS_ERR_ALLOC. */
+ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e,
+                                const double* energies, ms_prec prec, double* T, double* R,
+                                int64_t* n_open, int32_t* point_status);
+
+/* a7: average over the k_par mesh (Sec. II.B, Eq. T1_d):
+ *   tbar[e]        = (1/n_k) sum_k T[k][e]
+ *   per_channel[e] = sum_k T[k][e] / sum_k n_open[k][e]   (0 when no channel is open)
+ *   T [n_k][n_e] f64, n_open [n_k][n_e] int64, tbar, per_channel [n_e] f64 (device).
+ * Errors: MS_ERR_ARG. */
+ms_status ms_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open,
+                          double* tbar, double* per_channel);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MS_H */

@@ -1,0 +1,54 @@
+/*
+ * ms_debug.h -- kernel-level entry points of the same library, exported for
+ * unit tests of the building blocks behind ms.h (GEMM, LU solve, slice
+ * eigensolver).  Same conventions as ms.h: device pointers, row-major,
+ * interleaved complex, asynchronous on the context stream, numerical status
+ * via ms_ctx_sync.  Not needed by users of the transport path.
+ */
+#ifndef MS_DEBUG_H
+#define MS_DEBUG_H
+
+#include "ms.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha op(A) op(B) + beta C for one M x N x K product.  op codes:
+ * 0 = none, 1 = transpose, 2 = conjugate transpose.  prec = MS_PREC_FP64:
+ * A, B, C complex128.  prec = MS_PREC_FP32_MFMA: A, B complex64, C complex128
+ * (FP32 MFMA products with FP32 accumulation).  alpha/beta: {re, im} host pairs. */
+ms_status ms_debug_gemm(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, int64_t k, const void* a,
+                        int64_t lda, const void* b, int64_t ldb, void* c, int64_t ldc, const double* alpha,
+                        const double* beta, ms_prec prec);
+
+/* For each of `batch` row-major n x (n + nrhs) complex128 matrices [A | B]
+ * (batch stride n*(n+nrhs)), factor A with partial pivoting (in place) and
+ * write X = A^-1 B to x (n x nrhs per matrix, batch stride n*nrhs).
+ * status [batch] int32 device: MS_ERR_SINGULAR on a zero pivot. */
+ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, void* aug, void* x,
+                            int32_t* status);
+
+/* Eigenpairs of `batch` Hermitian n x n complex128 matrices h (not modified),
+ * with the positivity shifts c [batch] f64 (h + c I must be positive definite):
+ * eps [batch][n] ascending, u [batch][n][n] unit eigenvectors as columns. */
+ms_status ms_debug_eigh(ms_ctx ctx, int64_t n, int64_t batch, const void* h, const double* shift,
+                        double* eps, void* u);
+
+/* Kernel timing with HIP events recorded on the context stream around each
+ * launch of the categories whose bit is set in `mask` (0 stops recording).
+ * Categories, bit 0 upwards: "iface_gemm", "lu_panel", "lu_swap",
+ * "lu_update", "trsm", "jacobi", "prep_gemm", "elem", "other".  ms_debug_profile_read waits for the stream
+ * and returns, for the launches recorded since the previous read of that
+ * category: summed duration (ms), launch count, and the algorithmic flops
+ * and bytes the launches were sized for (GEMM: 8 M N K; bytes: operands read
+ * once plus C written, read too when beta != 0). */
+ms_status ms_debug_profile(ms_ctx ctx, uint32_t mask);
+ms_status ms_debug_profile_read(ms_ctx ctx, const char* category, double* total_ms, int64_t* launches,
+                                double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MS_DEBUG_H */

@@ -38,9 +38,9 @@ __all__ = [
     "ThresholdError", "SingularError", "kinetic", "slice_hamiltonians", "slice_eigen",
     "prepare", "wavevectors", "overlap", "interface_xy", "interface_smatrix",
     "transfer_matrix", "smatrix_from_transfer", "identity_smatrix", "star", "cascade",
-    "recurrence2_cascade", "interface_smatrices", "transmission_from_smatrix",
+    "recurrence2_cascade", "interface_smatrices", "iter_interface_smatrices", "transmission_from_smatrix",
     "transmission", "global_system", "transfer_product", "born_reflection",
-    "LEAD_THRESHOLD",
+    "LEAD_THRESHOLD", "kpar_average",
 ]
 
 LEAD_THRESHOLD = 1e-10
@@ -66,7 +66,7 @@ def kinetic(miller, bvec, kpar) -> np.ndarray:
 
 def slice_hamiltonians(kin, vq, q_of_ij) -> np.ndarray:
     """H^p_{ij} = |k_par+G_i|^2 delta_ij + V^p(G_i - G_j)  (Eq. loc), shape (N_s, N, N)."""
-    h = np.asarray(vq)[:, np.asarray(q_of_ij)]
+    h = np.ascontiguousarray(np.asarray(vq)[:, np.asarray(q_of_ij)])
     idx = np.arange(len(kin))
     h[:, idx, idx] += kin
     return h
@@ -75,7 +75,7 @@ def slice_hamiltonians(kin, vq, q_of_ij) -> np.ndarray:
 def slice_eigen(h):
     """Eigenpairs of each slice Hamiltonian: E^p_n ascending, U^p columns = phi^p_n(G)."""
     eps = np.empty(h.shape[:2])
-    u = np.empty_like(h)
+    u = np.empty(h.shape, dtype=np.complex128)
     for p in range(h.shape[0]):
         eps[p], u[p] = sla.eigh(h[p])
     return eps, u
@@ -111,7 +111,7 @@ def overlap(up, uq) -> np.ndarray:
         return np.array(uq, copy=True)
     if uq is None:
         return up.conj().T.copy()
-    return up.conj().T @ uq
+    return np.ascontiguousarray(up.conj().T) @ uq
 
 
 def interface_xy(o, kp, kq):
@@ -153,7 +153,7 @@ def interface_smatrix(o, kp, kq, dzq) -> dict:
     if np.any(np.abs(np.diag(lu[0])) == 0):
         raise SingularError("X is singular")
     n = x.shape[0]
-    xinv = sla.lu_solve(lu, np.eye(n, dtype=np.complex128))
+    xinv = np.ascontiguousarray(sla.lu_solve(lu, np.eye(n, dtype=np.complex128)))
     xinv_y = xinv @ y
     return dict(t=ph[:, None] * xinv,
                 rp=-(ph[:, None] * xinv_y) * ph[None, :],
@@ -176,8 +176,8 @@ def star(a: dict, b: dict) -> dict:
     lu = sla.lu_factor(f)
     if np.any(np.abs(np.diag(lu[0])) == 0):
         raise SingularError("I - S12(m,n) S21(n,k) is singular")
-    finv_t = sla.lu_solve(lu, a["t"])      # [I - S12 S21]^-1 S11(m,n)
-    finv_rp = sla.lu_solve(lu, a["rp"])    # [I - S12 S21]^-1 S12(m,n)
+    finv_t = np.ascontiguousarray(sla.lu_solve(lu, a["t"]))      # [I - S12 S21]^-1 S11(m,n)
+    finv_rp = np.ascontiguousarray(sla.lu_solve(lu, a["rp"]))    # [I - S12 S21]^-1 S12(m,n)
     return dict(t=b["t"] @ finv_t,
                 rp=b["rp"] + b["t"] @ finv_rp @ b["tp"],
                 r=a["r"] + a["tp"] @ b["r"] @ finv_t,
@@ -230,16 +230,20 @@ def _lead_check(energy, eps_lead):
         raise ThresholdError(f"E = {energy} is within {LEAD_THRESHOLD} of a lead channel threshold")
 
 
-def interface_smatrices(prep: dict, energy: float):
-    """[S(p,p+1) for p = 0..N] at one energy."""
+def iter_interface_smatrices(prep: dict, energy: float, reverse: bool = False):
+    """S(p,p+1) for p = 0..N (or N..0), produced one at a time."""
     _lead_check(energy, prep["eps"][0])
     _lead_check(energy, prep["eps"][-1])
     ks = [wavevectors(energy, e) for e in prep["eps"]]
-    out = []
-    for p in range(prep["n_slices"] + 1):
+    order = range(prep["n_slices"] + 1)
+    for p in (reversed(order) if reverse else order):
         o = overlap(prep["u"][p], prep["u"][p + 1])
-        out.append(interface_smatrix(o, ks[p], ks[p + 1], prep["dz"][p + 1]))
-    return out
+        yield interface_smatrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+
+
+def interface_smatrices(prep: dict, energy: float):
+    """[S(p,p+1) for p = 0..N] at one energy."""
+    return list(iter_interface_smatrices(prep, energy))
 
 
 def transmission_from_smatrix(s: dict, energy: float, eps_left, eps_right):
@@ -260,7 +264,18 @@ def transmission_from_smatrix(s: dict, energy: float, eps_left, eps_right):
 
 def transmission(prep: dict, energy: float, order: str = "left") -> dict:
     """Full path at one (E, k_par): slice S-matrices, star cascade, T and R."""
-    s = cascade(interface_smatrices(prep, energy), order)
+    if order == "left":            # streamed: S(0,1) * S(1,2) * ...
+        it = iter_interface_smatrices(prep, energy)
+        s = next(it)
+        for b in it:
+            s = star(s, b)
+    elif order == "right":         # streamed: ... * (S(N-1,N) * S(N,N+1))
+        it = iter_interface_smatrices(prep, energy, reverse=True)
+        s = next(it)
+        for a in it:
+            s = star(a, s)
+    else:
+        s = cascade(interface_smatrices(prep, energy), order)
     tt, rr, n_open = transmission_from_smatrix(s, energy, prep["eps"][0], prep["eps"][-1])
     return dict(T=tt, R=rr, n_open=n_open, S=s)
 
@@ -355,3 +370,15 @@ def born_reflection(kin, vq, q_of_ij, dz, energy: float) -> np.ndarray:
     v = np.asarray(vq)[:, np.asarray(q_of_ij)]                  # (N_s, N, N)
     ph = (np.exp(1j * kap[None] * z[1:, None, None]) - np.exp(1j * kap[None] * z[:-1, None, None])) / (1j * kap[None])
     return -(1j / (2.0 * k[:, None])) * np.sum(v * ph, axis=0)
+
+
+def kpar_average(t_k, n_open_k):
+    """Per-energy average over the k_par mesh, Sec. II.B Eq. (T1_d):
+    T_bar(E) = (1 / N^x N^y) sum_k T(E, k); also sum_k T / sum_k N_open.
+    Arrays are [n_k][n_e]."""
+    t_k = np.asarray(t_k, dtype=np.float64)
+    n = np.asarray(n_open_k, dtype=np.float64)
+    tbar = t_k.sum(axis=0) / t_k.shape[0]
+    tot = n.sum(axis=0)
+    per = np.where(tot > 0, t_k.sum(axis=0) / np.where(tot > 0, tot, 1.0), 0.0)
+    return tbar, per

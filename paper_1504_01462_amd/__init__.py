@@ -1,0 +1,303 @@
+"""Python binding of the MI355X plane-wave multiple-scattering transport library.
+
+Argument marshalling only: every step runs in the HIP kernels of ``libms.so``
+(built from ``csrc/`` by ``paper_1504_01462_amd.build``).  PyTorch supplies
+device memory and the stream.  The functions carry the names of the C entry
+points declared in ``include/ms.h`` and ``include/ms_debug.h``.
+
+Importing this package fails loudly when ``libms.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library with "
+                      "`python -m paper_1504_01462_amd.build` (or __graft_entry__.build())")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+MS_OK, MS_ERR_ARG, MS_ERR_ALLOC, MS_ERR_HIP, MS_ERR_SINGULAR, MS_ERR_THRESHOLD, MS_ERR_NONFINITE, \
+    MS_ERR_UNSUPPORTED, MS_ERR_NOCONV = range(9)
+MS_PREC_FP64, MS_PREC_FP32_MFMA = 0, 1
+_PREC = {"fp64": MS_PREC_FP64, "fp32": MS_PREC_FP32_MFMA, "fp32_mfma": MS_PREC_FP32_MFMA,
+         MS_PREC_FP64: MS_PREC_FP64, MS_PREC_FP32_MFMA: MS_PREC_FP32_MFMA}
+
+_vp, _i64, _i32, _f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+
+
+class MsSmat(ctypes.Structure):
+    _fields_ = [("n", _i64), ("t", _vp), ("rp", _vp), ("r", _vp), ("tp", _vp)]
+
+
+class MsSlices(ctypes.Structure):
+    _fields_ = [("n_g", _i64), ("n_slices", _i64), ("dz", _vp), ("eps", _vp), ("ovl", _vp), ("evec", _vp)]
+
+
+def _sig(name, args):
+    f = getattr(lib, name)
+    f.argtypes = args
+    f.restype = _i32
+    return f
+
+
+lib.ms_status_str.argtypes = [_i32]
+lib.ms_status_str.restype = ctypes.c_char_p
+_sig("ms_ctx_create", [_i32, _vp, ctypes.POINTER(_vp)])
+_sig("ms_ctx_destroy", [_vp])
+_sig("ms_ctx_sync", [_vp])
+_sig("ms_ctx_last_error", [_vp, ctypes.c_char_p, _i64])
+_sig("ms_slices_prepare", [_vp, _i64, _vp, _vp, _vp, _f64, _f64, _i64, _i64, _vp, _vp, ctypes.POINTER(MsSlices)])
+_sig("ms_slice_smatrix", [_vp, ctypes.POINTER(MsSlices), _f64, _i64, _i64, ctypes.POINTER(MsSmat)])
+_sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER(MsSmat)])
+_sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
+_sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
+_sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
+_sig("ms_debug_profile", [_vp, ctypes.c_uint32])
+_sig("ms_debug_profile_read", [_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp])
+_sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32])
+_sig("ms_debug_lu_solve", [_vp, _i64, _i64, _i64, _vp, _vp, _vp])
+_sig("ms_debug_eigh", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
+
+
+class MSError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        self.status = int(status)
+        name = lib.ms_status_str(int(status)).decode()
+        super().__init__(f"{name}: {message}" if message else name)
+
+
+def ms_status_str(status: int) -> str:
+    return lib.ms_status_str(int(status)).decode()
+
+
+def _check(ctx_handle, status):
+    if status != MS_OK:
+        buf = ctypes.create_string_buffer(512)
+        lib.ms_ctx_last_error(ctx_handle, buf, 512)
+        raise MSError(status, buf.value.decode(errors="replace"))
+
+
+def _ptr(t: torch.Tensor | None, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """ms_ctx bound to one device and the torch stream current at creation."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = torch.device("cuda", device)
+        stream = stream or torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(None, lib.ms_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def sync(self):
+        _check(self.handle, lib.ms_ctx_sync(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib.ms_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+ms_ctx_create = Context
+
+
+class Slices:
+    """E-independent slice data of one k_par (device tensors) and its C view."""
+
+    def __init__(self, n_g: int, n_slices: int, dz: torch.Tensor, eps: torch.Tensor, ovl: torch.Tensor,
+                 evec: torch.Tensor | None = None):
+        self.n_g, self.n_slices = int(n_g), int(n_slices)
+        self.dz, self.eps, self.ovl, self.evec = dz, eps, ovl, evec
+        self.c = MsSlices(self.n_g, self.n_slices, _ptr(dz, torch.float64, "dz"), _ptr(eps, torch.float64, "eps"),
+                          _ptr(ovl, torch.complex128, "ovl"),
+                          _ptr(evec, torch.complex128, "evec") if evec is not None else None)
+
+    @classmethod
+    def empty(cls, n_g, n_slices, dz, device, with_evec=False):
+        eps = torch.empty((n_slices + 2, n_g), dtype=torch.float64, device=device)
+        ovl = torch.empty((n_slices + 1, n_g, n_g), dtype=torch.complex128, device=device)
+        evec = torch.empty((n_slices, n_g, n_g), dtype=torch.complex128, device=device) if with_evec else None
+        return cls(n_g, n_slices, dz, eps, ovl, evec)
+
+
+def _smat(blocks):
+    t, rp, r, tp = blocks
+    n = t.shape[0]
+    return MsSmat(n, _ptr(t, torch.complex128, "t"), _ptr(rp, torch.complex128, "rp"),
+                  _ptr(r, torch.complex128, "r"), _ptr(tp, torch.complex128, "tp"))
+
+
+def ms_slices_prepare(ctx: Context, miller: torch.Tensor, bvec, kpar, q_of_ij: torch.Tensor, vq: torch.Tensor,
+                      dz: torch.Tensor, vlead=(0.0, 0.0), with_evec: bool = False) -> Slices:
+    n_g = int(miller.shape[0])
+    n_slices, n_q = int(vq.shape[0]), int(vq.shape[1])
+    s = Slices.empty(n_g, n_slices, dz, ctx.device, with_evec)
+    b = np.ascontiguousarray(np.asarray(bvec, dtype=np.float64).reshape(4))
+    k = np.ascontiguousarray(np.asarray(kpar, dtype=np.float64).reshape(2))
+    st = lib.ms_slices_prepare(ctx.handle, n_g, _ptr(miller, torch.int32, "miller"),
+                               b.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                               float(vlead[0]), float(vlead[1]), n_slices, n_q,
+                               _ptr(q_of_ij, torch.int32, "q_of_ij"), _ptr(vq, torch.complex128, "vq"),
+                               ctypes.byref(s.c))
+    _check(ctx.handle, st)
+    return s
+
+
+def ms_slice_smatrix(ctx: Context, slices: Slices, energy: float, p0: int, p1: int):
+    n = slices.n_g
+    outs = []
+    for _ in range(p1 - p0):
+        outs.append(tuple(torch.empty((n, n), dtype=torch.complex128, device=ctx.device) for _ in range(4)))
+    arr = (MsSmat * max(1, len(outs)))(*[_smat(o) for o in outs])
+    _check(ctx.handle, lib.ms_slice_smatrix(ctx.handle, ctypes.byref(slices.c), float(energy), p0, p1, arr))
+    return outs
+
+
+def ms_star_cascade(ctx: Context, smats, prec="fp64"):
+    n = smats[0][0].shape[0]
+    arr = (MsSmat * len(smats))(*[_smat(s) for s in smats])
+    whole = tuple(torch.empty((n, n), dtype=torch.complex128, device=ctx.device) for _ in range(4))
+    w = _smat(whole)
+    _check(ctx.handle, lib.ms_star_cascade(ctx.handle, arr, len(smats), _PREC[prec], ctypes.byref(w)))
+    return whole
+
+
+def ms_transmission(ctx: Context, whole, energy: float, eps_left: torch.Tensor, eps_right: torch.Tensor):
+    w = _smat(whole)
+    T = torch.empty(1, dtype=torch.float64, device=ctx.device)
+    R = torch.empty(1, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(1, dtype=torch.int64, device=ctx.device)
+    _check(ctx.handle, lib.ms_transmission(ctx.handle, ctypes.byref(w), float(energy),
+                                           _ptr(eps_left, torch.float64, "eps_left"),
+                                           _ptr(eps_right, torch.float64, "eps_right"),
+                                           _ptr(T), _ptr(R), _ptr(no)))
+    return T, R, no
+
+
+def ms_transmission_batch(ctx: Context, slices: Slices, energies, prec="fp64"):
+    e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).reshape(-1))
+    n_e = e.size
+    T = torch.empty(n_e, dtype=torch.float64, device=ctx.device)
+    R = torch.empty(n_e, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(n_e, dtype=torch.int64, device=ctx.device)
+    st = torch.empty(n_e, dtype=torch.int32, device=ctx.device)
+    _check(ctx.handle, lib.ms_transmission_batch(ctx.handle, ctypes.byref(slices.c), n_e,
+                                                 e.ctypes.data_as(ctypes.c_void_p), _PREC[prec],
+                                                 _ptr(T), _ptr(R), _ptr(no), _ptr(st)))
+    return T, R, no, st
+
+
+def ms_kpar_average(ctx: Context, T: torch.Tensor, n_open: torch.Tensor):
+    """T, n_open: [n_k][n_e] device tensors -> (tbar [n_e], per_channel [n_e])."""
+    n_k, n_e = T.shape
+    tbar = torch.empty(n_e, dtype=torch.float64, device=ctx.device)
+    pc = torch.empty(n_e, dtype=torch.float64, device=ctx.device)
+    _check(ctx.handle, lib.ms_kpar_average(ctx.handle, n_k, n_e, _ptr(T, torch.float64, "T"),
+                                           _ptr(n_open, torch.int64, "n_open"), _ptr(tbar), _ptr(pc)))
+    return tbar, pc
+
+
+PROFILE_CATEGORIES = ("iface_gemm", "lu_panel", "lu_swap", "lu_update", "trsm", "jacobi", "prep_gemm", "elem",
+                      "other")
+
+
+def ms_debug_profile(ctx: Context, categories=True):
+    """Time the launches of `categories` (True = all, False/None/() = stop, or names)."""
+    if categories is True:
+        mask = (1 << len(PROFILE_CATEGORIES)) - 1
+    elif not categories:
+        mask = 0
+    else:
+        names = [categories] if isinstance(categories, str) else list(categories)
+        mask = 0
+        for c in names:
+            mask |= 1 << PROFILE_CATEGORIES.index(c)
+    _check(ctx.handle, lib.ms_debug_profile(ctx.handle, mask))
+
+
+def ms_debug_profile_read(ctx: Context, category: str):
+    """(total_ms, launches, flops, bytes) of the launches recorded since the last read."""
+    tot, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(ctx.handle, lib.ms_debug_profile_read(ctx.handle, category.encode(), ctypes.byref(tot), ctypes.byref(n),
+                                                 ctypes.byref(fl), ctypes.byref(by)))
+    return tot.value, n.value, fl.value, by.value
+
+
+def ms_debug_gemm(ctx: Context, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None, op_a=0, op_b=0,
+                  alpha=1.0, beta=0.0, prec="fp64"):
+    m = a.shape[1] if op_a else a.shape[0]
+    k = a.shape[0] if op_a else a.shape[1]
+    n = b.shape[0] if op_b else b.shape[1]
+    if c is None:
+        c = torch.zeros((m, n), dtype=torch.complex128, device=ctx.device)
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    dt = torch.complex128 if _PREC[prec] == MS_PREC_FP64 else torch.complex64
+    _check(ctx.handle, lib.ms_debug_gemm(ctx.handle, op_a, op_b, m, n, k, _ptr(a, dt, "a"), a.shape[1],
+                                         _ptr(b, dt, "b"), b.shape[1], _ptr(c, torch.complex128, "c"), c.shape[1],
+                                         al.ctypes.data_as(ctypes.c_void_p), be.ctypes.data_as(ctypes.c_void_p),
+                                         _PREC[prec]))
+    return c
+
+
+def ms_debug_lu_solve(ctx: Context, aug: torch.Tensor, n: int):
+    batch, rows, cols = aug.shape
+    nrhs = cols - n
+    x = torch.empty((batch, n, nrhs), dtype=torch.complex128, device=ctx.device)
+    st = torch.empty(batch, dtype=torch.int32, device=ctx.device)
+    _check(ctx.handle, lib.ms_debug_lu_solve(ctx.handle, n, nrhs, batch, _ptr(aug, torch.complex128, "aug"),
+                                             _ptr(x), _ptr(st)))
+    return x, st
+
+
+def ms_debug_eigh(ctx: Context, h: torch.Tensor, shift: torch.Tensor):
+    batch, n, _ = h.shape
+    eps = torch.empty((batch, n), dtype=torch.float64, device=ctx.device)
+    u = torch.empty((batch, n, n), dtype=torch.complex128, device=ctx.device)
+    _check(ctx.handle, lib.ms_debug_eigh(ctx.handle, n, batch, _ptr(h, torch.complex128, "h"),
+                                         _ptr(shift, torch.float64, "shift"), _ptr(eps), _ptr(u)))
+    return eps, u
+
+
+def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=False) -> Slices:
+    """Upload one k_par's seeded inputs (``msgen.junction_inputs``) and run ms_slices_prepare."""
+    dev = ctx.device
+    miller = torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev)
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev)
+    vq = torch.as_tensor(np.ascontiguousarray(inp["vq"], dtype=np.complex128), device=dev)
+    dz = torch.as_tensor(np.ascontiguousarray(inp["dz"], dtype=np.float64), device=dev)
+    return ms_slices_prepare(ctx, miller, np.asarray(inp["bvec"]).reshape(4), inp["kpar"], q, vq, dz, vlead,
+                             with_evec)
+
+
+__all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
+           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_transmission",
+           "ms_transmission_batch", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
+           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_lu_solve", "ms_debug_eigh",
+           "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

@@ -1,0 +1,617 @@
+// C ABI of the MI355X multiple-scattering library: context, workspace, argument
+// checking and the orchestration of the kernels (include/ms.h documents the calls).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "elem.h"
+#include "ms_internal.h"
+
+static thread_local std::string g_create_error;
+
+namespace ms {
+
+ms_status fail(ms_ctx ctx, ms_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->last_error = buf;
+  else g_create_error = buf;
+  return s;
+}
+
+ms_status hip_fail(ms_ctx ctx, hipError_t e, const char* what) {
+  const ms_status s = (e == hipErrorOutOfMemory) ? MS_ERR_ALLOC : MS_ERR_HIP;
+  return fail(ctx, s, "%s: %s", what, hipGetErrorString(e));
+}
+
+ms_status check_launch(ms_ctx ctx, const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
+  return MS_OK;
+}
+
+ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out) {
+  if ((size_t)slot >= ctx->ws.size()) {
+    ctx->ws.resize(slot + 1, nullptr);
+    ctx->ws_size.resize(slot + 1, 0);
+  }
+  if (bytes == 0) bytes = 256;
+  if (ctx->ws_size[slot] < bytes) {
+    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->ws[slot]) MS_HIP(ctx, hipFree(ctx->ws[slot]));
+    ctx->ws[slot] = nullptr;
+    ctx->ws_size[slot] = 0;
+    const size_t want = (bytes + 4095) & ~(size_t)4095;
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return hip_fail(ctx, e, "workspace hipMalloc");
+    ctx->ws[slot] = p;
+    ctx->ws_size[slot] = want;
+  }
+  *out = ctx->ws[slot];
+  return MS_OK;
+}
+
+static hipEvent_t take_event(ms_ctx ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+Prof::Prof(ms_ctx c, int category, double fl, double by) : ctx(c), cat(category), flops(fl), bytes(by) {
+  if (ctx && (ctx->prof_mask >> category & 1u)) {
+    a = take_event(ctx);
+    if (a) (void)hipEventRecord(a, ctx->stream);
+  }
+}
+
+Prof::~Prof() {
+  if (!a) return;
+  hipEvent_t b = take_event(ctx);
+  if (!b) return;
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->prof[cat].push_back(ProfRec{a, b, flops, bytes});
+}
+
+ms_status upload(ms_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return MS_OK;
+  MS_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MS_OK;
+}
+
+}  // namespace ms
+
+using namespace ms;
+
+namespace {
+
+// workspace slots
+enum {
+  WS_KIN = 0, WS_SHIFT, WS_W, WS_U, WS_MISC, WS_K, WS_P, WS_AOP, WS_WG, WS_M,
+  WS_JPAIRS = 10, WS_JCOUNT = 11,
+  WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
+  WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V
+};
+
+constexpr int MAX_N = 4096;
+constexpr size_t BATCH_BUDGET = size_t(24) << 30;   // bytes of per-energy workspace per sub-batch
+constexpr size_t PREP_BUDGET = size_t(4) << 30;     // bytes of eigensolver workspace per chunk
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+ms_status check_slices(ms_ctx ctx, const ms_slices* s) {
+  if (!s) return fail(ctx, MS_ERR_ARG, "slices is NULL");
+  if (s->n_g <= 0 || s->n_slices <= 0) return fail(ctx, MS_ERR_ARG, "n_g and n_slices must be positive");
+  if (s->n_g > MAX_N) return fail(ctx, MS_ERR_UNSUPPORTED, "n_g = %lld > %d", (long long)s->n_g, MAX_N);
+  if (bad_ptr(s->dz) || bad_ptr(s->eps) || bad_ptr(s->ovl))
+    return fail(ctx, MS_ERR_ARG, "slices->dz, eps and ovl must be device pointers");
+  return MS_OK;
+}
+
+ms_status check_smat(ms_ctx ctx, const ms_smat* s, int64_t n, const char* name) {
+  if (!s) return fail(ctx, MS_ERR_ARG, "%s is NULL", name);
+  if (s->n != n) return fail(ctx, MS_ERR_ARG, "%s.n = %lld, expected %lld", name, (long long)s->n, (long long)n);
+  if (bad_ptr(s->t) || bad_ptr(s->rp) || bad_ptr(s->r) || bad_ptr(s->tp))
+    return fail(ctx, MS_ERR_ARG, "%s has a NULL block", name);
+  return MS_OK;
+}
+
+inline double2* c2(void* p) { return static_cast<double2*>(p); }
+inline const double2* c2(const void* p) { return static_cast<const double2*>(p); }
+
+ms_status gemm(ms_ctx ctx, int M, int N, int K, const void* A, int64_t lda, int opA, const void* B, int64_t ldb,
+               int opB, void* C, int64_t ldc, double2 alpha, double2 beta) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.opA = opA;
+  g.B = B; g.ldb = ldb; g.opB = opB;
+  g.C = c2(C); g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  return zgemm(ctx, g);
+}
+
+const double2 ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
+
+}  // namespace
+
+extern "C" {
+
+const char* ms_status_str(ms_status s) {
+  switch (s) {
+    case MS_OK: return "MS_OK";
+    case MS_ERR_ARG: return "MS_ERR_ARG";
+    case MS_ERR_ALLOC: return "MS_ERR_ALLOC";
+    case MS_ERR_HIP: return "MS_ERR_HIP";
+    case MS_ERR_SINGULAR: return "MS_ERR_SINGULAR";
+    case MS_ERR_THRESHOLD: return "MS_ERR_THRESHOLD";
+    case MS_ERR_NONFINITE: return "MS_ERR_NONFINITE";
+    case MS_ERR_UNSUPPORTED: return "MS_ERR_UNSUPPORTED";
+    case MS_ERR_NOCONV: return "MS_ERR_NOCONV";
+  }
+  return "MS_ERR_UNKNOWN";
+}
+
+ms_status ms_ctx_last_error(ms_ctx ctx, char* buf, int64_t len) {
+  if (!buf || len <= 0) return MS_ERR_ARG;
+  const std::string& m = ctx ? ctx->last_error : g_create_error;
+  const size_t k = std::min((size_t)(len - 1), m.size());
+  memcpy(buf, m.data(), k);
+  buf[k] = 0;
+  return MS_OK;
+}
+
+ms_status ms_ctx_create(int device, void* hip_stream, ms_ctx* out) {
+  if (!out) return fail(nullptr, MS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return fail(nullptr, MS_ERR_HIP, "no HIP device available");
+  if (device < 0 || device >= count) return fail(nullptr, MS_ERR_ARG, "device %d out of range [0,%d)", device, count);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(nullptr, MS_ERR_HIP, "hipSetDevice: %s", hipGetErrorString(e));
+  ms_ctx c = new ms_ctx_s;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  e = hipMalloc(&c->d_status, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream);
+  if (e != hipSuccess) {
+    if (c->d_status) (void)hipFree(c->d_status);
+    delete c;
+    return fail(nullptr, MS_ERR_HIP, "context status word: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return MS_OK;
+}
+
+ms_status ms_ctx_destroy(ms_ctx ctx) {
+  if (!ctx) return MS_ERR_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& v : ctx->prof)
+    for (auto& r : v) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : ctx->ws)
+    if (p) (void)hipFree(p);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  delete ctx;
+  return MS_OK;
+}
+
+ms_status ms_ctx_sync(ms_ctx ctx) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int32_t st = 0;
+  MS_HIP(ctx, hipMemcpy(&st, ctx->d_status, sizeof st, hipMemcpyDeviceToHost));
+  MS_HIP(ctx, hipMemset(ctx->d_status, 0, sizeof(int32_t)));
+  if (st != 0) return fail(ctx, (ms_status)st, "device reported %s", ms_status_str((ms_status)st));
+  return MS_OK;
+}
+
+static const char* const kProfNames[PC_COUNT] = {"iface_gemm", "lu_panel", "lu_swap", "lu_update", "trsm",
+                                                  "jacobi", "prep_gemm", "elem", "other"};
+
+ms_status ms_debug_profile(ms_ctx ctx, uint32_t mask) {
+  if (!ctx) return MS_ERR_ARG;
+  ctx->prof_mask = mask;
+  return MS_OK;
+}
+
+ms_status ms_debug_profile_read(ms_ctx ctx, const char* category, double* total_ms, int64_t* launches,
+                                double* flops, double* bytes) {
+  if (!ctx || !category || !total_ms || !launches || !flops || !bytes) return MS_ERR_ARG;
+  int cat = -1;
+  for (int i = 0; i < PC_COUNT; ++i)
+    if (strcmp(category, kProfNames[i]) == 0) cat = i;
+  if (cat < 0) return fail(ctx, MS_ERR_ARG, "unknown profiler category '%s'", category);
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0, fl = 0.0, by = 0.0;
+  for (auto& r : ctx->prof[cat]) {
+    float ms = 0.f;
+    MS_HIP(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    fl += r.flops;
+    by += r.bytes;
+    ctx->ev_pool.push_back(r.a);
+    ctx->ev_pool.push_back(r.b);
+  }
+  *launches = (int64_t)ctx->prof[cat].size();
+  ctx->prof[cat].clear();
+  *total_ms = tot;
+  *flops = fl;
+  *bytes = by;
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_slices_prepare(ms_ctx ctx, int64_t n_g, const int32_t* g_mn, const double* bvec, const double* kpar,
+                            double vlead_left, double vlead_right, int64_t n_slices, int64_t n_q,
+                            const int32_t* q_of_ij, const void* vq, ms_slices* inout) {
+  if (!ctx) return MS_ERR_ARG;
+  if (bad_ptr(g_mn) || bad_ptr(bvec) || bad_ptr(kpar) || bad_ptr(q_of_ij) || bad_ptr(vq))
+    return fail(ctx, MS_ERR_ARG, "NULL input pointer");
+  MS_TRY(check_slices(ctx, inout));
+  if (inout->n_g != n_g || inout->n_slices != n_slices)
+    return fail(ctx, MS_ERR_ARG, "inout sizes do not match n_g / n_slices");
+  if (n_q <= 0) return fail(ctx, MS_ERR_ARG, "n_q must be positive");
+  if (!std::isfinite(vlead_left) || !std::isfinite(vlead_right))
+    return fail(ctx, MS_ERR_ARG, "lead potentials must be finite");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)n_g;
+  const int ns = (int)n_slices;
+  const int64_t nn = (int64_t)n * n;
+  double* eps = inout->eps;
+  double2* ovl = c2(inout->ovl);
+
+  void *kin, *shift, *W, *U;
+  MS_TRY(workspace(ctx, WS_KIN, n * sizeof(double), &kin));
+  MS_TRY(launch_kin_eps(ctx, n, g_mn, bvec, kpar, vlead_left, vlead_right, (double*)kin, eps,
+                        eps + (int64_t)(ns + 1) * n));
+  MS_TRY(launch_nonfinite_scan(ctx, (int64_t)ns * n_q, c2(vq), ctx->d_status));
+  // every index of the difference map must address vq
+  void* mm = nullptr;
+  MS_TRY(workspace(ctx, WS_MISC, 4 * sizeof(int32_t), &mm));
+  MS_TRY(launch_minmax(ctx, nn, q_of_ij, (int32_t*)mm));
+  int32_t qr[3] = {0, 0, 0};
+  MS_HIP(ctx, hipMemcpyAsync(qr, mm, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(qr + 2, q_of_ij, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (qr[0] < 0 || qr[1] >= n_q)
+    return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
+  const int32_t q0 = qr[2];
+
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(PREP_BUDGET / (2 * nn * sizeof(double2)))));
+  chunk = std::min(chunk, 256);
+  MS_TRY(workspace(ctx, WS_SHIFT, chunk * sizeof(double), &shift));
+  MS_TRY(workspace(ctx, WS_W, (size_t)chunk * nn * sizeof(double2), &W));
+  MS_TRY(workspace(ctx, WS_U, (size_t)(chunk + 1) * nn * sizeof(double2), &U));
+  double2* Ub = c2(U);
+  for (int s0 = 0; s0 < ns; s0 += chunk) {
+    const int bc = std::min(chunk, ns - s0);
+    const double2* vq_c = c2(vq) + (int64_t)s0 * n_q;
+    MS_TRY(launch_slice_shift(ctx, n, bc, (const double*)kin, n_q, vq_c, q0, (double*)shift));
+    MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, (const double*)shift, n_q, vq_c, q_of_ij, c2(W)));
+    // slice s0+i (paper p = s0+i+1) -> eps row s0+i+1, U slot i+1
+    MS_TRY(jacobi_eigh(ctx, n, bc, c2(W), (const double*)shift, eps + (int64_t)(s0 + 1) * n, n, Ub + nn, nn,
+                       ctx->d_status));
+    // overlaps O^p = U^p^dagger U^{p+1}; slots: 0 = U^{s0} (previous chunk), i = U^{s0+i}
+    const int P0 = s0 + 1, P1 = s0 + bc;
+    if (P0 == 1) MS_TRY(launch_copy_boundary_overlaps(ctx, n, Ub + nn, ovl, 0));   // O^0 = U^1
+    const int pstart = (P0 == 1) ? P0 : P0 - 1;
+    if (P1 > pstart) {
+      GemmArgs g;
+      g.M = n; g.N = n; g.K = n;
+      g.opA = OP_C; g.A = Ub + (int64_t)(pstart - P0 + 1) * nn; g.lda = n; g.sA = nn;
+      g.opB = OP_N; g.B = Ub + (int64_t)(pstart - P0 + 2) * nn; g.ldb = n; g.sB = nn;
+      g.C = ovl + (int64_t)pstart * nn; g.ldc = n; g.sC = nn;
+      g.batch = P1 - pstart;
+      g.prof = PC_PREP_GEMM;
+      MS_TRY(zgemm(ctx, g));
+    }
+    if (inout->evec)
+      MS_HIP(ctx, hipMemcpyAsync(c2(inout->evec) + (int64_t)s0 * nn, Ub + nn, (size_t)bc * nn * sizeof(double2),
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(Ub, Ub + (int64_t)bc * nn, nn * sizeof(double2), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  }
+  // O^{n_slices} = U^{n_slices}^dagger
+  MS_TRY(launch_copy_boundary_overlaps(ctx, n, Ub, ovl + (int64_t)ns * nn, 1));
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_slice_smatrix(ms_ctx ctx, const ms_slices* slices, double energy, int64_t p0, int64_t p1,
+                           const ms_smat* out) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  if (p0 < 0 || p1 > slices->n_slices + 1 || p0 >= p1)
+    return fail(ctx, MS_ERR_ARG, "interface range [%lld,%lld) outside [0,%lld]", (long long)p0, (long long)p1,
+                (long long)slices->n_slices + 1);
+  if (!out) return fail(ctx, MS_ERR_ARG, "out is NULL");
+  for (int64_t i = 0; i < p1 - p0; ++i) MS_TRY(check_smat(ctx, out + i, slices->n_g, "out[i]"));
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
+  const int64_t nn = (int64_t)n * n;
+  void *en, *kb, *pb, *aug, *xc, *yc, *z, *s4, *piv;
+  MS_TRY(workspace(ctx, WS_EN, sizeof(double), &en));
+  MS_TRY(upload(ctx, en, &energy, sizeof(double)));
+  MS_TRY(workspace(ctx, WS_K, (size_t)nrows * n * sizeof(double2), &kb));
+  MS_TRY(workspace(ctx, WS_P, (size_t)nrows * n * sizeof(double2), &pb));
+  MS_TRY(launch_wavevectors(ctx, n, nrows, 1, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb)));
+  const int64_t per = 10 * nn * (int64_t)sizeof(double2);
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(p1 - p0, (int64_t)(PREP_BUDGET / per)));
+  chunk = std::min(chunk, 4096);
+  MS_TRY(workspace(ctx, WS_AUG, (size_t)chunk * 3 * nn * sizeof(double2), &aug));
+  MS_TRY(workspace(ctx, WS_XC, (size_t)chunk * nn * sizeof(double2), &xc));
+  MS_TRY(workspace(ctx, WS_YC, (size_t)chunk * nn * sizeof(double2), &yc));
+  MS_TRY(workspace(ctx, WS_Z, (size_t)chunk * 2 * nn * sizeof(double2), &z));
+  MS_TRY(workspace(ctx, WS_S4, (size_t)chunk * 4 * nn * sizeof(double2), &s4));
+  MS_TRY(workspace(ctx, WS_PIV, (size_t)chunk * n * sizeof(int32_t), &piv));
+  for (int64_t q = p0; q < p1; q += chunk) {
+    const int bc = (int)std::min<int64_t>(chunk, p1 - q);
+    MS_TRY(launch_xy(ctx, n, bc, c2(slices->ovl), c2(kb), (int)q, c2(aug), c2(xc), c2(yc)));
+    MS_TRY(getrf_aug(ctx, c2(aug), n, 3 * n, 3 * nn, bc, (int32_t*)piv, ctx->d_status, 0));
+    MS_TRY(trsm_upper_aug(ctx, c2(aug), n, 3 * n, 3 * nn, bc, c2(z), 2 * n, 2 * nn, ctx->d_status, 0));
+    double2* st = c2(s4);
+    double2* srp = st + (int64_t)bc * nn;
+    double2* sr = srp + (int64_t)bc * nn;
+    double2* stp = sr + (int64_t)bc * nn;
+    // S21 = Y X^-1
+    GemmArgs g;
+    g.M = n; g.N = n; g.K = n;
+    g.A = yc; g.lda = n; g.sA = nn;
+    g.B = z; g.ldb = 2 * n; g.sB = 2 * nn;
+    g.C = sr; g.ldc = n; g.sC = nn;
+    g.batch = bc;
+    MS_TRY(zgemm(ctx, g));
+    // Xc <- X - Y (X^-1 Y)
+    g.B = c2(z) + n;
+    g.C = c2(xc);
+    g.alpha = MONE;
+    g.beta = ONE;
+    MS_TRY(zgemm(ctx, g));
+    MS_TRY(launch_smat_finish(ctx, n, bc, c2(z), c2(xc), c2(pb), (int)q, st, srp, stp));
+    for (int i = 0; i < bc; ++i) {
+      const ms_smat& o = out[q - p0 + i];
+      const size_t bytes = nn * sizeof(double2);
+      MS_HIP(ctx, hipMemcpyAsync(o.t, st + i * nn, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      MS_HIP(ctx, hipMemcpyAsync(o.rp, srp + i * nn, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      MS_HIP(ctx, hipMemcpyAsync(o.r, sr + i * nn, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      MS_HIP(ctx, hipMemcpyAsync(o.tp, stp + i * nn, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct Blocks {
+  double2 *t, *rp, *r, *tp;
+};
+
+// out = a * b (Redheffer star product); out must not alias a or b.
+ms_status star(ms_ctx ctx, int n, Blocks a, Blocks b, Blocks out) {
+  const int64_t nn = (int64_t)n * n;
+  void *aug, *z, *g, *h, *v, *piv;
+  MS_TRY(workspace(ctx, WS_AUG, 3 * nn * sizeof(double2), &aug));
+  MS_TRY(workspace(ctx, WS_Z, 2 * nn * sizeof(double2), &z));
+  MS_TRY(workspace(ctx, WS_G, nn * sizeof(double2), &g));
+  MS_TRY(workspace(ctx, WS_H, nn * sizeof(double2), &h));
+  MS_TRY(workspace(ctx, WS_V, nn * sizeof(double2), &v));
+  MS_TRY(workspace(ctx, WS_PIV, n * sizeof(int32_t), &piv));
+  const size_t bytes = nn * sizeof(double2);
+  // [F | t_a | rp_a] with F = I - rp_a r_b
+  MS_TRY(launch_star_aug(ctx, n, a.t, a.rp, c2(aug)));
+  MS_TRY(gemm(ctx, n, n, n, a.rp, n, OP_N, b.r, n, OP_N, aug, 3 * n, MONE, ONE));
+  MS_TRY(getrf_aug(ctx, c2(aug), n, 3 * n, 3 * nn, 1, (int32_t*)piv, ctx->d_status, 0));
+  // Z = [F^-1 t_a | F^-1 rp_a]
+  MS_TRY(trsm_upper_aug(ctx, c2(aug), n, 3 * n, 3 * nn, 1, c2(z), 2 * n, 2 * nn, ctx->d_status, 0));
+  const double2* w1 = c2(z);
+  const double2* w2 = c2(z) + n;
+  // G = tp_a r_b
+  MS_TRY(gemm(ctx, n, n, n, a.tp, n, OP_N, b.r, n, OP_N, g, n, ONE, ZERO));
+  // t = t_b W1
+  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, w1, 2 * n, OP_N, out.t, n, ONE, ZERO));
+  // r = r_a + G W1
+  MS_HIP(ctx, hipMemcpyAsync(out.r, a.r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(gemm(ctx, n, n, n, g, n, OP_N, w1, 2 * n, OP_N, out.r, n, ONE, ONE));
+  // rp = rp_b + (t_b W2) tp_b
+  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, w2, 2 * n, OP_N, h, n, ONE, ZERO));
+  MS_HIP(ctx, hipMemcpyAsync(out.rp, b.rp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(gemm(ctx, n, n, n, h, n, OP_N, b.tp, n, OP_N, out.rp, n, ONE, ONE));
+  // tp = (tp_a + G W2) tp_b
+  MS_HIP(ctx, hipMemcpyAsync(v, a.tp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(gemm(ctx, n, n, n, g, n, OP_N, w2, 2 * n, OP_N, v, n, ONE, ONE));
+  MS_TRY(gemm(ctx, n, n, n, v, n, OP_N, b.tp, n, OP_N, out.tp, n, ONE, ZERO));
+  return MS_OK;
+}
+
+Blocks blocks_of(const ms_smat& s) { return Blocks{c2(s.t), c2(s.rp), c2(s.r), c2(s.tp)}; }
+
+}  // namespace
+
+ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec prec, ms_smat* whole) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!s || n_mats <= 0) return fail(ctx, MS_ERR_ARG, "need at least one S-matrix");
+  if (prec != MS_PREC_FP64) return fail(ctx, MS_ERR_UNSUPPORTED, "ms_star_cascade supports MS_PREC_FP64 only");
+  const int64_t n64 = s[0].n;
+  if (n64 <= 0) return fail(ctx, MS_ERR_ARG, "s[0].n must be positive");
+  if (n64 > MAX_N) return fail(ctx, MS_ERR_UNSUPPORTED, "n = %lld > %d", (long long)n64, MAX_N);
+  for (int64_t i = 0; i < n_mats; ++i) MS_TRY(check_smat(ctx, s + i, n64, "s[i]"));
+  MS_TRY(check_smat(ctx, whole, n64, "whole"));
+  const void* wp[4] = {whole->t, whole->rp, whole->r, whole->tp};
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      if (wp[a] == wp[b]) return fail(ctx, MS_ERR_ARG, "whole blocks must be distinct");
+  for (int64_t i = 0; i < n_mats; ++i) {
+    const void* sp[4] = {s[i].t, s[i].rp, s[i].r, s[i].tp};
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        if (wp[a] == sp[b]) return fail(ctx, MS_ERR_ARG, "whole aliases input %lld", (long long)i);
+  }
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)n64;
+  const int64_t nn = (int64_t)n * n;
+  const size_t bytes = nn * sizeof(double2);
+  if (n_mats == 1) {
+    MS_HIP(ctx, hipMemcpyAsync(whole->t, s[0].t, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(whole->rp, s[0].rp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(whole->r, s[0].r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(whole->tp, s[0].tp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    return MS_OK;
+  }
+  void *acc0, *acc1;
+  MS_TRY(workspace(ctx, WS_ACC0, 4 * bytes, &acc0));
+  MS_TRY(workspace(ctx, WS_ACC1, 4 * bytes, &acc1));
+  Blocks acc[2] = {{c2(acc0), c2(acc0) + nn, c2(acc0) + 2 * nn, c2(acc0) + 3 * nn},
+                   {c2(acc1), c2(acc1) + nn, c2(acc1) + 2 * nn, c2(acc1) + 3 * nn}};
+  Blocks a = blocks_of(s[0]);
+  int cur = 0;
+  for (int64_t i = 1; i < n_mats; ++i) {
+    Blocks dst = (i == n_mats - 1) ? blocks_of(*whole) : acc[cur];
+    MS_TRY(star(ctx, n, a, blocks_of(s[i]), dst));
+    a = dst;
+    cur ^= 1;
+  }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_transmission(ms_ctx ctx, const ms_smat* whole, double energy, const double* eps_left,
+                          const double* eps_right, double* T, double* R, int64_t* n_open) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!whole) return fail(ctx, MS_ERR_ARG, "whole is NULL");
+  if (whole->n <= 0 || whole->n > MAX_N) return fail(ctx, MS_ERR_ARG, "bad whole.n");
+  MS_TRY(check_smat(ctx, whole, whole->n, "whole"));
+  if (bad_ptr(eps_left) || bad_ptr(eps_right) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  return launch_whole_T(ctx, (int)whole->n, energy, c2(whole->t), c2(whole->r), eps_left, eps_right, T, R, n_open,
+                        ctx->d_status);
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const double* energies,
+                                ms_prec prec, double* T, double* R, int64_t* n_open, int32_t* point_status) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (n_e < 0) return fail(ctx, MS_ERR_ARG, "n_e must be >= 0");
+  if (n_e == 0) return MS_OK;
+  if (bad_ptr(energies) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open) || bad_ptr(point_status))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
+  for (int64_t e = 0; e < n_e; ++e)
+    if (!std::isfinite(energies[e])) return fail(ctx, MS_ERR_ARG, "energy %lld is not finite", (long long)e);
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const bool fp32 = prec == MS_PREC_FP32_MFMA;
+  const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
+  const int64_t nn = (int64_t)n * n;
+  const double* eps_l = slices->eps;
+  const double* eps_r = slices->eps + (int64_t)(ns + 1) * n;
+
+  // open channels of the right lead at the highest energy, lowest first
+  std::vector<double> er(n);
+  MS_HIP(ctx, hipMemcpyAsync(er.data(), eps_r, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const double emax = *std::max_element(energies, energies + n_e);
+  std::vector<int32_t> ch;
+  for (int i = 0; i < n; ++i)
+    if (er[i] < emax) ch.push_back(i);
+  std::stable_sort(ch.begin(), ch.end(), [&](int32_t a, int32_t b) { return er[a] < er[b]; });
+  const int n_o = (int)ch.size();
+  void *chd, *end;
+  MS_TRY(workspace(ctx, WS_CH, std::max<size_t>(1, ch.size()) * sizeof(int32_t), &chd));
+  MS_TRY(upload(ctx, chd, ch.data(), n_o * sizeof(int32_t)));
+  MS_TRY(workspace(ctx, WS_EN, n_e * sizeof(double), &end));
+  MS_TRY(upload(ctx, end, energies, n_e * sizeof(double)));
+  MS_HIP(ctx, hipMemsetAsync(point_status, 0, n_e * sizeof(int32_t), ctx->stream));
+
+  const int ldm = 2 * n + n_o, ldy = n + n_o;
+  const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
+  const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
+                       2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
+  int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(n_e, (int64_t)(BATCH_BUDGET / per_e)));
+  nbe = std::min(nbe, 65535);
+  void *kb, *pb, *aop, *wg, *mm, *yb, *piv, *oc = nullptr;
+  MS_TRY(workspace(ctx, WS_K, (size_t)nbe * sk * sizeof(double2), &kb));
+  MS_TRY(workspace(ctx, WS_P, (size_t)nbe * sk * sizeof(double2), &pb));
+  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
+  MS_TRY(workspace(ctx, WS_WG, (size_t)nbe * 2 * nn * sizeof(double2), &wg));
+  MS_TRY(workspace(ctx, WS_M, (size_t)nbe * sM * sizeof(double2), &mm));
+  MS_TRY(workspace(ctx, WS_Y, (size_t)nbe * sY * sizeof(double2), &yb));
+  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbe * n * sizeof(int32_t), &piv));
+  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
+
+  for (int64_t e0 = 0; e0 < n_e; e0 += nbe) {
+    const int be = (int)std::min<int64_t>(nbe, n_e - e0);
+    const double* en_d = (const double*)end + e0;
+    int32_t* pst = point_status + e0;
+    MS_TRY(launch_wavevectors(ctx, n, nrows, be, slices->eps, en_d, slices->dz, c2(kb), c2(pb)));
+    for (int p = ns; p >= 0; --p) {
+      const double2* kp = c2(kb) + (int64_t)p * n;
+      const double2* kq = c2(kb) + (int64_t)(p + 1) * n;
+      const double2* pq = c2(pb) + (int64_t)(p + 1) * n;
+      const double2* O = c2(slices->ovl) + (int64_t)p * nn;
+      const bool first = (p == ns);
+      if (!first) {
+        MS_TRY(launch_prologue(ctx, n, be, c2(yb), ldy, sY, kq, pq, sk, aop, fp32));
+        GemmArgs g;
+        g.M = 2 * n; g.N = n; g.K = n;
+        g.A = aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
+        g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
+        g.C = c2(wg); g.ldc = n; g.sC = 2 * nn;
+        g.batch = be;
+        g.prof = PC_IFACE_GEMM;
+        if (fp32) {
+          MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
+          g.B = oc;
+          MS_TRY(cgemm32(ctx, g));
+        } else {
+          MS_TRY(zgemm(ctx, g));
+        }
+      }
+      MS_TRY(launch_epilogue(ctx, n, be, O, first ? nullptr : c2(wg), kp, kq, sk, c2(mm), ldm, sM));
+      MS_TRY(launch_tcols(ctx, n, n_o, be, (const int32_t*)chd, c2(yb), ldy, sY, n, kq, pq, sk, first ? 1 : 0,
+                          c2(mm), ldm, sM));
+      MS_TRY(getrf_aug(ctx, c2(mm), n, ldm, sM, be, (int32_t*)piv, pst, 1));
+      MS_TRY(trsm_upper_aug(ctx, c2(mm), n, ldm, sM, be, c2(yb), ldy, sY, pst, 1));
+    }
+    MS_TRY(launch_batch_T(ctx, n, n_o, be, (const int32_t*)chd, en_d, eps_l, eps_r, c2(yb), ldy, sY, T + e0, R + e0,
+                          n_open + e0, pst));
+  }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open, double* tbar,
+                          double* per_channel) {
+  if (!ctx) return MS_ERR_ARG;
+  if (n_k <= 0 || n_e <= 0) return fail(ctx, MS_ERR_ARG, "n_k and n_e must be positive");
+  if (bad_ptr(T) || bad_ptr(n_open) || bad_ptr(tbar) || bad_ptr(per_channel))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  return launch_kpar_average(ctx, n_k, n_e, T, n_open, tbar, per_channel);
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Kernel-level entry points for unit tests (include/ms_debug.h).
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/ms_debug.h"
+#include "ms_internal.h"
+
+using namespace ms;
+
+namespace {
+__global__ void k_add_shift(int n, const double* shift, double2* W) {
+  const int64_t b = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) W[b * (int64_t)n * n + (int64_t)i * n + i].x += shift[b];
+}
+}  // namespace
+
+extern "C" {
+
+ms_status ms_debug_gemm(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, int64_t k, const void* a, int64_t lda,
+                        const void* b, int64_t ldb, void* c, int64_t ldc, const double* alpha, const double* beta,
+                        ms_prec prec) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!a || !b || !c || !alpha || !beta) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (op_a < 0 || op_a > 2 || op_b < 0 || op_b > 2) return fail(ctx, MS_ERR_ARG, "op codes are 0, 1, 2");
+  if (m <= 0 || n <= 0 || k < 0 || m > (1 << 30) || n > (1 << 30) || k > (1 << 30))
+    return fail(ctx, MS_ERR_ARG, "bad sizes");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  GemmArgs g;
+  g.M = (int)m; g.N = (int)n; g.K = (int)k;
+  g.opA = op_a; g.opB = op_b;
+  g.A = a; g.lda = lda; g.B = b; g.ldb = ldb;
+  g.C = static_cast<double2*>(c); g.ldc = ldc;
+  g.alpha = make_double2(alpha[0], alpha[1]);
+  g.beta = make_double2(beta[0], beta[1]);
+  if (prec == MS_PREC_FP64) return zgemm(ctx, g);
+  if (prec == MS_PREC_FP32_MFMA) return cgemm32(ctx, g);
+  return fail(ctx, MS_ERR_ARG, "unknown precision");
+}
+
+ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, void* aug, void* x, int32_t* status) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!aug || !x || !status) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n <= 0 || nrhs <= 0 || batch <= 0) return fail(ctx, MS_ERR_ARG, "bad sizes");
+  if (n > 4096 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond this build");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  void* piv = nullptr;
+  MS_TRY(workspace(ctx, 13, (size_t)batch * n * sizeof(int32_t), &piv));
+  MS_HIP(ctx, hipMemsetAsync(status, 0, batch * sizeof(int32_t), ctx->stream));
+  const int ncols = (int)(n + nrhs);
+  double2* A = static_cast<double2*>(aug);
+  MS_TRY(getrf_aug(ctx, A, (int)n, ncols, n * ncols, (int)batch, (int32_t*)piv, status, 1));
+  return trsm_upper_aug(ctx, A, (int)n, ncols, n * ncols, (int)batch, static_cast<double2*>(x), nrhs, n * nrhs, status,
+                        1);
+}
+
+ms_status ms_debug_eigh(ms_ctx ctx, int64_t n, int64_t batch, const void* h, const double* shift, double* eps,
+                        void* u) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!h || !shift || !eps || !u) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n <= 0 || batch <= 0) return fail(ctx, MS_ERR_ARG, "bad sizes");
+  if (n > 3000 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond this build");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t nn = n * n;
+  void* W = nullptr;
+  MS_TRY(workspace(ctx, 2, (size_t)batch * nn * sizeof(double2), &W));
+  MS_HIP(ctx, hipMemcpyAsync(W, h, (size_t)batch * nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  hipLaunchKernelGGL(k_add_shift, dim3((unsigned)((n + 255) / 256), (unsigned)batch), dim3(256), 0, ctx->stream, (int)n,
+                     shift, static_cast<double2*>(W));
+  MS_TRY(check_launch(ctx, "add shift"));
+  return jacobi_eigh(ctx, (int)n, (int)batch, static_cast<double2*>(W), shift, eps, n, static_cast<double2*>(u), nn,
+                     ctx->d_status);
+}
+
+}  // extern "C"

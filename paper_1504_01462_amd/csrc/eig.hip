@@ -1,0 +1,463 @@
+// E-independent stage: slice Hamiltonians (Sec. II.A, Eq. loc), their
+// eigenpairs, and the interface overlaps O^p = U^p^dagger U^{p+1} (App. A).
+//
+// Eigensolver: one-sided block Jacobi (Hestenes) on the shifted, positive
+// definite A = H + c I.  Columns are grouped in blocks of 16; a sweep visits
+// every pair of blocks once in round-robin order (nb-1 rounds of nb/2
+// disjoint pairs, one launch per round, one workgroup per pair and matrix).
+// For a pair, P = W[:, I u J] (n x 32):
+//   G = P^dagger P       Gram on the matrix cores (k split over the 4 waves)
+//   G = Q diag Q^dagger  cyclic Jacobi on the 32 x 32 Hermitian G in LDS
+//   P <- P Q             on the matrix cores, rows staged through LDS
+// which makes the 32 columns mutually orthogonal.  At convergence
+// W = A V has orthogonal columns; since A is Hermitian positive definite its
+// eigenvectors are the normalised columns u_j = w_j / |w_j| and its
+// eigenvalues |w_j|, so E_j = |w_j| - c.  Pairs already orthogonal to the
+// tolerance are skipped; a matrix whose previous sweep rotated nothing exits
+// at once.
+#include "ms_internal.h"
+
+namespace ms {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// ---- kinetic energies and lead channel energies ---------------------------------------
+__global__ void k_kin_eps(int n, const int32_t* g, double b1x, double b1y, double b2x, double b2y, double kx,
+                          double ky, double vl, double vr, double* kin, double* el, double* er) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double m1 = g[2 * i], m2 = g[2 * i + 1];
+  const double x = kx + m1 * b1x + m2 * b2x, y = ky + m1 * b1y + m2 * b2y;
+  const double q = x * x + y * y;
+  kin[i] = q;
+  el[i] = q + vl;
+  er[i] = q + vr;
+}
+
+// ---- positivity shift per slice --------------------------------------------------------
+// lambda_min(H^p) >= min_i |k+G_i|^2 + V^p(0) - sum_{Q != 0} |V^p(Q)|  (Gershgorin, every
+// difference vector appears at most once per row); c = max(0, -bound) + 1.
+__global__ __launch_bounds__(256) void k_shift(int n, const double* kin, int64_t n_q, const double2* vq, int q0,
+                                               double* shift) {
+  __shared__ double s_min[256], s_sum[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double2* v = vq + (int64_t)b * n_q;
+  double mn = 1e300, sm = 0.0;
+  for (int i = t; i < n; i += 256) mn = fmin(mn, kin[i]);
+  for (int64_t q = t; q < n_q; q += 256)
+    if (q != q0) sm += sqrt(v[q].x * v[q].x + v[q].y * v[q].y);
+  s_min[t] = mn;
+  s_sum[t] = sm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s_min[t] = fmin(s_min[t], s_min[t + o]);
+      s_sum[t] += s_sum[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double bound = s_min[0] + v[q0].x - s_sum[0];
+    shift[b] = fmax(0.0, -bound) + 1.0;
+  }
+}
+
+// ---- W = H^p + c_p I --------------------------------------------------------------------
+__global__ void k_hgather(int n, const double* kin, const double* shift, int64_t n_q, const double2* vq,
+                          const int32_t* q_of_ij, double2* W) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  double2 h = vq[b * n_q + q_of_ij[idx]];
+  if (i == j) h.x += kin[i] + shift[b];
+  W[b * (int64_t)n * n + idx] = h;
+}
+
+// ---- one round of the block Jacobi sweep -----------------------------------------------
+constexpr int BW = 16;     // block width
+constexpr int PW = 32;     // pair width
+constexpr int ROWS = 64;   // rows staged per update step
+
+struct JacobiArgs {
+  double2* W;
+  int n;
+  int nb_real;             // number of real column blocks
+  const int2* pairs;       // this round's pairs
+  int32_t* counter;        // [batch][max_sweeps] rotations per sweep
+  int max_sweeps;
+  int sweep;
+  double tol;              // relative off-diagonal tolerance
+};
+
+__device__ __forceinline__ int pair_col(int a, int I, int J, int mI, int mJ) {
+  // local column a (0..31) -> global column, or -1 for padding
+  if (a < BW) return a < mI ? I * BW + a : -1;
+  return (a - BW) < mJ ? J * BW + (a - BW) : -1;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
+  __shared__ double2 G[PW][PW + 1];
+  __shared__ double2 Q[PW][PW + 1];
+  __shared__ double Ps[2][ROWS][PW];
+  __shared__ double rc[PW / 2], rs[PW / 2];
+  __shared__ double2 rph[PW / 2];
+  __shared__ int ra[PW / 2], rb[PW / 2];
+  __shared__ int s_flag;
+
+  const int64_t b = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int32_t* cnt = args.counter + b * args.max_sweeps;
+  if (args.sweep > 0 && cnt[args.sweep - 1] == 0) return;  // converged in the previous sweep
+  const int n = args.n;
+  const int2 pr = args.pairs[blockIdx.x];
+  const int I = pr.x, J = pr.y;
+  const int mI = (I < args.nb_real) ? min(BW, n - I * BW) : 0;
+  const int mJ = (J < args.nb_real) ? min(BW, n - J * BW) : 0;
+  if (mI + mJ == 0) return;
+  double2* W = args.W + b * (int64_t)n * n;
+
+  // --- Gram G = P^dagger P: each wave takes a quarter of the rows for all three blocks
+  {
+    d4_t g00r = {0, 0, 0, 0}, g00i = {0, 0, 0, 0}, g01r = {0, 0, 0, 0}, g01i = {0, 0, 0, 0},
+         g11r = {0, 0, 0, 0}, g11i = {0, 0, 0, 0};
+    const int c = lane & 15;
+    const int colI = (c < mI) ? I * BW + c : -1;
+    const int colJ = (c < mJ) ? J * BW + c : -1;
+    const int kq = (n + 3) / 4;                 // rows per wave, rounded to steps of 4
+    const int kbeg = wave * ((kq + 3) / 4 * 4);
+    const int kend = min(n, kbeg + (kq + 3) / 4 * 4);
+    for (int k0 = kbeg; k0 < kend; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      double2 pi = make_double2(0.0, 0.0), pj = make_double2(0.0, 0.0);
+      if (k < kend) {
+        if (colI >= 0) pi = W[(int64_t)k * n + colI];
+        if (colJ >= 0) pj = W[(int64_t)k * n + colJ];
+      }
+      // A = conj(P_X)^T (16 x 4), B = P_Y (4 x 16): lane holds element (c, k) of both
+      g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.x, g00r, 0, 0, 0);
+      g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pi.y, g00r, 0, 0, 0);
+      g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.y, g00i, 0, 0, 0);
+      g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pi.x, g00i, 0, 0, 0);
+      g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.x, g01r, 0, 0, 0);
+      g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pj.y, g01r, 0, 0, 0);
+      g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.y, g01i, 0, 0, 0);
+      g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pj.x, g01i, 0, 0, 0);
+      g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.x, g11r, 0, 0, 0);
+      g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.y, pj.y, g11r, 0, 0, 0);
+      g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.y, g11i, 0, 0, 0);
+      g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj.y, pj.x, g11i, 0, 0, 0);
+    }
+    // reduce the four partial Grams through LDS (G then Q used as scratch)
+    for (int idx = t; idx < PW * PW; idx += 256) G[idx / PW][idx % PW] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int w = 0; w < 4; ++w) {
+      if (wave == w) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = (lane >> 4) + 4 * v, j = lane & 15;   // f64 MFMA accumulator layout
+          G[i][j] = cadd(G[i][j], make_double2(g00r[v], g00i[v]));
+          G[i][BW + j] = cadd(G[i][BW + j], make_double2(g01r[v], g01i[v]));
+          G[BW + i][BW + j] = cadd(G[BW + i][BW + j], make_double2(g11r[v], g11i[v]));
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = t; idx < BW * BW; idx += 256) {
+      const int i = idx / BW, j = idx % BW;
+      G[BW + j][i] = cconj(G[i][BW + j]);
+    }
+    if (t == 0) s_flag = 0;
+    __syncthreads();
+  }
+
+  // --- convergence test of the pair
+  {
+    bool rot = false;
+    for (int idx = t; idx < PW * PW; idx += 256) {
+      const int a = idx / PW, c = idx % PW;
+      if (a < c) {
+        const double gaa = G[a][a].x, gcc = G[c][c].x;
+        const double g2 = G[a][c].x * G[a][c].x + G[a][c].y * G[a][c].y;
+        if (gaa > 0.0 && gcc > 0.0 && g2 > args.tol * args.tol * gaa * gcc) rot = true;
+      }
+    }
+    if (rot) s_flag = 1;
+    __syncthreads();
+    if (s_flag == 0) return;
+    if (t == 0) atomicAdd(cnt + args.sweep, 1);
+  }
+
+  // --- cyclic Jacobi on G (32 x 32 Hermitian), Q accumulates the rotations
+  for (int idx = t; idx < PW * PW; idx += 256) {
+    const int a = idx / PW, c = idx % PW;
+    Q[a][c] = make_double2(a == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int sw = 0; sw < 12; ++sw) {
+    if (t == 0) s_flag = 0;
+    __syncthreads();
+    for (int r = 0; r < PW - 1; ++r) {
+      if (t < PW / 2) {
+        // circle-method pairing of 32 indices
+        const int k = t;
+        const int a = (k == 0) ? 0 : ((k - 1 + r) % (PW - 1)) + 1;
+        const int c = ((PW - 1 - k - 1 + r) % (PW - 1)) + 1;
+        const int lo = min(a, c), hi = max(a, c);
+        const double al = G[lo][lo].x, ga = G[hi][hi].x;
+        const double2 be = G[lo][hi];
+        const double mb = sqrt(be.x * be.x + be.y * be.y);
+        double cs = 1.0, sn = 0.0;
+        double2 ph = make_double2(1.0, 0.0);
+        if (mb > 1e-17 * sqrt(fabs(al * ga)) && mb > 0.0) {
+          const double zeta = (ga - al) / (2.0 * mb);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          cs = 1.0 / sqrt(1.0 + tt * tt);
+          sn = tt * cs;
+          ph = make_double2(be.x / mb, be.y / mb);
+          if (mb > 1e-15 * sqrt(fabs(al * ga))) s_flag = 1;
+        }
+        ra[k] = lo;
+        rb[k] = hi;
+        rc[k] = cs;
+        rs[k] = sn;
+        rph[k] = ph;
+      }
+      __syncthreads();
+      // rows: G'_a = c G_a - s e^{i phi} G_b ; G'_b = s e^{-i phi} G_a + c G_b
+      for (int idx = t; idx < (PW / 2) * PW; idx += 256) {
+        const int k = idx / PW, x = idx % PW;
+        const int a = ra[k], c = rb[k];
+        const double cs = rc[k], sn = rs[k];
+        const double2 ph = rph[k];
+        const double2 ga = G[a][x], gb = G[c][x];
+        G[a][x] = cadd(cscale(cs, ga), cscale(-sn, cmul(ph, gb)));
+        G[c][x] = cadd(cscale(sn, cmul(cconj(ph), ga)), cscale(cs, gb));
+      }
+      __syncthreads();
+      // columns of G and Q: X'_a = c X_a - s e^{-i phi} X_b ; X'_b = s e^{i phi} X_a + c X_b
+      for (int idx = t; idx < 2 * (PW / 2) * PW; idx += 256) {
+        const int which = idx / ((PW / 2) * PW);
+        const int rem = idx % ((PW / 2) * PW);
+        const int k = rem / PW, x = rem % PW;
+        const int a = ra[k], c = rb[k];
+        const double cs = rc[k], sn = rs[k];
+        const double2 ph = rph[k];
+        double2(*X)[PW + 1] = which ? Q : G;
+        const double2 xa = X[x][a], xb = X[x][c];
+        X[x][a] = cadd(cscale(cs, xa), cscale(-sn, cmul(cconj(ph), xb)));
+        X[x][c] = cadd(cscale(sn, cmul(ph, xa)), cscale(cs, xb));
+      }
+      __syncthreads();
+    }
+    if (s_flag == 0) break;
+  }
+
+  // --- P <- P Q, ROWS rows at a time; waves split the 64 x 32 output into 16-row slabs
+  for (int r0 = 0; r0 < n; r0 += ROWS) {
+    for (int idx = t; idx < ROWS * PW; idx += 256) {
+      const int i = idx / PW, a = idx % PW;
+      const int col = pair_col(a, I, J, mI, mJ);
+      double2 v = make_double2(0.0, 0.0);
+      if (r0 + i < n && col >= 0) v = W[(int64_t)(r0 + i) * n + col];
+      Ps[0][i][a] = v.x;
+      Ps[1][i][a] = v.y;
+    }
+    __syncthreads();
+    d4_t cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+    const int rr = wave * 16;
+#pragma unroll
+    for (int kk = 0; kk < PW; kk += 4) {
+      const int k = kk + (lane >> 4);
+      const double ar = Ps[0][rr + (lane & 15)][k], ai = Ps[1][rr + (lane & 15)][k];
+      const double2 q0 = Q[k][lane & 15], q1 = Q[k][16 + (lane & 15)];
+      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q0.x, cr0, 0, 0, 0);
+      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q0.y, ci0, 0, 0, 0);
+      cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q1.x, cr1, 0, 0, 0);
+      ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q1.y, ci1, 0, 0, 0);
+      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, q0.y, cr0, 0, 0, 0);
+      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q0.x, ci0, 0, 0, 0);
+      cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, q1.y, cr1, 0, 0, 0);
+      ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q1.x, ci1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + rr + (lane >> 4) + 4 * v;
+      if (row < n) {
+        const int c0 = pair_col(lane & 15, I, J, mI, mJ);
+        const int c1 = pair_col(16 + (lane & 15), I, J, mI, mJ);
+        if (c0 >= 0) W[(int64_t)row * n + c0] = make_double2(cr0[v], ci0[v]);
+        if (c1 >= 0) W[(int64_t)row * n + c1] = make_double2(cr1[v], ci1[v]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- normalise, sort ascending, emit eigenpairs ------------------------------------------
+__global__ __launch_bounds__(256) void k_jacobi_finalize(const double2* Wall, int n, const double* shift,
+                                                         const int32_t* counter, int max_sweeps, double* eps_out,
+                                                         int64_t eps_stride, double2* Uall, int64_t u_stride,
+                                                         int32_t* status) {
+  extern __shared__ double sh[];
+  double* lam = sh;          // [n]
+  double* sig = sh + n;      // [n]
+  int* rank = (int*)(sh + 2 * n);
+  const int64_t b = blockIdx.x;
+  const int t = threadIdx.x;
+  const double2* W = Wall + b * (int64_t)n * n;
+  double2* U = Uall + b * u_stride;
+  for (int j = t; j < n; j += 256) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double2 w = W[(int64_t)i * n + j];
+      s += w.x * w.x + w.y * w.y;
+    }
+    sig[j] = sqrt(s);
+    lam[j] = sig[j] - shift[b];
+  }
+  __syncthreads();
+  for (int j = t; j < n; j += 256) {
+    int r = 0;
+    const double lj = lam[j];
+    for (int i = 0; i < n; ++i) r += (lam[i] < lj) || (lam[i] == lj && i < j);
+    rank[j] = r;
+    eps_out[b * eps_stride + r] = lj;
+  }
+  __syncthreads();
+  for (int j = t; j < n; j += 256) {
+    const double inv = 1.0 / sig[j];
+    const int r = rank[j];
+    for (int i = 0; i < n; ++i) {
+      const double2 w = W[(int64_t)i * n + j];
+      U[(int64_t)i * n + r] = make_double2(w.x * inv, w.y * inv);
+    }
+  }
+  if (t == 0 && status) {
+    if (counter[b * max_sweeps + max_sweeps - 1] != 0) atomicCAS(status, 0, (int32_t)MS_ERR_NOCONV);
+  }
+}
+
+// min and max of an int32 array (one workgroup)
+__global__ __launch_bounds__(256) void k_minmax(int64_t count, const int32_t* v, int32_t* out) {
+  __shared__ int smin[256], smax[256];
+  const int t = threadIdx.x;
+  int mn = 0x7fffffff, mx = -0x7fffffff - 1;
+  for (int64_t i = t; i < count; i += 256) {
+    mn = min(mn, v[i]);
+    mx = max(mx, v[i]);
+  }
+  smin[t] = mn;
+  smax[t] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      smin[t] = min(smin[t], smin[t + o]);
+      smax[t] = max(smax[t], smax[t + o]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+  }
+}
+
+// O = U (copy) or O = U^dagger
+__global__ void k_copy_overlap(int n, const double2* U, double2* O, int conj_transpose) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  O[idx] = conj_transpose ? cconj(U[(int64_t)j * n + i]) : U[idx];
+}
+
+}  // namespace
+
+ms_status launch_kin_eps(ms_ctx ctx, int n, const int32_t* g_mn, const double* bvec, const double* kpar, double vl,
+                         double vr, double* kin, double* eps_left, double* eps_right) {
+  hipLaunchKernelGGL(k_kin_eps, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, n, g_mn, bvec[0], bvec[1], bvec[2],
+                     bvec[3], kpar[0], kpar[1], vl, vr, kin, eps_left, eps_right);
+  return check_launch(ctx, "kin/eps");
+}
+
+ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, const double2* vq, int q0,
+                             double* shift) {
+  hipLaunchKernelGGL(k_shift, dim3(nb), dim3(256), 0, ctx->stream, n, kin, n_q, vq, q0, shift);
+  return check_launch(ctx, "shift");
+}
+
+ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t n_q,
+                         const double2* vq, const int32_t* q_of_ij, double2* W) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_hgather, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, ctx->stream, n, kin, shift, n_q,
+                     vq, q_of_ij, W);
+  return check_launch(ctx, "hgather");
+}
+
+ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double* shift, double* eps_out, int64_t eps_stride,
+                      double2* U, int64_t u_stride, int32_t* status) {
+  const int nb_real = (n + BW - 1) / BW;
+  const int nblk = nb_real + (nb_real & 1);
+  const int rounds = nblk - 1, per = nblk / 2;
+  const int max_sweeps = 24;
+  // round-robin schedule (circle method), built on the host
+  std::vector<int2> pairs((size_t)std::max(rounds, 1) * per);
+  for (int r = 0; r < rounds; ++r)
+    for (int k = 0; k < per; ++k) {
+      const int a = (k == 0) ? 0 : ((k - 1 + r) % (nblk - 1)) + 1;
+      const int c = ((nblk - 1 - k - 1 + r) % (nblk - 1)) + 1;
+      pairs[(size_t)r * per + k] = make_int2(std::min(a, c), std::max(a, c));
+    }
+  if (nblk == 1) {  // cannot happen: nblk is even and >= 2
+    return fail(ctx, MS_ERR_ARG, "jacobi: no blocks");
+  }
+  void* wsp = nullptr;
+  void* wsc = nullptr;
+  MS_TRY(workspace(ctx, 10, pairs.size() * sizeof(int2), &wsp));
+  MS_TRY(workspace(ctx, 11, (size_t)nb * max_sweeps * sizeof(int32_t), &wsc));
+  MS_TRY(upload(ctx, wsp, pairs.data(), pairs.size() * sizeof(int2)));
+  MS_HIP(ctx, hipMemsetAsync(wsc, 0, (size_t)nb * max_sweeps * sizeof(int32_t), ctx->stream));
+  JacobiArgs a;
+  a.W = W;
+  a.n = n;
+  a.nb_real = nb_real;
+  a.counter = static_cast<int32_t*>(wsc);
+  a.max_sweeps = max_sweeps;
+  a.tol = std::max(1e-14, 4.0 * 2.220446049250313e-16 * std::sqrt((double)n));
+  for (int s = 0; s < max_sweeps; ++s) {
+    a.sweep = s;
+    for (int r = 0; r < rounds; ++r) {
+      a.pairs = static_cast<const int2*>(wsp) + (size_t)r * per;
+      Prof prof(ctx, PC_JACOBI, 2.0 * 8.0 * PW * PW * (double)n * per * nb, 3.0 * 16.0 * PW * (double)n * per * nb);
+      hipLaunchKernelGGL(k_jacobi_round, dim3(per, nb), dim3(256), 0, ctx->stream, a);
+      MS_TRY(check_launch(ctx, "jacobi round"));
+    }
+  }
+  const size_t shmem = (size_t)n * (2 * sizeof(double) + sizeof(int));
+  if (shmem > 64 * 1024) return fail(ctx, MS_ERR_UNSUPPORTED, "eigensolver size %d too large", n);
+  hipLaunchKernelGGL(k_jacobi_finalize, dim3(nb), dim3(256), shmem, ctx->stream, W, n, shift, a.counter, max_sweeps,
+                     eps_out, eps_stride, U, u_stride, status);
+  return check_launch(ctx, "jacobi finalize");
+}
+
+ms_status launch_minmax(ms_ctx ctx, int64_t count, const int32_t* v, int32_t* out2) {
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, ctx->stream, count, v, out2);
+  return check_launch(ctx, "minmax");
+}
+
+ms_status launch_copy_boundary_overlaps(ms_ctx ctx, int n, const double2* U, double2* O, int conj_transpose) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_copy_overlap, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, ctx->stream, n, U, O,
+                     conj_transpose);
+  return check_launch(ctx, "boundary overlap");
+}
+
+}  // namespace ms

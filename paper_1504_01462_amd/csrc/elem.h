@@ -1,0 +1,29 @@
+// Launchers of the per-energy elementwise kernels (elem.hip).
+#pragma once
+#include "ms_internal.h"
+
+namespace ms {
+
+ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t ldy, int64_t sY, const double2* kq,
+                          const double2* pq, int64_t sk, void* Aop, bool fp32);
+ms_status launch_epilogue(ms_ctx ctx, int n, int n_e, const double2* O, const double2* Wg, const double2* kp,
+                          const double2* kq, int64_t sk, double2* M, int64_t ldm, int64_t sM);
+ms_status launch_tcols(ms_ctx ctx, int n, int n_o, int n_e, const int32_t* ch, const double2* Y, int64_t ldy,
+                       int64_t sY, int y_off, const double2* kq, const double2* pq, int64_t sk, int first, double2* M,
+                       int64_t ldm, int64_t sM);
+ms_status launch_batch_T(ms_ctx ctx, int n, int n_o, int n_e, const int32_t* ch, const double* energies,
+                         const double* eps_l, const double* eps_r, const double2* Y, int64_t ldy, int64_t sY, double* T,
+                         double* R, int64_t* n_open, int32_t* status);
+ms_status launch_whole_T(ms_ctx ctx, int n, double E, const double2* t, const double2* r, const double* eps_l,
+                         const double* eps_r, double* T, double* R, int64_t* n_open, int32_t* status);
+ms_status launch_xy(ms_ctx ctx, int n, int nb, const double2* ovl, const double2* kbuf, int p0, double2* aug,
+                    double2* Xc, double2* Yc);
+ms_status launch_smat_finish(ms_ctx ctx, int n, int nb, const double2* Z, const double2* Xc, const double2* pbuf,
+                             int p0, double2* tout, double2* rpout, double2* tpout);
+ms_status launch_star_aug(ms_ctx ctx, int n, const double2* ta, const double2* rpa, double2* aug);
+ms_status launch_to_c64(ms_ctx ctx, int64_t count, const double2* in, float2* out);
+ms_status launch_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open,
+                               double* tbar, double* per_channel);
+ms_status launch_nonfinite_scan(ms_ctx ctx, int64_t count, const double2* v, int32_t* status);
+
+}  // namespace ms

@@ -1,0 +1,372 @@
+// Per-energy elementwise and reduction kernels of the transmission path.
+#include "elem.h"
+
+namespace ms {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// k = sqrt(E - eps) on the branch Im k >= 0;  P = exp(i k dz)
+__device__ __forceinline__ double2 kz(double e, double eps) {
+  const double d = e - eps;
+  return d >= 0.0 ? make_double2(sqrt(d), 0.0) : make_double2(0.0, sqrt(-d));
+}
+__device__ __forceinline__ double2 prop(double2 k, double dz) {
+  const double a = exp(-k.y * dz);
+  double s, c;
+  sincos(k.x * dz, &s, &c);
+  return make_double2(a * c, a * s);
+}
+
+// kbuf[e][p][i], pbuf[e][p][i] for p = 0..nrows-1 (nrows = n_slices + 2)
+__global__ void k_wavevectors(int n, int nrows, const double* eps, const double* energies, const double* dz,
+                              double2* kbuf, double2* pbuf) {
+  const int64_t e = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nrows * n) return;
+  const int p = (int)(idx / n);
+  const double2 k = kz(energies[e], eps[idx]);
+  const double d = (p >= 1 && p <= nrows - 2) ? dz[p - 1] : 0.0;
+  kbuf[e * nrows * n + idx] = k;
+  pbuf[e * nrows * n + idx] = prop(k, d);
+}
+
+__device__ __forceinline__ void put(double2* d, double2 v) { *d = v; }
+__device__ __forceinline__ void put(float2* d, double2 v) { *d = make_float2((float)v.x, (float)v.y); }
+
+// A_e = [rho^T ; rho^T K],  rho^T_ij = P_i k_i Y_ij P_j / k_j  (k, P of slice p+1)
+template <typename OutT>
+__global__ void k_prologue(int n, const double2* Y, int64_t ldy, int64_t sY, const double2* kq, const double2* pq,
+                           int64_t sk, OutT* Aop) {
+  const int64_t e = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const double2* k = kq + e * sk;
+  const double2* P = pq + e * sk;
+  const double2 y = Y[e * sY + (int64_t)i * ldy + j];
+  const double2 left = cmul(P[i], k[i]);
+  const double2 bot = cmul(cmul(left, y), P[j]);   // rho^T_ij k_j
+  const double2 top = cdiv(bot, k[j]);             // rho^T_ij
+  OutT* A = Aop + e * 2 * (int64_t)n * n;
+  put(A + idx, top);
+  put(A + (int64_t)n * n + idx, bot);
+}
+
+// M_e[:, 0:n]  = Phi_A^T = (O^T + W1) K_p + K_{p+1} O^T - W2
+// M_e[:, n:2n] = Phi_B^T = (O^T + W1) K_p - K_{p+1} O^T + W2
+// O^T read through a 32 x 32 LDS tile; W = [W1; W2] may be null (first interface).
+__global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const double2* Wg, const double2* kp,
+                                                  const double2* kq, int64_t sk, double2* M, int64_t ldm,
+                                                  int64_t sM) {
+  __shared__ double2 tile[32][33];
+  const int64_t e = blockIdx.z;
+  const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // O^T(i, j) = O(j, i): load O rows bj.., cols bi..
+  for (int r = ty; r < 32; r += 8) {
+    const int oi = bj + r, oj = bi + tx;
+    tile[r][tx] = (oi < n && oj < n) ? O[(int64_t)oi * n + oj] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double2* k_p = kp + e * sk;
+  const double2* k_q = kq + e * sk;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bi + r, j = bj + tx;
+    if (i >= n || j >= n) continue;
+    const double2 ot = tile[tx][r];
+    double2 w1 = make_double2(0.0, 0.0), w2 = make_double2(0.0, 0.0);
+    if (Wg) {
+      const double2* W = Wg + e * 2 * (int64_t)n * n;
+      w1 = W[(int64_t)i * n + j];
+      w2 = W[(int64_t)(n + i) * n + j];
+    }
+    const double2 psi = cmul(cadd(ot, w1), k_p[j]);
+    const double2 dpsi = csub(cmul(k_q[i], ot), w2);
+    double2* Mr = M + e * sM + (int64_t)i * ldm;
+    Mr[j] = cadd(psi, dpsi);
+    Mr[n + j] = csub(psi, dpsi);
+  }
+}
+
+// M_e[:, 2n + c] = P_i T~_ic,  T~ = unit columns e_{ch_c} (first interface) or 2 K Y2
+__global__ void k_tcols(int n, int n_o, const int32_t* ch, const double2* Y, int64_t ldy, int64_t sY, int y_off,
+                        const double2* kq, const double2* pq, int64_t sk, int first, double2* M, int64_t ldm,
+                        int64_t sM) {
+  const int64_t e = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n_o) return;
+  const int i = (int)(idx / n_o), c = (int)(idx % n_o);
+  double2 v;
+  if (first) {
+    v = make_double2(ch[c] == i ? 1.0 : 0.0, 0.0);
+  } else {
+    const double2 k = kq[e * sk + i];
+    v = cmul(make_double2(2.0 * k.x, 2.0 * k.y), Y[e * sY + (int64_t)i * ldy + y_off + c]);
+  }
+  M[e * sM + (int64_t)i * ldm + 2 * n + c] = cmul(pq[e * sk + i], v);
+}
+
+// T, R, N_open of the fused path from the final state (Y1 = K^-1 r^T K, Y2 = (2K)^-1 t^T)
+__global__ __launch_bounds__(256) void k_batch_T(int n, int n_o, const int32_t* ch, const double* energies,
+                                                 const double* eps_l, const double* eps_r, const double2* Y,
+                                                 int64_t ldy, int64_t sY, double* T, double* R, int64_t* n_open,
+                                                 int32_t* status) {
+  __shared__ double st[256], sr[256], sm[256];
+  __shared__ int so[256];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const double E = energies[e];
+  const double2* Yb = Y + e * sY;
+  double tt = 0.0, rr = 0.0, mind = 1e300;
+  int no = 0;
+  for (int i = t; i < n; i += 256) {
+    mind = fmin(mind, fmin(fabs(E - eps_l[i]), fabs(E - eps_r[i])));
+    if (eps_l[i] < E) no++;
+  }
+  for (int64_t idx = t; idx < (int64_t)n * n_o; idx += 256) {
+    const int j = (int)(idx / n_o), c = (int)(idx % n_o);
+    if (eps_l[j] < E && eps_r[ch[c]] < E) {
+      const double kl = sqrt(E - eps_l[j]), kr = sqrt(E - eps_r[ch[c]]);
+      tt += 4.0 * kr * kl * cabs2(Yb[(int64_t)j * ldy + n + c]);
+    }
+  }
+  for (int64_t idx = t; idx < (int64_t)n * n; idx += 256) {
+    const int a = (int)(idx / n), b = (int)(idx % n);
+    if (eps_l[a] < E && eps_l[b] < E) {
+      const double ka = sqrt(E - eps_l[a]), kb = sqrt(E - eps_l[b]);
+      rr += (ka / kb) * cabs2(Yb[(int64_t)a * ldy + b]);
+    }
+  }
+  st[t] = tt; sr[t] = rr; sm[t] = mind; so[t] = no;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      st[t] += st[t + o];
+      sr[t] += sr[t + o];
+      sm[t] = fmin(sm[t], sm[t + o]);
+      so[t] += so[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    T[e] = st[0];
+    R[e] = sr[0];
+    n_open[e] = so[0];
+    int32_t code = 0;
+    if (sm[0] < 1e-10) code = MS_ERR_THRESHOLD;
+    else if (!isfinite(st[0]) || !isfinite(sr[0])) code = MS_ERR_NONFINITE;
+    if (code) atomicCAS(status + e, 0, code);
+  }
+}
+
+// T, R, N_open from a whole-junction S-matrix (t = S11, r = S21)
+__global__ __launch_bounds__(256) void k_whole_T(int n, double E, const double2* t, const double2* r,
+                                                 const double* eps_l, const double* eps_r, double* T, double* R,
+                                                 int64_t* n_open, int32_t* status) {
+  __shared__ double st[256], sr[256], sm[256];
+  __shared__ int so[256];
+  const int tid = threadIdx.x;
+  double tt = 0.0, rr = 0.0, mind = 1e300;
+  int no = 0;
+  for (int i = tid; i < n; i += 256) {
+    mind = fmin(mind, fmin(fabs(E - eps_l[i]), fabs(E - eps_r[i])));
+    if (eps_l[i] < E) no++;
+  }
+  for (int64_t idx = tid; idx < (int64_t)n * n; idx += 256) {
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    if (eps_l[j] < E) {
+      const double kj = sqrt(E - eps_l[j]);
+      if (eps_r[i] < E) tt += (sqrt(E - eps_r[i]) / kj) * cabs2(t[idx]);
+      if (eps_l[i] < E) rr += (sqrt(E - eps_l[i]) / kj) * cabs2(r[idx]);
+    }
+  }
+  st[tid] = tt; sr[tid] = rr; sm[tid] = mind; so[tid] = no;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      st[tid] += st[tid + o];
+      sr[tid] += sr[tid + o];
+      sm[tid] = fmin(sm[tid], sm[tid + o]);
+      so[tid] += so[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    T[0] = st[0];
+    R[0] = sr[0];
+    n_open[0] = so[0];
+    if (sm[0] < 1e-10) atomicCAS(status, 0, (int32_t)MS_ERR_THRESHOLD);
+    else if (!isfinite(st[0]) || !isfinite(sr[0])) atomicCAS(status, 0, (int32_t)MS_ERR_NONFINITE);
+  }
+}
+
+// aug_b = [X | I | Y], Xc_b = X, Yc_b = Y for interface p = p0 + b
+//   X_ij = O_ij (kp_i + kq_j) / (2 kp_i),  Y_ij = O_ij (kp_i - kq_j) / (2 kp_i)
+__global__ void k_xy(int n, const double2* ovl, const double2* kbuf, int p0, double2* aug, double2* Xc, double2* Yc) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const int64_t nn = (int64_t)n * n;
+  const double2 o = ovl[(p0 + b) * nn + idx];
+  const double2 kp = kbuf[(p0 + b) * n + i], kq = kbuf[(p0 + b + 1) * n + j];
+  const double2 h = cdiv(o, make_double2(2.0 * kp.x, 2.0 * kp.y));
+  const double2 x = cmul(h, cadd(kp, kq)), y = cmul(h, csub(kp, kq));
+  double2* A = aug + b * 3 * nn + (int64_t)i * 3 * n;
+  A[j] = x;
+  A[n + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  A[2 * n + j] = y;
+  Xc[b * nn + idx] = x;
+  Yc[b * nn + idx] = y;
+}
+
+// S11 = P X^-1, S12 = -P X^-1 Y P, S22 = (X - Y X^-1 Y) P   (Z = [X^-1 | X^-1 Y], Xc = X - Y X^-1 Y)
+__global__ void k_smat_finish(int n, const double2* Z, const double2* Xc, const double2* pbuf, int p0, double2* tout,
+                              double2* rpout, double2* tpout) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const int64_t nn = (int64_t)n * n;
+  const double2* P = pbuf + (p0 + b + 1) * n;
+  const double2* Zr = Z + b * 2 * nn + (int64_t)i * 2 * n;
+  tout[b * nn + idx] = cmul(P[i], Zr[j]);
+  const double2 s12 = cmul(cmul(P[i], Zr[n + j]), P[j]);
+  rpout[b * nn + idx] = make_double2(-s12.x, -s12.y);
+  tpout[b * nn + idx] = cmul(Xc[b * nn + idx], P[j]);
+}
+
+// aug = [I | t_a | rp_a]  (the GEMM then adds -rp_a r_b to the first block)
+__global__ void k_star_aug(int n, const double2* ta, const double2* rpa, double2* aug) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  double2* A = aug + (int64_t)i * 3 * n;
+  A[j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  A[n + j] = ta[idx];
+  A[2 * n + j] = rpa[idx];
+}
+
+__global__ void k_to_c64(int64_t count, const double2* in, float2* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = make_float2((float)in[idx].x, (float)in[idx].y);
+}
+
+__global__ void k_nonfinite_scan(int64_t count, const double2* v, int32_t* status) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count && !(isfinite(v[idx].x) && isfinite(v[idx].y))) atomicCAS(status, 0, (int32_t)MS_ERR_NONFINITE);
+}
+
+// k_par average of T and transmission per open channel (one thread per energy)
+__global__ void k_kpar_average(int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open, double* tbar,
+                               double* per_channel) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_e) return;
+  double st = 0.0;
+  int64_t so = 0;
+  for (int64_t k = 0; k < n_k; ++k) {
+    st += T[k * n_e + e];
+    so += n_open[k * n_e + e];
+  }
+  tbar[e] = st / (double)n_k;
+  per_channel[e] = so > 0 ? st / (double)so : 0.0;
+}
+
+inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+}  // namespace
+
+ms_status launch_wavevectors(ms_ctx ctx, int n, int nrows, int n_e, const double* eps, const double* energies_dev,
+                             const double* dz, double2* kbuf, double2* pbuf) {
+  hipLaunchKernelGGL(k_wavevectors, dim3(blocks((int64_t)nrows * n), n_e), dim3(256), 0, ctx->stream, n, nrows, eps,
+                     energies_dev, dz, kbuf, pbuf);
+  return check_launch(ctx, "wavevectors");
+}
+
+ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t ldy, int64_t sY, const double2* kq,
+                          const double2* pq, int64_t sk, void* Aop, bool fp32) {
+  if (fp32)
+    hipLaunchKernelGGL((k_prologue<float2>), dim3(blocks((int64_t)n * n), n_e), dim3(256), 0, ctx->stream, n, Y, ldy,
+                       sY, kq, pq, sk, static_cast<float2*>(Aop));
+  else
+    hipLaunchKernelGGL((k_prologue<double2>), dim3(blocks((int64_t)n * n), n_e), dim3(256), 0, ctx->stream, n, Y,
+                       ldy, sY, kq, pq, sk, static_cast<double2*>(Aop));
+  return check_launch(ctx, "prologue");
+}
+
+ms_status launch_epilogue(ms_ctx ctx, int n, int n_e, const double2* O, const double2* Wg, const double2* kp,
+                          const double2* kq, int64_t sk, double2* M, int64_t ldm, int64_t sM) {
+  dim3 g((n + 31) / 32, (n + 31) / 32, n_e);
+  hipLaunchKernelGGL(k_epilogue, g, dim3(256), 0, ctx->stream, n, O, Wg, kp, kq, sk, M, ldm, sM);
+  return check_launch(ctx, "epilogue");
+}
+
+ms_status launch_tcols(ms_ctx ctx, int n, int n_o, int n_e, const int32_t* ch, const double2* Y, int64_t ldy,
+                       int64_t sY, int y_off, const double2* kq, const double2* pq, int64_t sk, int first, double2* M,
+                       int64_t ldm, int64_t sM) {
+  if (n_o <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_tcols, dim3(blocks((int64_t)n * n_o), n_e), dim3(256), 0, ctx->stream, n, n_o, ch, Y, ldy, sY,
+                     y_off, kq, pq, sk, first, M, ldm, sM);
+  return check_launch(ctx, "tcols");
+}
+
+ms_status launch_batch_T(ms_ctx ctx, int n, int n_o, int n_e, const int32_t* ch, const double* energies,
+                         const double* eps_l, const double* eps_r, const double2* Y, int64_t ldy, int64_t sY, double* T,
+                         double* R, int64_t* n_open, int32_t* status) {
+  hipLaunchKernelGGL(k_batch_T, dim3(n_e), dim3(256), 0, ctx->stream, n, n_o, ch, energies, eps_l, eps_r, Y, ldy, sY,
+                     T, R, n_open, status);
+  return check_launch(ctx, "batch T");
+}
+
+ms_status launch_whole_T(ms_ctx ctx, int n, double E, const double2* t, const double2* r, const double* eps_l,
+                         const double* eps_r, double* T, double* R, int64_t* n_open, int32_t* status) {
+  hipLaunchKernelGGL(k_whole_T, dim3(1), dim3(256), 0, ctx->stream, n, E, t, r, eps_l, eps_r, T, R, n_open, status);
+  return check_launch(ctx, "whole T");
+}
+
+ms_status launch_xy(ms_ctx ctx, int n, int nb, const double2* ovl, const double2* kbuf, int p0, double2* aug,
+                    double2* Xc, double2* Yc) {
+  hipLaunchKernelGGL(k_xy, dim3(blocks((int64_t)n * n), nb), dim3(256), 0, ctx->stream, n, ovl, kbuf, p0, aug, Xc, Yc);
+  return check_launch(ctx, "xy");
+}
+
+ms_status launch_smat_finish(ms_ctx ctx, int n, int nb, const double2* Z, const double2* Xc, const double2* pbuf,
+                             int p0, double2* tout, double2* rpout, double2* tpout) {
+  hipLaunchKernelGGL(k_smat_finish, dim3(blocks((int64_t)n * n), nb), dim3(256), 0, ctx->stream, n, Z, Xc, pbuf, p0,
+                     tout, rpout, tpout);
+  return check_launch(ctx, "smat finish");
+}
+
+ms_status launch_star_aug(ms_ctx ctx, int n, const double2* ta, const double2* rpa, double2* aug) {
+  hipLaunchKernelGGL(k_star_aug, dim3(blocks((int64_t)n * n)), dim3(256), 0, ctx->stream, n, ta, rpa, aug);
+  return check_launch(ctx, "star aug");
+}
+
+ms_status launch_to_c64(ms_ctx ctx, int64_t count, const double2* in, float2* out) {
+  hipLaunchKernelGGL(k_to_c64, dim3(blocks(count)), dim3(256), 0, ctx->stream, count, in, out);
+  return check_launch(ctx, "to c64");
+}
+
+ms_status launch_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open,
+                               double* tbar, double* per_channel) {
+  hipLaunchKernelGGL(k_kpar_average, dim3(blocks(n_e)), dim3(256), 0, ctx->stream, n_k, n_e, T, n_open, tbar,
+                     per_channel);
+  return check_launch(ctx, "kpar average");
+}
+
+ms_status launch_nonfinite_scan(ms_ctx ctx, int64_t count, const double2* v, int32_t* status) {
+  hipLaunchKernelGGL(k_nonfinite_scan, dim3(blocks(count)), dim3(256), 0, ctx->stream, count, v, status);
+  return check_launch(ctx, "nonfinite scan");
+}
+
+}  // namespace ms

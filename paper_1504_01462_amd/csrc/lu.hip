@@ -1,0 +1,367 @@
+// Batched LU with partial pivoting of an augmented matrix [A | B] and the
+// upper-triangular back substitution, complex128.
+//
+// Right-looking blocked algorithm, one panel of NB columns at a time:
+//   1. k_panel:       one workgroup per matrix holds the n x NB panel in
+//                     registers, finds each pivot with a wave-shuffle argmax
+//                     (|re| + |im|), swaps through LDS and eliminates.
+//   2. k_swap_trsm:   one thread per column right of the panel applies the
+//                     panel's row interchanges and solves with the unit lower
+//                     NB x NB block (rows of U12 and of L^-1 P^T B).
+//   3. zgemm:         trailing update A22 -= L21 U12 on the matrix cores.
+// The right-hand-side columns ride along in steps 2-3, so after the last
+// panel they hold L^-1 P^T B and only the back substitution remains:
+//   k_trsm_upper:     each workgroup owns 64 right-hand-side columns and walks
+//                     the 16-row block rows bottom-up; the off-diagonal part is
+//                     an MFMA product over the rows already solved, the 16x16
+//                     diagonal block is solved in LDS.
+#include <type_traits>
+
+#include "ms_internal.h"
+
+namespace ms {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cinv(double2 a) {
+  const double d = a.x * a.x + a.y * a.y;
+  return make_double2(a.x / d, -a.y / d);
+}
+
+constexpr int PANEL_THREADS = 512;
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [I0, I1)
+template <int I0, int I1, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
+
+__device__ __forceinline__ void set_status(int32_t* status, int64_t idx, int32_t code) {
+  if (status) atomicCAS(status + idx, 0, code);
+}
+
+// Factor columns [j0, j0+nbp) of rows [j0, n) of each matrix.
+template <int RPT, int NB>
+__global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREADS), amdgpu_waves_per_eu(1, 2))) void k_panel(double2* A, int n, int ld, int64_t strideA, int j0,
+                                                          int nbp, int32_t* piv, int32_t* status, int64_t sst) {
+  __shared__ double2 prow[NB];
+  __shared__ double2 jrow[NB];
+  __shared__ double red_v[PANEL_THREADS / 64];
+  __shared__ int red_i[PANEL_THREADS / 64];
+
+  const int64_t b = blockIdx.x;
+  double2* M = A + b * strideA;
+  int32_t* pv = piv + b * (int64_t)n;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+
+  double2 a[RPT][NB];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = j0 + t + PANEL_THREADS * s;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      a[s][c] = (r < n && c < nbp) ? M[(int64_t)r * ld + j0 + c] : make_double2(0.0, 0.0);
+  }
+
+  static_for<0, NB>([&](auto cidx) {
+    constexpr int c = decltype(cidx)::value;
+    const int j = j0 + c;
+    // local argmax of |re| + |im| over owned rows r >= j
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = j0 + t + PANEL_THREADS * s;
+      if (r >= j && r < n) {
+        const double v = fabs(a[s][c].x) + fabs(a[s][c].y);
+        if (v > bv) { bv = v; bi = r; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+    __syncthreads();
+    bv = red_v[0];
+    bi = red_i[0];
+#pragma unroll
+    for (int w = 1; w < PANEL_THREADS / 64; ++w) {
+      const double ov = red_v[w];
+      const int oi = red_i[w];
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    const bool active = c < nbp;
+    const bool ok = active && (bv > 0.0);
+    if (active && !ok && t == 0) {  // zero (or NaN) pivot column: record, leave it as is
+      pv[j] = j;
+      set_status(status, b * sst, bv == 0.0 ? MS_ERR_SINGULAR : MS_ERR_NONFINITE);
+    }
+    const int p = ok ? bi : j;
+    // rows j and p: owners publish, then exchange
+    const int op = p - j0, oj = j - j0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      if (ok && t + PANEL_THREADS * s == op) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) prow[cc] = a[s][cc];
+      }
+      if (ok && t + PANEL_THREADS * s == oj) {
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) jrow[cc] = a[s][cc];
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      if (p != j) {
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          if (t + PANEL_THREADS * s == oj) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) a[s][cc] = prow[cc];
+          }
+          if (t + PANEL_THREADS * s == op) {
+#pragma unroll
+            for (int cc = 0; cc < NB; ++cc) a[s][cc] = jrow[cc];
+          }
+        }
+      }
+      if (t == 0) pv[j] = p;
+      const double2 inv = cinv(prow[c]);
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int r = j0 + t + PANEL_THREADS * s;
+        if (r > j && r < n) {
+          const double2 l = cmul(a[s][c], inv);
+          a[s][c] = l;
+#pragma unroll
+          for (int cc = c + 1; cc < NB; ++cc) a[s][cc] = csub(a[s][cc], cmul(l, prow[cc]));
+        }
+      }
+    }
+    __syncthreads();
+  });
+
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = j0 + t + PANEL_THREADS * s;
+    if (r < n) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nbp) M[(int64_t)r * ld + j0 + c] = a[s][c];
+    }
+  }
+}
+
+// Apply the panel's interchanges to columns [c0, ncols) and solve with its unit lower block.
+template <int NB>
+__global__ __launch_bounds__(256) void k_swap_trsm(double2* A, int n, int ld, int64_t strideA, int j0, int nbp,
+                                                   int c0, int ncols, const int32_t* piv) {
+  __shared__ double2 L[NB][NB];
+  __shared__ int sp[NB];
+  const int64_t b = blockIdx.y;
+  double2* M = A + b * strideA;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, k = idx % NB;
+    L[i][k] = (i < nbp && k < i) ? M[(int64_t)(j0 + i) * ld + j0 + k] : make_double2(0.0, 0.0);
+  }
+  if (t < NB) sp[t] = (t < nbp) ? piv[b * (int64_t)n + j0 + t] : 0;
+  __syncthreads();
+  const int col = c0 + blockIdx.x * 256 + t;
+  if (col >= ncols) return;
+  double2 x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i < nbp) {
+      const int r = j0 + i, p = sp[i];
+      double2* pr = M + (int64_t)r * ld + col;
+      if (p != r) {
+        double2* pp = M + (int64_t)p * ld + col;
+        const double2 tmp = *pp;
+        *pp = *pr;
+        *pr = tmp;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i < nbp) {
+      double2 v = M[(int64_t)(j0 + i) * ld + col];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < i) v = csub(v, cmul(L[i][k], x[k]));
+      x[i] = v;
+      M[(int64_t)(j0 + i) * ld + col] = v;
+    }
+  }
+}
+
+// Back substitution U Y = Z, Z = A[:, n:ncols], 64 right-hand sides per workgroup.
+constexpr int TR_KC = 64;
+__global__ __launch_bounds__(256) void k_trsm_upper(const double2* A, int n, int ld, int64_t strideA, int nrhs,
+                                                    double2* Y, int64_t ldy, int64_t sY, int32_t* status,
+                                                    int64_t sst) {
+  __shared__ double Us[2][16][TR_KC];      // U row block, re/im
+  __shared__ double2 D[16][16];            // diagonal block
+  __shared__ double2 R[16][64];            // right-hand sides of the block row
+  const int64_t b = blockIdx.y;
+  const double2* M = A + b * strideA;
+  double2* Yb = Y + b * sY;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int cbase = blockIdx.x * 64;
+  const int c0 = cbase + wave * 16;          // this wave's 16 columns
+  const int myc = c0 + (lane & 15);
+  const int nblk = (n + 15) / 16;
+
+  for (int ib = nblk - 1; ib >= 0; --ib) {
+    const int r0 = ib * 16, r1 = min(n, r0 + 16);
+    d4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    for (int k0 = r1; k0 < n; k0 += TR_KC) {
+      // stage U[r0:r0+16][k0:k0+KC]
+      for (int idx = t; idx < 16 * TR_KC; idx += 256) {
+        const int i = idx / TR_KC, k = idx % TR_KC;
+        double2 v = make_double2(0.0, 0.0);
+        if (r0 + i < n && k0 + k < n) v = M[(int64_t)(r0 + i) * ld + k0 + k];
+        Us[0][i][k] = v.x;
+        Us[1][i][k] = v.y;
+      }
+      __syncthreads();
+      const int kend = min(TR_KC, n - k0);
+      for (int kk = 0; kk < kend; kk += 4) {
+        const int kl = kk + (lane >> 4);
+        const double ar = Us[0][lane & 15][kl], ai = Us[1][lane & 15][kl];
+        double2 y = make_double2(0.0, 0.0);
+        if (k0 + kl < n && myc < nrhs) y = Yb[(int64_t)(k0 + kl) * ldy + myc];
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, ci, 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    // right-hand sides minus the product, into LDS
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = (lane >> 4) + 4 * v;   // f64 MFMA accumulator row
+      const int r = r0 + i;
+      double2 z = make_double2(0.0, 0.0);
+      if (r < n && myc < nrhs) z = M[(int64_t)r * ld + n + myc];
+      R[i][wave * 16 + (lane & 15)] = make_double2(z.x - cr[v], z.y - ci[v]);
+    }
+    for (int idx = t; idx < 256; idx += 256) {
+      const int i = idx / 16, k = idx % 16;
+      D[i][k] = (r0 + i < n && r0 + k < n) ? M[(int64_t)(r0 + i) * ld + r0 + k] : make_double2(1.0, 0.0);
+    }
+    __syncthreads();
+    if (t < 64) {
+      const int col = cbase + t;
+      for (int i = r1 - r0 - 1; i >= 0; --i) {
+        double2 v = R[i][t];
+        for (int k = i + 1; k < r1 - r0; ++k) v = csub(v, cmul(D[i][k], R[k][t]));
+        const double2 d = D[i][i];
+        double2 y;
+        if (d.x == 0.0 && d.y == 0.0) {
+          set_status(status, b * sst, (int32_t)MS_ERR_SINGULAR);
+          y = make_double2(0.0, 0.0);
+        } else {
+          y = cmul(v, cinv(d));
+        }
+        R[i][t] = y;
+        if (col < nrhs) Yb[(int64_t)(r0 + i) * ldy + col] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int RPT, int NB>
+void launch_panel(ms_ctx ctx, double2* A, int n, int ld, int64_t sA, int batch, int j0, int nbp, int32_t* piv,
+                  int32_t* status, int64_t sst) {
+  hipLaunchKernelGGL((k_panel<RPT, NB>), dim3(batch), dim3(PANEL_THREADS), 0, ctx->stream, A, n, ld, sA, j0, nbp,
+                     piv, status, sst);
+}
+
+}  // namespace
+
+ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, int batch, int32_t* piv,
+                    int32_t* status, int64_t sst) {
+  if (n <= 0 || batch <= 0) return MS_OK;
+  if (n > 4096) return fail(ctx, MS_ERR_UNSUPPORTED, "LU size %d > 4096", n);
+  if (batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "LU batch %d > 65535", batch);
+  const int rpt = (n + PANEL_THREADS - 1) / PANEL_THREADS;
+  const int nb = rpt <= 3 ? 16 : (rpt <= 6 ? 8 : 4);
+  for (int j0 = 0; j0 < n; j0 += nb) {
+    const int nbp = std::min(nb, n - j0);
+    {
+    Prof prof(ctx, PC_LU_PANEL, 8.0 * nbp * nbp * (double)(n - j0) * batch, 32.0 * nbp * (double)(n - j0) * batch);
+    switch (rpt) {
+      case 1: launch_panel<1, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 2: launch_panel<2, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 3: launch_panel<3, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 4: launch_panel<4, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 5: launch_panel<5, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 6: launch_panel<6, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      case 7: launch_panel<7, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      default: launch_panel<8, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+    }
+    }
+    MS_TRY(check_launch(ctx, "lu panel"));
+    const int c0 = j0 + nbp;
+    if (c0 >= ncols) continue;
+    dim3 g((ncols - c0 + 255) / 256, batch);
+    Prof prof(ctx, PC_LU_SWAP, 4.0 * nbp * nbp * (double)(ncols - c0) * batch, 64.0 * nbp * (double)(ncols - c0) * batch);
+    if (nb == 16)
+      hipLaunchKernelGGL((k_swap_trsm<16>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
+    else if (nb == 8)
+      hipLaunchKernelGGL((k_swap_trsm<8>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
+    else
+      hipLaunchKernelGGL((k_swap_trsm<4>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
+    MS_TRY(check_launch(ctx, "lu swap/trsm"));
+    if (c0 < n) {
+      GemmArgs ga;
+      ga.M = n - c0;
+      ga.N = ncols - c0;
+      ga.K = nbp;
+      ga.A = A + (int64_t)c0 * ncols + j0;
+      ga.lda = ncols;
+      ga.sA = strideA;
+      ga.B = A + (int64_t)j0 * ncols + c0;
+      ga.ldb = ncols;
+      ga.sB = strideA;
+      ga.C = A + (int64_t)c0 * ncols + c0;
+      ga.ldc = ncols;
+      ga.sC = strideA;
+      ga.alpha = make_double2(-1.0, 0.0);
+      ga.beta = make_double2(1.0, 0.0);
+      ga.batch = batch;
+      ga.prof = PC_LU_UPDATE;
+      MS_TRY(zgemm(ctx, ga));
+    }
+  }
+  return MS_OK;
+}
+
+ms_status trsm_upper_aug(ms_ctx ctx, const double2* A, int n, int ncols, int64_t strideA, int batch, double2* Y,
+                         int64_t ldy, int64_t sY, int32_t* status, int64_t sst) {
+  const int nrhs = ncols - n;
+  if (n <= 0 || nrhs <= 0 || batch <= 0) return MS_OK;
+  if (batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "trsm batch %d > 65535", batch);
+  dim3 g((nrhs + 63) / 64, batch);
+  Prof prof(ctx, PC_TRSM, 4.0 * (double)n * n * nrhs * batch, 16.0 * batch * ((double)n * n / 2 + 2.0 * n * nrhs));
+  hipLaunchKernelGGL(k_trsm_upper, g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, nrhs, Y, ldy, sY, status, sst);
+  return check_launch(ctx, "trsm upper");
+}
+
+}  // namespace ms

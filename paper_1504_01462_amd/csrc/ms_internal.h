@@ -1,0 +1,129 @@
+// Internal declarations of the MI355X multiple-scattering library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/ms.h"
+
+namespace ms {
+// kernel categories timed by the optional event profiler
+enum ProfCat {
+  PC_IFACE_GEMM = 0,  // the interface GEMM of the fused fold (rho^T O^T, both halves)
+  PC_LU_PANEL,        // LU panel factorisation
+  PC_LU_SWAP,         // row interchanges + unit-lower solve of the panel rows
+  PC_LU_UPDATE,       // trailing GEMM update of the LU
+  PC_TRSM,            // back substitution
+  PC_JACOBI,          // one round of the block Jacobi eigensolver
+  PC_PREP_GEMM,       // overlap GEMMs of the E-independent stage
+  PC_ELEM,            // elementwise kernels of the fused fold (prologue/epilogue/T)
+  PC_OTHER,
+  PC_COUNT
+};
+struct ProfRec {
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+}  // namespace ms
+
+struct ms_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t* d_status = nullptr;   // device status word (first error wins)
+  std::vector<void*> ws;         // workspace slots, grown on demand
+  std::vector<size_t> ws_size;
+  std::string last_error;
+  uint32_t prof_mask = 0;        // categories timed by the event profiler
+  std::vector<ms::ProfRec> prof[ms::PC_COUNT];
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace ms {
+
+// Records HIP events around the launches in its scope when profiling is on.
+struct Prof {
+  ms_ctx ctx;
+  int cat;
+  double flops, bytes;
+  hipEvent_t a = nullptr;
+  Prof(ms_ctx c, int category, double fl = 0.0, double by = 0.0);
+  ~Prof();
+};
+
+enum Op { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+// ---- error plumbing -------------------------------------------------------------------
+ms_status fail(ms_ctx ctx, ms_status s, const char* fmt, ...);
+ms_status hip_fail(ms_ctx ctx, hipError_t e, const char* what);
+
+#define MS_TRY(expr)                         \
+  do {                                       \
+    ms_status _s = (expr);                   \
+    if (_s != MS_OK) return _s;              \
+  } while (0)
+
+#define MS_HIP(ctx, expr)                                   \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return ms::hip_fail(ctx, _e, #expr); \
+  } while (0)
+
+// workspace slot `slot` of at least `bytes` (synchronises the stream before growing)
+ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out);
+ms_status check_launch(ms_ctx ctx, const char* what);
+
+// ---- complex GEMM: C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b] (row-major) -------
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  int opA = OP_N, opB = OP_N;
+  const void* A = nullptr;
+  int64_t lda = 0, sA = 0;
+  const void* B = nullptr;
+  int64_t ldb = 0, sB = 0;
+  double2* C = nullptr;
+  int64_t ldc = 0, sC = 0;
+  double2 alpha = {1.0, 0.0};
+  double2 beta = {0.0, 0.0};
+  int batch = 1;
+  int prof = PC_OTHER;   // profiler category of this launch
+};
+// A, B complex128; FP64 MFMA.
+ms_status zgemm(ms_ctx ctx, const GemmArgs& g);
+// A, B complex64; FP32 MFMA with FP32 accumulation; C complex128.
+ms_status cgemm32(ms_ctx ctx, const GemmArgs& g);
+
+// ---- batched LU of an augmented matrix and triangular solves (FP64) -------------------
+// Factor the leading n x n block of each n x ncols row-major matrix (ld = ncols)
+// with partial pivoting; row operations are applied to all ncols columns, so the
+// columns [n, ncols) end up holding L^-1 P^T B.  piv: [batch][n] int32.
+// status: [batch] int32 (may be null); a zero pivot writes MS_ERR_SINGULAR.
+// status index of matrix b is b * sst (sst = 0: one shared word).
+ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, int batch,
+                    int32_t* piv, int32_t* status, int64_t sst);
+// Solve U Y = Z for the upper factor U (leading n x n of A) and Z = A[:, n:ncols];
+// Y written to Y (n x (ncols-n), leading dim ldy, batch stride sY).
+ms_status trsm_upper_aug(ms_ctx ctx, const double2* A, int n, int ncols, int64_t strideA, int batch,
+                         double2* Y, int64_t ldy, int64_t sY, int32_t* status, int64_t sst);
+
+// ---- elementwise and reduction kernels (launchers) ------------------------------------
+ms_status launch_kin_eps(ms_ctx ctx, int n, const int32_t* g_mn, const double* bvec, const double* kpar,
+                         double vl, double vr, double* kin, double* eps_left, double* eps_right);
+ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, const double2* vq,
+                             int q0, double* shift);
+ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t n_q,
+                         const double2* vq, const int32_t* q_of_ij, double2* W);
+ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double* shift, double* eps_out,
+                      int64_t eps_stride, double2* U, int64_t u_stride, int32_t* status);
+ms_status launch_copy_boundary_overlaps(ms_ctx ctx, int n, const double2* U, double2* O, int conj_transpose);
+ms_status launch_minmax(ms_ctx ctx, int64_t count, const int32_t* v, int32_t* out2);
+// copy `bytes` of host data to device memory and wait (the host buffer may be temporary)
+ms_status upload(ms_ctx ctx, void* dst, const void* src, size_t bytes);
+
+ms_status launch_wavevectors(ms_ctx ctx, int n, int nrows, int n_e, const double* eps, const double* energies_dev,
+                             const double* dz_rows, double2* kbuf, double2* pbuf);
+
+}  // namespace ms

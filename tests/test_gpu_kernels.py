@@ -1,0 +1,121 @@
+"""Kernel-level parity of the HIP building blocks (complex GEMM on MFMA, batched LU
+solve, slice eigensolver) against NumPy/LAPACK in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1504_01462_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def _rand(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _op(x, op):
+    return x if op == 0 else (x.T if op == 1 else x.conj().T)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (16, 16, 4), (37, 37, 37), (64, 64, 16), (65, 63, 17),
+                                   (130, 200, 70), (300, 300, 300), (5, 700, 3)])
+@pytest.mark.parametrize("ops", [(0, 0), (0, 1), (2, 0), (1, 2)])
+def test_gemm_fp64(lib, ctx, m, n, k, ops):
+    rng = np.random.default_rng(m * 1000 + n + k)
+    op_a, op_b = ops
+    a = _rand(rng, (m, k) if op_a == 0 else (k, m))
+    b = _rand(rng, (k, n) if op_b == 0 else (n, k))
+    c0 = _rand(rng, (m, n))
+    alpha, beta = 0.7 - 0.2j, -0.3 + 1.1j
+    ref = alpha * (_op(a, op_a) @ _op(b, op_b)) + beta * c0
+    c = to_dev(c0)
+    lib.ms_debug_gemm(ctx, to_dev(a), to_dev(b), c, op_a, op_b, alpha, beta, "fp64")
+    ctx.sync()
+    err = np.max(np.abs(c.cpu().numpy() - ref))
+    assert err <= 1e-14 * (k + 4) * 4.0, err
+
+
+@pytest.mark.parametrize("m,n,k", [(37, 37, 37), (130, 200, 70), (300, 300, 300)])
+def test_gemm_fp32(lib, ctx, m, n, k):
+    rng = np.random.default_rng(7 + m)
+    a = _rand(rng, (m, k)).astype(np.complex64)
+    b = _rand(rng, (k, n)).astype(np.complex64)
+    ref = a.astype(np.complex128) @ b.astype(np.complex128)
+    c = lib.ms_debug_gemm(ctx, to_dev(a), to_dev(b), prec="fp32")
+    ctx.sync()
+    err = np.max(np.abs(c.cpu().numpy() - ref))
+    # FP32 products, FP32 accumulation of k terms of size ~|a||b| ~ 2
+    assert err <= 6e-8 * 4 * k * 2, err
+
+
+@pytest.mark.parametrize("n,nrhs,batch", [(1, 1, 2), (5, 3, 3), (16, 16, 2), (17, 13, 2), (37, 74, 3),
+                                          (100, 64, 2), (300, 313, 2), (513, 70, 1), (1030, 20, 1)])
+def test_lu_solve(lib, ctx, n, nrhs, batch):
+    rng = np.random.default_rng(n + nrhs)
+    a = _rand(rng, (batch, n, n))
+    a[:, np.arange(n), np.arange(n)] *= 1e-3          # force pivoting
+    b = _rand(rng, (batch, n, nrhs))
+    aug = to_dev(np.concatenate([a, b], axis=2))
+    x, st = lib.ms_debug_lu_solve(ctx, aug, n)
+    ctx.sync()
+    assert np.all(st.cpu().numpy() == 0)
+    x = x.cpu().numpy()
+    for i in range(batch):
+        ref = np.linalg.solve(a[i], b[i])
+        res = np.linalg.norm(a[i] @ x[i] - b[i]) / (np.linalg.norm(a[i]) * np.linalg.norm(x[i]))
+        assert res < 1e-14 * max(1.0, np.sqrt(n)), res
+        cond = np.linalg.cond(a[i])
+        assert np.max(np.abs(x[i] - ref)) <= 1e-14 * cond * max(1.0, np.max(np.abs(ref))) * n
+
+
+def test_lu_singular_flag(lib, ctx):
+    n = 20
+    rng = np.random.default_rng(3)
+    a = _rand(rng, (2, n, n))
+    a[1, :, 7] = 0.0                                   # exactly singular second matrix
+    aug = to_dev(np.concatenate([a, _rand(rng, (2, n, 2))], axis=2))
+    _, st = lib.ms_debug_lu_solve(ctx, aug, n)
+    ctx.sync()
+    st = st.cpu().numpy()
+    assert st[0] == 0 and st[1] == lib.MS_ERR_SINGULAR
+
+
+def _gershgorin_shift(h):
+    off = np.sum(np.abs(h), axis=1) - np.abs(np.diag(h))
+    lo = np.min(np.real(np.diag(h)) - off)
+    return max(0.0, -lo) + 1.0
+
+
+@pytest.mark.parametrize("n,batch", [(1, 2), (7, 3), (16, 2), (33, 2), (37, 3), (65, 2), (300, 2)])
+def test_eigh(lib, ctx, n, batch):
+    rng = np.random.default_rng(100 + n)
+    h = _rand(rng, (batch, n, n))
+    h = 0.5 * (h + np.conj(np.transpose(h, (0, 2, 1))))
+    if n >= 7:   # an exactly degenerate block and a decoupled diagonal entry
+        h[0, :3, :] = 0.0
+        h[0, :, :3] = 0.0
+        h[0, 0, 0] = h[0, 1, 1] = h[0, 2, 2] = 0.25
+    shift = np.array([_gershgorin_shift(x) for x in h])
+    eps, u = lib.ms_debug_eigh(ctx, to_dev(h), to_dev(shift))
+    ctx.sync()
+    eps, u = eps.cpu().numpy(), u.cpu().numpy()
+    for i in range(batch):
+        ref = np.linalg.eigvalsh(h[i])
+        scale = max(1.0, np.linalg.norm(h[i], 2))
+        assert np.max(np.abs(eps[i] - ref)) < 1e-12 * scale
+        assert np.linalg.norm(h[i] @ u[i] - u[i] * eps[i]) < 1e-12 * scale * np.sqrt(n)
+        assert np.max(np.abs(u[i].conj().T @ u[i] - np.eye(n))) < 1e-12

@@ -1,0 +1,252 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP64 path): T within 1e-10 of the oracle, the per-slice and whole
+S-matrices within 1e-11 of the largest entry; these are the accumulated
+rounding of ~10 N^3 complex operations per interface over tens to hundreds of
+interfaces, several orders above machine epsilon and far below the 1e-10
+target on T.  The FP32-MFMA form is compared with the FP64 path on every
+point at |dT| <= 1e-6.
+"""
+import numpy as np
+import pytest
+import torch
+
+import msgen
+import oracle as orc
+from gpu_common import dev, to_dev, slices_from_oracle, rel_err, golden_points, junction_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_1504_01462_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(ms):
+    c = ms.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    j = msgen.config1()
+    inp = msgen.junction_inputs(j, j.kpars[0])
+    return j, inp, orc.prepare(inp)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------ a1-a3 -----------------
+def test_prepare_config1(ms, ctx, c1):
+    j, inp, prep = c1
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    ctx.sync()
+    eps, ovl, u = _np(s.eps), _np(s.ovl), _np(s.evec)
+    ns, n = prep["n_slices"], prep["n"]
+    assert np.allclose(eps[0], prep["kin"], rtol=0, atol=1e-13)
+    assert np.allclose(eps[ns + 1], prep["kin"], rtol=0, atol=1e-13)
+    h = orc.slice_hamiltonians(prep["kin"], inp["vq"], inp["q_of_ij"])
+    for p in range(ns):
+        assert np.max(np.abs(eps[p + 1] - prep["eps"][p + 1])) < 1e-12
+        sc = np.linalg.norm(h[p], 2)
+        assert np.linalg.norm(h[p] @ u[p] - u[p] * eps[p + 1]) < 1e-12 * sc
+        assert np.max(np.abs(u[p].conj().T @ u[p] - np.eye(n))) < 1e-12
+    assert np.max(np.abs(ovl[0] - u[0])) == 0.0
+    assert np.max(np.abs(ovl[ns] - u[ns - 1].conj().T)) == 0.0
+    for p in range(1, ns):
+        assert np.max(np.abs(ovl[p] - u[p - 1].conj().T @ u[p])) < 1e-13
+
+
+# ------------------------------------------------------------------ a4 --------------------
+def test_slice_smatrix_matches_oracle(ms, ctx, c1):
+    _, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    for e in (0.1, 0.55, 2.3):
+        out = ms.ms_slice_smatrix(ctx, s, e, 0, prep["n_slices"] + 1)
+        ctx.sync()
+        ref = orc.interface_smatrices(prep, e)
+        for p, (blocks, r) in enumerate(zip(out, ref)):
+            for b, key in zip(blocks, ("t", "rp", "r", "tp")):
+                assert rel_err(_np(b), r[key]) < 1e-12, (e, p, key)
+
+
+# ------------------------------------------------------------------ a5 + a6 ---------------
+@pytest.mark.parametrize("e", [0.1, 0.7, 3.1])
+def test_star_cascade_and_transmission_match_oracle(ms, ctx, c1, e):
+    _, inp, prep = c1
+    ref_s = orc.interface_smatrices(prep, e)
+    smats = [tuple(to_dev(r[k]) for k in ("t", "rp", "r", "tp")) for r in ref_s]
+    whole = ms.ms_star_cascade(ctx, smats)
+    ctx.sync()
+    ref = orc.cascade(ref_s, "left")
+    for b, key in zip(whole, ("t", "rp", "r", "tp")):
+        assert rel_err(_np(b), ref[key]) < 1e-11, key
+    T, R, no = ms.ms_transmission(ctx, whole, e, to_dev(prep["eps"][0]), to_dev(prep["eps"][-1]))
+    ctx.sync()
+    tt, rr, n_open = orc.transmission_from_smatrix(ref, e, prep["eps"][0], prep["eps"][-1])
+    assert abs(_np(T)[0] - tt) < 1e-10 and abs(_np(R)[0] - rr) < 1e-10 and int(_np(no)[0]) == n_open
+
+
+def test_star_cascade_single_and_two(ms, ctx, c1):
+    _, inp, prep = c1
+    ref_s = orc.interface_smatrices(prep, 0.4)[:2]
+    smats = [tuple(to_dev(r[k]) for k in ("t", "rp", "r", "tp")) for r in ref_s]
+    one = ms.ms_star_cascade(ctx, smats[:1])
+    two = ms.ms_star_cascade(ctx, smats)
+    ctx.sync()
+    for b, key in zip(one, ("t", "rp", "r", "tp")):
+        assert np.array_equal(_np(b), ref_s[0][key])
+    ref = orc.star(ref_s[0], ref_s[1])
+    for b, key in zip(two, ("t", "rp", "r", "tp")):
+        assert rel_err(_np(b), ref[key]) < 1e-12
+
+
+# ------------------------------------------------------------------ fused batch path -------
+def test_batch_with_oracle_eigendata(ms, ctx, c1):
+    """The fused fold alone (slice data from the oracle)."""
+    j, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    es = np.concatenate([j.energies, [2.2, 3.9]])
+    T, R, no, st = ms.ms_transmission_batch(ctx, s, es)
+    ctx.sync()
+    assert np.all(_np(st) == 0)
+    for i, e in enumerate(es):
+        ref = orc.transmission(prep, e)
+        assert abs(_np(T)[i] - ref["T"]) < 1e-11
+        assert abs(_np(R)[i] - ref["R"]) < 1e-11
+        assert int(_np(no)[i]) == ref["n_open"]
+
+
+def test_end_to_end_config1(ms, ctx, c1):
+    j, inp, prep = c1
+    s = ms.prepare_from_inputs(ctx, inp)
+    T, R, no, st = ms.ms_transmission_batch(ctx, s, j.energies)
+    ctx.sync()
+    assert np.all(_np(st) == 0)
+    for i, e in enumerate(j.energies):
+        ref = orc.transmission(prep, e)
+        assert abs(_np(T)[i] - ref["T"]) < 1e-10
+        assert abs(_np(T)[i] + _np(R)[i] - ref["n_open"]) < 1e-10
+
+
+def test_golden_config1(ms, ctx, c1):
+    j, inp, _ = c1
+    pts = golden_points("config1")
+    assert pts, "tests/golden/oracle_points.json has no config1 points"
+    s = ms.prepare_from_inputs(ctx, inp)
+    T, R, no, st = ms.ms_transmission_batch(ctx, s, [p["energy"] for p in pts])
+    ctx.sync()
+    for i, p in enumerate(pts):
+        assert abs(_np(T)[i] - p["T"]) < 1e-10 and int(_np(no)[i]) == p["n_open"]
+
+
+def test_golden_config2(ms, ctx):
+    """Full-size config-2 slices (N_G = 300, 160 slices) at the oracle's sample points."""
+    pts = golden_points("config2")
+    assert pts, "tests/golden/oracle_points.json has no config2 points"
+    groups = {}
+    for p in pts:
+        groups.setdefault((p["junction"], p["k_index"]), []).append(p)
+    for (name, ik), g in groups.items():
+        j = junction_for(g[0])
+        inp = msgen.junction_inputs(j, j.kpars[ik])
+        s = ms.prepare_from_inputs(ctx, inp)
+        T, R, no, st = ms.ms_transmission_batch(ctx, s, [p["energy"] for p in g])
+        ctx.sync()
+        assert np.all(_np(st) == 0)
+        for i, p in enumerate(g):
+            assert abs(_np(T)[i] - p["T"]) < 1e-10, (name, p["energy"], _np(T)[i], p["T"])
+            assert abs(_np(T)[i] + _np(R)[i] - p["n_open"]) < 1e-9
+
+
+def test_fp32_form_against_fp64(ms, ctx, c1):
+    j, inp, _ = c1
+    s = ms.prepare_from_inputs(ctx, inp)
+    es = np.linspace(0.1, 4.0, 12)
+    t64 = _np(ms.ms_transmission_batch(ctx, s, es, "fp64")[0])
+    t32, r32, no, st = ms.ms_transmission_batch(ctx, s, es, "fp32")
+    ctx.sync()
+    assert np.all(_np(st) == 0)
+    assert np.max(np.abs(_np(t32) - t64)) < 1e-6
+
+
+# ------------------------------------------------------------------ edge cases -------------
+def test_single_plane_wave_square_barrier(ms, ctx):
+    """N_G = 1, V(z) = V0 on [0.5, 2.5]: the 1D closed form."""
+    j = msgen.config1()
+    j.dz = np.full(12, 0.25)
+    inp = msgen.junction_inputs(j, (0.0, 0.0), n_g=1)
+    v0 = 0.5
+    vz = np.zeros(12)
+    vz[2:10] = v0
+    inp["vq"] = vz.reshape(12, 1).astype(np.complex128)
+    s = ms.prepare_from_inputs(ctx, inp)
+    es = np.array([0.2, 0.45, 0.7, 1.3])
+    T, R, no, st = ms.ms_transmission_batch(ctx, s, es)
+    ctx.sync()
+    for i, e in enumerate(es):
+        if e > v0:
+            q = np.sqrt(e - v0)
+            ref = 1 / (1 + v0 ** 2 * np.sin(2 * q) ** 2 / (4 * e * (e - v0)))
+        else:
+            kap = np.sqrt(v0 - e)
+            ref = 1 / (1 + v0 ** 2 * np.sinh(2 * kap) ** 2 / (4 * e * (v0 - e)))
+        assert abs(_np(T)[i] - ref) < 1e-12
+
+
+def test_single_slice_and_ragged_sizes(ms, ctx):
+    for n_g, ns in ((13, 1), (65, 3), (130, 5)):
+        j = msgen.config1()
+        j.dz = np.full(ns, 6.0 / ns)
+        inp = msgen.junction_inputs(j, (0.1, -0.05), n_g=n_g)
+        prep = orc.prepare(inp)
+        s = ms.prepare_from_inputs(ctx, inp)
+        es = np.array([0.35, 2.9])
+        T, R, no, st = ms.ms_transmission_batch(ctx, s, es)
+        ctx.sync()
+        for i, e in enumerate(es):
+            ref = orc.transmission(prep, e)
+            assert abs(_np(T)[i] - ref["T"]) < 1e-10, (n_g, ns, e)
+
+
+def test_no_open_channel_and_threshold(ms, ctx, c1):
+    j, inp, prep = c1
+    s = ms.prepare_from_inputs(ctx, inp)
+    es = np.array([-0.3, float(prep["kin"][4]), 0.5])
+    T, R, no, st = ms.ms_transmission_batch(ctx, s, es)
+    ctx.sync()
+    st = _np(st)
+    assert st[0] == 0 and _np(T)[0] == 0.0 and _np(R)[0] == 0.0 and _np(no)[0] == 0
+    assert st[1] == ms.MS_ERR_THRESHOLD
+    assert st[2] == 0
+
+
+def test_argument_errors(ms, ctx, c1):
+    _, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_slice_smatrix(ctx, s, 0.5, 3, 2)
+    assert ei.value.status == ms.MS_ERR_ARG
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_transmission_batch(ctx, s, [0.5, float("nan")])
+    assert ei.value.status == ms.MS_ERR_ARG
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_star_cascade(ctx, [], "fp64") if False else ms.ms_star_cascade(
+            ctx, [tuple(to_dev(np.eye(4, dtype=complex)) for _ in range(4))], "fp32")
+    assert ei.value.status == ms.MS_ERR_UNSUPPORTED
+
+
+def test_deterministic(ms, ctx, c1):
+    j, inp, _ = c1
+    s = ms.prepare_from_inputs(ctx, inp)
+    a = _np(ms.ms_transmission_batch(ctx, s, j.energies)[0])
+    s2 = ms.prepare_from_inputs(ctx, inp)
+    b = _np(ms.ms_transmission_batch(ctx, s2, j.energies)[0])
+    ctx.sync()
+    assert np.array_equal(a, b)

@@ -333,3 +333,19 @@ def test_singular_star_raises():
     b = dict(t=e.copy(), rp=z.copy(), r=e.copy(), tp=e.copy())
     with pytest.raises(orc.SingularError):
         orc.star(a, b)
+
+
+def test_kpar_average():
+    """Eq. (T1_d): the mesh average; when T does not depend on k_y it reduces to the
+    k_x average of Eq. (T2_d); per-channel transmission is sum T / sum N_open."""
+    rng = np.random.default_rng(5)
+    tx = rng.uniform(0, 3, size=(6, 4))              # T(m_x, E)
+    nx = rng.integers(1, 5, size=(6, 4))
+    t2 = np.repeat(tx, 3, axis=0)                    # the same for 3 values of k_y
+    n2 = np.repeat(nx, 3, axis=0)
+    tbar2, per2 = orc.kpar_average(t2, n2)
+    tbar1, per1 = orc.kpar_average(tx, nx)
+    assert np.allclose(tbar2, tx.mean(axis=0), rtol=1e-15) and np.allclose(tbar1, tbar2, rtol=1e-15)
+    assert np.allclose(per1, tx.sum(0) / nx.sum(0), rtol=1e-15) and np.allclose(per1, per2, rtol=1e-15)
+    tb, pc = orc.kpar_average(np.zeros((2, 3)), np.zeros((2, 3), dtype=int))
+    assert np.all(tb == 0) and np.all(pc == 0)
