@@ -1,0 +1,46 @@
+"""Full-size check at N_G = 1200, 400 slices (the benchmark workload), in the launch
+configuration bench.py times: one (gap, k_par) with its 32 energies per batch.
+
+The oracle takes about 13 minutes per point here, so its values at two sample
+points are stored (tests/golden/make_golden.py); every other point is checked
+through properties that hold at any size: current conservation R + T = N_open
+and agreement of the FP32-MFMA form with the FP64 form."""
+import numpy as np
+import pytest
+
+import msgen
+from gpu_common import golden_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_1504_01462_amd as m
+    return m
+
+
+def test_config3_full_batch(ms):
+    pts = golden_points("config3")
+    assert pts, "tests/golden/oracle_points.json has no config3 points"
+    p0 = pts[0]
+    j = msgen.config3(p0["meta"]["gap"], p0["meta"]["registry"])
+    inp = msgen.junction_inputs(j, j.kpars[p0["k_index"]])
+    ctx = ms.Context(0)
+    s = ms.prepare_from_inputs(ctx, inp)
+    T, R, no, st = (x.cpu().numpy() for x in ms.ms_transmission_batch(ctx, s, j.energies, "fp64"))
+    ctx.sync()
+    assert np.all(st == 0)
+    assert np.max(np.abs(T + R - no)) < 1e-9
+    for p in pts:
+        i = p["e_index"]
+        assert abs(j.energies[i] - p["energy"]) < 1e-15
+        assert int(no[i]) == p["n_open"]
+        assert abs(T[i] - p["T"]) < 1e-10, (p["energy"], T[i], p["T"])
+    T32, R32, no32, st32 = (x.cpu().numpy() for x in ms.ms_transmission_batch(ctx, s, j.energies, "fp32"))
+    ctx.sync()
+    assert np.all(st32 == 0)
+    dT = np.max(np.abs(T32 - T))
+    print(f"\nconfig3 FP32-MFMA form: max |dT| vs FP64 over {T.size} points = {dT:.3e}")
+    assert dT < 1e-6
+    ctx.close()
