@@ -298,19 +298,23 @@ ms_status ms_slices_prepare(ms_ctx ctx, int64_t n_g, const int32_t* g_mn, const 
     return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
   const int32_t q0 = qr[2];
 
-  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(PREP_BUDGET / (2 * nn * sizeof(double2)))));
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(PREP_BUDGET / (3 * nn * sizeof(double2)))));
   chunk = std::min(chunk, 256);
+  void* Z = nullptr;
   MS_TRY(workspace(ctx, WS_SHIFT, chunk * sizeof(double), &shift));
   MS_TRY(workspace(ctx, WS_W, (size_t)chunk * nn * sizeof(double2), &W));
   MS_TRY(workspace(ctx, WS_U, (size_t)(chunk + 1) * nn * sizeof(double2), &U));
+  MS_TRY(workspace(ctx, WS_Z, (size_t)chunk * nn * sizeof(double2), &Z));
   double2* Ub = c2(U);
   for (int s0 = 0; s0 < ns; s0 += chunk) {
     const int bc = std::min(chunk, ns - s0);
     const double2* vq_c = c2(vq) + (int64_t)s0 * n_q;
     MS_TRY(launch_slice_shift(ctx, n, bc, (const double*)kin, n_q, vq_c, q0, (double*)shift));
     MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, (const double*)shift, n_q, vq_c, q_of_ij, c2(W)));
+    // H itself into U slots 1..bc (the eigenvectors overwrite it at the end)
+    MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, nullptr, n_q, vq_c, q_of_ij, Ub + nn));
     // slice s0+i (paper p = s0+i+1) -> eps row s0+i+1, U slot i+1
-    MS_TRY(jacobi_eigh(ctx, n, bc, c2(W), (const double*)shift, eps + (int64_t)(s0 + 1) * n, n, Ub + nn, nn,
+    MS_TRY(jacobi_eigh(ctx, n, bc, c2(W), Ub + nn, c2(Z), eps + (int64_t)(s0 + 1) * n, n, Ub + nn, nn,
                        ctx->d_status));
     // overlaps O^p = U^p^dagger U^{p+1}; slots: 0 = U^{s0} (previous chunk), i = U^{s0+i}
     const int P0 = s0 + 1, P1 = s0 + bc;

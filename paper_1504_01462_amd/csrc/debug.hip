@@ -63,13 +63,15 @@ ms_status ms_debug_eigh(ms_ctx ctx, int64_t n, int64_t batch, const void* h, con
   MS_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t nn = n * n;
   void* W = nullptr;
+  void* Z = nullptr;
   MS_TRY(workspace(ctx, 2, (size_t)batch * nn * sizeof(double2), &W));
+  MS_TRY(workspace(ctx, 20, (size_t)batch * nn * sizeof(double2), &Z));
   MS_HIP(ctx, hipMemcpyAsync(W, h, (size_t)batch * nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
   hipLaunchKernelGGL(k_add_shift, dim3((unsigned)((n + 255) / 256), (unsigned)batch), dim3(256), 0, ctx->stream, (int)n,
                      shift, static_cast<double2*>(W));
   MS_TRY(check_launch(ctx, "add shift"));
-  return jacobi_eigh(ctx, (int)n, (int)batch, static_cast<double2*>(W), shift, eps, n, static_cast<double2*>(u), nn,
-                     ctx->d_status);
+  return jacobi_eigh(ctx, (int)n, (int)batch, static_cast<double2*>(W), static_cast<const double2*>(h),
+                     static_cast<double2*>(Z), eps, n, static_cast<double2*>(u), nn, ctx->d_status);
 }
 
 }  // extern "C"

@@ -12,9 +12,10 @@
 // which makes the 32 columns mutually orthogonal.  At convergence
 // W = A V has orthogonal columns; since A is Hermitian positive definite its
 // eigenvectors are the normalised columns u_j = w_j / |w_j| and its
-// eigenvalues |w_j|, so E_j = |w_j| - c.  Pairs already orthogonal to the
-// tolerance are skipped; a matrix whose previous sweep rotated nothing exits
-// at once.
+// eigenvalues |w_j| - c.  The eigenvalues returned are the Rayleigh quotients
+// u_j^dagger H u_j (one extra GEMM), whose error is second order in the
+// eigenvector error.  Pairs already orthogonal to the tolerance are skipped; a
+// matrix whose previous sweep rotated nothing exits at once.
 #include "ms_internal.h"
 
 namespace ms {
@@ -78,7 +79,7 @@ __global__ void k_hgather(int n, const double* kin, const double* shift, int64_t
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), j = (int)(idx % n);
   double2 h = vq[b * n_q + q_of_ij[idx]];
-  if (i == j) h.x += kin[i] + shift[b];
+  if (i == j) h.x += kin[i] + (shift ? shift[b] : 0.0);
   W[b * (int64_t)n * n + idx] = h;
 }
 
@@ -107,7 +108,7 @@ __device__ __forceinline__ int pair_col(int a, int I, int J, int mI, int mJ) {
 __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   __shared__ double2 G[PW][PW + 1];
   __shared__ double2 Q[PW][PW + 1];
-  __shared__ double Ps[2][ROWS][PW];
+  __shared__ __align__(16) double Ps[2][ROWS][PW];
   __shared__ double rc[PW / 2], rs[PW / 2];
   __shared__ double2 rph[PW / 2];
   __shared__ int ra[PW / 2], rb[PW / 2];
@@ -258,7 +259,38 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
       }
       __syncthreads();
     }
-    if (s_flag == 0) break;
+    // every thread reads the flag before thread 0 may reset it for the next sweep
+    const bool rotated = s_flag != 0;
+    __syncthreads();
+    if (!rotated) break;
+  }
+
+  // --- Q <- Q (3 I - Q^dagger Q) / 2: one Newton-Schulz step restores unitarity to
+  //     O(|Q^dagger Q - I|^2), so repeated pair updates do not drift the column norms
+  {
+    double2(*Qn)[PW] = reinterpret_cast<double2(*)[PW]>(&Ps[0][0][0]);
+    for (int idx = t; idx < PW * PW; idx += 256) {      // G <- Q^dagger Q
+      const int a = idx / PW, c = idx % PW;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = 0; k < PW; ++k) acc = cadd(acc, cmul(cconj(Q[k][a]), Q[k][c]));
+      G[a][c] = acc;
+    }
+    __syncthreads();
+    for (int idx = t; idx < PW * PW; idx += 256) {      // G <- (3 I - G) / 2
+      const int a = idx / PW, c = idx % PW;
+      const double2 g = G[a][c];
+      G[a][c] = make_double2((a == c ? 1.5 : 0.0) - 0.5 * g.x, -0.5 * g.y);
+    }
+    __syncthreads();
+    for (int idx = t; idx < PW * PW; idx += 256) {      // Qn <- Q G
+      const int a = idx / PW, c = idx % PW;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = 0; k < PW; ++k) acc = cadd(acc, cmul(Q[a][k], G[k][c]));
+      Qn[a][c] = acc;
+    }
+    __syncthreads();
+    for (int idx = t; idx < PW * PW; idx += 256) Q[idx / PW][idx % PW] = Qn[idx / PW][idx % PW];
+    __syncthreads();
   }
 
   // --- P <- P Q, ROWS rows at a time; waves split the 64 x 32 output into 16-row slabs
@@ -302,27 +334,44 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   }
 }
 
-// ---- normalise, sort ascending, emit eigenpairs ------------------------------------------
-__global__ __launch_bounds__(256) void k_jacobi_finalize(const double2* Wall, int n, const double* shift,
-                                                         const int32_t* counter, int max_sweeps, double* eps_out,
-                                                         int64_t eps_stride, double2* Uall, int64_t u_stride,
-                                                         int32_t* status) {
+// ---- normalise the converged columns in place: w_j <- w_j / |w_j| ---------------------------
+__global__ __launch_bounds__(256) void k_jacobi_normalize(double2* Wall, int n, const int32_t* counter, int max_sweeps,
+                                                          int32_t* status) {
+  const int64_t b = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double2* W = Wall + b * (int64_t)n * n;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double2 w = W[(int64_t)i * n + j];
+    s += w.x * w.x + w.y * w.y;
+  }
+  const double inv = 1.0 / sqrt(s);
+  for (int i = 0; i < n; ++i) {
+    const double2 w = W[(int64_t)i * n + j];
+    W[(int64_t)i * n + j] = make_double2(w.x * inv, w.y * inv);
+  }
+  if (j == 0 && status && counter[b * max_sweeps + max_sweeps - 1] != 0) atomicCAS(status, 0, (int32_t)MS_ERR_NOCONV);
+}
+
+// ---- Rayleigh quotients lambda_j = Re(u_j^dagger (H u_j)), sort ascending, emit eigenpairs ----
+__global__ __launch_bounds__(256) void k_jacobi_emit(const double2* Wall, const double2* Zall, int n, double* eps_out,
+                                                     int64_t eps_stride, double2* Uall, int64_t u_stride) {
   extern __shared__ double sh[];
-  double* lam = sh;          // [n]
-  double* sig = sh + n;      // [n]
-  int* rank = (int*)(sh + 2 * n);
+  double* lam = sh;                  // [n]
+  int* rank = (int*)(sh + n);        // [n]
   const int64_t b = blockIdx.x;
   const int t = threadIdx.x;
   const double2* W = Wall + b * (int64_t)n * n;
+  const double2* Z = Zall + b * (int64_t)n * n;
   double2* U = Uall + b * u_stride;
   for (int j = t; j < n; j += 256) {
     double s = 0.0;
     for (int i = 0; i < n; ++i) {
-      const double2 w = W[(int64_t)i * n + j];
-      s += w.x * w.x + w.y * w.y;
+      const double2 w = W[(int64_t)i * n + j], z = Z[(int64_t)i * n + j];
+      s += w.x * z.x + w.y * z.y;
     }
-    sig[j] = sqrt(s);
-    lam[j] = sig[j] - shift[b];
+    lam[j] = s;
   }
   __syncthreads();
   for (int j = t; j < n; j += 256) {
@@ -334,15 +383,8 @@ __global__ __launch_bounds__(256) void k_jacobi_finalize(const double2* Wall, in
   }
   __syncthreads();
   for (int j = t; j < n; j += 256) {
-    const double inv = 1.0 / sig[j];
     const int r = rank[j];
-    for (int i = 0; i < n; ++i) {
-      const double2 w = W[(int64_t)i * n + j];
-      U[(int64_t)i * n + r] = make_double2(w.x * inv, w.y * inv);
-    }
-  }
-  if (t == 0 && status) {
-    if (counter[b * max_sweeps + max_sweeps - 1] != 0) atomicCAS(status, 0, (int32_t)MS_ERR_NOCONV);
+    for (int i = 0; i < n; ++i) U[(int64_t)i * n + r] = W[(int64_t)i * n + j];
   }
 }
 
@@ -402,8 +444,8 @@ ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const dou
   return check_launch(ctx, "hgather");
 }
 
-ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double* shift, double* eps_out, int64_t eps_stride,
-                      double2* U, int64_t u_stride, int32_t* status) {
+ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, double2* Z, double* eps_out,
+                      int64_t eps_stride, double2* U, int64_t u_stride, int32_t* status) {
   const int nb_real = (n + BW - 1) / BW;
   const int nblk = nb_real + (nb_real & 1);
   const int rounds = nblk - 1, per = nblk / 2;
@@ -441,11 +483,23 @@ ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double* shift
       MS_TRY(check_launch(ctx, "jacobi round"));
     }
   }
-  const size_t shmem = (size_t)n * (2 * sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(k_jacobi_normalize, dim3((n + 255) / 256, nb), dim3(256), 0, ctx->stream, W, n, a.counter,
+                     max_sweeps, status);
+  MS_TRY(check_launch(ctx, "jacobi normalize"));
+  // Z = H U (unsorted), then Rayleigh quotients
+  GemmArgs g;
+  g.M = n; g.N = n; g.K = n;
+  g.A = H; g.lda = n; g.sA = (int64_t)n * n;
+  g.B = W; g.ldb = n; g.sB = (int64_t)n * n;
+  g.C = Z; g.ldc = n; g.sC = (int64_t)n * n;
+  g.batch = nb;
+  g.prof = PC_PREP_GEMM;
+  MS_TRY(zgemm(ctx, g));
+  const size_t shmem = (size_t)n * (sizeof(double) + sizeof(int));
   if (shmem > 64 * 1024) return fail(ctx, MS_ERR_UNSUPPORTED, "eigensolver size %d too large", n);
-  hipLaunchKernelGGL(k_jacobi_finalize, dim3(nb), dim3(256), shmem, ctx->stream, W, n, shift, a.counter, max_sweeps,
-                     eps_out, eps_stride, U, u_stride, status);
-  return check_launch(ctx, "jacobi finalize");
+  hipLaunchKernelGGL(k_jacobi_emit, dim3(nb), dim3(256), shmem, ctx->stream, W, Z, n, eps_out, eps_stride, U,
+                     u_stride);
+  return check_launch(ctx, "jacobi emit");
 }
 
 ms_status launch_minmax(ms_ctx ctx, int64_t count, const int32_t* v, int32_t* out2) {

@@ -114,9 +114,12 @@ ms_status launch_kin_eps(ms_ctx ctx, int n, const int32_t* g_mn, const double* b
                          double vl, double vr, double* kin, double* eps_left, double* eps_right);
 ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, const double2* vq,
                              int q0, double* shift);
+// W = H + diag(shift) (shift may be null for H itself)
 ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t n_q,
                          const double2* vq, const int32_t* q_of_ij, double2* W);
-ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double* shift, double* eps_out,
+// Eigenpairs of nb Hermitian matrices H (n x n each, not modified): W holds H + c I on entry
+// (destroyed), Z is an nb x n x n scratch; eps ascending, U columns = unit eigenvectors.
+ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, double2* Z, double* eps_out,
                       int64_t eps_stride, double2* U, int64_t u_stride, int32_t* status);
 ms_status launch_copy_boundary_overlaps(ms_ctx ctx, int n, const double2* U, double2* O, int conj_transpose);
 ms_status launch_minmax(ms_ctx ctx, int64_t count, const int32_t* v, int32_t* out2);
