@@ -143,6 +143,11 @@ def main():
     no_store = torch.zeros((n_k, n_e), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    log(f"inputs staged: {len(staged)} steps of {args.config}")
+
     def step(st, prec):
         s = ms.ms_slices_prepare(ctx, st["miller"], st["bvec"], st["kpar"], st["q"], st["vq"], st["dz"])
         T, R, no, status = ms.ms_transmission_batch(ctx, s, st["j"].energies, prec)
@@ -158,8 +163,10 @@ def main():
         # warmup (the first form's warmup also picks the dominant kernel)
         ms.ms_debug_profile(ctx, True)
         for i in range(args.warmup):
+            tw = time.perf_counter()
             step(staged[i], prec)
-        ctx.sync()
+            ctx.sync()
+            log(f"{prec} warmup step {i + 1}/{args.warmup}: {time.perf_counter() - tw:.2f} s")
         prof = {c: ms.ms_debug_profile_read(ctx, c) for c in ms.PROFILE_CATEGORIES}
         if prof_pick is None:
             prof_pick = max(prof, key=lambda c: prof[c][0])
@@ -169,8 +176,11 @@ def main():
         t0 = time.perf_counter()
         for i in range(args.warmup, nsteps):
             outs.append(step(staged[i], prec))
+            if i < nsteps - 1:   # progress line without a device sync inside the timed region
+                log(f"{prec} timed step {i - args.warmup + 1}/{args.steps} enqueued")
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        log(f"{prec}: {args.steps} timed steps in {dt:.2f} s")
         ctx.sync()
         timed = {c: ms.ms_debug_profile_read(ctx, c) for c in ms.PROFILE_CATEGORIES}
         ms.ms_debug_profile(ctx, False)
@@ -236,6 +246,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)
     ctx.close()
     print(json.dumps(line), flush=True)

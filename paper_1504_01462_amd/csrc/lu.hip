@@ -1,14 +1,17 @@
 // Batched LU with partial pivoting of an augmented matrix [A | B] and the
 // upper-triangular back substitution, complex128.
 //
-// Right-looking blocked algorithm, one panel of NB columns at a time:
+// Right-looking blocked algorithm (two levels: 64-column outer panels made of
+// NB-column sub-panels), per sub-panel:
 //   1. k_panel:       one workgroup per matrix holds the n x NB panel in
 //                     registers, finds each pivot with a wave-shuffle argmax
 //                     (|re| + |im|), swaps through LDS and eliminates.
 //   2. k_swap_trsm:   one thread per column right of the panel applies the
 //                     panel's row interchanges and solves with the unit lower
 //                     NB x NB block (rows of U12 and of L^-1 P^T B).
-//   3. zgemm:         trailing update A22 -= L21 U12 on the matrix cores.
+//   3. zgemm:         update of the outer panel's own columns and rows; after
+//                     the outer panel, one rank-64 trailing update of the rest
+//                     on the matrix cores.
 // The right-hand-side columns ride along in steps 2-3, so after the last
 // panel they hold L^-1 P^T B and only the back substitution remains:
 //   k_trsm_upper:     each workgroup owns 64 right-hand-side columns and walks
@@ -164,10 +167,12 @@ __global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREA
   }
 }
 
-// Apply the panel's interchanges to columns [c0, ncols) and solve with its unit lower block.
+// Apply the sub-panel's interchanges to columns [c0, cend) and solve with its unit
+// lower block there; columns [s0, s1) (the L columns of the earlier sub-panels of
+// the same outer panel) only receive the interchanges.
 template <int NB>
 __global__ __launch_bounds__(256) void k_swap_trsm(double2* A, int n, int ld, int64_t strideA, int j0, int nbp,
-                                                   int c0, int ncols, const int32_t* piv) {
+                                                   int c0, int cend, int s0, int s1, const int32_t* piv) {
   __shared__ double2 L[NB][NB];
   __shared__ int sp[NB];
   const int64_t b = blockIdx.y;
@@ -179,9 +184,11 @@ __global__ __launch_bounds__(256) void k_swap_trsm(double2* A, int n, int ld, in
   }
   if (t < NB) sp[t] = (t < nbp) ? piv[b * (int64_t)n + j0 + t] : 0;
   __syncthreads();
-  const int col = c0 + blockIdx.x * 256 + t;
-  if (col >= ncols) return;
-  double2 x[NB];
+  const int g = blockIdx.x * 256 + t;
+  const int nright = cend - c0;
+  const bool solve = g < nright;
+  const int col = solve ? c0 + g : s0 + (g - nright);
+  if (!solve && col >= s1) return;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if (i < nbp) {
@@ -195,6 +202,8 @@ __global__ __launch_bounds__(256) void k_swap_trsm(double2* A, int n, int ld, in
       }
     }
   }
+  if (!solve) return;
+  double2 x[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     if (i < nbp) {
@@ -206,6 +215,59 @@ __global__ __launch_bounds__(256) void k_swap_trsm(double2* A, int n, int ld, in
       M[(int64_t)(j0 + i) * ld + col] = v;
     }
   }
+}
+
+// Right of an outer panel [J0, J1): apply its interchanges (in order) to columns
+// [c0, ncols) and copy rows [J0, J1) of those columns to T (ldt = ncols - c0).
+__global__ __launch_bounds__(256) void k_swap_rows_copy(double2* A, int n, int ld, int64_t strideA, int J0, int J1,
+                                                        int c0, int ncols, const int32_t* piv, double2* T,
+                                                        int64_t sT) {
+  __shared__ int sp[64];
+  const int64_t b = blockIdx.y;
+  double2* M = A + b * strideA;
+  const int t = threadIdx.x;
+  if (t < J1 - J0) sp[t] = piv[b * (int64_t)n + J0 + t];
+  __syncthreads();
+  const int col = c0 + blockIdx.x * 256 + t;
+  if (col >= ncols) return;
+  for (int i = 0; i < J1 - J0; ++i) {
+    const int r = J0 + i, p = sp[i];
+    if (p != r) {
+      double2* pr = M + (int64_t)r * ld + col;
+      double2* pp = M + (int64_t)p * ld + col;
+      const double2 tmp = *pp;
+      *pp = *pr;
+      *pr = tmp;
+    }
+  }
+  double2* Tb = T + b * sT;
+  const int ldt = ncols - c0;
+  for (int i = 0; i < J1 - J0; ++i) Tb[(int64_t)i * ldt + (col - c0)] = M[(int64_t)(J0 + i) * ld + col];
+}
+
+// Inverse of the unit lower triangular m x m block at (J0, J0) (m <= 64), into Linv (ld 64).
+__global__ __launch_bounds__(64) void k_unit_lower_inverse(const double2* A, int ld, int64_t strideA, int J0, int m,
+                                                           double2* Linv) {
+  __shared__ double2 L[64][65];
+  __shared__ double2 X[64][65];
+  const int64_t b = blockIdx.x;
+  const double2* M = A + b * strideA;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < m * m; idx += 64) {
+    const int i = idx / m, k = idx % m;
+    L[i][k] = (k < i) ? M[(int64_t)(J0 + i) * ld + J0 + k] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (t < m) {   // column t of L^-1 by forward substitution
+    for (int i = 0; i < m; ++i) {
+      double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+      for (int k = t; k < i; ++k) v = csub(v, cmul(L[i][k], X[k][t]));
+      X[i][t] = (i < t) ? make_double2(0.0, 0.0) : v;
+    }
+  }
+  __syncthreads();
+  double2* Lb = Linv + b * 64 * 64;
+  for (int idx = t; idx < m * m; idx += 64) Lb[(idx / m) * 64 + idx % m] = X[idx / m][idx % m];
 }
 
 // Back substitution U Y = Z, Z = A[:, n:ncols], 64 right-hand sides per workgroup.
@@ -295,6 +357,37 @@ void launch_panel(ms_ctx ctx, double2* A, int n, int ld, int64_t sA, int batch, 
 
 }  // namespace
 
+namespace {
+void trailing(ms_ctx ctx, double2* A, int ncols, int64_t strideA, int batch, int r0, int r1, int c0, int c1, int k0,
+              int k1, ms_status* st) {
+  if (*st != MS_OK || r1 <= r0 || c1 <= c0 || k1 <= k0) return;
+  GemmArgs ga;
+  ga.M = r1 - r0;
+  ga.N = c1 - c0;
+  ga.K = k1 - k0;
+  ga.A = A + (int64_t)r0 * ncols + k0;
+  ga.lda = ncols;
+  ga.sA = strideA;
+  ga.B = A + (int64_t)k0 * ncols + c0;
+  ga.ldb = ncols;
+  ga.sB = strideA;
+  ga.C = A + (int64_t)r0 * ncols + c0;
+  ga.ldc = ncols;
+  ga.sC = strideA;
+  ga.alpha = make_double2(-1.0, 0.0);
+  ga.beta = make_double2(1.0, 0.0);
+  ga.batch = batch;
+  ga.prof = PC_LU_UPDATE;
+  *st = zgemm(ctx, ga);
+}
+}  // namespace
+
+// Two-level right-looking LU.  An outer panel [J0, J1) of up to 64 columns is
+// factored as sub-panels of nb columns touching only its own columns (panel
+// kernel, interchanges + unit-lower solve, update G1 of the outer panel's
+// remaining columns).  Then, right of it: all of its interchanges and a copy of
+// its rows (k_swap_rows_copy), U12 = L11^-1 B (k_unit_lower_inverse + GEMM) and
+// one rank-64 update of the trailing rows (G3).
 ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, int batch, int32_t* piv,
                     int32_t* status, int64_t sst) {
   if (n <= 0 || batch <= 0) return MS_OK;
@@ -302,53 +395,81 @@ ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, i
   if (batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "LU batch %d > 65535", batch);
   const int rpt = (n + PANEL_THREADS - 1) / PANEL_THREADS;
   const int nb = rpt <= 3 ? 16 : (rpt <= 6 ? 8 : 4);
-  for (int j0 = 0; j0 < n; j0 += nb) {
-    const int nbp = std::min(nb, n - j0);
+  constexpr int OUTER = 64;
+  void *tbuf = nullptr, *linv = nullptr;
+  const int64_t sT = (int64_t)OUTER * ncols;
+  MS_TRY(workspace(ctx, 30, (size_t)batch * sT * sizeof(double2), &tbuf));
+  MS_TRY(workspace(ctx, 31, (size_t)batch * OUTER * OUTER * sizeof(double2), &linv));
+  ms_status st = MS_OK;
+  for (int J0 = 0; J0 < n; J0 += OUTER) {
+    const int J1 = std::min(n, J0 + OUTER);
+    for (int j0 = J0; j0 < J1; j0 += nb) {
+      const int nbp = std::min(nb, J1 - j0);
+      {
+        Prof prof(ctx, PC_LU_PANEL, 8.0 * nbp * nbp * (double)(n - j0) * batch, 32.0 * nbp * (double)(n - j0) * batch);
+        switch (rpt) {
+          case 1: launch_panel<1, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 2: launch_panel<2, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 3: launch_panel<3, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 4: launch_panel<4, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 5: launch_panel<5, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 6: launch_panel<6, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          case 7: launch_panel<7, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+          default: launch_panel<8, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+        }
+        MS_TRY(check_launch(ctx, "lu panel"));
+      }
+      const int c0 = j0 + nbp;
+      const int nright = J1 - c0, nleft = j0 - J0;
+      if (nright + nleft > 0) {
+        dim3 g((nright + nleft + 255) / 256, batch);
+        Prof prof(ctx, PC_LU_SWAP, 4.0 * nbp * nbp * (double)nright * batch,
+                  64.0 * nbp * (double)(nright + nleft) * batch);
+        if (nb == 16)
+          hipLaunchKernelGGL((k_swap_trsm<16>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, J1, J0,
+                             j0, piv);
+        else if (nb == 8)
+          hipLaunchKernelGGL((k_swap_trsm<8>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, J1, J0,
+                             j0, piv);
+        else
+          hipLaunchKernelGGL((k_swap_trsm<4>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, J1, J0,
+                             j0, piv);
+        MS_TRY(check_launch(ctx, "lu swap/trsm"));
+      }
+      trailing(ctx, A, ncols, strideA, batch, c0, n, c0, J1, j0, c0, &st);   // G1
+      MS_TRY(st);
+    }
+    if (J1 >= ncols) continue;
+    const int m = J1 - J0;
     {
-    Prof prof(ctx, PC_LU_PANEL, 8.0 * nbp * nbp * (double)(n - j0) * batch, 32.0 * nbp * (double)(n - j0) * batch);
-    switch (rpt) {
-      case 1: launch_panel<1, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 2: launch_panel<2, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 3: launch_panel<3, 16>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 4: launch_panel<4, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 5: launch_panel<5, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 6: launch_panel<6, 8>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      case 7: launch_panel<7, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
-      default: launch_panel<8, 4>(ctx, A, n, ncols, strideA, batch, j0, nbp, piv, status, sst); break;
+      Prof prof(ctx, PC_LU_SWAP, 0.0, 64.0 * m * (double)(ncols - J1) * batch);
+      hipLaunchKernelGGL(k_swap_rows_copy, dim3((ncols - J1 + 255) / 256, batch), dim3(256), 0, ctx->stream, A, n,
+                         ncols, strideA, J0, J1, J1, ncols, piv, static_cast<double2*>(tbuf), sT);
+      MS_TRY(check_launch(ctx, "lu row interchanges"));
+      hipLaunchKernelGGL(k_unit_lower_inverse, dim3(batch), dim3(64), 0, ctx->stream, A, ncols, strideA, J0, m,
+                         static_cast<double2*>(linv));
+      MS_TRY(check_launch(ctx, "lu unit-lower inverse"));
     }
-    }
-    MS_TRY(check_launch(ctx, "lu panel"));
-    const int c0 = j0 + nbp;
-    if (c0 >= ncols) continue;
-    dim3 g((ncols - c0 + 255) / 256, batch);
-    Prof prof(ctx, PC_LU_SWAP, 4.0 * nbp * nbp * (double)(ncols - c0) * batch, 64.0 * nbp * (double)(ncols - c0) * batch);
-    if (nb == 16)
-      hipLaunchKernelGGL((k_swap_trsm<16>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
-    else if (nb == 8)
-      hipLaunchKernelGGL((k_swap_trsm<8>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
-    else
-      hipLaunchKernelGGL((k_swap_trsm<4>), g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, j0, nbp, c0, ncols, piv);
-    MS_TRY(check_launch(ctx, "lu swap/trsm"));
-    if (c0 < n) {
+    {  // U12 = L11^-1 B
       GemmArgs ga;
-      ga.M = n - c0;
-      ga.N = ncols - c0;
-      ga.K = nbp;
-      ga.A = A + (int64_t)c0 * ncols + j0;
-      ga.lda = ncols;
-      ga.sA = strideA;
-      ga.B = A + (int64_t)j0 * ncols + c0;
-      ga.ldb = ncols;
-      ga.sB = strideA;
-      ga.C = A + (int64_t)c0 * ncols + c0;
+      ga.M = m;
+      ga.N = ncols - J1;
+      ga.K = m;
+      ga.A = linv;
+      ga.lda = OUTER;
+      ga.sA = OUTER * OUTER;
+      ga.B = tbuf;
+      ga.ldb = ncols - J1;
+      ga.sB = sT;
+      ga.C = A + (int64_t)J0 * ncols + J1;
       ga.ldc = ncols;
       ga.sC = strideA;
-      ga.alpha = make_double2(-1.0, 0.0);
-      ga.beta = make_double2(1.0, 0.0);
       ga.batch = batch;
       ga.prof = PC_LU_UPDATE;
       MS_TRY(zgemm(ctx, ga));
     }
+    trailing(ctx, A, ncols, strideA, batch, J1, n, J1, ncols, J0, J1, &st);   // G3: rank-64 update
+    MS_TRY(st);
   }
   return MS_OK;
 }
