@@ -22,6 +22,14 @@ ms_status ms_debug_gemm(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, in
                         int64_t lda, const void* b, int64_t ldb, void* c, int64_t ldc, const double* alpha,
                         const double* beta, ms_prec prec);
 
+/* Batched form of ms_debug_gemm: C[i] = alpha op(A[i]) op(B[i]) + beta C[i] for
+ * i < batch, with element strides s_a, s_b, s_c between consecutive matrices
+ * (0 = the same matrix for every i). */
+ms_status ms_debug_gemm_batched(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, int64_t k, const void* a,
+                                int64_t lda, int64_t s_a, const void* b, int64_t ldb, int64_t s_b, void* c,
+                                int64_t ldc, int64_t s_c, int64_t batch, const double* alpha, const double* beta,
+                                ms_prec prec);
+
 /* For each of `batch` row-major n x (n + nrhs) complex128 matrices [A | B]
  * (batch stride n*(n+nrhs)), factor A with partial pivoting (in place) and
  * write X = A^-1 B to x (n x nrhs per matrix, batch stride n*nrhs).

@@ -63,6 +63,8 @@ _sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 _sig("ms_debug_profile", [_vp, ctypes.c_uint32])
 _sig("ms_debug_profile_read", [_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp])
 _sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32])
+_sig("ms_debug_gemm_batched", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
+                                _i64, _i64, _vp, _vp, _i32])
 _sig("ms_debug_lu_solve", [_vp, _i64, _i64, _i64, _vp, _vp, _vp])
 _sig("ms_debug_eigh", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 
@@ -266,6 +268,25 @@ def ms_debug_gemm(ctx: Context, a: torch.Tensor, b: torch.Tensor, c: torch.Tenso
     return c
 
 
+def ms_debug_gemm_batched(ctx: Context, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor, op_a=0, op_b=0,
+                          alpha=1.0, beta=0.0, prec="fp64"):
+    """a: [batch or 1][..], b: [batch or 1][..], c: [batch][m][n]; a batch of 1 is shared (stride 0)."""
+    batch = c.shape[0]
+    m, n = c.shape[1], c.shape[2]
+    k = a.shape[1] if op_a else a.shape[2]
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    dt = torch.complex128 if _PREC[prec] == MS_PREC_FP64 else torch.complex64
+    s_a = 0 if a.shape[0] == 1 else a.shape[1] * a.shape[2]
+    s_b = 0 if b.shape[0] == 1 else b.shape[1] * b.shape[2]
+    _check(ctx.handle, lib.ms_debug_gemm_batched(ctx.handle, op_a, op_b, m, n, k, _ptr(a, dt, "a"), a.shape[2], s_a,
+                                                 _ptr(b, dt, "b"), b.shape[2], s_b,
+                                                 _ptr(c, torch.complex128, "c"), n, m * n, batch,
+                                                 al.ctypes.data_as(ctypes.c_void_p),
+                                                 be.ctypes.data_as(ctypes.c_void_p), _PREC[prec]))
+    return c
+
+
 def ms_debug_lu_solve(ctx: Context, aug: torch.Tensor, n: int):
     batch, rows, cols = aug.shape
     nrhs = cols - n
@@ -299,5 +320,5 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_transmission",
            "ms_transmission_batch", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
-           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_lu_solve", "ms_debug_eigh",
+           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

@@ -86,6 +86,24 @@ Prof::~Prof() {
   ctx->prof[cat].push_back(ProfRec{a, b, flops, bytes});
 }
 
+ms_status child(ms_ctx ctx, int i, ms_ctx* out) {
+  while ((int)ctx->kids.size() <= i) {
+    ms_ctx k = new ms_ctx_s;
+    k->device = ctx->device;
+    k->d_status = ctx->d_status;
+    k->owns_status = false;
+    const hipError_t e = hipStreamCreate(&k->stream);
+    if (e != hipSuccess) {
+      delete k;
+      return hip_fail(ctx, e, "hipStreamCreate");
+    }
+    ctx->kids.push_back(k);
+  }
+  ctx->kids[i]->prof_mask = ctx->prof_mask;
+  *out = ctx->kids[i];
+  return MS_OK;
+}
+
 ms_status upload(ms_ctx ctx, void* dst, const void* src, size_t bytes) {
   if (bytes == 0) return MS_OK;
   MS_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
@@ -201,15 +219,22 @@ ms_status ms_ctx_destroy(ms_ctx ctx) {
   if (!ctx) return MS_ERR_ARG;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (ms_ctx k : ctx->kids) {
+    (void)hipStreamSynchronize(k->stream);
+    ms_ctx_destroy(k);
+  }
+  ctx->kids.clear();
   for (auto& v : ctx->prof)
     for (auto& r : v) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->sync_ev) (void)hipEventDestroy(e);
+  if (!ctx->owns_status && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   for (void* p : ctx->ws)
     if (p) (void)hipFree(p);
-  if (ctx->d_status) (void)hipFree(ctx->d_status);
+  if (ctx->owns_status && ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
   return MS_OK;
 }
@@ -231,6 +256,7 @@ static const char* const kProfNames[PC_COUNT] = {"iface_gemm", "lu_panel", "lu_s
 ms_status ms_debug_profile(ms_ctx ctx, uint32_t mask) {
   if (!ctx) return MS_ERR_ARG;
   ctx->prof_mask = mask;
+  for (ms_ctx k : ctx->kids) k->prof_mask = mask;
   return MS_OK;
 }
 
@@ -244,17 +270,24 @@ ms_status ms_debug_profile_read(ms_ctx ctx, const char* category, double* total_
   MS_HIP(ctx, hipSetDevice(ctx->device));
   MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   double tot = 0.0, fl = 0.0, by = 0.0;
-  for (auto& r : ctx->prof[cat]) {
-    float ms = 0.f;
-    MS_HIP(ctx, hipEventElapsedTime(&ms, r.a, r.b));
-    tot += ms;
-    fl += r.flops;
-    by += r.bytes;
-    ctx->ev_pool.push_back(r.a);
-    ctx->ev_pool.push_back(r.b);
+  int64_t cnt = 0;
+  std::vector<ms_ctx> all{ctx};
+  for (ms_ctx k : ctx->kids) all.push_back(k);
+  for (ms_ctx c : all) {
+    MS_HIP(ctx, hipStreamSynchronize(c->stream));
+    for (auto& r : c->prof[cat]) {
+      float ms = 0.f;
+      MS_HIP(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+      tot += ms;
+      fl += r.flops;
+      by += r.bytes;
+      c->ev_pool.push_back(r.a);
+      c->ev_pool.push_back(r.b);
+    }
+    cnt += (int64_t)c->prof[cat].size();
+    c->prof[cat].clear();
   }
-  *launches = (int64_t)ctx->prof[cat].size();
-  ctx->prof[cat].clear();
+  *launches = cnt;
   *total_ms = tot;
   *flops = fl;
   *bytes = by;
@@ -555,54 +588,111 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
   const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
   const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
                        2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
-  int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(n_e, (int64_t)(BATCH_BUDGET / per_e)));
-  nbe = std::min(nbe, 65535);
-  void *kb, *pb, *aop, *wg, *mm, *yb, *piv, *oc = nullptr;
-  MS_TRY(workspace(ctx, WS_K, (size_t)nbe * sk * sizeof(double2), &kb));
-  MS_TRY(workspace(ctx, WS_P, (size_t)nbe * sk * sizeof(double2), &pb));
-  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
-  MS_TRY(workspace(ctx, WS_WG, (size_t)nbe * 2 * nn * sizeof(double2), &wg));
-  MS_TRY(workspace(ctx, WS_M, (size_t)nbe * sM * sizeof(double2), &mm));
-  MS_TRY(workspace(ctx, WS_Y, (size_t)nbe * sY * sizeof(double2), &yb));
-  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbe * n * sizeof(int32_t), &piv));
-  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
+  // energies are folded in G groups on G internal streams, so that the latency-bound LU
+  // panels of one group overlap the GEMMs of the other
+  const int G = (n_e >= 8) ? 2 : 1;
+  struct Group {
+    ms_ctx c;
+    int64_t e0, ne;
+    int nbe;
+    double2 *kb, *pb, *wg, *mm, *yb;
+    void *aop, *oc;
+    int32_t* piv;
+  };
+  std::vector<Group> grp(G);
+  while ((int)ctx->sync_ev.size() < G + 1) {
+    hipEvent_t e = nullptr;
+    MS_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->sync_ev.push_back(e);
+  }
+  hipEvent_t fork = ctx->sync_ev[0];
+  if (G > 1) MS_HIP(ctx, hipEventRecord(fork, ctx->stream));
+  for (int g = 0; g < G; ++g) {
+    Group& q = grp[g];
+    q.e0 = n_e * g / G;
+    q.ne = n_e * (g + 1) / G - q.e0;
+    if (G > 1) {
+      MS_TRY(child(ctx, g, &q.c));
+      MS_HIP(ctx, hipStreamWaitEvent(q.c->stream, fork, 0));
+    } else {
+      q.c = ctx;
+    }
+    q.nbe = (int)std::max<int64_t>(1, std::min<int64_t>(q.ne, (int64_t)(BATCH_BUDGET / G / per_e)));
+    q.nbe = std::min(q.nbe, 65535);
+    void *kb, *pb, *wg, *mm, *yb, *piv;
+    MS_TRY(workspace(q.c, WS_K, (size_t)q.nbe * sk * sizeof(double2), &kb));
+    MS_TRY(workspace(q.c, WS_P, (size_t)q.nbe * sk * sizeof(double2), &pb));
+    MS_TRY(workspace(q.c, WS_AOP, (size_t)q.nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &q.aop));
+    MS_TRY(workspace(q.c, WS_WG, (size_t)q.nbe * 2 * nn * sizeof(double2), &wg));
+    MS_TRY(workspace(q.c, WS_M, (size_t)q.nbe * sM * sizeof(double2), &mm));
+    MS_TRY(workspace(q.c, WS_Y, (size_t)q.nbe * sY * sizeof(double2), &yb));
+    MS_TRY(workspace(q.c, WS_PIV, (size_t)q.nbe * n * sizeof(int32_t), &piv));
+    q.oc = nullptr;
+    if (fp32) MS_TRY(workspace(q.c, WS_OC, nn * sizeof(float2), &q.oc));
+    q.kb = c2(kb); q.pb = c2(pb); q.wg = c2(wg); q.mm = c2(mm); q.yb = c2(yb); q.piv = (int32_t*)piv;
+  }
 
-  for (int64_t e0 = 0; e0 < n_e; e0 += nbe) {
-    const int be = (int)std::min<int64_t>(nbe, n_e - e0);
-    const double* en_d = (const double*)end + e0;
-    int32_t* pst = point_status + e0;
-    MS_TRY(launch_wavevectors(ctx, n, nrows, be, slices->eps, en_d, slices->dz, c2(kb), c2(pb)));
+  // all groups advance in lock step over sub-batches and interfaces (launches interleaved)
+  int64_t max_sub = 0;
+  for (const Group& q : grp) max_sub = std::max<int64_t>(max_sub, (q.ne + q.nbe - 1) / q.nbe);
+  for (int64_t sb = 0; sb < max_sub; ++sb) {
+    for (Group& q : grp) {
+      const int64_t e0 = q.e0 + sb * q.nbe;
+      const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
+      if (be <= 0) continue;
+      MS_TRY(launch_wavevectors(q.c, n, nrows, be, slices->eps, (const double*)end + e0, slices->dz, q.kb, q.pb));
+    }
     for (int p = ns; p >= 0; --p) {
-      const double2* kp = c2(kb) + (int64_t)p * n;
-      const double2* kq = c2(kb) + (int64_t)(p + 1) * n;
-      const double2* pq = c2(pb) + (int64_t)(p + 1) * n;
       const double2* O = c2(slices->ovl) + (int64_t)p * nn;
       const bool first = (p == ns);
-      if (!first) {
-        MS_TRY(launch_prologue(ctx, n, be, c2(yb), ldy, sY, kq, pq, sk, aop, fp32));
-        GemmArgs g;
-        g.M = 2 * n; g.N = n; g.K = n;
-        g.A = aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
-        g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
-        g.C = c2(wg); g.ldc = n; g.sC = 2 * nn;
-        g.batch = be;
-        g.prof = PC_IFACE_GEMM;
-        if (fp32) {
-          MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
-          g.B = oc;
-          MS_TRY(cgemm32(ctx, g));
-        } else {
-          MS_TRY(zgemm(ctx, g));
+      for (Group& q : grp) {
+        const int64_t e0 = q.e0 + sb * q.nbe;
+        const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
+        if (be <= 0) continue;
+        ms_ctx c = q.c;
+        int32_t* pst = point_status + e0;
+        const double2* kp = q.kb + (int64_t)p * n;
+        const double2* kq = q.kb + (int64_t)(p + 1) * n;
+        const double2* pq = q.pb + (int64_t)(p + 1) * n;
+        if (!first) {
+          MS_TRY(launch_prologue(c, n, be, q.yb, ldy, sY, kq, pq, sk, q.aop, fp32));
+          GemmArgs g;
+          g.M = 2 * n; g.N = n; g.K = n;
+          g.A = q.aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
+          g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
+          g.C = q.wg; g.ldc = n; g.sC = 2 * nn;
+          g.batch = be;
+          g.prof = PC_IFACE_GEMM;
+          if (fp32) {
+            MS_TRY(launch_to_c64(c, nn, O, static_cast<float2*>(q.oc)));
+            g.B = q.oc;
+            MS_TRY(cgemm32(c, g));
+          } else {
+            MS_TRY(zgemm(c, g));
+          }
         }
+        MS_TRY(launch_epilogue(c, n, be, O, first ? nullptr : q.wg, kp, kq, sk, q.mm, ldm, sM));
+        MS_TRY(launch_tcols(c, n, n_o, be, (const int32_t*)chd, q.yb, ldy, sY, n, kq, pq, sk, first ? 1 : 0, q.mm,
+                            ldm, sM));
+        MS_TRY(getrf_aug(c, q.mm, n, ldm, sM, be, q.piv, pst, 1));
+        MS_TRY(trsm_upper_aug(c, q.mm, n, ldm, sM, be, q.yb, ldy, sY, pst, 1));
       }
-      MS_TRY(launch_epilogue(ctx, n, be, O, first ? nullptr : c2(wg), kp, kq, sk, c2(mm), ldm, sM));
-      MS_TRY(launch_tcols(ctx, n, n_o, be, (const int32_t*)chd, c2(yb), ldy, sY, n, kq, pq, sk, first ? 1 : 0,
-                          c2(mm), ldm, sM));
-      MS_TRY(getrf_aug(ctx, c2(mm), n, ldm, sM, be, (int32_t*)piv, pst, 1));
-      MS_TRY(trsm_upper_aug(ctx, c2(mm), n, ldm, sM, be, c2(yb), ldy, sY, pst, 1));
     }
-    MS_TRY(launch_batch_T(ctx, n, n_o, be, (const int32_t*)chd, en_d, eps_l, eps_r, c2(yb), ldy, sY, T + e0, R + e0,
-                          n_open + e0, pst));
+    for (Group& q : grp) {
+      const int64_t e0 = q.e0 + sb * q.nbe;
+      const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
+      if (be <= 0) continue;
+      MS_TRY(launch_batch_T(q.c, n, n_o, be, (const int32_t*)chd, (const double*)end + e0, eps_l, eps_r, q.yb, ldy, sY,
+                            T + e0, R + e0, n_open + e0, point_status + e0));
+    }
+  }
+  // join: the caller's stream waits for every group
+  if (G > 1) {
+    for (int g = 0; g < G; ++g) {
+      hipEvent_t done = ctx->sync_ev[1 + g];
+      MS_HIP(ctx, hipEventRecord(done, grp[g].c->stream));
+      MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, done, 0));
+    }
   }
   return MS_OK;
 }

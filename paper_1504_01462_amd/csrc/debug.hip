@@ -38,6 +38,31 @@ ms_status ms_debug_gemm(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, in
   return fail(ctx, MS_ERR_ARG, "unknown precision");
 }
 
+ms_status ms_debug_gemm_batched(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, int64_t k, const void* a,
+                                int64_t lda, int64_t s_a, const void* b, int64_t ldb, int64_t s_b, void* c,
+                                int64_t ldc, int64_t s_c, int64_t batch, const double* alpha, const double* beta,
+                                ms_prec prec) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!a || !b || !c || !alpha || !beta) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (op_a < 0 || op_a > 2 || op_b < 0 || op_b > 2) return fail(ctx, MS_ERR_ARG, "op codes are 0, 1, 2");
+  if (m <= 0 || n <= 0 || k < 0 || batch <= 0 || m > (1 << 30) || n > (1 << 30) || k > (1 << 30) ||
+      batch > (1 << 20))
+    return fail(ctx, MS_ERR_ARG, "bad sizes");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  GemmArgs g;
+  g.M = (int)m; g.N = (int)n; g.K = (int)k;
+  g.opA = op_a; g.opB = op_b;
+  g.A = a; g.lda = lda; g.sA = s_a;
+  g.B = b; g.ldb = ldb; g.sB = s_b;
+  g.C = static_cast<double2*>(c); g.ldc = ldc; g.sC = s_c;
+  g.batch = (int)batch;
+  g.alpha = make_double2(alpha[0], alpha[1]);
+  g.beta = make_double2(beta[0], beta[1]);
+  if (prec == MS_PREC_FP64) return zgemm(ctx, g);
+  if (prec == MS_PREC_FP32_MFMA) return cgemm32(ctx, g);
+  return fail(ctx, MS_ERR_ARG, "unknown precision");
+}
+
 ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, void* aug, void* x, int32_t* status) {
   if (!ctx) return MS_ERR_ARG;
   if (!aug || !x || !status) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");

@@ -8,8 +8,11 @@
 // accumulation for complex64).  Operand layouts of both: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator layouts differ
 // (see Mfma<T>::crow).  Workgroup = 4 wave64s in a 2x2 grid; each wave
-// owns a (BM/2) x (BN/2) sub-tile.  Global->LDS staging is register
-// double-buffered (the next K-slab is fetched while the current one is used).
+// owns a sub-tile (64x64 tiles with 4 waves for small problems, 128x128 tiles
+// with 8 waves otherwise).  Global->LDS staging is register double-buffered
+// (the next K-slab is fetched while the current one is used).
+#include <algorithm>
+
 #include "ms_internal.h"
 
 namespace ms {
@@ -53,24 +56,37 @@ struct KParams {
 };
 
 constexpr int BK = 16;
-constexpr int NT = 256;
 
-template <typename T, int BM, int BN>
-__global__ __launch_bounds__(NT) void k_gemm(KParams p) {
+// Tile BM x BN, WM x WN waves (each owning a (BM/WM) x (BN/WN) sub-tile).
+// LDS rows are padded by one element so the transposing stores of the
+// staging pass spread over the banks.  Blocks are launched as a 1D grid whose
+// index is remapped so that consecutive logical tiles (same A row-panel, all
+// column tiles) land on the same XCD and share its L2.
+template <typename T, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int ntm, int total) {
   typedef typename Mfma<T>::c_t CT;
   typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int TM = BM / 2, TN = BN / 2;
+  constexpr int NT = 64 * WM * WN;
+  constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 16, FN = TN / 16;
   constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
-  __shared__ T As[2][BK][BM];
-  __shared__ T Bs[2][BK][BN];
+  constexpr int PA = BM + 1, PB = BN + 1;
+  __shared__ T As[2][2][BK][PA];   // [stage][re/im][k][m]
+  __shared__ T Bs[2][2][BK][PB];
+
+  // XCD-aware remap of the linear block index
+  const int hw = blockIdx.x;
+  int lid = hw;
+  if ((total & 7) == 0) lid = (hw & 7) * (total >> 3) + (hw >> 3);
+  const int tn = lid % ntn;
+  const int tm = (lid / ntn) % ntm;
+  const int64_t b = lid / (ntn * ntm);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm0 = (wave >> 1) * TM, wn0 = (wave & 1) * TN;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int64_t b = blockIdx.z;
+  const int wm0 = (wave / WN) * TM, wn0 = (wave % WN) * TN;
+  const int m0 = tm * BM, n0 = tn * BN;
   const CT* A = static_cast<const CT*>(p.A) + b * p.sA;
   const CT* B = static_cast<const CT*>(p.B) + b * p.sB;
 
@@ -105,22 +121,22 @@ __global__ __launch_bounds__(NT) void k_gemm(KParams p) {
       rb[e] = v;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int st) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
       int i, k;
       if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
-      As[0][k][i] = ra[e].x;
-      As[1][k][i] = ra[e].y;
+      As[st][0][k][i] = ra[e].x;
+      As[st][1][k][i] = ra[e].y;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = tid + NT * e;
       int j, k;
       if (p.opB == OP_N) { k = idx / BN; j = idx % BN; } else { j = idx / BK; k = idx % BK; }
-      Bs[0][k][j] = rb[e].x;
-      Bs[1][k][j] = rb[e].y;
+      Bs[st][0][k][j] = rb[e].x;
+      Bs[st][1][k][j] = rb[e].y;
     }
   };
 
@@ -133,26 +149,28 @@ __global__ __launch_bounds__(NT) void k_gemm(KParams p) {
       ci[a][c] = acc_t{0, 0, 0, 0};
     }
 
+  // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
+  // other one; one barrier per slab
   load(0);
-  stash();
+  stash(0);
+  if (BK < p.K) load(BK);
   __syncthreads();
+  int cur = 0;
   for (int k0 = 0; k0 < p.K; k0 += BK) {
-    const bool more = k0 + BK < p.K;
-    if (more) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
       T ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
-        ar[a] = As[0][kr][wm0 + a * 16 + (lane & 15)];
-        ai[a] = As[1][kr][wm0 + a * 16 + (lane & 15)];
+        ar[a] = As[cur][0][kr][wm0 + a * 16 + (lane & 15)];
+        ai[a] = As[cur][1][kr][wm0 + a * 16 + (lane & 15)];
         nai[a] = -ai[a];
       }
 #pragma unroll
       for (int c = 0; c < FN; ++c) {
-        br[c] = Bs[0][kr][wn0 + c * 16 + (lane & 15)];
-        bi[c] = Bs[1][kr][wn0 + c * 16 + (lane & 15)];
+        br[c] = Bs[cur][0][kr][wn0 + c * 16 + (lane & 15)];
+        bi[c] = Bs[cur][1][kr][wn0 + c * 16 + (lane & 15)];
       }
 #pragma unroll
       for (int a = 0; a < FM; ++a)
@@ -169,11 +187,12 @@ __global__ __launch_bounds__(NT) void k_gemm(KParams p) {
           ci[a][c] = Mfma<T>::mac(ai[a], br[c], ci[a][c]);
         }
     }
-    __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
+    if (k0 + BK < p.K) {
+      stash(cur ^ 1);                       // slab k0+BK (already in registers)
+      if (k0 + 2 * BK < p.K) load(k0 + 2 * BK);
     }
+    __syncthreads();
+    cur ^= 1;
   }
 
   double2* C = p.C + b * p.sC;
@@ -202,21 +221,26 @@ __global__ __launch_bounds__(NT) void k_gemm(KParams p) {
       }
 }
 
+template <typename T, int BM, int BN, int WM, int WN>
+ms_status launch(ms_ctx ctx, const KParams& p, int batch) {
+  const int ntn = (p.N + BN - 1) / BN, ntm = (p.M + BM - 1) / BM;
+  const int64_t total = (int64_t)ntn * ntm * batch;
+  if (total > 0x7fffffff) return fail(ctx, MS_ERR_UNSUPPORTED, "gemm grid too large");
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN>), dim3((unsigned)total), dim3(64 * WM * WN), 0, ctx->stream, p, ntn,
+                     ntm, (int)total);
+  return check_launch(ctx, "gemm");
+}
+
 template <typename T>
 ms_status run(ms_ctx ctx, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return MS_OK;
-  if (g.batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "gemm batch %d > 65535", g.batch);
-  KParams p{g.M, g.N, g.K, g.opA, g.opB, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha, g.beta};
-  if (g.K <= 0) {  // C = beta C
-    p.K = 0;
-  }
-  constexpr int BM = 64, BN = 64;
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch);
-  Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * g.K * g.batch,
-            (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * g.K + (double)g.K * g.N) +
+  KParams p{g.M, g.N, std::max(g.K, 0), g.opA, g.opB, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha,
+            g.beta};
+  Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * p.K * g.batch,
+            (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K + (double)p.K * g.N) +
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1));
-  hipLaunchKernelGGL((k_gemm<T, BM, BN>), grid, dim3(NT), 0, ctx->stream, p);
-  return check_launch(ctx, "gemm");
+  if (g.M >= 128 && g.N >= 128) return launch<T, 128, 128, 2, 4>(ctx, p, g.batch);
+  return launch<T, 64, 64, 2, 2>(ctx, p, g.batch);
 }
 
 }  // namespace

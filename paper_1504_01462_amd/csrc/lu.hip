@@ -15,9 +15,10 @@
 // The right-hand-side columns ride along in steps 2-3, so after the last
 // panel they hold L^-1 P^T B and only the back substitution remains:
 //   k_trsm_upper:     each workgroup owns 64 right-hand-side columns and walks
-//                     the 16-row block rows bottom-up; the off-diagonal part is
-//                     an MFMA product over the rows already solved, the 16x16
-//                     diagonal block is solved in LDS.
+//                     the 64-row block rows bottom-up; the off-diagonal part is
+//                     an MFMA product over the rows already solved, and the
+//                     diagonal block is applied as a product with its inverse
+//                     (k_upper_block_inverse, once per matrix and block).
 #include <type_traits>
 
 #include "ms_internal.h"
@@ -153,7 +154,8 @@ __global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREA
         }
       }
     }
-    __syncthreads();
+    // no barrier here: the next column writes red_v/red_i only after every thread has
+    // passed this column's second barrier, and prow/jrow only after its own first one
   });
 
 #pragma unroll
@@ -270,32 +272,74 @@ __global__ __launch_bounds__(64) void k_unit_lower_inverse(const double2* A, int
   for (int idx = t; idx < m * m; idx += 64) Lb[(idx / m) * 64 + idx % m] = X[idx / m][idx % m];
 }
 
-// Back substitution U Y = Z, Z = A[:, n:ncols], 64 right-hand sides per workgroup.
-constexpr int TR_KC = 64;
+// Inverses of the 64 x 64 upper triangular diagonal blocks of U (leading n x n of A):
+// Dinv[b][ib] (ld 64), one workgroup of 64 threads per block, thread c solves column c.
+__global__ __launch_bounds__(64) void k_upper_block_inverse(const double2* A, int n, int ld, int64_t strideA,
+                                                           int nblk, double2* Dinv, int32_t* status, int64_t sst) {
+  __shared__ double2 D[64][65];
+  __shared__ double2 X[64][65];
+  const int ib = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  const double2* M = A + b * strideA;
+  const int t = threadIdx.x;
+  const int r0 = ib * 64, m = min(64, n - r0);
+  for (int idx = t; idx < 64 * 64; idx += 64) {
+    const int i = idx / 64, k = idx % 64;
+    D[i][k] = (i < m && k < m && k >= i) ? M[(int64_t)(r0 + i) * ld + r0 + k] : make_double2(i == k ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int i = 63; i >= 0; --i) {   // column t of D^-1: D x = e_t, x_i = 0 for i > t
+    double2 v = make_double2(i == t ? 1.0 : 0.0, 0.0);
+    if (i <= t) {
+      for (int k = i + 1; k <= t; ++k) v = csub(v, cmul(D[i][k], X[k][t]));
+      const double2 d = D[i][i];
+      if (d.x == 0.0 && d.y == 0.0) {
+        singular = true;
+        v = make_double2(0.0, 0.0);
+      } else {
+        v = cmul(v, cinv(d));
+      }
+    } else {
+      v = make_double2(0.0, 0.0);
+    }
+    X[i][t] = v;
+  }
+  if (singular) set_status(status, b * sst, (int32_t)MS_ERR_SINGULAR);
+  __syncthreads();
+  double2* Db = Dinv + (b * nblk + ib) * 64 * 64;
+  for (int idx = t; idx < 64 * 64; idx += 64) Db[idx] = X[idx / 64][idx % 64];
+}
+
+// Back substitution U Y = Z, Z = A[:, n:ncols]: each workgroup owns 64 right-hand-side
+// columns (16 per wave) and walks the 64-row block rows bottom-up.  Per block row,
+// R = Z_rows - U_rows,below Y_below (MFMA, U staged through LDS in 64 x TR_KC
+// chunks, Y read from global), then Y_rows = Dinv R (MFMA, Dinv staged the same way).
+constexpr int TR_KC = 32;
 __global__ __launch_bounds__(256) void k_trsm_upper(const double2* A, int n, int ld, int64_t strideA, int nrhs,
-                                                    double2* Y, int64_t ldy, int64_t sY, int32_t* status,
-                                                    int64_t sst) {
-  __shared__ double Us[2][16][TR_KC];      // U row block, re/im
-  __shared__ double2 D[16][16];            // diagonal block
-  __shared__ double2 R[16][64];            // right-hand sides of the block row
+                                                    const double2* Dinv, int nblk, double2* Y, int64_t ldy,
+                                                    int64_t sY) {
+  __shared__ double Us[2][64][TR_KC + 1];    // staged U (or Dinv) chunk, re/im
+  __shared__ double2 Rs[64][65];             // right-hand sides of the block row
   const int64_t b = blockIdx.y;
   const double2* M = A + b * strideA;
   double2* Yb = Y + b * sY;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int cbase = blockIdx.x * 64;
-  const int c0 = cbase + wave * 16;          // this wave's 16 columns
-  const int myc = c0 + (lane & 15);
-  const int nblk = (n + 15) / 16;
+  const int myc = cbase + wave * 16 + (lane & 15);
+  typedef double d4v __attribute__((ext_vector_type(4)));
 
   for (int ib = nblk - 1; ib >= 0; --ib) {
-    const int r0 = ib * 16, r1 = min(n, r0 + 16);
-    d4_t cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const int r0 = ib * 64, r1 = min(n, r0 + 64);
+    d4v cr[4], ci[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; }
+    // acc = U[r0:r1, r1:n] Y[r1:n, cols]
     for (int k0 = r1; k0 < n; k0 += TR_KC) {
-      // stage U[r0:r0+16][k0:k0+KC]
-      for (int idx = t; idx < 16 * TR_KC; idx += 256) {
+      for (int idx = t; idx < 64 * TR_KC; idx += 256) {
         const int i = idx / TR_KC, k = idx % TR_KC;
         double2 v = make_double2(0.0, 0.0);
-        if (r0 + i < n && k0 + k < n) v = M[(int64_t)(r0 + i) * ld + k0 + k];
+        if (r0 + i < r1 && k0 + k < n) v = M[(int64_t)(r0 + i) * ld + k0 + k];
         Us[0][i][k] = v.x;
         Us[1][i][k] = v.y;
       }
@@ -303,48 +347,64 @@ __global__ __launch_bounds__(256) void k_trsm_upper(const double2* A, int n, int
       const int kend = min(TR_KC, n - k0);
       for (int kk = 0; kk < kend; kk += 4) {
         const int kl = kk + (lane >> 4);
-        const double ar = Us[0][lane & 15][kl], ai = Us[1][lane & 15][kl];
         double2 y = make_double2(0.0, 0.0);
         if (k0 + kl < n && myc < nrhs) y = Yb[(int64_t)(k0 + kl) * ldy + myc];
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, ci, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, ci, 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double ar = Us[0][a * 16 + (lane & 15)][kl], ai = Us[1][a * 16 + (lane & 15)][kl];
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, cr[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, ci[a], 0, 0, 0);
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, cr[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, ci[a], 0, 0, 0);
+        }
       }
       __syncthreads();
     }
-    // right-hand sides minus the product, into LDS
+    // R = Z - acc
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = (lane >> 4) + 4 * v;   // f64 MFMA accumulator row
-      const int r = r0 + i;
-      double2 z = make_double2(0.0, 0.0);
-      if (r < n && myc < nrhs) z = M[(int64_t)r * ld + n + myc];
-      R[i][wave * 16 + (lane & 15)] = make_double2(z.x - cr[v], z.y - ci[v]);
-    }
-    for (int idx = t; idx < 256; idx += 256) {
-      const int i = idx / 16, k = idx % 16;
-      D[i][k] = (r0 + i < n && r0 + k < n) ? M[(int64_t)(r0 + i) * ld + r0 + k] : make_double2(1.0, 0.0);
-    }
-    __syncthreads();
-    if (t < 64) {
-      const int col = cbase + t;
-      for (int i = r1 - r0 - 1; i >= 0; --i) {
-        double2 v = R[i][t];
-        for (int k = i + 1; k < r1 - r0; ++k) v = csub(v, cmul(D[i][k], R[k][t]));
-        const double2 d = D[i][i];
-        double2 y;
-        if (d.x == 0.0 && d.y == 0.0) {
-          set_status(status, b * sst, (int32_t)MS_ERR_SINGULAR);
-          y = make_double2(0.0, 0.0);
-        } else {
-          y = cmul(v, cinv(d));
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = a * 16 + (lane >> 4) + 4 * v;   // f64 MFMA accumulator row
+        const int r = r0 + i;
+        double2 z = make_double2(0.0, 0.0);
+        if (r < r1 && myc < nrhs) z = M[(int64_t)r * ld + n + myc];
+        Rs[i][wave * 16 + (lane & 15)] = make_double2(z.x - cr[a][v], z.y - ci[a][v]);
+      }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; }
+    // Y_rows = Dinv R
+    const double2* Di = Dinv + (b * nblk + ib) * 64 * 64;
+    for (int k0 = 0; k0 < 64; k0 += TR_KC) {
+      __syncthreads();   // Rs complete / previous chunk consumed
+      for (int idx = t; idx < 64 * TR_KC; idx += 256) {
+        const int i = idx / TR_KC, k = idx % TR_KC;
+        const double2 v = Di[i * 64 + k0 + k];
+        Us[0][i][k] = v.x;
+        Us[1][i][k] = v.y;
+      }
+      __syncthreads();
+      for (int kk = 0; kk < TR_KC; kk += 4) {
+        const int kl = kk + (lane >> 4);
+        const double2 rr = Rs[k0 + kl][wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double ar = Us[0][a * 16 + (lane & 15)][kl], ai = Us[1][a * 16 + (lane & 15)][kl];
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, rr.x, cr[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, rr.y, ci[a], 0, 0, 0);
+          cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, rr.y, cr[a], 0, 0, 0);
+          ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, rr.x, ci[a], 0, 0, 0);
         }
-        R[i][t] = y;
-        if (col < nrhs) Yb[(int64_t)(r0 + i) * ldy + col] = y;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + a * 16 + (lane >> 4) + 4 * v;
+        if (r < r1 && myc < nrhs) Yb[(int64_t)r * ldy + myc] = make_double2(cr[a][v], ci[a][v]);
+      }
+    __syncthreads();   // Y rows visible to the whole workgroup; Us/Rs free
   }
 }
 
@@ -479,9 +539,16 @@ ms_status trsm_upper_aug(ms_ctx ctx, const double2* A, int n, int ncols, int64_t
   const int nrhs = ncols - n;
   if (n <= 0 || nrhs <= 0 || batch <= 0) return MS_OK;
   if (batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "trsm batch %d > 65535", batch);
-  dim3 g((nrhs + 63) / 64, batch);
+  const int nblk = (n + 63) / 64;
+  void* dinv = nullptr;
+  MS_TRY(workspace(ctx, 32, (size_t)batch * nblk * 64 * 64 * sizeof(double2), &dinv));
   Prof prof(ctx, PC_TRSM, 4.0 * (double)n * n * nrhs * batch, 16.0 * batch * ((double)n * n / 2 + 2.0 * n * nrhs));
-  hipLaunchKernelGGL(k_trsm_upper, g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, nrhs, Y, ldy, sY, status, sst);
+  hipLaunchKernelGGL(k_upper_block_inverse, dim3(nblk, batch), dim3(64), 0, ctx->stream, A, n, ncols, strideA, nblk,
+                     static_cast<double2*>(dinv), status, sst);
+  MS_TRY(check_launch(ctx, "upper block inverse"));
+  dim3 g((nrhs + 63) / 64, batch);
+  hipLaunchKernelGGL(k_trsm_upper, g, dim3(256), 0, ctx->stream, A, n, ncols, strideA, nrhs,
+                     static_cast<const double2*>(dinv), nblk, Y, ldy, sY);
   return check_launch(ctx, "trsm upper");
 }
 

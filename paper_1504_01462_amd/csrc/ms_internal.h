@@ -40,6 +40,9 @@ struct ms_ctx_s {
   uint32_t prof_mask = 0;        // categories timed by the event profiler
   std::vector<ms::ProfRec> prof[ms::PC_COUNT];
   std::vector<hipEvent_t> ev_pool;
+  bool owns_status = true;
+  std::vector<ms_ctx_s*> kids;   // internal contexts with their own stream and workspace
+  std::vector<hipEvent_t> sync_ev;  // fork/join events (reused; destroyed with the context)
 };
 
 namespace ms {
@@ -75,6 +78,9 @@ ms_status hip_fail(ms_ctx ctx, hipError_t e, const char* what);
 // workspace slot `slot` of at least `bytes` (synchronises the stream before growing)
 ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out);
 ms_status check_launch(ms_ctx ctx, const char* what);
+// internal child context i of ctx (own stream of default priority, own workspace,
+// the parent's status word and profiler mask), created on first use
+ms_status child(ms_ctx ctx, int i, ms_ctx* out);
 
 // ---- complex GEMM: C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b] (row-major) -------
 struct GemmArgs {
