@@ -155,10 +155,16 @@ def _smat(blocks):
 
 
 def ms_slices_prepare(ctx: Context, miller: torch.Tensor, bvec, kpar, q_of_ij: torch.Tensor, vq: torch.Tensor,
-                      dz: torch.Tensor, vlead=(0.0, 0.0), with_evec: bool = False) -> Slices:
+                      dz: torch.Tensor, vlead=(0.0, 0.0), with_evec: bool = False, out: Slices | None = None) -> Slices:
+    """Fill a new Slices object (or `out`, reusing its buffers) for one k_par."""
     n_g = int(miller.shape[0])
     n_slices, n_q = int(vq.shape[0]), int(vq.shape[1])
-    s = Slices.empty(n_g, n_slices, dz, ctx.device, with_evec)
+    if out is None:
+        s = Slices.empty(n_g, n_slices, dz, ctx.device, with_evec)
+    else:
+        if out.n_g != n_g or out.n_slices != n_slices:
+            raise ValueError("out has different sizes")
+        s = Slices(n_g, n_slices, dz, out.eps, out.ovl, out.evec)
     b = np.ascontiguousarray(np.asarray(bvec, dtype=np.float64).reshape(4))
     k = np.ascontiguousarray(np.asarray(kpar, dtype=np.float64).reshape(2))
     st = lib.ms_slices_prepare(ctx.handle, n_g, _ptr(miller, torch.int32, "miller"),

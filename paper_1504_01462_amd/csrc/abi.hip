@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -590,7 +591,9 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
                        2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
   // energies are folded in G groups on G internal streams, so that the latency-bound LU
   // panels of one group overlap the GEMMs of the other
-  const int G = (n_e >= 8) ? 2 : 1;
+  int G = (n_e >= 8) ? 2 : 1;
+  if (const char* env = getenv("MS_FOLD_STREAMS")) G = std::max(1, std::min<int>(4, atoi(env)));
+  G = (int)std::min<int64_t>(G, n_e);
   struct Group {
     ms_ctx c;
     int64_t e0, ne;

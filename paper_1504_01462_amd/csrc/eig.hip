@@ -463,9 +463,15 @@ ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, d
   }
   void* wsp = nullptr;
   void* wsc = nullptr;
-  MS_TRY(workspace(ctx, 10, pairs.size() * sizeof(int2), &wsp));
+  const size_t pbytes = pairs.size() * sizeof(int2);
+  const bool have = ctx->ws.size() > 10 && ctx->ws[10] && ctx->jacobi_n == n;
+  MS_TRY(workspace(ctx, 10, pbytes, &wsp));
   MS_TRY(workspace(ctx, 11, (size_t)nb * max_sweeps * sizeof(int32_t), &wsc));
-  MS_TRY(upload(ctx, wsp, pairs.data(), pairs.size() * sizeof(int2)));
+  if (!have || wsp != ctx->jacobi_pairs) {   // the schedule depends on n only: upload once
+    MS_TRY(upload(ctx, wsp, pairs.data(), pbytes));
+    ctx->jacobi_n = n;
+    ctx->jacobi_pairs = wsp;
+  }
   MS_HIP(ctx, hipMemsetAsync(wsc, 0, (size_t)nb * max_sweeps * sizeof(int32_t), ctx->stream));
   JacobiArgs a;
   a.W = W;

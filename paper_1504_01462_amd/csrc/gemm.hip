@@ -61,8 +61,10 @@ constexpr int BK = 16;
 // LDS rows are padded by one element so the transposing stores of the
 // staging pass spread over the banks.  Blocks are launched as a 1D grid whose
 // index is remapped so that consecutive logical tiles (same A row-panel, all
-// column tiles) land on the same XCD and share its L2.
-template <typename T, int BM, int BN, int WM, int WN>
+// column tiles) land on the same XCD and share its L2.  ROLE does not change
+// the code: it gives the interface products of the fold their own kernel name
+// in kernel traces.
+template <typename T, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int ntm, int total) {
   typedef typename Mfma<T>::c_t CT;
   typedef typename Mfma<T>::acc_t acc_t;
@@ -221,12 +223,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       }
 }
 
-template <typename T, int BM, int BN, int WM, int WN>
+template <typename T, int BM, int BN, int WM, int WN, int ROLE>
 ms_status launch(ms_ctx ctx, const KParams& p, int batch) {
   const int ntn = (p.N + BN - 1) / BN, ntm = (p.M + BM - 1) / BM;
   const int64_t total = (int64_t)ntn * ntm * batch;
   if (total > 0x7fffffff) return fail(ctx, MS_ERR_UNSUPPORTED, "gemm grid too large");
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN>), dim3((unsigned)total), dim3(64 * WM * WN), 0, ctx->stream, p, ntn,
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, ROLE>), dim3((unsigned)total), dim3(64 * WM * WN), 0, ctx->stream, p, ntn,
                      ntm, (int)total);
   return check_launch(ctx, "gemm");
 }
@@ -239,8 +241,10 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
   Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * p.K * g.batch,
             (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K + (double)p.K * g.N) +
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1));
-  if (g.M >= 128 && g.N >= 128) return launch<T, 128, 128, 2, 4>(ctx, p, g.batch);
-  return launch<T, 64, 64, 2, 2>(ctx, p, g.batch);
+  const bool big = g.M >= 128 && g.N >= 128;
+  if (g.prof == PC_IFACE_GEMM)
+    return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch);
+  return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch);
 }
 
 }  // namespace

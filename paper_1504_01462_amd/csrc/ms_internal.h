@@ -43,6 +43,8 @@ struct ms_ctx_s {
   bool owns_status = true;
   std::vector<ms_ctx_s*> kids;   // internal contexts with their own stream and workspace
   std::vector<hipEvent_t> sync_ev;  // fork/join events (reused; destroyed with the context)
+  int jacobi_n = -1;                // n of the round-robin schedule held in workspace slot 10
+  void* jacobi_pairs = nullptr;
 };
 
 namespace ms {
