@@ -43,14 +43,18 @@ ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, 
 ms_status ms_debug_eigh(ms_ctx ctx, int64_t n, int64_t batch, const void* h, const double* shift,
                         double* eps, void* u);
 
-/* Kernel timing with HIP events recorded on the context stream around each
- * launch of the categories whose bit is set in `mask` (0 stops recording).
- * Categories, bit 0 upwards: "iface_gemm", "lu_panel", "lu_swap",
- * "lu_update", "trsm", "jacobi", "prep_gemm", "elem", "other".  ms_debug_profile_read waits for the stream
- * and returns, for the launches recorded since the previous read of that
- * category: summed duration (ms), launch count, and the algorithmic flops
- * and bytes the launches were sized for (GEMM: 8 M N K; bytes: operands read
- * once plus C written, read too when beta != 0). */
+/* Kernel timing with HIP events for the launches of the categories whose bit
+ * is set in `mask` (0 stops recording).  GEMM launches pass their events to
+ * hipExtLaunchKernel, so they measure the kernel's own execution; the other
+ * kernels are bracketed by events recorded on the stream around the launch.
+ * Categories, bit 0 upwards: "iface_gemm" (interface product of the fused
+ * fold), "lu_panel", "lu_swap", "lu_update" (rank-128 trailing update),
+ * "trsm", "jacobi", "prep_gemm", "elem", "other", "lu_inner" (updates inside
+ * an outer LU panel and the U12 product).  ms_debug_profile_read waits for
+ * the streams and returns, for the launches recorded since the previous read
+ * of that category: summed duration (ms), launch count, and the algorithmic
+ * flops and bytes the launches were sized for (GEMM: 8 M N K; bytes: operands
+ * read once plus C written, read too when beta != 0). */
 ms_status ms_debug_profile(ms_ctx ctx, uint32_t mask);
 ms_status ms_debug_profile_read(ms_ctx ctx, const char* category, double* total_ms, int64_t* launches,
                                 double* flops, double* bytes);

@@ -231,7 +231,7 @@ def ms_kpar_average(ctx: Context, T: torch.Tensor, n_open: torch.Tensor):
 
 
 PROFILE_CATEGORIES = ("iface_gemm", "lu_panel", "lu_swap", "lu_update", "trsm", "jacobi", "prep_gemm", "elem",
-                      "other")
+                      "other", "lu_inner")
 
 
 def ms_debug_profile(ctx: Context, categories=True):

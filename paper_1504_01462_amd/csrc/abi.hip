@@ -72,18 +72,30 @@ static hipEvent_t take_event(ms_ctx ctx) {
   return e;
 }
 
-Prof::Prof(ms_ctx c, int category, double fl, double by) : ctx(c), cat(category), flops(fl), bytes(by) {
+Prof::Prof(ms_ctx c, int category, double fl, double by, bool kernel_events)
+    : ctx(c), cat(category), flops(fl), bytes(by), ext(kernel_events) {
   if (ctx && (ctx->prof_mask >> category & 1u)) {
     a = take_event(ctx);
-    if (a) (void)hipEventRecord(a, ctx->stream);
+    if (!a) return;
+    if (ext) {
+      b = take_event(ctx);
+      if (!b) {
+        ctx->ev_pool.push_back(a);
+        a = nullptr;
+      }
+    } else {
+      (void)hipEventRecord(a, ctx->stream);
+    }
   }
 }
 
 Prof::~Prof() {
   if (!a) return;
-  hipEvent_t b = take_event(ctx);
-  if (!b) return;
-  (void)hipEventRecord(b, ctx->stream);
+  if (!ext) {
+    b = take_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, ctx->stream);
+  }
   ctx->prof[cat].push_back(ProfRec{a, b, flops, bytes});
 }
 
@@ -232,6 +244,7 @@ ms_status ms_ctx_destroy(ms_ctx ctx) {
     }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->sync_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->lu_ev) (void)hipEventDestroy(e);
   if (!ctx->owns_status && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   for (void* p : ctx->ws)
     if (p) (void)hipFree(p);
@@ -252,12 +265,15 @@ ms_status ms_ctx_sync(ms_ctx ctx) {
 }
 
 static const char* const kProfNames[PC_COUNT] = {"iface_gemm", "lu_panel", "lu_swap", "lu_update", "trsm",
-                                                  "jacobi", "prep_gemm", "elem", "other"};
+                                                  "jacobi",     "prep_gemm", "elem", "other", "lu_inner"};
 
 ms_status ms_debug_profile(ms_ctx ctx, uint32_t mask) {
   if (!ctx) return MS_ERR_ARG;
-  ctx->prof_mask = mask;
-  for (ms_ctx k : ctx->kids) k->prof_mask = mask;
+  std::vector<ms_ctx> all{ctx};
+  for (size_t i = 0; i < all.size(); ++i) {
+    all[i]->prof_mask = mask;
+    for (ms_ctx k : all[i]->kids) all.push_back(k);
+  }
   return MS_OK;
 }
 
@@ -272,8 +288,9 @@ ms_status ms_debug_profile_read(ms_ctx ctx, const char* category, double* total_
   MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
   double tot = 0.0, fl = 0.0, by = 0.0;
   int64_t cnt = 0;
-  std::vector<ms_ctx> all{ctx};
-  for (ms_ctx k : ctx->kids) all.push_back(k);
+  std::vector<ms_ctx> all{ctx};   // the context and all its internal descendants
+  for (size_t i = 0; i < all.size(); ++i)
+    for (ms_ctx k : all[i]->kids) all.push_back(k);
   for (ms_ctx c : all) {
     MS_HIP(ctx, hipStreamSynchronize(c->stream));
     for (auto& r : c->prof[cat]) {
@@ -589,113 +606,88 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
   const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
   const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
                        2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
-  // energies are folded in G groups on G internal streams, so that the latency-bound LU
-  // panels of one group overlap the GEMMs of the other
-  int G = (n_e >= 8) ? 2 : 1;
+  // Buffers for a sub-batch of nbe energies.  Per interface, the prologue and the
+  // interface GEMM run on the caller's stream for the whole sub-batch (the GEMM
+  // then has the GPU to itself); the energies are then split into G groups whose
+  // epilogue, LU and back substitution run on G internal streams, so that the
+  // latency-bound LU panels of one group overlap the updates of the other.
+  int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(n_e, (int64_t)(BATCH_BUDGET / per_e)));
+  nbe = std::min(nbe, 65535);
+  int G = (nbe >= 8) ? 2 : 1;
   if (const char* env = getenv("MS_FOLD_STREAMS")) G = std::max(1, std::min<int>(4, atoi(env)));
-  G = (int)std::min<int64_t>(G, n_e);
-  struct Group {
-    ms_ctx c;
-    int64_t e0, ne;
-    int nbe;
-    double2 *kb, *pb, *wg, *mm, *yb;
-    void *aop, *oc;
-    int32_t* piv;
-  };
-  std::vector<Group> grp(G);
+  G = std::min(G, nbe);
+  void *kbv, *pbv, *aop, *wgv, *mmv, *ybv, *pivv, *oc = nullptr;
+  MS_TRY(workspace(ctx, WS_K, (size_t)nbe * sk * sizeof(double2), &kbv));
+  MS_TRY(workspace(ctx, WS_P, (size_t)nbe * sk * sizeof(double2), &pbv));
+  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
+  MS_TRY(workspace(ctx, WS_WG, (size_t)nbe * 2 * nn * sizeof(double2), &wgv));
+  MS_TRY(workspace(ctx, WS_M, (size_t)nbe * sM * sizeof(double2), &mmv));
+  MS_TRY(workspace(ctx, WS_Y, (size_t)nbe * sY * sizeof(double2), &ybv));
+  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbe * n * sizeof(int32_t), &pivv));
+  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
+  double2 *kb = c2(kbv), *pb = c2(pbv), *wg = c2(wgv), *mm = c2(mmv), *yb = c2(ybv);
+  int32_t* piv = (int32_t*)pivv;
+  std::vector<ms_ctx> gc(G, ctx);   // G = 1: everything on the caller's stream
+  if (G > 1)
+    for (int g = 0; g < G; ++g) MS_TRY(child(ctx, g, &gc[g]));
   while ((int)ctx->sync_ev.size() < G + 1) {
     hipEvent_t e = nullptr;
     MS_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ctx->sync_ev.push_back(e);
   }
   hipEvent_t fork = ctx->sync_ev[0];
-  if (G > 1) MS_HIP(ctx, hipEventRecord(fork, ctx->stream));
-  for (int g = 0; g < G; ++g) {
-    Group& q = grp[g];
-    q.e0 = n_e * g / G;
-    q.ne = n_e * (g + 1) / G - q.e0;
-    if (G > 1) {
-      MS_TRY(child(ctx, g, &q.c));
-      MS_HIP(ctx, hipStreamWaitEvent(q.c->stream, fork, 0));
-    } else {
-      q.c = ctx;
-    }
-    q.nbe = (int)std::max<int64_t>(1, std::min<int64_t>(q.ne, (int64_t)(BATCH_BUDGET / G / per_e)));
-    q.nbe = std::min(q.nbe, 65535);
-    void *kb, *pb, *wg, *mm, *yb, *piv;
-    MS_TRY(workspace(q.c, WS_K, (size_t)q.nbe * sk * sizeof(double2), &kb));
-    MS_TRY(workspace(q.c, WS_P, (size_t)q.nbe * sk * sizeof(double2), &pb));
-    MS_TRY(workspace(q.c, WS_AOP, (size_t)q.nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &q.aop));
-    MS_TRY(workspace(q.c, WS_WG, (size_t)q.nbe * 2 * nn * sizeof(double2), &wg));
-    MS_TRY(workspace(q.c, WS_M, (size_t)q.nbe * sM * sizeof(double2), &mm));
-    MS_TRY(workspace(q.c, WS_Y, (size_t)q.nbe * sY * sizeof(double2), &yb));
-    MS_TRY(workspace(q.c, WS_PIV, (size_t)q.nbe * n * sizeof(int32_t), &piv));
-    q.oc = nullptr;
-    if (fp32) MS_TRY(workspace(q.c, WS_OC, nn * sizeof(float2), &q.oc));
-    q.kb = c2(kb); q.pb = c2(pb); q.wg = c2(wg); q.mm = c2(mm); q.yb = c2(yb); q.piv = (int32_t*)piv;
-  }
 
-  // all groups advance in lock step over sub-batches and interfaces (launches interleaved)
-  int64_t max_sub = 0;
-  for (const Group& q : grp) max_sub = std::max<int64_t>(max_sub, (q.ne + q.nbe - 1) / q.nbe);
-  for (int64_t sb = 0; sb < max_sub; ++sb) {
-    for (Group& q : grp) {
-      const int64_t e0 = q.e0 + sb * q.nbe;
-      const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
-      if (be <= 0) continue;
-      MS_TRY(launch_wavevectors(q.c, n, nrows, be, slices->eps, (const double*)end + e0, slices->dz, q.kb, q.pb));
-    }
+  for (int64_t e0 = 0; e0 < n_e; e0 += nbe) {
+    const int be = (int)std::min<int64_t>(nbe, n_e - e0);
+    const int gn = std::min(G, be);
+    MS_TRY(launch_wavevectors(ctx, n, nrows, be, slices->eps, (const double*)end + e0, slices->dz, kb, pb));
     for (int p = ns; p >= 0; --p) {
       const double2* O = c2(slices->ovl) + (int64_t)p * nn;
       const bool first = (p == ns);
-      for (Group& q : grp) {
-        const int64_t e0 = q.e0 + sb * q.nbe;
-        const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
-        if (be <= 0) continue;
-        ms_ctx c = q.c;
-        int32_t* pst = point_status + e0;
-        const double2* kp = q.kb + (int64_t)p * n;
-        const double2* kq = q.kb + (int64_t)(p + 1) * n;
-        const double2* pq = q.pb + (int64_t)(p + 1) * n;
-        if (!first) {
-          MS_TRY(launch_prologue(c, n, be, q.yb, ldy, sY, kq, pq, sk, q.aop, fp32));
-          GemmArgs g;
-          g.M = 2 * n; g.N = n; g.K = n;
-          g.A = q.aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
-          g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
-          g.C = q.wg; g.ldc = n; g.sC = 2 * nn;
-          g.batch = be;
-          g.prof = PC_IFACE_GEMM;
-          if (fp32) {
-            MS_TRY(launch_to_c64(c, nn, O, static_cast<float2*>(q.oc)));
-            g.B = q.oc;
-            MS_TRY(cgemm32(c, g));
-          } else {
-            MS_TRY(zgemm(c, g));
-          }
+      const double2* kp = kb + (int64_t)p * n;
+      const double2* kq = kb + (int64_t)(p + 1) * n;
+      const double2* pq = pb + (int64_t)(p + 1) * n;
+      if (!first) {
+        MS_TRY(launch_prologue(ctx, n, be, yb, ldy, sY, kq, pq, sk, aop, fp32));
+        GemmArgs g;
+        g.M = 2 * n; g.N = n; g.K = n;
+        g.A = aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
+        g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
+        g.C = wg; g.ldc = n; g.sC = 2 * nn;
+        g.batch = be;
+        g.prof = PC_IFACE_GEMM;
+        if (fp32) {
+          MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
+          g.B = oc;
+          MS_TRY(cgemm32(ctx, g));
+        } else {
+          MS_TRY(zgemm(ctx, g));
         }
-        MS_TRY(launch_epilogue(c, n, be, O, first ? nullptr : q.wg, kp, kq, sk, q.mm, ldm, sM));
-        MS_TRY(launch_tcols(c, n, n_o, be, (const int32_t*)chd, q.yb, ldy, sY, n, kq, pq, sk, first ? 1 : 0, q.mm,
-                            ldm, sM));
-        MS_TRY(getrf_aug(c, q.mm, n, ldm, sM, be, q.piv, pst, 1));
-        MS_TRY(trsm_upper_aug(c, q.mm, n, ldm, sM, be, q.yb, ldy, sY, pst, 1));
+      }
+      if (gn > 1) MS_HIP(ctx, hipEventRecord(fork, ctx->stream));
+      for (int g = 0; g < gn; ++g) {
+        const int a = be * g / gn, nb = be * (g + 1) / gn - a;
+        ms_ctx c = gc[g];
+        if (gn > 1) MS_HIP(ctx, hipStreamWaitEvent(c->stream, fork, 0));
+        int32_t* pst = point_status + e0 + a;
+        MS_TRY(launch_epilogue(c, n, nb, O, first ? nullptr : wg + (int64_t)a * 2 * nn, kp + (int64_t)a * sk,
+                               kq + (int64_t)a * sk, sk, mm + (int64_t)a * sM, ldm, sM));
+        MS_TRY(launch_tcols(c, n, n_o, nb, (const int32_t*)chd, yb + (int64_t)a * sY, ldy, sY, n,
+                            kq + (int64_t)a * sk, pq + (int64_t)a * sk, sk, first ? 1 : 0, mm + (int64_t)a * sM, ldm,
+                            sM));
+        MS_TRY(getrf_aug(c, mm + (int64_t)a * sM, n, ldm, sM, nb, piv + (int64_t)a * n, pst, 1));
+        MS_TRY(trsm_upper_aug(c, mm + (int64_t)a * sM, n, ldm, sM, nb, yb + (int64_t)a * sY, ldy, sY, pst, 1));
+      }
+      if (gn > 1) {   // join: the next interface (and T) needs every group's state
+        for (int g = 0; g < gn; ++g) {
+          hipEvent_t done = ctx->sync_ev[1 + g];
+          MS_HIP(ctx, hipEventRecord(done, gc[g]->stream));
+          MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, done, 0));
+        }
       }
     }
-    for (Group& q : grp) {
-      const int64_t e0 = q.e0 + sb * q.nbe;
-      const int be = (int)std::min<int64_t>(q.nbe, q.e0 + q.ne - e0);
-      if (be <= 0) continue;
-      MS_TRY(launch_batch_T(q.c, n, n_o, be, (const int32_t*)chd, (const double*)end + e0, eps_l, eps_r, q.yb, ldy, sY,
-                            T + e0, R + e0, n_open + e0, point_status + e0));
-    }
-  }
-  // join: the caller's stream waits for every group
-  if (G > 1) {
-    for (int g = 0; g < G; ++g) {
-      hipEvent_t done = ctx->sync_ev[1 + g];
-      MS_HIP(ctx, hipEventRecord(done, grp[g].c->stream));
-      MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, done, 0));
-    }
+    MS_TRY(launch_batch_T(ctx, n, n_o, be, (const int32_t*)chd, (const double*)end + e0, eps_l, eps_r, yb, ldy, sY,
+                          T + e0, R + e0, n_open + e0, point_status + e0));
   }
   return MS_OK;
 }

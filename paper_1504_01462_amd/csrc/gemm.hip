@@ -12,6 +12,9 @@
 // with 8 waves otherwise).  Global->LDS staging is register double-buffered
 // (the next K-slab is fetched while the current one is used).
 #include <algorithm>
+#include <type_traits>
+
+#include <hip/hip_ext.h>
 
 #include "ms_internal.h"
 
@@ -62,8 +65,8 @@ constexpr int BK = 16;
 // staging pass spread over the banks.  Blocks are launched as a 1D grid whose
 // index is remapped so that consecutive logical tiles (same A row-panel, all
 // column tiles) land on the same XCD and share its L2.  ROLE does not change
-// the code: it gives the interface products of the fold their own kernel name
-// in kernel traces.
+// the code: it gives the interface products of the fold (1) and the LU's
+// trailing updates (2) their own kernel names in kernel traces.
 template <typename T, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int ntm, int total) {
   typedef typename Mfma<T>::c_t CT;
@@ -91,6 +94,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   const int m0 = tm * BM, n0 = tn * BN;
   const CT* A = static_cast<const CT*>(p.A) + b * p.sA;
   const CT* B = static_cast<const CT*>(p.B) + b * p.sB;
+  double2* C = p.C + b * p.sC;
+  const bool use_beta = (p.beta.x != 0.0 || p.beta.y != 0.0);
+  // FP64: alpha is applied to A as it is staged and beta C is loaded into the
+  // accumulators before the K loop, so the C read overlaps the first K-slabs
+  // instead of trailing the last one.  FP32 accumulators keep the epilogue form.
+  constexpr bool kFold = std::is_same<T, double>::value;
+  const bool scale_a = !(p.alpha.x == 1.0 && p.alpha.y == 0.0);
 
   CT ra[EA], rb[EB];
   auto load = [&](int k0) {
@@ -105,6 +115,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       if (gi < p.M && gk < p.K) {
         v = (p.opA == OP_N) ? A[(int64_t)gi * p.lda + gk] : A[(int64_t)gk * p.lda + gi];
         if (p.opA == OP_C) v.y = -v.y;
+        if (kFold && scale_a) {   // alpha op(A), staged
+          const T re = (T)p.alpha.x * v.x - (T)p.alpha.y * v.y;
+          v.y = (T)p.alpha.x * v.y + (T)p.alpha.y * v.x;
+          v.x = re;
+        }
       }
       ra[e] = v;
     }
@@ -154,6 +169,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
   // other one; one barrier per slab
   load(0);
+  if (kFold && use_beta) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int c = 0; c < FN; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm0 + a * 16 + Mfma<T>::crow(lane, v);
+          const int col = n0 + wn0 + c * 16 + (lane & 15);
+          if (row < p.M && col < p.N) {
+            const double2 o = C[(int64_t)row * p.ldc + col];
+            cr[a][c][v] = p.beta.x * o.x - p.beta.y * o.y;
+            ci[a][c][v] = p.beta.x * o.y + p.beta.y * o.x;
+          }
+        }
+  }
   stash(0);
   if (BK < p.K) load(BK);
   __syncthreads();
@@ -197,8 +228,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
     cur ^= 1;
   }
 
-  double2* C = p.C + b * p.sC;
-  const bool use_beta = (p.beta.x != 0.0 || p.beta.y != 0.0);
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -208,6 +237,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
         const int row = m0 + wm0 + a * 16 + Mfma<T>::crow(lane, v);
         const int col = n0 + wn0 + c * 16 + (lane & 15);
         if (row < p.M && col < p.N) {
+          if (kFold) {
+            C[(int64_t)row * p.ldc + col] = make_double2((double)cr[a][c][v], (double)ci[a][c][v]);
+            continue;
+          }
           const double re = (double)cr[a][c][v], im = (double)ci[a][c][v];
           double2 out;
           out.x = p.alpha.x * re - p.alpha.y * im;
@@ -224,12 +257,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 }
 
 template <typename T, int BM, int BN, int WM, int WN, int ROLE>
-ms_status launch(ms_ctx ctx, const KParams& p, int batch) {
+ms_status launch(ms_ctx ctx, const KParams& p, int batch, const Prof& prof) {
   const int ntn = (p.N + BN - 1) / BN, ntm = (p.M + BM - 1) / BM;
   const int64_t total = (int64_t)ntn * ntm * batch;
   if (total > 0x7fffffff) return fail(ctx, MS_ERR_UNSUPPORTED, "gemm grid too large");
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, ROLE>), dim3((unsigned)total), dim3(64 * WM * WN), 0, ctx->stream, p, ntn,
-                     ntm, (int)total);
+  if (prof.a)   // timed: the events bracket the kernel's execution
+    hipExtLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, ROLE>), dim3((unsigned)total), dim3(64 * WM * WN), 0,
+                          ctx->stream, prof.a, prof.b, 0, p, ntn, ntm, (int)total);
+  else
+    hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, ROLE>), dim3((unsigned)total), dim3(64 * WM * WN), 0, ctx->stream,
+                       p, ntn, ntm, (int)total);
   return check_launch(ctx, "gemm");
 }
 
@@ -240,11 +277,14 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
             g.beta};
   Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * p.K * g.batch,
             (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K + (double)p.K * g.N) +
-                (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1));
+                (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
+            true);
   const bool big = g.M >= 128 && g.N >= 128;
+  if (g.prof == PC_LU_UPDATE)   // one kernel for every trailing update, whatever its height
+    return launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof);
   if (g.prof == PC_IFACE_GEMM)
-    return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch);
-  return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch);
+    return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
+  return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
 }
 
 }  // namespace

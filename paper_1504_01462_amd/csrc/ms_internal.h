@@ -16,12 +16,13 @@ enum ProfCat {
   PC_IFACE_GEMM = 0,  // the interface GEMM of the fused fold (rho^T O^T, both halves)
   PC_LU_PANEL,        // LU panel factorisation
   PC_LU_SWAP,         // row interchanges + unit-lower solve of the panel rows
-  PC_LU_UPDATE,       // trailing GEMM update of the LU
+  PC_LU_UPDATE,       // rank-128 trailing GEMM update of the LU (right of an outer panel)
   PC_TRSM,            // back substitution
   PC_JACOBI,          // one round of the block Jacobi eigensolver
   PC_PREP_GEMM,       // overlap GEMMs of the E-independent stage
   PC_ELEM,            // elementwise kernels of the fused fold (prologue/epilogue/T)
   PC_OTHER,
+  PC_LU_INNER,        // GEMM updates inside an outer panel and the U12 product
   PC_COUNT
 };
 struct ProfRec {
@@ -43,6 +44,7 @@ struct ms_ctx_s {
   bool owns_status = true;
   std::vector<ms_ctx_s*> kids;   // internal contexts with their own stream and workspace
   std::vector<hipEvent_t> sync_ev;  // fork/join events (reused; destroyed with the context)
+  std::vector<hipEvent_t> lu_ev;    // look-ahead events of the LU (reused)
   int jacobi_n = -1;                // n of the round-robin schedule held in workspace slot 10
   void* jacobi_pairs = nullptr;
 };
@@ -50,12 +52,17 @@ struct ms_ctx_s {
 namespace ms {
 
 // Records HIP events around the launches in its scope when profiling is on.
+// With kernel_events = true the scope holds exactly one launch, which passes
+// a and b to hipExtLaunchKernel: the events then carry that kernel's own start
+// and end instead of the moments the stream reached them, so time spent waiting
+// for compute units held by other streams is not counted.
 struct Prof {
   ms_ctx ctx;
   int cat;
   double flops, bytes;
-  hipEvent_t a = nullptr;
-  Prof(ms_ctx c, int category, double fl = 0.0, double by = 0.0);
+  hipEvent_t a = nullptr, b = nullptr;
+  bool ext = false;
+  Prof(ms_ctx c, int category, double fl = 0.0, double by = 0.0, bool kernel_events = false);
   ~Prof();
 };
 

@@ -63,7 +63,7 @@ def test_gemm_fp32(lib, ctx, m, n, k):
 
 
 @pytest.mark.parametrize("n,nrhs,batch", [(1, 1, 2), (5, 3, 3), (16, 16, 2), (17, 13, 2), (37, 74, 3),
-                                          (100, 64, 2), (300, 313, 2), (513, 70, 1), (1030, 20, 1)])
+                                          (100, 64, 2), (128, 7, 2), (300, 313, 2), (513, 70, 1), (1030, 20, 1)])
 def test_lu_solve(lib, ctx, n, nrhs, batch):
     rng = np.random.default_rng(n + nrhs)
     a = _rand(rng, (batch, n, n))
