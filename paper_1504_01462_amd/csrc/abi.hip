@@ -135,12 +135,13 @@ enum {
   WS_KIN = 0, WS_SHIFT, WS_W, WS_U, WS_MISC, WS_K, WS_P, WS_AOP, WS_WG, WS_M,
   WS_JPAIRS = 10, WS_JCOUNT = 11,
   WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
-  WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V
+  WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V
 };
 
 constexpr int MAX_N = 4096;
 constexpr size_t BATCH_BUDGET = size_t(24) << 30;   // bytes of per-energy workspace per sub-batch
-constexpr size_t PREP_BUDGET = size_t(4) << 30;     // bytes of eigensolver workspace per chunk
+constexpr size_t PREP_BUDGET = size_t(8) << 30;     // bytes of eigensolver workspace per chunk
+constexpr int WARM_STRIDE = 8;                       // reference slices for the warm-started eigensolver
 
 bool bad_ptr(const void* p) { return p == nullptr; }
 
@@ -349,23 +350,59 @@ ms_status ms_slices_prepare(ms_ctx ctx, int64_t n_g, const int32_t* g_mn, const 
     return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
   const int32_t q0 = qr[2];
 
-  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(PREP_BUDGET / (3 * nn * sizeof(double2)))));
+  // Warm start: slices 0, S, 2S, ... are solved first from V = I; every slice is then
+  // solved from V = the eigenvectors of its nearest such reference slice, which leaves
+  // the one-sided Jacobi far fewer sweeps (adjacent slices differ by a thin layer).
+  int S = WARM_STRIDE;
+  if (const char* env = getenv("MS_EIG_WARM_STRIDE")) S = std::max(0, atoi(env));
+  const bool warm = S > 1 && ns > S;
+  const int nref = warm ? (ns + S - 1) / S : 0;
+  const int nbuf = warm ? 4 : 3;
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(PREP_BUDGET / (nbuf * nn * sizeof(double2)))));
   chunk = std::min(chunk, 256);
-  void* Z = nullptr;
+  void *Z = nullptr, *V = nullptr, *Uref = nullptr;
   MS_TRY(workspace(ctx, WS_SHIFT, chunk * sizeof(double), &shift));
   MS_TRY(workspace(ctx, WS_W, (size_t)chunk * nn * sizeof(double2), &W));
   MS_TRY(workspace(ctx, WS_U, (size_t)(chunk + 1) * nn * sizeof(double2), &U));
   MS_TRY(workspace(ctx, WS_Z, (size_t)chunk * nn * sizeof(double2), &Z));
+  if (warm) {
+    MS_TRY(workspace(ctx, WS_PREP_V, (size_t)chunk * nn * sizeof(double2), &V));
+    MS_TRY(workspace(ctx, WS_UREF, (size_t)nref * nn * sizeof(double2), &Uref));
+  }
   double2* Ub = c2(U);
+  // pass 1: the reference slices from V = I (their eps rows are rewritten by pass 2)
+  for (int r0 = 0; r0 < nref; r0 += chunk) {
+    const int bc = std::min(chunk, nref - r0);
+    const double2* vq_r = c2(vq) + (int64_t)r0 * S * n_q;
+    MS_TRY(launch_slice_shift(ctx, n, bc, (const double*)kin, n_q, (int64_t)S * n_q, vq_r, q0, (double*)shift));
+    MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, (const double*)shift, (int64_t)S * n_q, vq_r, q_of_ij,
+                          c2(W)));
+    MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, nullptr, (int64_t)S * n_q, vq_r, q_of_ij, Ub + nn));
+    MS_TRY(jacobi_eigh(ctx, n, bc, c2(W), Ub + nn, c2(Z), eps + (int64_t)(r0 * S + 1) * n, (int64_t)S * n,
+                       c2(Uref) + (int64_t)r0 * nn, nn, ctx->d_status));
+  }
   for (int s0 = 0; s0 < ns; s0 += chunk) {
     const int bc = std::min(chunk, ns - s0);
     const double2* vq_c = c2(vq) + (int64_t)s0 * n_q;
-    MS_TRY(launch_slice_shift(ctx, n, bc, (const double*)kin, n_q, vq_c, q0, (double*)shift));
+    MS_TRY(launch_slice_shift(ctx, n, bc, (const double*)kin, n_q, n_q, vq_c, q0, (double*)shift));
     MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, (const double*)shift, n_q, vq_c, q_of_ij, c2(W)));
     // H itself into U slots 1..bc (the eigenvectors overwrite it at the end)
     MS_TRY(launch_hgather(ctx, n, bc, (const double*)kin, nullptr, n_q, vq_c, q_of_ij, Ub + nn));
+    double2* Wstart = c2(W);
+    if (warm) {   // (H + cI) U_ref
+      MS_TRY(launch_gather_ref(ctx, n, bc, s0, S, nref, c2(Uref), c2(Z)));
+      GemmArgs g;
+      g.M = n; g.N = n; g.K = n;
+      g.A = W; g.lda = n; g.sA = nn;
+      g.B = Z; g.ldb = n; g.sB = nn;
+      g.C = c2(V); g.ldc = n; g.sC = nn;
+      g.batch = bc;
+      g.prof = PC_PREP_GEMM;
+      MS_TRY(zgemm(ctx, g));
+      Wstart = c2(V);
+    }
     // slice s0+i (paper p = s0+i+1) -> eps row s0+i+1, U slot i+1
-    MS_TRY(jacobi_eigh(ctx, n, bc, c2(W), Ub + nn, c2(Z), eps + (int64_t)(s0 + 1) * n, n, Ub + nn, nn,
+    MS_TRY(jacobi_eigh(ctx, n, bc, Wstart, Ub + nn, c2(Z), eps + (int64_t)(s0 + 1) * n, n, Ub + nn, nn,
                        ctx->d_status));
     // overlaps O^p = U^p^dagger U^{p+1}; slots: 0 = U^{s0} (previous chunk), i = U^{s0+i}
     const int P0 = s0 + 1, P1 = s0 + bc;
@@ -608,12 +645,12 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
                        2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
   // Buffers for a sub-batch of nbe energies.  Per interface, the prologue and the
   // interface GEMM run on the caller's stream for the whole sub-batch (the GEMM
-  // then has the GPU to itself); the energies are then split into G groups whose
-  // epilogue, LU and back substitution run on G internal streams, so that the
-  // latency-bound LU panels of one group overlap the updates of the other.
+  // then has the GPU to itself); the energies can then be split into G groups whose
+  // epilogue, LU and back substitution run on G internal streams (MS_FOLD_STREAMS),
+  // so that the latency-bound LU panels of one group overlap the updates of another.
   int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(n_e, (int64_t)(BATCH_BUDGET / per_e)));
   nbe = std::min(nbe, 65535);
-  int G = (nbe >= 8) ? 2 : 1;
+  int G = 1;   // measured: two groups give no gain once the GEMM has the GPU to itself
   if (const char* env = getenv("MS_FOLD_STREAMS")) G = std::max(1, std::min<int>(4, atoi(env)));
   G = std::min(G, nbe);
   void *kbv, *pbv, *aop, *wgv, *mmv, *ybv, *pivv, *oc = nullptr;

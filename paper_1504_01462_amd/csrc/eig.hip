@@ -46,11 +46,11 @@ __global__ void k_kin_eps(int n, const int32_t* g, double b1x, double b1y, doubl
 // ---- positivity shift per slice --------------------------------------------------------
 // lambda_min(H^p) >= min_i |k+G_i|^2 + V^p(0) - sum_{Q != 0} |V^p(Q)|  (Gershgorin, every
 // difference vector appears at most once per row); c = max(0, -bound) + 1.
-__global__ __launch_bounds__(256) void k_shift(int n, const double* kin, int64_t n_q, const double2* vq, int q0,
-                                               double* shift) {
+__global__ __launch_bounds__(256) void k_shift(int n, const double* kin, int64_t n_q, int64_t vstride,
+                                               const double2* vq, int q0, double* shift) {
   __shared__ double s_min[256], s_sum[256];
   const int b = blockIdx.x, t = threadIdx.x;
-  const double2* v = vq + (int64_t)b * n_q;
+  const double2* v = vq + (int64_t)b * vstride;
   double mn = 1e300, sm = 0.0;
   for (int i = t; i < n; i += 256) mn = fmin(mn, kin[i]);
   for (int64_t q = t; q < n_q; q += 256)
@@ -72,13 +72,13 @@ __global__ __launch_bounds__(256) void k_shift(int n, const double* kin, int64_t
 }
 
 // ---- W = H^p + c_p I --------------------------------------------------------------------
-__global__ void k_hgather(int n, const double* kin, const double* shift, int64_t n_q, const double2* vq,
+__global__ void k_hgather(int n, const double* kin, const double* shift, int64_t vstride, const double2* vq,
                           const int32_t* q_of_ij, double2* W) {
   const int64_t b = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), j = (int)(idx % n);
-  double2 h = vq[b * n_q + q_of_ij[idx]];
+  double2 h = vq[b * vstride + q_of_ij[idx]];
   if (i == j) h.x += kin[i] + (shift ? shift[b] : 0.0);
   W[b * (int64_t)n * n + idx] = h;
 }
@@ -430,18 +430,36 @@ ms_status launch_kin_eps(ms_ctx ctx, int n, const int32_t* g_mn, const double* b
   return check_launch(ctx, "kin/eps");
 }
 
-ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, const double2* vq, int q0,
-                             double* shift) {
-  hipLaunchKernelGGL(k_shift, dim3(nb), dim3(256), 0, ctx->stream, n, kin, n_q, vq, q0, shift);
+ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, int64_t vstride,
+                             const double2* vq, int q0, double* shift) {
+  hipLaunchKernelGGL(k_shift, dim3(nb), dim3(256), 0, ctx->stream, n, kin, n_q, vstride, vq, q0, shift);
   return check_launch(ctx, "shift");
 }
 
-ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t n_q,
+ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t vstride,
                          const double2* vq, const int32_t* q_of_ij, double2* W) {
   const int64_t nn = (int64_t)n * n;
-  hipLaunchKernelGGL(k_hgather, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, ctx->stream, n, kin, shift, n_q,
-                     vq, q_of_ij, W);
+  hipLaunchKernelGGL(k_hgather, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, ctx->stream, n, kin, shift,
+                     vstride, vq, q_of_ij, W);
   return check_launch(ctx, "hgather");
+}
+
+// Z[i] = Uref[r(i)], r(i) = the reference slice nearest to slice s0 + i (references at
+// multiples of stride, nref of them)
+__global__ void k_gather_ref(int64_t nn, int s0, int stride, int nref, const double2* Uref, double2* Z) {
+  const int64_t i = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const int r = min(nref - 1, (int)((s0 + i + stride / 2) / stride));
+  Z[i * nn + idx] = Uref[(int64_t)r * nn + idx];
+}
+
+ms_status launch_gather_ref(ms_ctx ctx, int n, int nb, int s0, int stride, int nref, const double2* Uref,
+                            double2* Z) {
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_gather_ref, dim3((unsigned)((nn + 255) / 256), nb), dim3(256), 0, ctx->stream, nn, s0, stride,
+                     nref, Uref, Z);
+  return check_launch(ctx, "gather reference eigenvectors");
 }
 
 ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, double2* Z, double* eps_out,

@@ -127,13 +127,18 @@ ms_status trsm_upper_aug(ms_ctx ctx, const double2* A, int n, int ncols, int64_t
 // ---- elementwise and reduction kernels (launchers) ------------------------------------
 ms_status launch_kin_eps(ms_ctx ctx, int n, const int32_t* g_mn, const double* bvec, const double* kpar,
                          double vl, double vr, double* kin, double* eps_left, double* eps_right);
-ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, const double2* vq,
-                             int q0, double* shift);
-// W = H + diag(shift) (shift may be null for H itself)
-ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t n_q,
+// positivity shifts of nb slices whose V(Q) rows are vstride elements apart
+ms_status launch_slice_shift(ms_ctx ctx, int n, int nb, const double* kin, int64_t n_q, int64_t vstride,
+                             const double2* vq, int q0, double* shift);
+// W = H + diag(shift) (shift may be null for H itself); V(Q) rows vstride elements apart
+ms_status launch_hgather(ms_ctx ctx, int n, int nb, const double* kin, const double* shift, int64_t vstride,
                          const double2* vq, const int32_t* q_of_ij, double2* W);
-// Eigenpairs of nb Hermitian matrices H (n x n each, not modified): W holds H + c I on entry
-// (destroyed), Z is an nb x n x n scratch; eps ascending, U columns = unit eigenvectors.
+// Z[i] = Uref[nearest reference of slice s0 + i] (references every `stride` slices)
+ms_status launch_gather_ref(ms_ctx ctx, int n, int nb, int s0, int stride, int nref, const double2* Uref,
+                            double2* Z);
+// Eigenpairs of nb Hermitian matrices H (n x n each, not modified): W holds (H + c I) V on
+// entry for some unitary V (V = I: W = H + c I; a nearby slice's eigenvectors: a warm start),
+// and is destroyed; Z is an nb x n x n scratch; eps ascending, U columns = unit eigenvectors.
 ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, double2* Z, double* eps_out,
                       int64_t eps_stride, double2* U, int64_t u_stride, int32_t* status);
 ms_status launch_copy_boundary_overlaps(ms_ctx ctx, int n, const double2* U, double2* O, int conj_transpose);
