@@ -55,14 +55,46 @@ __device__ __forceinline__ void set_status(int32_t* status, int64_t idx, int32_t
   if (status) atomicCAS(status + idx, 0, code);
 }
 
+// Pivot search key of row offset r (< 4096) with magnitude v >= 0: the bits of a
+// non-negative double order like the value, so the top 51 bits carry v and the low 13
+// bits 8191 - r make the smaller row win a tie (magnitudes equal to ~1e-12 relative
+// count as ties).  Ineligible rows get key 0, below every eligible key.
+__device__ __forceinline__ unsigned long long pivot_key(double v, int r) {
+  return ((unsigned long long)__double_as_longlong(v) & ~0x1FFFull) | (unsigned long long)(8191 - r);
+}
+
+// max over the 64 lanes of a wave: DPP butterflies inside each row of 16 lanes, then the
+// four row results read as scalars
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
+  auto step = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)k, C, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), C, 0xF, 0xF, false);
+    const unsigned long long o = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    k = o > k ? o : k;
+  };
+  step(std::integral_constant<int, 0xB1>{});    // quad_perm [1,0,3,2]
+  step(std::integral_constant<int, 0x4E>{});    // quad_perm [2,3,0,1]
+  step(std::integral_constant<int, 0x141>{});   // row_half_mirror
+  step(std::integral_constant<int, 0x140>{});   // row_mirror
+  unsigned long long m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)k, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 16 * r);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    m = o > m ? o : m;
+  }
+  return m;
+}
+
 // Factor columns [j0, j0+nbp) of rows [j0, n) of each matrix.
 template <int RPT, int NB>
 __global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREADS), amdgpu_waves_per_eu(1, 2))) void k_panel(double2* A, int n, int ld, int64_t strideA, int j0,
                                                           int nbp, int32_t* piv, int32_t* status, int64_t sst) {
   __shared__ double2 prow[NB];
   __shared__ double2 jrow[NB];
-  __shared__ double red_v[PANEL_THREADS / 64];
-  __shared__ int red_i[PANEL_THREADS / 64];
+  __shared__ unsigned long long red_k[PANEL_THREADS / 64];
 
   const int64_t b = blockIdx.x;
   double2* M = A + b * strideA;
@@ -82,40 +114,33 @@ __global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREA
   static_for<0, NB>([&](auto cidx) {
     constexpr int c = decltype(cidx)::value;
     const int j = j0 + c;
-    // local argmax of |re| + |im| over owned rows r >= j
-    double bv = -1.0;
-    int bi = 0x7fffffff;
+    // argmax of |re| + |im| over rows r >= j: per thread, per wave (DPP), per block (LDS)
+    unsigned long long key = 0;
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int r = j0 + t + PANEL_THREADS * s;
       if (r >= j && r < n) {
-        const double v = fabs(a[s][c].x) + fabs(a[s][c].y);
-        if (v > bv) { bv = v; bi = r; }
+        const unsigned long long kk = pivot_key(fabs(a[s][c].x) + fabs(a[s][c].y), r - j0);
+        key = kk > key ? kk : key;
       }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+    key = wave_max_u64(key);
+    if (lane == 0) red_k[wave] = key;
     __syncthreads();
-    bv = red_v[0];
-    bi = red_i[0];
+    key = red_k[0];
 #pragma unroll
     for (int w = 1; w < PANEL_THREADS / 64; ++w) {
-      const double ov = red_v[w];
-      const int oi = red_i[w];
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      const unsigned long long o = red_k[w];
+      key = o > key ? o : key;
     }
+    const double bv = __longlong_as_double((long long)(key & ~0x1FFFull));
     const bool active = c < nbp;
-    const bool ok = active && (bv > 0.0);
+    const bool ok = active && key != 0 && bv > 0.0;   // false for a zero or NaN column
     if (active && !ok && t == 0) {  // zero (or NaN) pivot column: record, leave it as is
       pv[j] = j;
-      set_status(status, b * sst, bv == 0.0 ? MS_ERR_SINGULAR : MS_ERR_NONFINITE);
+      set_status(status, b * sst, (key == 0 || bv == 0.0) ? MS_ERR_SINGULAR : MS_ERR_NONFINITE);
     }
-    const int p = ok ? bi : j;
+    const int p = ok ? j0 + (8191 - (int)(key & 0x1FFFull)) : j;
     // rows j and p: owners publish, then exchange
     const int op = p - j0, oj = j - j0;
 #pragma unroll
@@ -157,7 +182,7 @@ __global__ __attribute__((amdgpu_flat_work_group_size(PANEL_THREADS, PANEL_THREA
         }
       }
     }
-    // no barrier here: the next column writes red_v/red_i only after every thread has
+    // no barrier here: the next column writes red_k only after every thread has
     // passed this column's second barrier, and prow/jrow only after its own first one
   });
 
