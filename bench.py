@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-next3", dest="next3", action="store_false",
+                    help="skip the timing of the mixed-recurrence doubling (ms_mixed_doubling)")
     ap.add_argument("--roofline-kernel", default="iface_gemm",
                     help="profiler category reported in 'roofline' ('auto': the largest summed time in the warmup)")
     ap.add_argument("--no-event-profile", action="store_true",
@@ -133,6 +135,36 @@ def measured_traffic(cat, flops_per_launch, form):
         return float(kv["traffic_bytes"])
     except (KeyError, ValueError, OSError):
         return None
+
+
+def mixed_doubling_measure(ms, ctx, st, buf, results, log):
+    """The paper's doubling with the mixed recurrence (App. A, Eq. recurrence2) and the switch
+    to star products, at one (E, k_par) point of the same workload: time per point, the
+    number of mixed levels, and its T against the fused fold's T for the same point."""
+    import torch
+    j = st["j"]
+    ie = len(j.energies) // 2
+    e = float(j.energies[ie])
+    ms.ms_slices_prepare(ctx, st["miller"], st["bvec"], st["kpar"], st["q"], st["vq"], st["dz"], out=buf)
+    eps_l, eps_r = buf.eps[0].contiguous(), buf.eps[-1].contiguous()
+    ms.ms_mixed_doubling(ctx, buf, e, 1e6)            # warmup (workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    whole, levels = ms.ms_mixed_doubling(ctx, buf, e, 1e6)
+    T, R, no = ms.ms_transmission(ctx, whole, e, eps_l, eps_r)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.sync()
+    t_fold = float(results["fp64"]["T"][ie]) if "fp64" in results else None
+    n, ns = j.n_g, j.n_slices
+    log(f"mixed doubling: {dt:.2f} s per point, {levels} mixed levels")
+    return {"config": f"first timed (gap, k_par) of the workload, E = {e:.6f} Ry, max_cond = 1e6",
+            "seconds_per_point": dt, "mixed_levels": levels, "T": float(T.cpu()[0]),
+            "T_fused_fold": t_fold, "abs_dT": abs(float(T.cpu()[0]) - t_fold) if t_fold is not None else None,
+            "n_open": int(no.cpu()[0]),
+            "note": (f"whole S of {ns + 1} interfaces by a doubling tree: about 9 1/3 N^3 complex MACs per mixed "
+                     "pair, 10 1/3 per star pair and 4/3 N^3 per block for the condition numbers, against "
+                     "3 1/3 N^3 per interface for the fused fold")}
 
 
 def main():
@@ -282,6 +314,8 @@ def main():
         "forms": out_forms,
         "roofline": roof,
     }
+    if args.next3 and args.config == "config3":
+        line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], buf, results, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)

@@ -157,6 +157,27 @@ ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n, ms_prec prec,
 ms_status ms_transmission(ms_ctx ctx, const ms_smat* whole, double energy, const double* eps_left,
                           const double* eps_right, double* T, double* R, int64_t* n_open);
 
+/* The doubling of App. A with the mixed recurrence (after Eq. recurrence2): the
+ * interface blocks (I11, I12, S21, S22) of every S(p,p+1), p = 0..n_slices, with
+ *   I11 = X P^-1, I12 = Y P  (Eq. transfer),  S21, S22 as in ms_slice_smatrix,
+ * are combined pairwise, level after level (pairs formed left to right; an odd last
+ * block moves up unchanged), by
+ *   M = I11(m,n) + I12(m,n) S21(n,k),   I11(m,k) = M I11(n,k),
+ *   I12(m,k) = M I12(n,k) + I12(m,n) S22(n,k),
+ *   S21(m,k) = S21(m,n) + S22(m,n) S21(n,k) M^-1,
+ *   S22(m,k) = S22(m,n) S22(n,k) - S22(m,n) S21(n,k) M^-1 I12(m,n) S22(n,k),
+ * while the 1-norm condition number ||I11||_1 ||I11^-1||_1 of every block stays at
+ * or below max_cond; then every block becomes S by Eq. scatter (S11 = I11^-1,
+ * S12 = -I11^-1 I12) and the remaining levels use the star product (Eq. recurrence).
+ *   max_cond      >= 1; +inf keeps the mixed form to the end, 1 uses S throughout
+ *   whole         the S-matrix of the whole junction (four distinct n_g x n_g blocks)
+ *   mixed_levels  [1] int32 (host): number of levels done in the mixed form
+ * The condition numbers are read back after every mixed level (the call waits for
+ * the stream then).  Workspace: about (6 + 4.5) (n_slices + 1) n_g^2 c128.
+ * Errors: MS_ERR_ARG, MS_ERR_ALLOC; MS_ERR_SINGULAR via ms_ctx_sync. */
+ms_status ms_mixed_doubling(ms_ctx ctx, const ms_slices* slices, double energy, double max_cond, ms_smat* whole,
+                            int32_t* mixed_levels);
+
 /* a4+a5+a6 fused, batched over energies that share the slice data: the
  * interfaces are folded from the right lead to the left one; each step is
  * the star product of S(p,p+1) with the accumulated right part, written so

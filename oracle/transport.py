@@ -35,6 +35,7 @@ import numpy as np
 import scipy.linalg as sla
 
 __all__ = [
+    "recurrence2_step", "cond1", "mixed_doubling",
     "ThresholdError", "SingularError", "kinetic", "slice_hamiltonians", "slice_eigen",
     "prepare", "wavevectors", "overlap", "interface_xy", "interface_smatrix",
     "transfer_matrix", "smatrix_from_transfer", "identity_smatrix", "star", "cascade",
@@ -223,6 +224,63 @@ def recurrence2_cascade(transfers_and_smats) -> dict:
                  tp=a["tp"] @ b["tp"] - a["tp"] @ b["r"] @ minv @ a["i12"] @ b["tp"])
     s11 = np.linalg.inv(a["i11"])
     return dict(t=s11, rp=-s11 @ a["i12"], r=a["r"], tp=a["tp"])
+
+
+def recurrence2_step(a: dict, b: dict) -> dict:
+    """One step of the mixed recurrence of App. A, Eq. (recurrence2), without the h
+    terms: a = (I11, I12, S21, S22)(m,n), b = (I11, I12, S21, S22)(n,k)  ->  (m,k)."""
+    m = a["i11"] + a["i12"] @ b["r"]
+    minv = np.linalg.inv(m)
+    return dict(i11=m @ b["i11"],
+                i12=m @ b["i12"] + a["i12"] @ b["tp"],
+                r=a["r"] + a["tp"] @ b["r"] @ minv,
+                tp=a["tp"] @ b["tp"] - a["tp"] @ b["r"] @ minv @ a["i12"] @ b["tp"])
+
+
+def cond1(a) -> float:
+    """1-norm condition number ||A||_1 ||A^-1||_1 (dense inverse)."""
+    return float(np.linalg.norm(a, 1) * np.linalg.norm(np.linalg.inv(a), 1))
+
+
+def mixed_doubling(prep: dict, energy: float, max_cond: float) -> dict:
+    """Whole S by doubling, as App. A describes after Eq. (recurrence2): the interface
+    blocks (I11, I12, S21, S22) are combined pairwise, level after level, with the mixed
+    recurrence while cond_1(I11) of every block stays at or below max_cond; then every
+    block is turned into S through Eq. (scatter) (S11 = I11^-1, S12 = -I11^-1 I12) and
+    the remaining levels use the star product of Eq. (recurrence).  Pairs are formed
+    left to right; an odd last block moves up a level unchanged.  Returns the whole S
+    and the number of levels done in the mixed form."""
+    _lead_check(energy, prep["eps"][0])
+    _lead_check(energy, prep["eps"][-1])
+    ks = [wavevectors(energy, e) for e in prep["eps"]]
+    blocks = []
+    for p in range(prep["n_slices"] + 1):
+        o = overlap(prep["u"][p], prep["u"][p + 1])
+        i11, i12, _, _ = transfer_matrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+        sm = interface_smatrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+        blocks.append(dict(i11=i11, i12=i12, r=sm["r"], tp=sm["tp"]))
+
+    def to_s(blk):
+        s11 = np.linalg.inv(blk["i11"])
+        return dict(t=s11, rp=-s11 @ blk["i12"], r=blk["r"], tp=blk["tp"])
+
+    levels = 0
+    mixed = max(cond1(b["i11"]) for b in blocks) <= max_cond
+    if not mixed:
+        blocks = [to_s(b) for b in blocks]
+    while len(blocks) > 1:
+        pair = recurrence2_step if mixed else star
+        nxt = [pair(blocks[i], blocks[i + 1]) for i in range(0, len(blocks) - 1, 2)]
+        if len(blocks) % 2:
+            nxt.append(blocks[-1])
+        blocks = nxt
+        if mixed:
+            levels += 1
+            if max(cond1(b["i11"]) for b in blocks) > max_cond:
+                mixed = False
+                blocks = [to_s(b) for b in blocks]
+    whole = to_s(blocks[0]) if mixed else blocks[0]
+    return dict(S=whole, mixed_levels=levels)
 
 
 def _lead_check(energy, eps_lead):

@@ -60,6 +60,7 @@ _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
+_sig("ms_mixed_doubling", [_vp, ctypes.POINTER(MsSlices), _f64, _f64, ctypes.POINTER(MsSmat), ctypes.POINTER(_i32)])
 _sig("ms_debug_profile", [_vp, ctypes.c_uint32])
 _sig("ms_debug_profile_read", [_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp])
 _sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32])
@@ -195,6 +196,18 @@ def ms_star_cascade(ctx: Context, smats, prec="fp64"):
     return whole
 
 
+def ms_mixed_doubling(ctx: Context, slices: Slices, energy: float, max_cond: float = 1e6):
+    """Whole S of the junction at one energy by doubling with the mixed recurrence while
+    cond_1(I11) <= max_cond, then star products.  Returns (t, rp, r, tp), mixed levels."""
+    n = slices.n_g
+    whole = tuple(torch.empty((n, n), dtype=torch.complex128, device=ctx.device) for _ in range(4))
+    w = _smat(whole)
+    lv = _i32(0)
+    _check(ctx.handle, lib.ms_mixed_doubling(ctx.handle, ctypes.byref(slices.c), float(energy), float(max_cond),
+                                             ctypes.byref(w), ctypes.byref(lv)))
+    return whole, int(lv.value)
+
+
 def ms_transmission(ctx: Context, whole, energy: float, eps_left: torch.Tensor, eps_right: torch.Tensor):
     w = _smat(whole)
     T = torch.empty(1, dtype=torch.float64, device=ctx.device)
@@ -324,7 +337,7 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
-           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_transmission",
+           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
            "ms_transmission_batch", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

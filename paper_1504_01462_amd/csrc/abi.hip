@@ -135,7 +135,8 @@ enum {
   WS_KIN = 0, WS_SHIFT, WS_W, WS_U, WS_MISC, WS_K, WS_P, WS_AOP, WS_WG, WS_M,
   WS_JPAIRS = 10, WS_JCOUNT = 11,
   WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
-  WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V
+  WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V,
+  WS_MD_A = 33, WS_MD_B, WS_MD_INV, WS_MD_T, WS_MD_NRM
 };
 
 constexpr int MAX_N = 4096;
@@ -686,12 +687,14 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
       const double2* pq = pb + (int64_t)(p + 1) * n;
       if (!first) {
         MS_TRY(launch_prologue(ctx, n, be, yb, ldy, sY, kq, pq, sk, aop, fp32));
+        // the energies' operands are contiguous, so the batch is one GEMM with M = 2 n be
+        // (no per-energy row padding of the last tile); O^T is shared
         GemmArgs g;
-        g.M = 2 * n; g.N = n; g.K = n;
-        g.A = aop; g.lda = n; g.sA = 2 * nn; g.opA = OP_N;
+        g.M = 2 * n * be; g.N = n; g.K = n;
+        g.A = aop; g.lda = n; g.sA = 0; g.opA = OP_N;
         g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
-        g.C = wg; g.ldc = n; g.sC = 2 * nn;
-        g.batch = be;
+        g.C = wg; g.ldc = n; g.sC = 0;
+        g.batch = 1;
         g.prof = PC_IFACE_GEMM;
         if (fp32) {
           MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
@@ -726,6 +729,187 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
     MS_TRY(launch_batch_T(ctx, n, n_o, be, (const int32_t*)chd, (const double*)end + e0, eps_l, eps_r, yb, ldy, sY,
                           T + e0, R + e0, n_open + e0, point_status + e0));
   }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Doubling with the mixed recurrence (App. A, Eq. recurrence2), then the star product.
+namespace {
+
+struct BlockSet {   // four arrays of n x n blocks: (I11, I12, S21, S22) or (S11, S12, S21, S22)
+  double2 *a11, *a12, *r, *tp;
+};
+
+ms_status mm(ms_ctx ctx, int n, const double2* A, int64_t lda, int64_t sA, const double2* B, int64_t ldb, int64_t sB,
+             double2* C, int64_t ldc, int64_t sC, int batch, double alpha, double beta) {
+  GemmArgs g;
+  g.M = n; g.N = n; g.K = n;
+  g.A = A; g.lda = lda; g.sA = sA;
+  g.B = B; g.ldb = ldb; g.sB = sB;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.batch = batch;
+  g.alpha = make_double2(alpha, 0.0);
+  g.beta = make_double2(beta, 0.0);
+  return zgemm(ctx, g);
+}
+
+}  // namespace
+
+ms_status ms_mixed_doubling(ms_ctx ctx, const ms_slices* slices, double energy, double max_cond, ms_smat* whole,
+                            int32_t* mixed_levels) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  if (!(max_cond >= 1.0)) return fail(ctx, MS_ERR_ARG, "max_cond must be >= 1 (may be +inf)");
+  if (!mixed_levels) return fail(ctx, MS_ERR_ARG, "mixed_levels is NULL");
+  MS_TRY(check_smat(ctx, whole, slices->n_g, "whole"));
+  {
+    const void* wp[4] = {whole->t, whole->rp, whole->r, whole->tp};
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (wp[a] == wp[b]) return fail(ctx, MS_ERR_ARG, "whole blocks must be distinct");
+  }
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
+  const int64_t nn = (int64_t)n * n;
+  const int nb0 = ns + 1;                 // interfaces S(p,p+1), p = 0..ns
+  const int half = nb0 / 2 + 1;           // the most blocks any later level holds
+  void *en, *kb, *pb, *sa, *sb, *aug, *inv, *tmp, *piv, *nrm;
+  MS_TRY(workspace(ctx, WS_EN, sizeof(double), &en));
+  MS_TRY(upload(ctx, en, &energy, sizeof(double)));
+  MS_TRY(workspace(ctx, WS_K, (size_t)nrows * n * sizeof(double2), &kb));
+  MS_TRY(workspace(ctx, WS_P, (size_t)nrows * n * sizeof(double2), &pb));
+  MS_TRY(launch_wavevectors(ctx, n, nrows, 1, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb)));
+  MS_TRY(workspace(ctx, WS_MD_A, (size_t)4 * nb0 * nn * sizeof(double2), &sa));
+  MS_TRY(workspace(ctx, WS_MD_B, (size_t)4 * half * nn * sizeof(double2), &sb));
+  MS_TRY(workspace(ctx, WS_AUG, (size_t)half * 3 * nn * sizeof(double2), &aug));
+  MS_TRY(workspace(ctx, WS_MD_INV, (size_t)half * nn * sizeof(double2), &inv));
+  MS_TRY(workspace(ctx, WS_MD_T, (size_t)5 * half * nn * sizeof(double2), &tmp));
+  MS_TRY(workspace(ctx, WS_PIV, (size_t)half * n * sizeof(int32_t), &piv));
+  MS_TRY(workspace(ctx, WS_MD_NRM, (size_t)2 * nb0 * sizeof(double), &nrm));
+  BlockSet A{c2(sa), c2(sa) + (int64_t)nb0 * nn, c2(sa) + 2 * (int64_t)nb0 * nn, c2(sa) + 3 * (int64_t)nb0 * nn};
+  BlockSet B{c2(sb), c2(sb) + (int64_t)half * nn, c2(sb) + 2 * (int64_t)half * nn, c2(sb) + 3 * (int64_t)half * nn};
+  double2* AUG = c2(aug);
+  double2* INV = c2(inv);
+  double2* T0 = c2(tmp);
+  int32_t* PIV = (int32_t*)piv;
+  double* NRM = (double*)nrm;
+  const double2* ovl = c2(slices->ovl);
+
+  // level 0: S21, S22 in the cancelled form of Eq. scatter, I11 = X P^-1, I12 = Y P (Eq. transfer)
+  for (int q = 0; q < nb0; q += half) {
+    const int bc = std::min(half, nb0 - q);
+    double2 *xc = T0, *yc = T0 + (int64_t)bc * nn, *z = T0 + 2 * (int64_t)bc * nn;
+    MS_TRY(launch_xy(ctx, n, bc, ovl, c2(kb), q, AUG, xc, yc));   // [X | I | Y]
+    MS_TRY(getrf_aug(ctx, AUG, n, 3 * n, 3 * nn, bc, PIV, ctx->d_status, 0));
+    MS_TRY(trsm_upper_aug(ctx, AUG, n, 3 * n, 3 * nn, bc, z, 2 * n, 2 * nn, ctx->d_status, 0));
+    MS_TRY(mm(ctx, n, yc, n, nn, z, 2 * n, 2 * nn, A.r + q * nn, n, nn, bc, 1.0, 0.0));        // Y X^-1
+    MS_TRY(mm(ctx, n, yc, n, nn, z + n, 2 * n, 2 * nn, xc, n, nn, bc, -1.0, 1.0));            // X - Y X^-1 Y
+    MS_TRY(launch_smat_finish(ctx, n, bc, z, xc, c2(pb), q, A.a11 + q * nn, A.a12 + q * nn, A.tp + q * nn));
+    MS_TRY(launch_transfer_blocks(ctx, n, bc, ovl, c2(kb), c2(pb), q, A.a11 + q * nn, A.a12 + q * nn));
+  }
+
+  // max_i cond_1(I11_i) over the nb blocks of S; with `convert`, also S11 = I11^-1 and
+  // S12 = -I11^-1 I12 in place (Eq. scatter)
+  auto cond_pass = [&](BlockSet& S, int nb, bool convert, double* cmax) -> ms_status {
+    for (int q = 0; q < nb; q += half) {
+      const int bc = std::min(half, nb - q);
+      MS_TRY(launch_aug_build(ctx, n, bc, 2 * n, S.a11 + q * nn, nn, nullptr, 0, nullptr, 0, AUG));
+      MS_TRY(getrf_aug(ctx, AUG, n, 2 * n, 2 * nn, bc, PIV, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, AUG, n, 2 * n, 2 * nn, bc, INV, n, nn, ctx->d_status, 0));
+      if (convert) {
+        MS_TRY(mm(ctx, n, INV, n, nn, S.a12 + q * nn, n, nn, T0, n, nn, bc, -1.0, 0.0));
+        MS_TRY(launch_axpby(ctx, nn, bc, 1.0, T0, nn, 0.0, nullptr, 0, S.a12 + q * nn, nn));
+        MS_TRY(launch_axpby(ctx, nn, bc, 1.0, INV, nn, 0.0, nullptr, 0, S.a11 + q * nn, nn));
+      } else {
+        MS_TRY(launch_norm1(ctx, n, bc, S.a11 + q * nn, n, nn, NRM + q));
+        MS_TRY(launch_norm1(ctx, n, bc, INV, n, nn, NRM + nb0 + q));
+      }
+    }
+    if (!convert) {
+      std::vector<double> h(2 * (size_t)nb0);
+      MS_HIP(ctx, hipMemcpyAsync(h.data(), NRM, h.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      double c = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        const double v = h[i] * h[nb0 + i];
+        c = (v == v) ? std::max(c, v) : INFINITY;
+      }
+      *cmax = c;
+    }
+    return MS_OK;
+  };
+
+  BlockSet* cur = &A;
+  BlockSet* nxt = &B;
+  int nb = nb0, levels = 0;
+  double cmax = 0.0;
+  MS_TRY(cond_pass(*cur, nb, false, &cmax));
+  bool mixed = cmax <= max_cond;
+  if (!mixed) MS_TRY(cond_pass(*cur, nb, true, nullptr));
+  while (nb > 1) {
+    const int np = nb / 2;
+    const int64_t s2 = 2 * nn;
+    BlockSet& X = *cur;
+    BlockSet& Y = *nxt;
+    if (mixed) {   // Eq. recurrence2: a = block 2i, b = block 2i+1
+      double2 *W = T0, *Q = T0 + (int64_t)np * nn, *QM = T0 + 2 * (int64_t)np * nn;
+      MS_TRY(launch_aug_build(ctx, n, np, 2 * n, X.a11, s2, nullptr, 0, nullptr, 0, AUG));       // [I11_a | I]
+      MS_TRY(mm(ctx, n, X.a12, n, s2, X.r + nn, n, s2, AUG, 2 * n, s2, np, 1.0, 1.0));          // M
+      MS_TRY(mm(ctx, n, X.a12, n, s2, X.tp + nn, n, s2, W, n, nn, np, 1.0, 0.0));               // W = I12_a S22_b
+      MS_TRY(launch_axpby(ctx, nn, np, 1.0, W, nn, 0.0, nullptr, 0, Y.a12, nn));
+      MS_TRY(mm(ctx, n, AUG, 2 * n, s2, X.a12 + nn, n, s2, Y.a12, n, nn, np, 1.0, 1.0));       // I12 = M I12_b + W
+      MS_TRY(mm(ctx, n, AUG, 2 * n, s2, X.a11 + nn, n, s2, Y.a11, n, nn, np, 1.0, 0.0));       // I11 = M I11_b
+      MS_TRY(getrf_aug(ctx, AUG, n, 2 * n, s2, np, PIV, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, AUG, n, 2 * n, s2, np, INV, n, nn, ctx->d_status, 0));         // M^-1
+      MS_TRY(mm(ctx, n, X.tp, n, s2, X.r + nn, n, s2, Q, n, nn, np, 1.0, 0.0));                 // S22_a S21_b
+      MS_TRY(mm(ctx, n, Q, n, nn, INV, n, nn, QM, n, nn, np, 1.0, 0.0));                        // ... M^-1
+      MS_TRY(launch_axpby(ctx, nn, np, 1.0, X.r, s2, 1.0, QM, nn, Y.r, nn));                    // S21
+      MS_TRY(mm(ctx, n, X.tp, n, s2, X.tp + nn, n, s2, Y.tp, n, nn, np, 1.0, 0.0));
+      MS_TRY(mm(ctx, n, QM, n, nn, W, n, nn, Y.tp, n, nn, np, -1.0, 1.0));                      // S22
+    } else {       // Eq. recurrence: the star product of a = block 2i and b = block 2i+1
+      double2 *Z = T0, *G = T0 + 2 * (int64_t)np * nn, *H = T0 + 3 * (int64_t)np * nn,
+              *V = T0 + 4 * (int64_t)np * nn;
+      MS_TRY(launch_aug_build(ctx, n, np, 3 * n, nullptr, 0, X.a11, s2, X.a12, s2, AUG));        // [I | t_a | rp_a]
+      MS_TRY(mm(ctx, n, X.a12, n, s2, X.r + nn, n, s2, AUG, 3 * n, 3 * nn, np, -1.0, 1.0));     // F
+      MS_TRY(getrf_aug(ctx, AUG, n, 3 * n, 3 * nn, np, PIV, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, AUG, n, 3 * n, 3 * nn, np, Z, 2 * n, s2, ctx->d_status, 0));  // [F^-1 t_a | F^-1 rp_a]
+      MS_TRY(mm(ctx, n, X.tp, n, s2, X.r + nn, n, s2, G, n, nn, np, 1.0, 0.0));                 // G = tp_a r_b
+      MS_TRY(mm(ctx, n, X.a11 + nn, n, s2, Z, 2 * n, s2, Y.a11, n, nn, np, 1.0, 0.0));          // t
+      MS_TRY(launch_axpby(ctx, nn, np, 1.0, X.r, s2, 0.0, nullptr, 0, Y.r, nn));
+      MS_TRY(mm(ctx, n, G, n, nn, Z, 2 * n, s2, Y.r, n, nn, np, 1.0, 1.0));                     // r
+      MS_TRY(mm(ctx, n, X.a11 + nn, n, s2, Z + n, 2 * n, s2, H, n, nn, np, 1.0, 0.0));
+      MS_TRY(launch_axpby(ctx, nn, np, 1.0, X.a12 + nn, s2, 0.0, nullptr, 0, Y.a12, nn));
+      MS_TRY(mm(ctx, n, H, n, nn, X.tp + nn, n, s2, Y.a12, n, nn, np, 1.0, 1.0));              // rp
+      MS_TRY(launch_axpby(ctx, nn, np, 1.0, X.tp, s2, 0.0, nullptr, 0, V, nn));
+      MS_TRY(mm(ctx, n, G, n, nn, Z + n, 2 * n, s2, V, n, nn, np, 1.0, 1.0));
+      MS_TRY(mm(ctx, n, V, n, nn, X.tp + nn, n, s2, Y.tp, n, nn, np, 1.0, 0.0));                // tp
+    }
+    if (nb & 1) {   // the odd last block moves up unchanged
+      const int64_t o = (int64_t)(nb - 1) * nn, d = (int64_t)np * nn;
+      MS_TRY(launch_axpby(ctx, nn, 1, 1.0, X.a11 + o, 0, 0.0, nullptr, 0, Y.a11 + d, 0));
+      MS_TRY(launch_axpby(ctx, nn, 1, 1.0, X.a12 + o, 0, 0.0, nullptr, 0, Y.a12 + d, 0));
+      MS_TRY(launch_axpby(ctx, nn, 1, 1.0, X.r + o, 0, 0.0, nullptr, 0, Y.r + d, 0));
+      MS_TRY(launch_axpby(ctx, nn, 1, 1.0, X.tp + o, 0, 0.0, nullptr, 0, Y.tp + d, 0));
+    }
+    nb = np + (nb & 1);
+    std::swap(cur, nxt);
+    if (mixed) {
+      ++levels;
+      MS_TRY(cond_pass(*cur, nb, false, &cmax));
+      if (cmax > max_cond) {
+        mixed = false;
+        MS_TRY(cond_pass(*cur, nb, true, nullptr));
+      }
+    }
+  }
+  if (mixed) MS_TRY(cond_pass(*cur, 1, true, nullptr));
+  const size_t bytes = nn * sizeof(double2);
+  MS_HIP(ctx, hipMemcpyAsync(whole->t, cur->a11, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(whole->rp, cur->a12, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(whole->r, cur->r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(whole->tp, cur->tp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  *mixed_levels = levels;
   return MS_OK;
 }
 

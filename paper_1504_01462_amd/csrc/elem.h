@@ -25,5 +25,13 @@ ms_status launch_to_c64(ms_ctx ctx, int64_t count, const double2* in, float2* ou
 ms_status launch_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open,
                                double* tbar, double* per_channel);
 ms_status launch_nonfinite_scan(ms_ctx ctx, int64_t count, const double2* v, int32_t* status);
+// mixed doubling (App. A, Eq. recurrence2)
+ms_status launch_transfer_blocks(ms_ctx ctx, int n, int nb, const double2* ovl, const double2* kbuf,
+                                 const double2* pbuf, int p0, double2* I11, double2* I12);
+ms_status launch_aug_build(ms_ctx ctx, int n, int nb, int w, const double2* src, int64_t s_src, const double2* src2,
+                           int64_t s_src2, const double2* src3, int64_t s_src3, double2* aug);
+ms_status launch_axpby(ms_ctx ctx, int64_t nn, int nb, double alpha, const double2* a, int64_t s_a, double beta,
+                       const double2* c, int64_t s_c, double2* out, int64_t s_o);
+ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, int64_t s, double* out);
 
 }  // namespace ms

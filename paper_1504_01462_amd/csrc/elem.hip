@@ -282,6 +282,76 @@ __global__ void k_kpar_average(int64_t n_k, int64_t n_e, const double* T, const 
   per_channel[e] = so > 0 ? st / (double)so : 0.0;
 }
 
+// Transfer blocks of App. A, Eq. (transfer): I11 = X P^-1, I12 = Y P for interfaces
+// p0 + b, with X, Y as in k_xy and P = diag e^{i k^{p+1} dz_{p+1}}.
+__global__ void k_transfer_blocks(int n, const double2* ovl, const double2* kbuf, const double2* pbuf, int p0,
+                                  double2* I11, double2* I12) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const int64_t nn = (int64_t)n * n;
+  const double2 o = ovl[(p0 + b) * nn + idx];
+  const double2 kp = kbuf[(p0 + b) * n + i], kq = kbuf[(p0 + b + 1) * n + j];
+  const double2 h = cdiv(o, make_double2(2.0 * kp.x, 2.0 * kp.y));
+  const double2 x = cmul(h, cadd(kp, kq)), y = cmul(h, csub(kp, kq));
+  const double2 P = pbuf[(p0 + b + 1) * n + j];
+  I11[b * nn + idx] = cdiv(x, P);
+  I12[b * nn + idx] = cmul(y, P);
+}
+
+// aug[b] (n x w, w = 2n or 3n) = [first | I | ...]: first = src[b] (stride s_src) or, when
+// src is null, the identity; the block after it is the identity when ident2 is set,
+// else copied from src2[b]; a third block (w = 3n) is copied from src3[b].
+__global__ void k_aug_build(int n, int w, const double2* src, int64_t s_src, const double2* src2, int64_t s_src2,
+                            const double2* src3, int64_t s_src3, double2* aug) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  double2* A = aug + b * (int64_t)n * w + (int64_t)i * w;
+  const double2 id = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  A[j] = src ? src[b * s_src + idx] : id;
+  A[n + j] = src2 ? src2[b * s_src2 + idx] : id;
+  if (w == 3 * n) A[2 * n + j] = src3[b * s_src3 + idx];
+}
+
+// out[b] = alpha a[b] + beta c[b] (element strides per batch entry)
+__global__ void k_axpby(int64_t nn, double alpha, const double2* a, int64_t s_a, double beta, const double2* c,
+                        int64_t s_c, double2* out, int64_t s_o) {
+  const int64_t b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn) return;
+  const double2 x = a[b * s_a + idx];
+  double2 v = make_double2(alpha * x.x, alpha * x.y);
+  if (c) {
+    const double2 y = c[b * s_c + idx];
+    v.x += beta * y.x;
+    v.y += beta * y.y;
+  }
+  out[b * s_o + idx] = v;
+}
+
+// 1-norm (largest column sum of |a_ij|) of each n x n matrix (row stride ld, batch stride s)
+__global__ __launch_bounds__(256) void k_norm1(int n, const double2* A, int64_t ld, int64_t s, double* out) {
+  __shared__ double red[256];
+  const int64_t b = blockIdx.x;
+  const double2* M = A + b * s;
+  double best = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) sum += hypot(M[(int64_t)i * ld + j].x, M[(int64_t)i * ld + j].y);
+    best = fmax(best, sum);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
 inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
 
 }  // namespace
@@ -367,6 +437,33 @@ ms_status launch_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double
 ms_status launch_nonfinite_scan(ms_ctx ctx, int64_t count, const double2* v, int32_t* status) {
   hipLaunchKernelGGL(k_nonfinite_scan, dim3(blocks(count)), dim3(256), 0, ctx->stream, count, v, status);
   return check_launch(ctx, "nonfinite scan");
+}
+
+
+ms_status launch_transfer_blocks(ms_ctx ctx, int n, int nb, const double2* ovl, const double2* kbuf,
+                                 const double2* pbuf, int p0, double2* I11, double2* I12) {
+  hipLaunchKernelGGL(k_transfer_blocks, dim3(blocks((int64_t)n * n), nb), dim3(256), 0, ctx->stream, n, ovl, kbuf,
+                     pbuf, p0, I11, I12);
+  return check_launch(ctx, "transfer blocks");
+}
+
+ms_status launch_aug_build(ms_ctx ctx, int n, int nb, int w, const double2* src, int64_t s_src, const double2* src2,
+                           int64_t s_src2, const double2* src3, int64_t s_src3, double2* aug) {
+  hipLaunchKernelGGL(k_aug_build, dim3(blocks((int64_t)n * n), nb), dim3(256), 0, ctx->stream, n, w, src, s_src, src2,
+                     s_src2, src3, s_src3, aug);
+  return check_launch(ctx, "augmented matrix");
+}
+
+ms_status launch_axpby(ms_ctx ctx, int64_t nn, int nb, double alpha, const double2* a, int64_t s_a, double beta,
+                       const double2* c, int64_t s_c, double2* out, int64_t s_o) {
+  hipLaunchKernelGGL(k_axpby, dim3(blocks(nn), nb), dim3(256), 0, ctx->stream, nn, alpha, a, s_a, beta, c, s_c, out,
+                     s_o);
+  return check_launch(ctx, "axpby");
+}
+
+ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, int64_t s, double* out) {
+  hipLaunchKernelGGL(k_norm1, dim3(nb), dim3(256), 0, ctx->stream, n, A, ld, s, out);
+  return check_launch(ctx, "1-norm");
 }
 
 }  // namespace ms

@@ -12,6 +12,7 @@
 // with 8 waves otherwise).  Global->LDS staging is register double-buffered
 // (the next K-slab is fetched while the current one is used).
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -279,9 +280,15 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
             (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K + (double)p.K * g.N) +
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
             true);
-  const bool big = g.M >= 128 && g.N >= 128;
+  bool big = g.M >= 128 && g.N >= 128;
+  static const int tile_env = [] {   // MS_GEMM_TILE=64: 64 x 64 tiles (two workgroups per CU) everywhere
+    const char* e = getenv("MS_GEMM_TILE");
+    return e ? atoi(e) : 0;
+  }();
+  if (tile_env == 64) big = false;
   if (g.prof == PC_LU_UPDATE)   // one kernel for every trailing update, whatever its height
-    return launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof);
+    return tile_env == 64 ? launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof)
+                          : launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof);
   if (g.prof == PC_IFACE_GEMM)
     return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
   return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);

@@ -61,3 +61,33 @@ def test_config3_fp32_form(ms, full):
     print(f"\nconfig3 FP32-MFMA form: max |dT| vs FP64 over {T32.size} points = {dT:.3e}")
     assert dT < 1e-3
     assert np.max(np.abs(T32 + R32 - no32)) < 1e-3
+
+
+def test_config3_slices_sampled_against_oracle(ms, full):
+    """a1-a3 at full size on sampled slices: eigenvalues against the oracle's dense
+    eigensolver, eigen-residuals, and the stored overlaps against U^p^dagger U^(p+1)
+    formed from the returned eigenvectors."""
+    import oracle as orc
+    import torch
+    j, ctx = full["j"], full["ctx"]
+    p0 = full["pts"][0]
+    inp = msgen.junction_inputs(j, j.kpars[p0["k_index"]])
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    ctx.sync()
+    kin = orc.kinetic(inp["miller"], inp["bvec"], inp["kpar"])
+    eps = s.eps.cpu().numpy()
+    for p in (0, 137, 398):   # slice index p is the paper's slice p+1
+        h = orc.slice_hamiltonians(kin, inp["vq"][p:p + 1], inp["q_of_ij"])[0]
+        lam_ref, _ = orc.slice_eigen(h[None])
+        lam_ref = lam_ref[0]
+        scale = np.max(np.abs(lam_ref))
+        assert np.max(np.abs(eps[p + 1] - lam_ref)) < 1e-11 * scale, p
+        u = s.evec[p].cpu().numpy()
+        res = np.linalg.norm(h @ u - u * eps[p + 1][None, :]) / np.linalg.norm(h)
+        assert res < 1e-12, (p, res)
+        assert np.linalg.norm(u.conj().T @ u - np.eye(u.shape[0])) < 1e-11
+        un = s.evec[p + 1].cpu().numpy()
+        o = s.ovl[p + 1].cpu().numpy()
+        assert np.max(np.abs(o - u.conj().T @ un)) < 1e-12, p
+    del s
+    torch.cuda.empty_cache()

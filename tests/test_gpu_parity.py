@@ -255,3 +255,111 @@ def test_deterministic(ms, ctx, c1):
     b = _np(ms.ms_transmission_batch(ctx, s2, j.energies)[0])
     ctx.sync()
     assert np.array_equal(a, b)
+
+
+def test_eigensolver_warm_start_and_lu_lookahead_do_not_change_T(ms, ctx):
+    """The warm-started eigensolver (default) against cold starts everywhere, and the
+    look-ahead LU against the default schedule, at config2 size: T and R agree to
+    rounding (the eigenvector gauge differs, T does not)."""
+    import os
+    j = msgen.config2("AA", n_g=300, n_slices=160)
+    inp = msgen.junction_inputs(j, j.kpars[0])
+    es = j.energies[::8]
+    out = {}
+    for name, env in (("warm", {}), ("cold", {"MS_EIG_WARM_STRIDE": "0"}),
+                      ("lookahead", {"MS_LU_LOOKAHEAD": "1"})):
+        saved = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            s = ms.prepare_from_inputs(ctx, inp)
+            T, R, no, st = (_np(x) for x in ms.ms_transmission_batch(ctx, s, es, "fp64"))
+            ctx.sync()
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        assert np.all(st == 0), name
+        out[name] = (T, R)
+    for name in ("cold", "lookahead"):
+        assert np.max(np.abs(out[name][0] - out["warm"][0])) < 1e-10, name
+        assert np.max(np.abs(out[name][1] - out["warm"][1])) < 1e-10, name
+
+
+# ------------------------------------------------------------------ mixed doubling ---------
+def _small_junction():
+    j = msgen.config1()
+    j.dz = np.full(8, 2.0 / 8)
+    inp = msgen.junction_inputs(j, j.kpars[0], 13)
+    return orc.prepare(inp)
+
+
+def _mixed_levels_conds(prep, e, levels):
+    """cond_1(I11) after each of the first `levels` mixed doubling levels (oracle steps)."""
+    ks = [orc.wavevectors(e, x) for x in prep["eps"]]
+    b = []
+    for p in range(prep["n_slices"] + 1):
+        o = orc.overlap(prep["u"][p], prep["u"][p + 1])
+        i11, i12, _, _ = orc.transfer_matrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+        sm = orc.interface_smatrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+        b.append(dict(i11=i11, i12=i12, r=sm["r"], tp=sm["tp"]))
+    out = [max(orc.cond1(x["i11"]) for x in b)]
+    for _ in range(levels):
+        nxt = [orc.recurrence2_step(b[i], b[i + 1]) for i in range(0, len(b) - 1, 2)]
+        if len(b) % 2:
+            nxt.append(b[-1])
+        b = nxt
+        out.append(max(orc.cond1(x["i11"]) for x in b))
+    return out
+
+
+@pytest.mark.parametrize("which", ["pure_s", "switch", "mixed_to_end"])
+def test_mixed_doubling_matches_oracle(ms, ctx, which):
+    """Doubling with the mixed recurrence (App. A, Eq. recurrence2) and the switch to
+    star products: whole S against the oracle's mixed doubling and the plain left fold,
+    and the number of mixed levels against the oracle's, for thresholds placed between
+    the condition numbers the oracle sees (so both sides take the same decisions)."""
+    prep = _small_junction()
+    e = 0.55
+    conds = _mixed_levels_conds(prep, e, 4)
+    if which == "pure_s":
+        max_cond = 1.0
+    elif which == "switch":
+        max_cond = float(np.sqrt(conds[1] * conds[2]))
+    else:
+        max_cond = float("inf")
+    ref = orc.mixed_doubling(prep, e, max_cond)
+    fold = orc.transmission(prep, e)["S"]
+    s = slices_from_oracle(ms, prep)
+    whole, levels = ms.ms_mixed_doubling(ctx, s, e, max_cond)
+    ctx.sync()
+    assert levels == ref["mixed_levels"], (levels, ref["mixed_levels"], conds)
+    for b, key in zip(whole, ("t", "rp", "r", "tp")):
+        assert rel_err(_np(b), ref["S"][key]) < 1e-11, key
+        assert rel_err(_np(b), fold[key]) < 1e-10, key
+
+
+def test_mixed_doubling_config1_transmission(ms, ctx, c1):
+    """config1 (24 slices of 0.25 bohr, N_G = 37) with a 1e6 threshold: T and R of the
+    whole S against the oracle at several energies."""
+    _, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    for e in (0.3, 1.1, 3.3):
+        whole, levels = ms.ms_mixed_doubling(ctx, s, e, 1e6)
+        T, R, no = ms.ms_transmission(ctx, whole, e, to_dev(prep["eps"][0]), to_dev(prep["eps"][-1]))
+        ctx.sync()
+        ref = orc.transmission(prep, e)
+        assert 0 <= levels <= int(np.ceil(np.log2(prep["n_slices"] + 1)))
+        assert abs(_np(T)[0] - ref["T"]) < 1e-9, (e, _np(T)[0], ref["T"])
+        assert abs(_np(R)[0] - ref["R"]) < 1e-9
+        assert int(_np(no)[0]) == ref["n_open"]
+
+
+def test_mixed_doubling_argument_errors(ms, ctx, c1):
+    _, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    with pytest.raises(ms.MSError):
+        ms.ms_mixed_doubling(ctx, s, 0.5, 0.5)
+    with pytest.raises(ms.MSError):
+        ms.ms_mixed_doubling(ctx, s, float("nan"), 1e6)

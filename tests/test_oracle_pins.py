@@ -249,6 +249,51 @@ def test_recurrence2_matches_recurrence():
         assert np.max(np.abs(a[key] - b[key])) < 1e-10 * max(1.0, np.max(np.abs(b[key])))
 
 
+def test_mixed_doubling_matches_star_cascade():
+    """Doubling with the mixed recurrence until cond_1(I11) passes a threshold, then the
+    star product (App. A after Eq. recurrence2), gives the whole S of the plain left fold
+    of star products, whatever the threshold: 1 (pure S from the start), a moderate one
+    (a switch part-way) and none (mixed to the end)."""
+    _, inp = _c1(n_g=13, n_slices=8, slab=2.0)
+    prep = orc.prepare(inp)
+    e = 0.55
+    ref = orc.transmission(prep, e)["S"]
+    nb = prep["n_slices"] + 1
+    full_levels = int(np.ceil(np.log2(nb)))
+    seen = set()
+    for max_cond, levels in ((1.0, 0), (None, None), (np.inf, full_levels)):
+        if max_cond is None:    # a threshold between the conds of levels 1 and 2
+            ks = [orc.wavevectors(e, x) for x in prep["eps"]]
+            b = []
+            for p in range(nb):
+                o = orc.overlap(prep["u"][p], prep["u"][p + 1])
+                i11, i12, _, _ = orc.transfer_matrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+                sm = orc.interface_smatrix(o, ks[p], ks[p + 1], prep["dz"][p + 1])
+                b.append(dict(i11=i11, i12=i12, r=sm["r"], tp=sm["tp"]))
+            c = []
+            for _ in range(2):
+                nxt = [orc.recurrence2_step(b[i], b[i + 1]) for i in range(0, len(b) - 1, 2)]
+                if len(b) % 2:
+                    nxt.append(b[-1])
+                b = nxt
+                c.append(max(orc.cond1(x["i11"]) for x in b))
+            assert c[1] > c[0] * 1.5
+            max_cond, levels = float(np.sqrt(c[0] * c[1])), 2
+        out = orc.mixed_doubling(prep, e, max_cond)
+        assert out["mixed_levels"] == levels, (max_cond, out["mixed_levels"])
+        seen.add(out["mixed_levels"])
+        for key in ("t", "rp", "r", "tp"):
+            assert np.max(np.abs(out["S"][key] - ref[key])) < 1e-10 * max(1.0, np.max(np.abs(ref[key]))), key
+    assert len(seen) == 3
+
+
+def test_cond1_pins():
+    """cond_1 of a diagonal matrix is max|d| / min|d|; of a unitary permutation, 1."""
+    d = np.array([3.0, -0.5, 2j, 8.0])
+    assert abs(orc.cond1(np.diag(d)) - 16.0) < 1e-12
+    assert abs(orc.cond1(np.eye(5)[[3, 0, 4, 1, 2]]) - 1.0) < 1e-12
+
+
 def test_slice_splitting():
     """One slice of thickness 2 dz is the same as two identical slices of dz."""
     j, inp = _c1(n_slices=12)
