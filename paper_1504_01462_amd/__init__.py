@@ -1,7 +1,7 @@
 """Python binding of the MI355X plane-wave multiple-scattering transport library.
 
 Argument marshalling only: every step runs in the HIP kernels of ``libms.so``
-(built from ``csrc/`` by ``paper_1504_01462_amd.build``).  PyTorch supplies
+(built from ``csrc/`` by ``paper_1504_01462_amd/build.py``).  PyTorch supplies
 device memory and the stream.  The functions carry the names of the C entry
 points declared in ``include/ms.h`` and ``include/ms_debug.h``.
 
@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libms.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library with "
-                      "`python -m paper_1504_01462_amd.build` (or __graft_entry__.build())")
+                      "`python paper_1504_01462_amd/build.py` (or __graft_entry__.build())")
 
 lib = ctypes.CDLL(LIB_PATH)
 
