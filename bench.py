@@ -4,15 +4,16 @@
 Workload (default): the side-contact overlap junction -- rectangular 4.65 x 40
 bohr cell, two graphene-like Gaussian-well sheets overlapping 15 bohr along
 the transport direction, N_G = 1200 plane waves, 400 slices of 0.05 bohr,
-free-electron leads.  One step = one (vacuum gap, k_par) pair of the 3 x 8
-grid with its 32 energies: slice Hamiltonians, eigenpairs and overlaps
-(E-independent), the fused slice-S / star-product fold for all 32 energies,
-T and R per point, and the k_par average.  Inputs are seeded and synthetic,
-uploaded to HBM before the timed region.
+free-electron leads, 32 energies at each of 8 k_par for 3 vacuum gaps.  One
+step = two k_par of one gap (64 points): slice Hamiltonians, eigenpairs and
+overlaps (E-independent) of each, the fused slice-S / star-product fold of
+all 64 points in one batch, T and R per point, and the k_par average.
+Inputs are seeded and synthetic, uploaded to HBM before the timed region.
 
 The steps run twice, in FP64 and in the FP32-MFMA form, over the same
 (gap, k_par) pairs; the FP32 number is the headline only when its largest
-|dT| against the FP64 run stays below 1e-6.
+|dT| against the FP64 run stays below 1e-6.  One point of the workload is
+also solved with the paper's mixed transfer/scattering doubling.
 
     python bench.py [--steps K] [--warmup W] [--config config3|config2|config1]
 Prints one JSON line.
@@ -42,6 +43,8 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kpar-per-step", type=int, default=2,
+                    help="k_par values of one junction folded together in one batch per step")
     ap.add_argument("--no-next3", dest="next3", action="store_false",
                     help="skip the timing of the mixed-recurrence doubling (ms_mixed_doubling)")
     ap.add_argument("--roofline-kernel", default="iface_gemm",
@@ -57,11 +60,11 @@ def workload(name):
         combos = [(gap, ik) for gap in (6.3, 5.0, 7.5) for ik in range(8)]
         make = lambda gap: msgen.config3(gap, "AA")
         desc = ("side-contact overlap junction: 4.65x40 bohr cell, two Gaussian-well sheets overlapping 15 bohr, "
-                "N_G=1200, 400 slices x 0.05 bohr, 32 energies x one (gap, k_par) per step")
+                "N_G=1200, 400 slices x 0.05 bohr, 32 energies per k_par, 8 k_par x 3 gaps")
     elif name == "config2":
         combos = [(reg, ik) for reg in ("AA", "AB") for ik in range(16)]
         make = lambda reg: msgen.config2(reg)
-        desc = "bilayer-gap junction: 2x2 hexagonal supercell, N_G=300, 160 slices x 0.1 bohr, 64 energies x one k_par per step"
+        desc = "bilayer-gap junction: 2x2 hexagonal supercell, N_G=300, 160 slices x 0.1 bohr, 64 energies per k_par"
     else:
         combos = [(None, 0)]
         make = lambda _: msgen.config1()
@@ -143,9 +146,10 @@ def mixed_doubling_measure(ms, ctx, st, buf, results, log):
     number of mixed levels, and its T against the fused fold's T for the same point."""
     import torch
     j = st["j"]
+    kk = st["ks"][0]
     ie = len(j.energies) // 2
     e = float(j.energies[ie])
-    ms.ms_slices_prepare(ctx, st["miller"], st["bvec"], st["kpar"], st["q"], st["vq"], st["dz"], out=buf)
+    ms.ms_slices_prepare(ctx, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"], out=buf)
     eps_l, eps_r = buf.eps[0].contiguous(), buf.eps[-1].contiguous()
     ms.ms_mixed_doubling(ctx, buf, e, 1e6)            # warmup (workspace)
     torch.cuda.synchronize()
@@ -179,28 +183,39 @@ def main():
     import paper_1504_01462_amd as ms
 
     combos, make, desc = workload(args.config)
+    # a step takes kps consecutive k_par of one junction (one batch of kps x n_e points)
+    kps = max(1, args.kpar_per_step)
+    groups = []
+    for key, ik in combos:
+        if groups and groups[-1][0] == key and len(groups[-1][1]) < kps:
+            groups[-1][1].append(ik)
+        else:
+            groups.append((key, [ik]))
     nsteps = args.warmup + args.steps
-    sel = [combos[i % len(combos)] for i in range(nsteps)]
+    sel = [groups[i % len(groups)] for i in range(nsteps)]
     ctx = ms.Context(0)
     dev = ctx.device
     # seeded inputs, uploaded to HBM before timing
     cache = {}
     staged = []
-    for key, ik in sel:
+    for key, iks in sel:
         if key not in cache:
             cache[key] = make(key)
         j = cache[key]
-        inp = msgen.junction_inputs(j, j.kpars[ik])
-        staged.append(dict(
-            j=j, key=key, ik=ik,
-            miller=torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev),
-            q=torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev),
-            vq=torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev),
-            dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
-            bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
+        ks = []
+        for ik in iks:
+            inp = msgen.junction_inputs(j, j.kpars[ik])
+            ks.append(dict(
+                ik=ik,
+                miller=torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev),
+                q=torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev),
+                vq=torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev),
+                dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
+                bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
+        staged.append(dict(j=j, key=key, iks=list(iks), ks=ks))
     j0 = staged[0]["j"]
     n_e, n_k = len(j0.energies), len(j0.kpars)
-    buf = ms.Slices.empty(j0.n_g, j0.n_slices, staged[0]["dz"], dev)
+    bufs = [ms.Slices.empty(j0.n_g, j0.n_slices, staged[0]["ks"][0]["dz"], dev) for _ in range(kps)]
     t_store = torch.zeros((n_k, n_e), dtype=torch.float64, device=dev)
     no_store = torch.zeros((n_k, n_e), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
@@ -208,19 +223,24 @@ def main():
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    log(f"inputs staged: {len(staged)} steps of {args.config}")
+    log(f"inputs staged: {len(staged)} steps of {args.config}, {kps} k_par per step")
 
     def run(steps, prec):
-        """One step: slice eigenproblems and overlaps, the fused fold over the energies, T and R,
-        the k_par average -- all on the current stream, one after the other."""
+        """One step: the slice eigenproblems and overlaps of each of its k_par, the fused fold
+        over all their energies in one batch, T and R, the k_par average -- all on the current
+        stream, one after the other."""
         outs = []
         for i, st in enumerate(steps):
-            ms.ms_slices_prepare(ctx, st["miller"], st["bvec"], st["kpar"], st["q"], st["vq"], st["dz"], out=buf)
-            T, R, no, status = ms.ms_transmission_batch(ctx, buf, st["j"].energies, prec)
-            t_store[st["ik"]].copy_(T)
-            no_store[st["ik"]].copy_(no)
+            m = len(st["ks"])
+            for b, kk in zip(bufs, st["ks"]):
+                ms.ms_slices_prepare(ctx, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"], out=b)
+            es = np.tile(np.asarray(st["j"].energies, dtype=np.float64), (m, 1))
+            T, R, no, status = ms.ms_transmission_multi(ctx, bufs[:m], es, prec)
+            for r, ik in enumerate(st["iks"]):
+                t_store[ik].copy_(T[r])
+                no_store[ik].copy_(no[r])
             ms.ms_kpar_average(ctx, t_store, no_store)
-            outs.append((T, R, no, status))
+            outs.append((T.reshape(-1), R.reshape(-1), no.reshape(-1), status.reshape(-1)))
             log(f"{prec} step {i + 1}/{len(steps)} enqueued")
         return outs
 
@@ -309,13 +329,14 @@ def main():
         "dtype": "c64-mfma+f64" if head == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {desc}", "n_g": j0.n_g, "n_slices": j0.n_slices,
-                   "energies_per_step": n_e, "steps_over": [[str(st["key"]), st["ik"]] for st in staged],
+                   "energies_per_kpar": n_e, "kpar_per_step": kps,
+                   "steps_over": [[str(st["key"]), st["iks"]] for st in staged],
                    "headline_form": head},
         "forms": out_forms,
         "roofline": roof,
     }
     if args.next3 and args.config == "config3":
-        line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], buf, results, log)
+        line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)

@@ -193,6 +193,17 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
                                 const double* energies, ms_prec prec, double* T, double* R,
                                 int64_t* n_open, int32_t* point_status);
 
+/* ms_transmission_batch for n_k slice sets at once (e.g. several k_par of one junction),
+ * n_e energies each: slices [n_k] (equal n_g and n_slices), energies [n_k][n_e] (host),
+ * T, R [n_k][n_e] f64, n_open [n_k][n_e] int64, point_status [n_k][n_e] int32 (device).
+ * The LU factorisations and back substitutions of all n_k * n_e points run as one batch
+ * per interface, which amortises their latency-bound panel steps over more matrices.
+ * Errors: MS_ERR_ARG (sizes differ between sets, nulls, non-finite energies),
+ * MS_ERR_UNSUPPORTED (n_k > 65535), MS_ERR_ALLOC. */
+ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices, int64_t n_e,
+                                const double* energies, ms_prec prec, double* T, double* R, int64_t* n_open,
+                                int32_t* point_status);
+
 /* a7: average over the k_par mesh (Sec. II.B, Eq. T1_d):
  *   tbar[e]        = (1/n_k) sum_k T[k][e]
  *   per_channel[e] = sum_k T[k][e] / sum_k n_open[k][e]   (0 when no channel is open)

@@ -59,6 +59,7 @@ _sig("ms_slice_smatrix", [_vp, ctypes.POINTER(MsSlices), _f64, _i64, _i64, ctype
 _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER(MsSmat)])
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
+_sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 _sig("ms_mixed_doubling", [_vp, ctypes.POINTER(MsSlices), _f64, _f64, ctypes.POINTER(MsSmat), ctypes.POINTER(_i32)])
 _sig("ms_debug_profile", [_vp, ctypes.c_uint32])
@@ -233,6 +234,24 @@ def ms_transmission_batch(ctx: Context, slices: Slices, energies, prec="fp64"):
     return T, R, no, st
 
 
+def ms_transmission_multi(ctx: Context, slices_list, energies, prec="fp64"):
+    """Several slice sets of equal sizes, energies [n_k][n_e]: returns T, R, n_open,
+    status as [n_k][n_e] device tensors."""
+    e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64))
+    n_k = len(slices_list)
+    if e.ndim != 2 or e.shape[0] != n_k:
+        raise ValueError("energies must be [n_k][n_e]")
+    n_e = e.shape[1]
+    arr = (MsSlices * n_k)(*[s.c for s in slices_list])
+    T = torch.empty((n_k, n_e), dtype=torch.float64, device=ctx.device)
+    R = torch.empty((n_k, n_e), dtype=torch.float64, device=ctx.device)
+    no = torch.empty((n_k, n_e), dtype=torch.int64, device=ctx.device)
+    st = torch.empty((n_k, n_e), dtype=torch.int32, device=ctx.device)
+    _check(ctx.handle, lib.ms_transmission_multi(ctx.handle, n_k, arr, n_e, e.ctypes.data_as(ctypes.c_void_p),
+                                                 _PREC[prec], _ptr(T), _ptr(R), _ptr(no), _ptr(st)))
+    return T, R, no, st
+
+
 def ms_kpar_average(ctx: Context, T: torch.Tensor, n_open: torch.Tensor):
     """T, n_open: [n_k][n_e] device tensors -> (tbar [n_e], per_channel [n_e])."""
     n_k, n_e = T.shape
@@ -338,6 +357,6 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
-           "ms_transmission_batch", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
+           "ms_transmission_batch", "ms_transmission_multi", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

@@ -605,6 +605,140 @@ ms_status ms_transmission(ms_ctx ctx, const ms_smat* whole, double energy, const
 }
 
 // ------------------------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// The fused fold for n_k slice sets (equal sizes) and n_e energies each: instances
+// i = k n_e + e, processed in sub-batches of consecutive instances.  Per interface the
+// prologue, the LU and the back substitution run once over the whole sub-batch; the
+// interface GEMM, the epilogue and the transmission columns run per slice set (each has
+// its own overlaps and channel list) over its share of the sub-batch.
+ms_status fold_multi(ms_ctx ctx, int n_k, const ms_slices* sl, int64_t n_e, const double* energies, ms_prec prec,
+                     double* T, double* R, int64_t* n_open, int32_t* point_status) {
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const bool fp32 = prec == MS_PREC_FP32_MFMA;
+  const int n = (int)sl[0].n_g, ns = (int)sl[0].n_slices, nrows = ns + 2;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t ni = (int64_t)n_k * n_e;
+
+  // open channels of each right lead at that set's highest energy, lowest first; the
+  // lists are padded to the longest with -1 (columns that stay zero)
+  std::vector<std::vector<int32_t>> chs(n_k);
+  int n_o = 0;
+  {
+    std::vector<double> er(n);
+    for (int k = 0; k < n_k; ++k) {
+      const double* eps_r = sl[k].eps + (int64_t)(ns + 1) * n;
+      MS_HIP(ctx, hipMemcpyAsync(er.data(), eps_r, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      const double emax = *std::max_element(energies + (int64_t)k * n_e, energies + (int64_t)(k + 1) * n_e);
+      for (int i = 0; i < n; ++i)
+        if (er[i] < emax) chs[k].push_back(i);
+      std::stable_sort(chs[k].begin(), chs[k].end(), [&](int32_t x, int32_t y) { return er[x] < er[y]; });
+      n_o = std::max(n_o, (int)chs[k].size());
+    }
+  }
+  const int n_oc = std::max(1, n_o);
+  std::vector<int32_t> chh((size_t)n_k * n_oc, -1);
+  for (int k = 0; k < n_k; ++k) std::copy(chs[k].begin(), chs[k].end(), chh.begin() + (size_t)k * n_oc);
+  void *chd, *end;
+  MS_TRY(workspace(ctx, WS_CH, chh.size() * sizeof(int32_t), &chd));
+  MS_TRY(upload(ctx, chd, chh.data(), chh.size() * sizeof(int32_t)));
+  MS_TRY(workspace(ctx, WS_EN, ni * sizeof(double), &end));
+  MS_TRY(upload(ctx, end, energies, ni * sizeof(double)));
+  MS_HIP(ctx, hipMemsetAsync(point_status, 0, ni * sizeof(int32_t), ctx->stream));
+  const int32_t* chk = (const int32_t*)chd;
+  const double* en = (const double*)end;
+
+  const int ldm = 2 * n + n_o, ldy = n + n_o;
+  const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
+  const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
+                       2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
+  int nbi = (int)std::max<int64_t>(1, std::min<int64_t>(ni, (int64_t)(BATCH_BUDGET / per_e)));
+  nbi = std::min(nbi, 65535);
+  void *kbv, *pbv, *aop, *wgv, *mmv, *ybv, *pivv, *oc = nullptr;
+  MS_TRY(workspace(ctx, WS_K, (size_t)nbi * sk * sizeof(double2), &kbv));
+  MS_TRY(workspace(ctx, WS_P, (size_t)nbi * sk * sizeof(double2), &pbv));
+  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbi * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
+  MS_TRY(workspace(ctx, WS_WG, (size_t)nbi * 2 * nn * sizeof(double2), &wgv));
+  MS_TRY(workspace(ctx, WS_M, (size_t)nbi * sM * sizeof(double2), &mmv));
+  MS_TRY(workspace(ctx, WS_Y, (size_t)nbi * sY * sizeof(double2), &ybv));
+  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbi * n * sizeof(int32_t), &pivv));
+  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
+  double2 *kb = c2(kbv), *pb = c2(pbv), *wg = c2(wgv), *mm = c2(mmv), *yb = c2(ybv);
+  int32_t* piv = (int32_t*)pivv;
+  const size_t asz = fp32 ? sizeof(float2) : sizeof(double2);
+
+  for (int64_t i0 = 0; i0 < ni; i0 += nbi) {
+    const int be = (int)std::min<int64_t>(nbi, ni - i0);
+    struct Seg { int k, a, m; };   // slice set k owns local instances [a, a + m)
+    std::vector<Seg> segs;
+    for (int64_t k = i0 / n_e; k * n_e < i0 + be; ++k) {
+      const int64_t lo = std::max<int64_t>(i0, k * n_e), hi = std::min<int64_t>(i0 + be, (k + 1) * n_e);
+      segs.push_back(Seg{(int)k, (int)(lo - i0), (int)(hi - lo)});
+    }
+    for (const Seg& g : segs)
+      MS_TRY(launch_wavevectors(ctx, n, nrows, g.m, sl[g.k].eps, en + i0 + g.a, sl[g.k].dz, kb + g.a * sk,
+                                pb + g.a * sk));
+    for (int p = ns; p >= 0; --p) {
+      const bool first = (p == ns);
+      const double2* kp = kb + (int64_t)p * n;
+      const double2* kq = kb + (int64_t)(p + 1) * n;
+      const double2* pq = pb + (int64_t)(p + 1) * n;
+      if (!first) {
+        MS_TRY(launch_prologue(ctx, n, be, yb, ldy, sY, kq, pq, sk, aop, fp32));
+        for (const Seg& g : segs) {
+          // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
+          // (no per-energy row padding of the last tile); O^T is shared
+          const double2* O = c2(sl[g.k].ovl) + (int64_t)p * nn;
+          GemmArgs q;
+          q.M = 2 * n * g.m; q.N = n; q.K = n;
+          q.A = static_cast<char*>(aop) + (size_t)g.a * 2 * nn * asz; q.lda = n; q.sA = 0; q.opA = OP_N;
+          q.B = O; q.ldb = n; q.sB = 0; q.opB = OP_T;
+          q.C = wg + (int64_t)g.a * 2 * nn; q.ldc = n; q.sC = 0;
+          q.batch = 1;
+          q.prof = PC_IFACE_GEMM;
+          if (fp32) {
+            MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
+            q.B = oc;
+            MS_TRY(cgemm32(ctx, q));
+          } else {
+            MS_TRY(zgemm(ctx, q));
+          }
+        }
+      }
+      for (const Seg& g : segs) {
+        const double2* O = c2(sl[g.k].ovl) + (int64_t)p * nn;
+        MS_TRY(launch_epilogue(ctx, n, g.m, O, first ? nullptr : wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
+                               kq + g.a * sk, sk, mm + g.a * sM, ldm, sM));
+        MS_TRY(launch_tcols(ctx, n, n_o, g.m, chk + (int64_t)g.k * n_oc, yb + g.a * sY, ldy, sY, n, kq + g.a * sk,
+                            pq + g.a * sk, sk, first ? 1 : 0, mm + g.a * sM, ldm, sM));
+      }
+      MS_TRY(getrf_aug(ctx, mm, n, ldm, sM, be, piv, point_status + i0, 1));
+      MS_TRY(trsm_upper_aug(ctx, mm, n, ldm, sM, be, yb, ldy, sY, point_status + i0, 1));
+    }
+    for (const Seg& g : segs) {
+      const double* eps_l = sl[g.k].eps;
+      const double* eps_r = sl[g.k].eps + (int64_t)(ns + 1) * n;
+      MS_TRY(launch_batch_T(ctx, n, (int)chs[g.k].size(), g.m, chk + (int64_t)g.k * n_oc, en + i0 + g.a, eps_l,
+                            eps_r, yb + g.a * sY, ldy, sY, T + i0 + g.a, R + i0 + g.a, n_open + i0 + g.a,
+                            point_status + i0 + g.a));
+    }
+  }
+  return MS_OK;
+}
+
+ms_status check_energies(ms_ctx ctx, int64_t count, const double* energies) {
+  for (int64_t e = 0; e < count; ++e)
+    if (!std::isfinite(energies[e])) return fail(ctx, MS_ERR_ARG, "energy %lld is not finite", (long long)e);
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const double* energies,
                                 ms_prec prec, double* T, double* R, int64_t* n_open, int32_t* point_status) {
   if (!ctx) return MS_ERR_ARG;
@@ -614,122 +748,27 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
   if (bad_ptr(energies) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open) || bad_ptr(point_status))
     return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
   if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
-  for (int64_t e = 0; e < n_e; ++e)
-    if (!std::isfinite(energies[e])) return fail(ctx, MS_ERR_ARG, "energy %lld is not finite", (long long)e);
-  MS_HIP(ctx, hipSetDevice(ctx->device));
-  const bool fp32 = prec == MS_PREC_FP32_MFMA;
-  const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
-  const int64_t nn = (int64_t)n * n;
-  const double* eps_l = slices->eps;
-  const double* eps_r = slices->eps + (int64_t)(ns + 1) * n;
+  MS_TRY(check_energies(ctx, n_e, energies));
+  return fold_multi(ctx, 1, slices, n_e, energies, prec, T, R, n_open, point_status);
+}
 
-  // open channels of the right lead at the highest energy, lowest first
-  std::vector<double> er(n);
-  MS_HIP(ctx, hipMemcpyAsync(er.data(), eps_r, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  const double emax = *std::max_element(energies, energies + n_e);
-  std::vector<int32_t> ch;
-  for (int i = 0; i < n; ++i)
-    if (er[i] < emax) ch.push_back(i);
-  std::stable_sort(ch.begin(), ch.end(), [&](int32_t a, int32_t b) { return er[a] < er[b]; });
-  const int n_o = (int)ch.size();
-  void *chd, *end;
-  MS_TRY(workspace(ctx, WS_CH, std::max<size_t>(1, ch.size()) * sizeof(int32_t), &chd));
-  MS_TRY(upload(ctx, chd, ch.data(), n_o * sizeof(int32_t)));
-  MS_TRY(workspace(ctx, WS_EN, n_e * sizeof(double), &end));
-  MS_TRY(upload(ctx, end, energies, n_e * sizeof(double)));
-  MS_HIP(ctx, hipMemsetAsync(point_status, 0, n_e * sizeof(int32_t), ctx->stream));
-
-  const int ldm = 2 * n + n_o, ldy = n + n_o;
-  const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
-  const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
-                       2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
-  // Buffers for a sub-batch of nbe energies.  Per interface, the prologue and the
-  // interface GEMM run on the caller's stream for the whole sub-batch (the GEMM
-  // then has the GPU to itself); the energies can then be split into G groups whose
-  // epilogue, LU and back substitution run on G internal streams (MS_FOLD_STREAMS),
-  // so that the latency-bound LU panels of one group overlap the updates of another.
-  int nbe = (int)std::max<int64_t>(1, std::min<int64_t>(n_e, (int64_t)(BATCH_BUDGET / per_e)));
-  nbe = std::min(nbe, 65535);
-  int G = 1;   // measured: two groups give no gain once the GEMM has the GPU to itself
-  if (const char* env = getenv("MS_FOLD_STREAMS")) G = std::max(1, std::min<int>(4, atoi(env)));
-  G = std::min(G, nbe);
-  void *kbv, *pbv, *aop, *wgv, *mmv, *ybv, *pivv, *oc = nullptr;
-  MS_TRY(workspace(ctx, WS_K, (size_t)nbe * sk * sizeof(double2), &kbv));
-  MS_TRY(workspace(ctx, WS_P, (size_t)nbe * sk * sizeof(double2), &pbv));
-  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbe * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
-  MS_TRY(workspace(ctx, WS_WG, (size_t)nbe * 2 * nn * sizeof(double2), &wgv));
-  MS_TRY(workspace(ctx, WS_M, (size_t)nbe * sM * sizeof(double2), &mmv));
-  MS_TRY(workspace(ctx, WS_Y, (size_t)nbe * sY * sizeof(double2), &ybv));
-  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbe * n * sizeof(int32_t), &pivv));
-  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
-  double2 *kb = c2(kbv), *pb = c2(pbv), *wg = c2(wgv), *mm = c2(mmv), *yb = c2(ybv);
-  int32_t* piv = (int32_t*)pivv;
-  std::vector<ms_ctx> gc(G, ctx);   // G = 1: everything on the caller's stream
-  if (G > 1)
-    for (int g = 0; g < G; ++g) MS_TRY(child(ctx, g, &gc[g]));
-  while ((int)ctx->sync_ev.size() < G + 1) {
-    hipEvent_t e = nullptr;
-    MS_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ctx->sync_ev.push_back(e);
+ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices, int64_t n_e,
+                                const double* energies, ms_prec prec, double* T, double* R, int64_t* n_open,
+                                int32_t* point_status) {
+  if (!ctx) return MS_ERR_ARG;
+  if (n_k < 0 || n_e < 0) return fail(ctx, MS_ERR_ARG, "n_k and n_e must be >= 0");
+  if (n_k == 0 || n_e == 0) return MS_OK;
+  if (bad_ptr(slices) || bad_ptr(energies) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open) || bad_ptr(point_status))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n_k > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "n_k %lld > 65535", (long long)n_k);
+  for (int64_t k = 0; k < n_k; ++k) {
+    MS_TRY(check_slices(ctx, slices + k));
+    if (slices[k].n_g != slices[0].n_g || slices[k].n_slices != slices[0].n_slices)
+      return fail(ctx, MS_ERR_ARG, "slice set %lld has other sizes than set 0", (long long)k);
   }
-  hipEvent_t fork = ctx->sync_ev[0];
-
-  for (int64_t e0 = 0; e0 < n_e; e0 += nbe) {
-    const int be = (int)std::min<int64_t>(nbe, n_e - e0);
-    const int gn = std::min(G, be);
-    MS_TRY(launch_wavevectors(ctx, n, nrows, be, slices->eps, (const double*)end + e0, slices->dz, kb, pb));
-    for (int p = ns; p >= 0; --p) {
-      const double2* O = c2(slices->ovl) + (int64_t)p * nn;
-      const bool first = (p == ns);
-      const double2* kp = kb + (int64_t)p * n;
-      const double2* kq = kb + (int64_t)(p + 1) * n;
-      const double2* pq = pb + (int64_t)(p + 1) * n;
-      if (!first) {
-        MS_TRY(launch_prologue(ctx, n, be, yb, ldy, sY, kq, pq, sk, aop, fp32));
-        // the energies' operands are contiguous, so the batch is one GEMM with M = 2 n be
-        // (no per-energy row padding of the last tile); O^T is shared
-        GemmArgs g;
-        g.M = 2 * n * be; g.N = n; g.K = n;
-        g.A = aop; g.lda = n; g.sA = 0; g.opA = OP_N;
-        g.B = O; g.ldb = n; g.sB = 0; g.opB = OP_T;
-        g.C = wg; g.ldc = n; g.sC = 0;
-        g.batch = 1;
-        g.prof = PC_IFACE_GEMM;
-        if (fp32) {
-          MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
-          g.B = oc;
-          MS_TRY(cgemm32(ctx, g));
-        } else {
-          MS_TRY(zgemm(ctx, g));
-        }
-      }
-      if (gn > 1) MS_HIP(ctx, hipEventRecord(fork, ctx->stream));
-      for (int g = 0; g < gn; ++g) {
-        const int a = be * g / gn, nb = be * (g + 1) / gn - a;
-        ms_ctx c = gc[g];
-        if (gn > 1) MS_HIP(ctx, hipStreamWaitEvent(c->stream, fork, 0));
-        int32_t* pst = point_status + e0 + a;
-        MS_TRY(launch_epilogue(c, n, nb, O, first ? nullptr : wg + (int64_t)a * 2 * nn, kp + (int64_t)a * sk,
-                               kq + (int64_t)a * sk, sk, mm + (int64_t)a * sM, ldm, sM));
-        MS_TRY(launch_tcols(c, n, n_o, nb, (const int32_t*)chd, yb + (int64_t)a * sY, ldy, sY, n,
-                            kq + (int64_t)a * sk, pq + (int64_t)a * sk, sk, first ? 1 : 0, mm + (int64_t)a * sM, ldm,
-                            sM));
-        MS_TRY(getrf_aug(c, mm + (int64_t)a * sM, n, ldm, sM, nb, piv + (int64_t)a * n, pst, 1));
-        MS_TRY(trsm_upper_aug(c, mm + (int64_t)a * sM, n, ldm, sM, nb, yb + (int64_t)a * sY, ldy, sY, pst, 1));
-      }
-      if (gn > 1) {   // join: the next interface (and T) needs every group's state
-        for (int g = 0; g < gn; ++g) {
-          hipEvent_t done = ctx->sync_ev[1 + g];
-          MS_HIP(ctx, hipEventRecord(done, gc[g]->stream));
-          MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, done, 0));
-        }
-      }
-    }
-    MS_TRY(launch_batch_T(ctx, n, n_o, be, (const int32_t*)chd, (const double*)end + e0, eps_l, eps_r, yb, ldy, sY,
-                          T + e0, R + e0, n_open + e0, point_status + e0));
-  }
-  return MS_OK;
+  if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
+  MS_TRY(check_energies(ctx, n_k * n_e, energies));
+  return fold_multi(ctx, (int)n_k, slices, n_e, energies, prec, T, R, n_open, point_status);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -363,3 +363,42 @@ def test_mixed_doubling_argument_errors(ms, ctx, c1):
         ms.ms_mixed_doubling(ctx, s, 0.5, 0.5)
     with pytest.raises(ms.MSError):
         ms.ms_mixed_doubling(ctx, s, float("nan"), 1e6)
+
+
+# ------------------------------------------------------------------ several slice sets -----
+def test_transmission_multi_matches_single_sets(ms, ctx):
+    """Two k_par of config1 folded in one batch (different lead channel counts, different
+    energies per set) give the same T, R, N_open as one call per set, and the oracle's."""
+    j = msgen.config1()
+    kps = [(0.0, 0.0), (0.31, 0.17)]
+    inps = [msgen.junction_inputs(j, kp) for kp in kps]
+    sets = [ms.prepare_from_inputs(ctx, inp) for inp in inps]
+    es = np.array([np.linspace(0.2, 3.9, 7), np.linspace(0.15, 4.2, 7)])
+    T, R, no, st = (_np(x) for x in ms.ms_transmission_multi(ctx, sets, es, "fp64"))
+    ctx.sync()
+    assert np.all(st == 0)
+    n_open_lead = []
+    for k in range(2):
+        t1, r1, n1, s1 = (_np(x) for x in ms.ms_transmission_batch(ctx, sets[k], es[k], "fp64"))
+        ctx.sync()
+        assert np.all(s1 == 0)
+        assert np.max(np.abs(T[k] - t1)) < 1e-12 and np.max(np.abs(R[k] - r1)) < 1e-12
+        assert np.array_equal(no[k], n1)
+        prep = orc.prepare(inps[k])
+        n_open_lead.append(int(np.sum(prep["eps"][-1] < es[k].max())))
+        for i in (0, 3, 6):
+            ref = orc.transmission(prep, es[k][i])
+            assert abs(T[k][i] - ref["T"]) < 1e-10 and abs(R[k][i] - ref["R"]) < 1e-10
+    assert n_open_lead[0] != n_open_lead[1]   # the channel lists are padded
+
+
+def test_transmission_multi_argument_errors(ms, ctx, c1):
+    j, inp, prep = c1
+    a = ms.prepare_from_inputs(ctx, inp)
+    j2 = msgen.config1()
+    j2.dz = np.full(12, 0.5)
+    b = ms.prepare_from_inputs(ctx, msgen.junction_inputs(j2, (0.0, 0.0)))
+    with pytest.raises(ms.MSError):
+        ms.ms_transmission_multi(ctx, [a, b], np.ones((2, 3)) * 0.5)
+    with pytest.raises(ms.MSError):
+        ms.ms_transmission_multi(ctx, [a, a], np.array([[0.5, np.nan], [0.5, 0.6]]))
