@@ -103,6 +103,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   constexpr bool kFold = std::is_same<T, double>::value;
   const bool scale_a = !(p.alpha.x == 1.0 && p.alpha.y == 0.0);
 
+  // Register double buffer.  load() issues the global loads of a K-slab with
+  // indices clamped into the matrices (every address valid, no branch), so the
+  // loads stay in flight while the MFMAs of the current slab run; stash()
+  // consumes them afterwards: zeroes the out-of-range elements, conjugates,
+  // scales by alpha and stores the split planes into LDS.
   CT ra[EA], rb[EB];
   auto load = [&](int k0) {
 #pragma unroll
@@ -110,51 +115,45 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       const int idx = tid + NT * e;
       int i, k;
       if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
-      const int gi = m0 + i, gk = k0 + k;
-      CT v;
-      v.x = 0; v.y = 0;
-      if (gi < p.M && gk < p.K) {
-        v = (p.opA == OP_N) ? A[(int64_t)gi * p.lda + gk] : A[(int64_t)gk * p.lda + gi];
-        if (p.opA == OP_C) v.y = -v.y;
-        if (kFold && scale_a) {   // alpha op(A), staged
-          const T re = (T)p.alpha.x * v.x - (T)p.alpha.y * v.y;
-          v.y = (T)p.alpha.x * v.y + (T)p.alpha.y * v.x;
-          v.x = re;
-        }
-      }
-      ra[e] = v;
+      const int gi = min(m0 + i, p.M - 1), gk = min(k0 + k, p.K - 1);
+      ra[e] = (p.opA == OP_N) ? A[(int64_t)gi * p.lda + gk] : A[(int64_t)gk * p.lda + gi];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = tid + NT * e;
       int j, k;
       if (p.opB == OP_N) { k = idx / BN; j = idx % BN; } else { j = idx / BK; k = idx % BK; }
-      const int gj = n0 + j, gk = k0 + k;
-      CT v;
-      v.x = 0; v.y = 0;
-      if (gj < p.N && gk < p.K) {
-        v = (p.opB == OP_N) ? B[(int64_t)gk * p.ldb + gj] : B[(int64_t)gj * p.ldb + gk];
-        if (p.opB == OP_C) v.y = -v.y;
-      }
-      rb[e] = v;
+      const int gj = min(n0 + j, p.N - 1), gk = min(k0 + k, p.K - 1);
+      rb[e] = (p.opB == OP_N) ? B[(int64_t)gk * p.ldb + gj] : B[(int64_t)gj * p.ldb + gk];
     }
   };
-  auto stash = [&](int st) {
+  auto stash = [&](int st, int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
       int i, k;
       if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
-      As[st][0][k][i] = ra[e].x;
-      As[st][1][k][i] = ra[e].y;
+      const bool ok = m0 + i < p.M && k0 + k < p.K;
+      T re = ok ? ra[e].x : (T)0, im = ok ? ra[e].y : (T)0;
+      if (p.opA == OP_C) im = -im;
+      if (kFold && scale_a) {   // alpha op(A), staged
+        const T r2 = (T)p.alpha.x * re - (T)p.alpha.y * im;
+        im = (T)p.alpha.x * im + (T)p.alpha.y * re;
+        re = r2;
+      }
+      As[st][0][k][i] = re;
+      As[st][1][k][i] = im;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int idx = tid + NT * e;
       int j, k;
       if (p.opB == OP_N) { k = idx / BN; j = idx % BN; } else { j = idx / BK; k = idx % BK; }
-      Bs[st][0][k][j] = rb[e].x;
-      Bs[st][1][k][j] = rb[e].y;
+      const bool ok = n0 + j < p.N && k0 + k < p.K;
+      T re = ok ? rb[e].x : (T)0, im = ok ? rb[e].y : (T)0;
+      if (p.opB == OP_C) im = -im;
+      Bs[st][0][k][j] = re;
+      Bs[st][1][k][j] = im;
     }
   };
 
@@ -169,7 +168,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 
   // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
   // other one; one barrier per slab
-  load(0);
+  if (p.K > 0) load(0);
   if (kFold && use_beta) {
 #pragma unroll
     for (int a = 0; a < FM; ++a)
@@ -186,7 +185,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
           }
         }
   }
-  stash(0);
+  stash(0, 0);
   if (BK < p.K) load(BK);
   __syncthreads();
   int cur = 0;
@@ -222,7 +221,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
         }
     }
     if (k0 + BK < p.K) {
-      stash(cur ^ 1);                       // slab k0+BK (already in registers)
+      stash(cur ^ 1, k0 + BK);              // slab k0+BK (already in registers)
       if (k0 + 2 * BK < p.K) load(k0 + 2 * BK);
     }
     __syncthreads();
