@@ -18,6 +18,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: without it the 64 x 64 GEMM tiles take 200 VGPRs + 68
+    # AGPRs (one wave per SIMD) and loop-carried accumulators are copied to AGPRs and back
+    # around every MFMA group
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-result", "-Wno-unused-variable",
 ]
 

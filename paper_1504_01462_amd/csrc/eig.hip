@@ -115,7 +115,9 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   __shared__ int s_flag;
 
   const int64_t b = blockIdx.y;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // the wave index is uniform across the wave: keeping it scalar keeps the per-wave row
+  // loops below scalar loops (no exec-masked divergence around the MFMAs)
+  const int t = threadIdx.x, lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   int32_t* cnt = args.counter + b * args.max_sweeps;
   if (args.sweep > 0 && cnt[args.sweep - 1] == 0) return;  // converged in the previous sweep
   const int n = args.n;
@@ -126,36 +128,59 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   if (mI + mJ == 0) return;
   double2* W = args.W + b * (int64_t)n * n;
 
+  // Columns of the pair are read with indices clamped into this workgroup's own columns
+  // (padding lanes read a real column of the pair and discard it), so every load is
+  // unconditional and the next rows' loads can be in flight while the MFMAs run.
+  const int own0 = (mI > 0) ? I * BW : J * BW;
+
   // --- Gram G = P^dagger P: each wave takes a quarter of the rows for all three blocks
   {
     d4_t g00r = {0, 0, 0, 0}, g00i = {0, 0, 0, 0}, g01r = {0, 0, 0, 0}, g01i = {0, 0, 0, 0},
          g11r = {0, 0, 0, 0}, g11i = {0, 0, 0, 0};
     const int c = lane & 15;
-    const int colI = (c < mI) ? I * BW + c : -1;
-    const int colJ = (c < mJ) ? J * BW + c : -1;
+    const bool okI = c < mI, okJ = c < mJ;
+    const int colI = okI ? I * BW + c : own0;
+    const int colJ = okJ ? J * BW + c : own0;
     const int kq = (n + 3) / 4;                 // rows per wave, rounded to steps of 4
     const int kbeg = wave * ((kq + 3) / 4 * 4);
     const int kend = min(n, kbeg + (kq + 3) / 4 * 4);
-    for (int k0 = kbeg; k0 < kend; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      double2 pi = make_double2(0.0, 0.0), pj = make_double2(0.0, 0.0);
-      if (k < kend) {
-        if (colI >= 0) pi = W[(int64_t)k * n + colI];
-        if (colJ >= 0) pj = W[(int64_t)k * n + colJ];
+    constexpr int GS = 4;                       // steps of 4 rows per group
+    double2 xi[GS], xj[GS], yi[GS], yj[GS];
+    auto fetch = [&](int k0, double2* vi, double2* vj) {
+#pragma unroll
+      for (int s = 0; s < GS; ++s) {
+        const int64_t k = min(k0 + 4 * s + (lane >> 4), n - 1);
+        vi[s] = W[k * n + colI];
+        vj[s] = W[k * n + colJ];
       }
-      // A = conj(P_X)^T (16 x 4), B = P_Y (4 x 16): lane holds element (c, k) of both
-      g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.x, g00r, 0, 0, 0);
-      g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pi.y, g00r, 0, 0, 0);
-      g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.y, g00i, 0, 0, 0);
-      g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pi.x, g00i, 0, 0, 0);
-      g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.x, g01r, 0, 0, 0);
-      g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pj.y, g01r, 0, 0, 0);
-      g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.y, g01i, 0, 0, 0);
-      g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pj.x, g01i, 0, 0, 0);
-      g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.x, g11r, 0, 0, 0);
-      g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.y, pj.y, g11r, 0, 0, 0);
-      g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.y, g11i, 0, 0, 0);
-      g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj.y, pj.x, g11i, 0, 0, 0);
+    };
+    if (kbeg < kend) fetch(kbeg, xi, xj);
+    for (int k0 = kbeg; k0 < kend; k0 += 4 * GS) {
+      if (k0 + 4 * GS < kend) fetch(k0 + 4 * GS, yi, yj);
+#pragma unroll
+      for (int s = 0; s < GS; ++s) {
+        const bool okk = k0 + 4 * s + (lane >> 4) < kend;
+        const double2 pi = (okk && okI) ? xi[s] : make_double2(0.0, 0.0);
+        const double2 pj = (okk && okJ) ? xj[s] : make_double2(0.0, 0.0);
+        // A = conj(P_X)^T (16 x 4), B = P_Y (4 x 16): lane holds element (c, k) of both
+        g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.x, g00r, 0, 0, 0);
+        g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pi.y, g00r, 0, 0, 0);
+        g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.y, g00i, 0, 0, 0);
+        g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pi.x, g00i, 0, 0, 0);
+        g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.x, g01r, 0, 0, 0);
+        g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pj.y, g01r, 0, 0, 0);
+        g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.y, g01i, 0, 0, 0);
+        g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pj.x, g01i, 0, 0, 0);
+        g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.x, g11r, 0, 0, 0);
+        g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.y, pj.y, g11r, 0, 0, 0);
+        g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.y, g11i, 0, 0, 0);
+        g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj.y, pj.x, g11i, 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < GS; ++s) {
+        xi[s] = yi[s];
+        xj[s] = yj[s];
+      }
     }
     // reduce the four partial Grams through LDS (G then Q used as scratch)
     for (int idx = t; idx < PW * PW; idx += 256) G[idx / PW][idx % PW] = make_double2(0.0, 0.0);
@@ -293,17 +318,33 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
     __syncthreads();
   }
 
-  // --- P <- P Q, ROWS rows at a time; waves split the 64 x 32 output into 16-row slabs
-  for (int r0 = 0; r0 < n; r0 += ROWS) {
-    for (int idx = t; idx < ROWS * PW; idx += 256) {
+  // --- P <- P Q, ROWS rows at a time; waves split the 64 x 32 output into 16-row slabs.
+  //     The next chunk's loads are issued before the current chunk's MFMAs (rows clamped,
+  //     never into the chunk being written: only issued while r0 + ROWS < n).
+  constexpr int EP = ROWS * PW / 256;
+  double2 pv[EP];
+  auto pload = [&](int r0) {
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int idx = t + 256 * e;
       const int i = idx / PW, a = idx % PW;
       const int col = pair_col(a, I, J, mI, mJ);
-      double2 v = make_double2(0.0, 0.0);
-      if (r0 + i < n && col >= 0) v = W[(int64_t)(r0 + i) * n + col];
-      Ps[0][i][a] = v.x;
-      Ps[1][i][a] = v.y;
+      const int64_t row = min(r0 + i, n - 1);
+      pv[e] = W[row * n + (col >= 0 ? col : own0)];
+    }
+  };
+  pload(0);
+  for (int r0 = 0; r0 < n; r0 += ROWS) {
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      const int idx = t + 256 * e;
+      const int i = idx / PW, a = idx % PW;
+      const bool ok = r0 + i < n && pair_col(a, I, J, mI, mJ) >= 0;
+      Ps[0][i][a] = ok ? pv[e].x : 0.0;
+      Ps[1][i][a] = ok ? pv[e].y : 0.0;
     }
     __syncthreads();
+    if (r0 + ROWS < n) pload(r0 + ROWS);
     d4_t cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
     const int rr = wave * 16;
 #pragma unroll
