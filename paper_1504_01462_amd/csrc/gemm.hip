@@ -169,7 +169,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
   // other one; one barrier per slab
   if (p.K > 0) load(0);
-  if (kFold && use_beta) {
+  if (kFold && use_beta) {   // C loads unconditional (clamped) so they are all in flight at once
+    const bool beta_one = p.beta.x == 1.0 && p.beta.y == 0.0;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -178,11 +179,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
         for (int v = 0; v < 4; ++v) {
           const int row = m0 + wm0 + a * 16 + Mfma<T>::crow(lane, v);
           const int col = n0 + wn0 + c * 16 + (lane & 15);
-          if (row < p.M && col < p.N) {
-            const double2 o = C[(int64_t)row * p.ldc + col];
-            cr[a][c][v] = p.beta.x * o.x - p.beta.y * o.y;
-            ci[a][c][v] = p.beta.x * o.y + p.beta.y * o.x;
-          }
+          const double2 o = C[(int64_t)min(row, p.M - 1) * p.ldc + min(col, p.N - 1)];
+          const bool ok = row < p.M && col < p.N;
+          const double re = beta_one ? o.x : p.beta.x * o.x - p.beta.y * o.y;
+          const double im = beta_one ? o.y : p.beta.x * o.y + p.beta.y * o.x;
+          cr[a][c][v] = ok ? re : 0.0;
+          ci[a][c][v] = ok ? im : 0.0;
         }
   }
   stash(0, 0);

@@ -486,18 +486,21 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
 #pragma unroll
     for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; }
     double2 up[UE], yp[TR_KC / 4];
+    // loads with indices clamped into the matrices (no branch, all in flight together);
+    // the out-of-range elements are zeroed when the chunk is consumed
+    const int mycc = min(myc, nrhs - 1);
     auto fetch = [&](int c) {
       const int k0 = r1 + c * TR_KC;
 #pragma unroll
       for (int e = 0; e < UE; ++e) {
         const int idx = th + 256 * e;
         const int i = idx / TR_KC, k = idx % TR_KC;
-        up[e] = (r0 + i < r1 && k0 + k < n) ? M[(int64_t)(r0 + i) * ld + k0 + k] : make_double2(0.0, 0.0);
+        up[e] = M[(int64_t)min(r0 + i, r1 - 1) * ld + min(k0 + k, n - 1)];
       }
 #pragma unroll
       for (int q = 0; q < TR_KC / 4; ++q) {
         const int k = k0 + 4 * q + (lane >> 4);
-        yp[q] = (k < n && cok) ? Yb[(int64_t)k * ldy + myc] : make_double2(0.0, 0.0);
+        yp[q] = Yb[(int64_t)min(k, n - 1) * ldy + mycc];
       }
     };
     int c = h;
@@ -506,14 +509,19 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
       const bool have = c < nch;
       double2 yc[TR_KC / 4];
       if (have) {
+        const int k0 = r1 + c * TR_KC;
 #pragma unroll
         for (int e = 0; e < UE; ++e) {
           const int idx = th + 256 * e;
-          Us[h][0][idx / TR_KC][idx % TR_KC] = up[e].x;
-          Us[h][1][idx / TR_KC][idx % TR_KC] = up[e].y;
+          const bool ok = r0 + idx / TR_KC < r1 && k0 + idx % TR_KC < n;
+          Us[h][0][idx / TR_KC][idx % TR_KC] = ok ? up[e].x : 0.0;
+          Us[h][1][idx / TR_KC][idx % TR_KC] = ok ? up[e].y : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < TR_KC / 4; ++q) yc[q] = yp[q];
+        for (int q = 0; q < TR_KC / 4; ++q) {
+          const bool ok = k0 + 4 * q + (lane >> 4) < n && cok;
+          yc[q] = ok ? yp[q] : make_double2(0.0, 0.0);
+        }
       }
       __syncthreads();
       if (have && c + 2 < nch) fetch(c + 2);
@@ -533,25 +541,34 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
       }
       __syncthreads();
     }
-    // R = Z - (partial sum of half 0) - (partial sum of half 1)
-    if (h == 1) {
+    // R = Z - (partial sum of half 0) - (partial sum of half 1).  Half 0 loads its 16
+    // elements of Z (clamped, all in flight together) and writes Z - S0; half 1 then
+    // subtracts S1
+    if (h == 0) {
+      double2 zz[16];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Rs[a * 16 + (lane >> 4) + 4 * v][cl] = make_double2(cr[a][v], ci[a][v]);
-    }
-    __syncthreads();
-    if (h == 0) {
+        for (int v = 0; v < 4; ++v)
+          zz[4 * a + v] = M[(int64_t)min(r0 + a * 16 + (lane >> 4) + 4 * v, r1 - 1) * ld + n + mycc];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = a * 16 + (lane >> 4) + 4 * v;   // f64 MFMA accumulator row
-          const int r = r0 + i;
-          double2 z = make_double2(0.0, 0.0);
-          if (r < r1 && cok) z = M[(int64_t)r * ld + n + myc];
+          const double2 z = (r0 + i < r1 && cok) ? zz[4 * a + v] : make_double2(0.0, 0.0);
+          Rs[i][cl] = make_double2(z.x - cr[a][v], z.y - ci[a][v]);
+        }
+    }
+    __syncthreads();
+    if (h == 1) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = a * 16 + (lane >> 4) + 4 * v;
           const double2 o = Rs[i][cl];
-          Rs[i][cl] = make_double2(z.x - cr[a][v] - o.x, z.y - ci[a][v] - o.y);
+          Rs[i][cl] = make_double2(o.x - cr[a][v], o.y - ci[a][v]);
         }
     }
     __syncthreads();
