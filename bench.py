@@ -13,7 +13,10 @@ Inputs are seeded and synthetic, uploaded to HBM before the timed region.
 The steps run twice, in FP64 and in the FP32-MFMA form, over the same
 (gap, k_par) pairs; the FP32 number is the headline only when its largest
 |dT| against the FP64 run stays below 1e-6.  One point of the workload is
-also solved with the paper's mixed transfer/scattering doubling.
+also solved with the paper's mixed transfer/scattering doubling, and the first
+instances of the uneven workload (N_G from 200 to 1200, 100-400 slices, one point
+each) are folded in one call, the small ones also in a captured hipGraph
+(`uneven_batch`).
 
     python bench.py [--steps K] [--warmup W] [--config config3|config2|config1]
 Prints one JSON line.
@@ -49,6 +52,9 @@ def parse():
                     help="skip the timing of the mixed-recurrence doubling (ms_mixed_doubling)")
     ap.add_argument("--roofline-kernel", default="iface_gemm",
                     help="profiler category reported in 'roofline' ('auto': the largest summed time in the warmup)")
+    ap.add_argument("--uneven", type=int, default=16,
+                    help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
+                         "captured graph after the main measurement; 0 skips it")
     ap.add_argument("--no-event-profile", action="store_true",
                     help="record no HIP events around launches (no roofline figure; for external profilers)")
     return ap.parse_args()
@@ -169,6 +175,103 @@ def mixed_doubling_measure(ms, ctx, st, buf, results, log):
             "note": (f"whole S of {ns + 1} interfaces by a doubling tree: about 9 1/3 N^3 complex MACs per mixed "
                      "pair, 10 1/3 per star pair and 4/3 N^3 per block for the condition numbers, against "
                      "3 1/3 N^3 per interface for the fused fold")}
+
+
+def uneven_measure(ms, ctx, count, log, replays=2):
+    """The uneven workload: the first `count` seeded instances of the bilayer junction with
+    N_G drawn from {200, 450, 800, 1200}, 100-400 slices and one (E, k_par) each.  Their
+    slice eigenproblems and overlaps are prepared instance by instance (timed), then all
+    instances are folded in one call, in the FP32-MFMA form and in FP64 (timed; |dT| between
+    the forms per instance).  The instances with N_G <= 450 are also folded in one captured
+    hipGraph, whose replays are timed and checked against the direct call: a graph holds at
+    most 96000 kernels, which the whole set (about 213000) exceeds."""
+    import torch
+    import msgen
+    dev = ctx.device
+    inst = msgen.config4_instances()[:count]
+    staged = []
+    for it in inst:
+        j = it["junction"]
+        inp = msgen.junction_inputs(j, j.kpars[it["k_index"]])
+        staged.append(dict(
+            n_g=j.n_g, ns=len(j.dz), e=float(it["energy"]),
+            miller=torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev),
+            q=torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev),
+            vq=torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev),
+            dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
+            bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
+    bufs = [ms.Slices.empty(x["n_g"], x["ns"], x["dz"], dev) for x in staged]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, x in zip(bufs, staged):
+        ms.ms_slices_prepare(ctx, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    log(f"uneven: {count} instances prepared in {prep_s:.2f} s")
+    es = [[x["e"]] for x in staged]
+    out = {}
+    for prec in ("fp32", "fp64"):
+        ms.ms_transmission_uneven(ctx, bufs, es, prec)          # warm: workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, R, no, st = ms.ms_transmission_uneven(ctx, bufs, es, prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[prec] = dict(T=T.cpu().numpy(), R=R.cpu().numpy(), no=no.cpu().numpy(), st=st.cpu().numpy(), s=dt)
+        log(f"uneven {prec}: {count} instances folded in {dt:.2f} s")
+    d32, d64 = out["fp32"], out["fp64"]
+    dT = np.abs(d32["T"] - d64["T"])
+    mix = {}
+    for x in staged:
+        mix[str(x["n_g"])] = mix.get(str(x["n_g"]), 0) + 1
+    res = {
+        "workload": "uneven instances of the bilayer-gap junction (hexagonal 2x2 cell, 16 bohr): "
+                    "N_G in {200, 450, 800, 1200}, 100-400 slices, one (E, k_par) each, seeded; "
+                    f"the first {count} of 512",
+        "instances": count,
+        "n_g_mix": mix,
+        "slices_total": int(sum(x["ns"] for x in staged)),
+        "prepare_s": round(prep_s, 4),
+        "fold_s": {"fp32": round(d32["s"], 4), "fp64": round(d64["s"], 4)},
+        "instances_per_s_fold": {"fp32": round(count / d32["s"], 3), "fp64": round(count / d64["s"], 3)},
+        "instances_per_s_end_to_end": {"fp32": round(count / (prep_s + d32["s"]), 3),
+                                       "fp64": round(count / (prep_s + d64["s"]), 3)},
+        "abs_dT_fp32_vs_fp64": [float(f"{v:.3g}") for v in dT],
+        "max_abs_dT_fp32_vs_fp64": float(dT.max()),
+        "max_abs_R_plus_T_minus_Nopen_fp64": float(np.max(np.abs(d64["T"] + d64["R"] - d64["no"]))),
+        "bad_points": int(np.sum(d32["st"] != 0) + np.sum(d64["st"] != 0)),
+    }
+    small = [i for i, x in enumerate(staged) if x["n_g"] <= 450]
+    if small:
+        sb, se = [bufs[i] for i in small], [es[i] for i in small]
+        t0 = time.perf_counter()
+        Tg = ms.ms_transmission_uneven(ctx, sb, se, "fp32", graph=True)[0]
+        torch.cuda.synchronize()
+        first_s = time.perf_counter() - t0
+        ts = []
+        for _ in range(replays):
+            Tg.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ms.ms_graph_replay(ctx)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms.ms_transmission_uneven(ctx, sb, se, "fp32")           # the same instances, no graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Te = ms.ms_transmission_uneven(ctx, sb, se, "fp32")[0]
+        torch.cuda.synchronize()
+        eager_s = time.perf_counter() - t0
+        res["graph"] = {
+            "instances": len(small), "which": small, "form": "fp32",
+            "capture_and_first_launch_s": round(first_s, 4),
+            "replay_s": round(min(ts), 4),
+            "direct_call_s": round(eager_s, 4),
+            "max_abs_T_replay_minus_direct": float(np.max(np.abs(Tg.cpu().numpy() - Te.cpu().numpy()))),
+        }
+        log(f"uneven graph ({len(small)} instances): capture+launch {first_s:.2f} s, replay {min(ts):.3f} s, "
+            f"direct {eager_s:.3f} s")
+    return res
 
 
 def main():
@@ -337,6 +440,10 @@ def main():
     }
     if args.next3 and args.config == "config3":
         line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)
+    if args.uneven > 0:
+        bufs.clear()                        # the main workload's slice buffers
+        torch.cuda.empty_cache()
+        line["uneven_batch"] = uneven_measure(ms, ctx, args.uneven, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)

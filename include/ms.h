@@ -204,6 +204,43 @@ ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices
                                 const double* energies, ms_prec prec, double* T, double* R, int64_t* n_open,
                                 int32_t* point_status);
 
+/* Flag of ms_transmission_uneven: capture the whole fold into one hipGraph and launch it. */
+#define MS_FOLD_GRAPH 1
+
+/* The fused fold for slice sets of uneven sizes (n_g and n_slices may differ from set to
+ * set), each with its own energies: many independent (E, k_par) instances in one call.
+ * Sets of equal n_g form one batch whose LU factorisations and back substitutions run
+ * together per fold step; inside it the sets are folded longest first and a set leaves
+ * the batch once its left lead is reached (the T of each point is that of
+ * ms_transmission_batch for its set and energy, up to rounding).
+ *   sets        [n_sets] slice sets (device data, as for ms_transmission_batch)
+ *   n_e         [n_sets] int64 (host): energies of each set (0 allowed)
+ *   energies    [sum n_e] f64 (host), set 0's first, then set 1's, ...
+ *   flags       0 or MS_FOLD_GRAPH: all kernels of the call are captured (on an internal
+ *               stream) into one hipGraph, launched once on the context's stream and kept
+ *               by the context for ms_graph_replay (until the next capture or destroy);
+ *               the graph has a workspace of its own, which other calls do not touch.
+ *               One graph holds at most 96000 kernels (about 300 per fold step at
+ *               n_g = 1200, 200 at 800, 115 at 450, 55 at 200, times the longest set's
+ *               n_slices per n_g group); a larger fold fails with MS_ERR_UNSUPPORTED
+ *               (nothing launched) and is run by several calls or without the flag
+ *   T, R        [sum n_e] f64, n_open [sum n_e] int64, point_status [sum n_e] int32
+ *               (device outputs, in the order of `energies`)
+ * Before launching, the call reads each set's right-lead channel energies (it waits for
+ * the stream then) and grows its workspace; nothing is allocated inside a capture.
+ * Errors: MS_ERR_ARG (nulls, negative counts, unknown flags or precision, non-finite
+ * energies), MS_ERR_UNSUPPORTED (n_g > 4096, graph too large), MS_ERR_ALLOC,
+ * MS_ERR_HIP (capture). */
+ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* sets, const int64_t* n_e,
+                                 const double* energies, ms_prec prec, int32_t flags, double* T, double* R,
+                                 int64_t* n_open, int32_t* point_status);
+
+/* Launch the graph captured by the last ms_transmission_uneven(..., MS_FOLD_GRAPH, ...) on
+ * this context again, on the context's stream: the same slice data, energies, channel
+ * lists and output buffers (their contents may have changed; the sizes may not).
+ * Errors: MS_ERR_ARG (no graph), MS_ERR_HIP. */
+ms_status ms_graph_replay(ms_ctx ctx);
+
 /* a7: average over the k_par mesh (Sec. II.B, Eq. T1_d):
  *   tbar[e]        = (1/n_k) sum_k T[k][e]
  *   per_channel[e] = sum_k T[k][e] / sum_k n_open[k][e]   (0 when no channel is open)

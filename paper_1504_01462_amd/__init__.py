@@ -60,6 +60,8 @@ _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
+_sig("ms_transmission_uneven", [_vp, _i64, ctypes.POINTER(MsSlices), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
+_sig("ms_graph_replay", [_vp])
 _sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 _sig("ms_mixed_doubling", [_vp, ctypes.POINTER(MsSlices), _f64, _f64, ctypes.POINTER(MsSmat), ctypes.POINTER(_i32)])
 _sig("ms_debug_profile", [_vp, ctypes.c_uint32])
@@ -252,6 +254,37 @@ def ms_transmission_multi(ctx: Context, slices_list, energies, prec="fp64"):
     return T, R, no, st
 
 
+MS_FOLD_GRAPH = 1
+
+
+def ms_transmission_uneven(ctx: Context, slices_list, energies_list, prec="fp64", graph=False):
+    """Slice sets of any sizes, each with its own energies (energies_list[k] is a 1-D list):
+    returns T, R, n_open, status as flat device tensors in the order of the concatenated
+    energies.  graph=True captures the fold into one hipGraph (see ms_graph_replay)."""
+    n_sets = len(slices_list)
+    if len(energies_list) != n_sets:
+        raise ValueError("one energy list per slice set")
+    ne = np.array([len(np.atleast_1d(e)) for e in energies_list], dtype=np.int64)
+    e = np.ascontiguousarray(np.concatenate([np.atleast_1d(np.asarray(x, dtype=np.float64))
+                                             for x in energies_list]) if n_sets else np.zeros(0))
+    total = int(ne.sum())
+    arr = (MsSlices * max(n_sets, 1))(*[s.c for s in slices_list])
+    T = torch.empty(total, dtype=torch.float64, device=ctx.device)
+    R = torch.empty(total, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(total, dtype=torch.int64, device=ctx.device)
+    st = torch.empty(total, dtype=torch.int32, device=ctx.device)
+    _check(ctx.handle, lib.ms_transmission_uneven(ctx.handle, n_sets, arr, ne.ctypes.data_as(ctypes.c_void_p),
+                                                  e.ctypes.data_as(ctypes.c_void_p), _PREC[prec],
+                                                  MS_FOLD_GRAPH if graph else 0, _ptr(T), _ptr(R), _ptr(no),
+                                                  _ptr(st)))
+    return T, R, no, st
+
+
+def ms_graph_replay(ctx: Context):
+    """Launch the fold graph captured by the last ms_transmission_uneven(graph=True) again."""
+    _check(ctx.handle, lib.ms_graph_replay(ctx.handle))
+
+
 def ms_kpar_average(ctx: Context, T: torch.Tensor, n_open: torch.Tensor):
     """T, n_open: [n_k][n_e] device tensors -> (tbar [n_e], per_channel [n_e])."""
     n_k, n_e = T.shape
@@ -357,6 +390,7 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
-           "ms_transmission_batch", "ms_transmission_multi", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
+           "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
+           "MS_FOLD_GRAPH", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

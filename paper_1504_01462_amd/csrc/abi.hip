@@ -36,28 +36,36 @@ ms_status hip_fail(ms_ctx ctx, hipError_t e, const char* what) {
 ms_status check_launch(ms_ctx ctx, const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, what);
+  if (ctx->capturing && ++ctx->cap_kernels > ctx->cap_limit)
+    return fail(ctx, MS_ERR_UNSUPPORTED,
+                "the fold needs more than %lld kernels in one graph; split the sets over several calls "
+                "or call without MS_FOLD_GRAPH", (long long)ctx->cap_limit);
   return MS_OK;
 }
 
 ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out) {
-  if ((size_t)slot >= ctx->ws.size()) {
-    ctx->ws.resize(slot + 1, nullptr);
-    ctx->ws_size.resize(slot + 1, 0);
+  std::vector<void*>& ws = ctx->use_gws ? ctx->gws : ctx->ws;
+  std::vector<size_t>& ws_size = ctx->use_gws ? ctx->gws_size : ctx->ws_size;
+  if ((size_t)slot >= ws.size()) {
+    ws.resize(slot + 1, nullptr);
+    ws_size.resize(slot + 1, 0);
   }
   if (bytes == 0) bytes = 256;
-  if (ctx->ws_size[slot] < bytes) {
+  if (ws_size[slot] < bytes) {
+    if (ctx->capturing)   // the planning pass sizes every slot a captured launch uses
+      return fail(ctx, MS_ERR_UNSUPPORTED, "workspace slot %d would grow inside a graph capture", slot);
     MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->ws[slot]) MS_HIP(ctx, hipFree(ctx->ws[slot]));
-    ctx->ws[slot] = nullptr;
-    ctx->ws_size[slot] = 0;
+    if (ws[slot]) MS_HIP(ctx, hipFree(ws[slot]));
+    ws[slot] = nullptr;
+    ws_size[slot] = 0;
     const size_t want = (bytes + 4095) & ~(size_t)4095;
     void* p = nullptr;
     const hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) return hip_fail(ctx, e, "workspace hipMalloc");
-    ctx->ws[slot] = p;
-    ctx->ws_size[slot] = want;
+    ws[slot] = p;
+    ws_size[slot] = want;
   }
-  *out = ctx->ws[slot];
+  *out = ws[slot];
   return MS_OK;
 }
 
@@ -74,7 +82,7 @@ static hipEvent_t take_event(ms_ctx ctx) {
 
 Prof::Prof(ms_ctx c, int category, double fl, double by, bool kernel_events)
     : ctx(c), cat(category), flops(fl), bytes(by), ext(kernel_events) {
-  if (ctx && (ctx->prof_mask >> category & 1u)) {
+  if (ctx && !ctx->capturing && (ctx->prof_mask >> category & 1u)) {
     a = take_event(ctx);
     if (!a) return;
     if (ext) {
@@ -136,10 +144,12 @@ enum {
   WS_JPAIRS = 10, WS_JCOUNT = 11,
   WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
   WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V,
-  WS_MD_A = 33, WS_MD_B, WS_MD_INV, WS_MD_T, WS_MD_NRM
+  WS_MD_A = 33, WS_MD_B, WS_MD_INV, WS_MD_T, WS_MD_NRM,
+  WS_PERM, WS_RT, WS_RR, WS_RNO, WS_RST
 };
 
 constexpr int MAX_N = 4096;
+constexpr int64_t MAX_GRAPH_KERNELS = 96000;   // kernels one captured fold graph may hold
 constexpr size_t BATCH_BUDGET = size_t(24) << 30;   // bytes of per-energy workspace per sub-batch
 constexpr size_t PREP_BUDGET = size_t(8) << 30;     // bytes of eigensolver workspace per chunk
 constexpr int WARM_STRIDE = 8;                       // reference slices for the warm-started eigensolver
@@ -247,8 +257,12 @@ ms_status ms_ctx_destroy(ms_ctx ctx) {
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->sync_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->lu_ev) (void)hipEventDestroy(e);
+  if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (!ctx->owns_status && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   for (void* p : ctx->ws)
+    if (p) (void)hipFree(p);
+  for (void* p : ctx->gws)
     if (p) (void)hipFree(p);
   if (ctx->owns_status && ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
@@ -614,118 +628,307 @@ namespace {
 // prologue, the LU and the back substitution run once over the whole sub-batch; the
 // interface GEMM, the epilogue and the transmission columns run per slice set (each has
 // its own overlaps and channel list) over its share of the sub-batch.
-ms_status fold_multi(ms_ctx ctx, int n_k, const ms_slices* sl, int64_t n_e, const double* energies, ms_prec prec,
-                     double* T, double* R, int64_t* n_open, int32_t* point_status) {
-  MS_HIP(ctx, hipSetDevice(ctx->device));
-  const bool fp32 = prec == MS_PREC_FP32_MFMA;
-  const int n = (int)sl[0].n_g, ns = (int)sl[0].n_slices, nrows = ns + 2;
-  const int64_t nn = (int64_t)n * n;
-  const int64_t ni = (int64_t)n_k * n_e;
+// ---- the fused right fold over several slice sets ------------------------------------------
+//
+// Every (slice set, energy) pair is one instance.  Sets are grouped by n_g; inside a group
+// they are sorted by slice count, longest first, and each instance's k and P rows are stored
+// right-aligned (slice p of a set with ns slices at row p + nsmax - ns), so at fold step s
+// every set is at its interface p = ns - s, on the same rows, and the sets still folding are
+// a prefix of the batch.  fold_plan does all host work (channel lists, uploads, workspace);
+// fold_enqueue only launches kernels, so it can be captured into a graph.
 
-  // open channels of each right lead at that set's highest energy, lowest first; the
-  // lists are padded to the longest with -1 (columns that stay zero)
-  std::vector<std::vector<int32_t>> chs(n_k);
-  int n_o = 0;
-  {
-    std::vector<double> er(n);
-    for (int k = 0; k < n_k; ++k) {
-      const double* eps_r = sl[k].eps + (int64_t)(ns + 1) * n;
-      MS_HIP(ctx, hipMemcpyAsync(er.data(), eps_r, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-      MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      const double emax = *std::max_element(energies + (int64_t)k * n_e, energies + (int64_t)(k + 1) * n_e);
-      for (int i = 0; i < n; ++i)
-        if (er[i] < emax) chs[k].push_back(i);
-      std::stable_sort(chs[k].begin(), chs[k].end(), [&](int32_t x, int32_t y) { return er[x] < er[y]; });
-      n_o = std::max(n_o, (int)chs[k].size());
+struct FoldSet {            // one slice set and its energies [e0, e0 + ne) of the caller's arrays
+  const ms_slices* sl;
+  int64_t e0, ne;
+};
+
+struct FoldGroup {          // the sets of one n_g, longest first
+  int n = 0, n_o = 0, n_oc = 1, nsmax = 0, nbi = 1;
+  std::vector<int> sets;            // indices into FoldPlan::sets
+  std::vector<int> n_ch;            // open channels of each set's right lead
+  std::vector<int64_t> set_inst0;   // first instance of each set (fold order)
+  int64_t inst0 = 0, ni = 0;        // the group's instances [inst0, inst0 + ni)
+  int64_t ch0 = 0;                  // channel table [sets][n_oc] at ch0 of the channel buffer
+};
+
+struct FoldPlan {
+  std::vector<FoldSet> sets;
+  std::vector<FoldGroup> groups;
+  int64_t ni = 0;
+  bool fp32 = false;
+  const int32_t* ch = nullptr;     // device: channel tables
+  const double* en = nullptr;      // device: energy of each instance (fold order)
+  const int64_t* perm = nullptr;   // device: caller's index of each instance
+  double* t = nullptr;             // device: results in fold order
+  double* r = nullptr;
+  int64_t* no = nullptr;
+  int32_t* st = nullptr;
+  double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
+  void *aop = nullptr, *oc = nullptr;
+  int32_t* piv = nullptr;
+};
+
+struct FoldDims {
+  int ldm, ldy;
+  int64_t nn, sM, sY, sk;
+  size_t asz, per_e;
+};
+
+FoldDims fold_dims(const FoldGroup& G, bool fp32) {
+  FoldDims d;
+  const int n = G.n;
+  d.nn = (int64_t)n * n;
+  d.ldm = 2 * n + G.n_o;
+  d.ldy = n + G.n_o;
+  d.sM = (int64_t)n * d.ldm;
+  d.sY = (int64_t)n * d.ldy;
+  d.sk = (int64_t)(G.nsmax + 2) * n;
+  d.asz = fp32 ? sizeof(float2) : sizeof(double2);
+  d.per_e = (size_t)(2 * d.sk) * sizeof(double2) + 2 * d.nn * d.asz + 2 * d.nn * sizeof(double2) +
+            d.sM * sizeof(double2) + d.sY * sizeof(double2) + n * sizeof(int32_t);
+  return d;
+}
+
+ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& P) {
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  P.fp32 = prec == MS_PREC_FP32_MFMA;
+  // groups by n_g in order of first appearance, longest set first inside a group
+  for (int k = 0; k < (int)P.sets.size(); ++k) {
+    if (P.sets[k].ne <= 0) continue;
+    const int n = (int)P.sets[k].sl->n_g;
+    auto it = std::find_if(P.groups.begin(), P.groups.end(), [&](const FoldGroup& g) { return g.n == n; });
+    if (it == P.groups.end()) {
+      P.groups.emplace_back();
+      P.groups.back().n = n;
+      it = P.groups.end() - 1;
     }
+    it->sets.push_back(k);
   }
-  const int n_oc = std::max(1, n_o);
-  std::vector<int32_t> chh((size_t)n_k * n_oc, -1);
-  for (int k = 0; k < n_k; ++k) std::copy(chs[k].begin(), chs[k].end(), chh.begin() + (size_t)k * n_oc);
-  void *chd, *end;
+  std::vector<int32_t> chh;
+  std::vector<double> enh;
+  std::vector<int64_t> permh;
+  size_t need_k = 0, need_aop = 0, need_wg = 0, need_m = 0, need_y = 0, need_piv = 0, need_oc = 0;
+  std::vector<double> er;
+  for (FoldGroup& G : P.groups) {
+    std::stable_sort(G.sets.begin(), G.sets.end(),
+                     [&](int a, int b) { return P.sets[a].sl->n_slices > P.sets[b].sl->n_slices; });
+    G.nsmax = (int)P.sets[G.sets.front()].sl->n_slices;
+    // open channels of each right lead at that set's highest energy, lowest first; the
+    // tables are padded to the longest with -1 (columns that stay zero)
+    std::vector<std::vector<int32_t>> chs(G.sets.size());
+    er.resize(G.n);
+    for (size_t j = 0; j < G.sets.size(); ++j) {
+      const FoldSet& fs = P.sets[G.sets[j]];
+      const double* eps_r = fs.sl->eps + (int64_t)(fs.sl->n_slices + 1) * G.n;
+      MS_HIP(ctx, hipMemcpyAsync(er.data(), eps_r, G.n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      const double emax = *std::max_element(energies + fs.e0, energies + fs.e0 + fs.ne);
+      for (int i = 0; i < G.n; ++i)
+        if (er[i] < emax) chs[j].push_back(i);
+      std::stable_sort(chs[j].begin(), chs[j].end(), [&](int32_t x, int32_t y) { return er[x] < er[y]; });
+      G.n_o = std::max(G.n_o, (int)chs[j].size());
+    }
+    G.n_oc = std::max(1, G.n_o);
+    G.ch0 = (int64_t)chh.size();
+    G.inst0 = P.ni;
+    for (size_t j = 0; j < G.sets.size(); ++j) {
+      const FoldSet& fs = P.sets[G.sets[j]];
+      G.n_ch.push_back((int)chs[j].size());
+      std::vector<int32_t> row(G.n_oc, -1);
+      std::copy(chs[j].begin(), chs[j].end(), row.begin());
+      chh.insert(chh.end(), row.begin(), row.end());
+      G.set_inst0.push_back(P.ni);
+      for (int64_t e = 0; e < fs.ne; ++e) {
+        enh.push_back(energies[fs.e0 + e]);
+        permh.push_back(fs.e0 + e);
+      }
+      P.ni += fs.ne;
+    }
+    G.ni = P.ni - G.inst0;
+    const FoldDims d = fold_dims(G, P.fp32);
+    int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, (int64_t)(BATCH_BUDGET / d.per_e)));
+    G.nbi = (int)std::min<int64_t>(nbi, 65535);
+    need_k = std::max(need_k, (size_t)G.nbi * d.sk * sizeof(double2));
+    need_aop = std::max(need_aop, (size_t)G.nbi * 2 * d.nn * d.asz);
+    need_wg = std::max(need_wg, (size_t)G.nbi * 2 * d.nn * sizeof(double2));
+    need_m = std::max(need_m, (size_t)G.nbi * d.sM * sizeof(double2));
+    need_y = std::max(need_y, (size_t)G.nbi * d.sY * sizeof(double2));
+    need_piv = std::max(need_piv, (size_t)G.nbi * G.n * sizeof(int32_t));
+    if (P.fp32) need_oc = std::max(need_oc, (size_t)d.nn * sizeof(float2));
+    MS_TRY(lu_reserve(ctx, G.n, d.ldm, G.nbi));
+  }
+  if (P.ni == 0) return MS_OK;
+  void *chd, *end, *pmd, *v;
   MS_TRY(workspace(ctx, WS_CH, chh.size() * sizeof(int32_t), &chd));
   MS_TRY(upload(ctx, chd, chh.data(), chh.size() * sizeof(int32_t)));
-  MS_TRY(workspace(ctx, WS_EN, ni * sizeof(double), &end));
-  MS_TRY(upload(ctx, end, energies, ni * sizeof(double)));
-  MS_HIP(ctx, hipMemsetAsync(point_status, 0, ni * sizeof(int32_t), ctx->stream));
-  const int32_t* chk = (const int32_t*)chd;
-  const double* en = (const double*)end;
+  MS_TRY(workspace(ctx, WS_EN, P.ni * sizeof(double), &end));
+  MS_TRY(upload(ctx, end, enh.data(), P.ni * sizeof(double)));
+  MS_TRY(workspace(ctx, WS_PERM, P.ni * sizeof(int64_t), &pmd));
+  MS_TRY(upload(ctx, pmd, permh.data(), P.ni * sizeof(int64_t)));
+  P.ch = (const int32_t*)chd;
+  P.en = (const double*)end;
+  P.perm = (const int64_t*)pmd;
+  MS_TRY(workspace(ctx, WS_RT, P.ni * sizeof(double), &v));
+  P.t = (double*)v;
+  MS_TRY(workspace(ctx, WS_RR, P.ni * sizeof(double), &v));
+  P.r = (double*)v;
+  MS_TRY(workspace(ctx, WS_RNO, P.ni * sizeof(int64_t), &v));
+  P.no = (int64_t*)v;
+  MS_TRY(workspace(ctx, WS_RST, P.ni * sizeof(int32_t), &v));
+  P.st = (int32_t*)v;
+  MS_TRY(workspace(ctx, WS_K, need_k, &v));
+  P.kb = c2(v);
+  MS_TRY(workspace(ctx, WS_P, need_k, &v));
+  P.pb = c2(v);
+  MS_TRY(workspace(ctx, WS_AOP, need_aop, &P.aop));
+  MS_TRY(workspace(ctx, WS_WG, need_wg, &v));
+  P.wg = c2(v);
+  MS_TRY(workspace(ctx, WS_M, need_m, &v));
+  P.mm = c2(v);
+  MS_TRY(workspace(ctx, WS_Y, need_y, &v));
+  P.yb = c2(v);
+  MS_TRY(workspace(ctx, WS_PIV, need_piv, &v));
+  P.piv = (int32_t*)v;
+  if (P.fp32) MS_TRY(workspace(ctx, WS_OC, need_oc, &P.oc));
+  return MS_OK;
+}
 
-  const int ldm = 2 * n + n_o, ldy = n + n_o;
-  const int64_t sM = (int64_t)n * ldm, sY = (int64_t)n * ldy, sk = (int64_t)nrows * n;
-  const size_t per_e = (size_t)(2 * sk) * sizeof(double2) + 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)) +
-                       2 * nn * sizeof(double2) + sM * sizeof(double2) + sY * sizeof(double2) + n * sizeof(int32_t);
-  int nbi = (int)std::max<int64_t>(1, std::min<int64_t>(ni, (int64_t)(BATCH_BUDGET / per_e)));
-  nbi = std::min(nbi, 65535);
-  void *kbv, *pbv, *aop, *wgv, *mmv, *ybv, *pivv, *oc = nullptr;
-  MS_TRY(workspace(ctx, WS_K, (size_t)nbi * sk * sizeof(double2), &kbv));
-  MS_TRY(workspace(ctx, WS_P, (size_t)nbi * sk * sizeof(double2), &pbv));
-  MS_TRY(workspace(ctx, WS_AOP, (size_t)nbi * 2 * nn * (fp32 ? sizeof(float2) : sizeof(double2)), &aop));
-  MS_TRY(workspace(ctx, WS_WG, (size_t)nbi * 2 * nn * sizeof(double2), &wgv));
-  MS_TRY(workspace(ctx, WS_M, (size_t)nbi * sM * sizeof(double2), &mmv));
-  MS_TRY(workspace(ctx, WS_Y, (size_t)nbi * sY * sizeof(double2), &ybv));
-  MS_TRY(workspace(ctx, WS_PIV, (size_t)nbi * n * sizeof(int32_t), &pivv));
-  if (fp32) MS_TRY(workspace(ctx, WS_OC, nn * sizeof(float2), &oc));
-  double2 *kb = c2(kbv), *pb = c2(pbv), *wg = c2(wgv), *mm = c2(mmv), *yb = c2(ybv);
-  int32_t* piv = (int32_t*)pivv;
-  const size_t asz = fp32 ? sizeof(float2) : sizeof(double2);
-
-  for (int64_t i0 = 0; i0 < ni; i0 += nbi) {
-    const int be = (int)std::min<int64_t>(nbi, ni - i0);
-    struct Seg { int k, a, m; };   // slice set k owns local instances [a, a + m)
-    std::vector<Seg> segs;
-    for (int64_t k = i0 / n_e; k * n_e < i0 + be; ++k) {
-      const int64_t lo = std::max<int64_t>(i0, k * n_e), hi = std::min<int64_t>(i0 + be, (k + 1) * n_e);
-      segs.push_back(Seg{(int)k, (int)(lo - i0), (int)(hi - lo)});
-    }
-    for (const Seg& g : segs)
-      MS_TRY(launch_wavevectors(ctx, n, nrows, g.m, sl[g.k].eps, en + i0 + g.a, sl[g.k].dz, kb + g.a * sk,
-                                pb + g.a * sk));
-    for (int p = ns; p >= 0; --p) {
-      const bool first = (p == ns);
-      const double2* kp = kb + (int64_t)p * n;
-      const double2* kq = kb + (int64_t)(p + 1) * n;
-      const double2* pq = pb + (int64_t)(p + 1) * n;
-      if (!first) {
-        MS_TRY(launch_prologue(ctx, n, be, yb, ldy, sY, kq, pq, sk, aop, fp32));
-        for (const Seg& g : segs) {
-          // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
-          // (no per-energy row padding of the last tile); O^T is shared
-          const double2* O = c2(sl[g.k].ovl) + (int64_t)p * nn;
-          GemmArgs q;
-          q.M = 2 * n * g.m; q.N = n; q.K = n;
-          q.A = static_cast<char*>(aop) + (size_t)g.a * 2 * nn * asz; q.lda = n; q.sA = 0; q.opA = OP_N;
-          q.B = O; q.ldb = n; q.sB = 0; q.opB = OP_T;
-          q.C = wg + (int64_t)g.a * 2 * nn; q.ldc = n; q.sC = 0;
-          q.batch = 1;
-          q.prof = PC_IFACE_GEMM;
-          if (fp32) {
-            MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(oc)));
-            q.B = oc;
-            MS_TRY(cgemm32(ctx, q));
-          } else {
-            MS_TRY(zgemm(ctx, q));
-          }
-        }
+ms_status fold_enqueue(ms_ctx ctx, const FoldPlan& P, double* T, double* R, int64_t* n_open, int32_t* status) {
+  if (P.ni == 0) return MS_OK;
+  MS_TRY(launch_fill_i32(ctx, P.ni, P.st, 0));
+  const bool fp32 = P.fp32;
+  for (const FoldGroup& G : P.groups) {
+    const int n = G.n, n_o = G.n_o;
+    const FoldDims d = fold_dims(G, fp32);
+    const int64_t nn = d.nn, sk = d.sk, sM = d.sM, sY = d.sY;
+    for (int64_t i0 = 0; i0 < G.ni; i0 += G.nbi) {
+      const int be = (int)std::min<int64_t>(G.nbi, G.ni - i0);
+      const int64_t g0 = G.inst0 + i0;   // fold-order index of local instance 0
+      struct Seg { int j, a, m, ns; };   // group set j owns local instances [a, a + m)
+      std::vector<Seg> segs;
+      for (int j = 0; j < (int)G.sets.size(); ++j) {
+        const int64_t s0 = G.set_inst0[j] - G.inst0, s1 = s0 + P.sets[G.sets[j]].ne;
+        const int64_t lo = std::max<int64_t>(i0, s0), hi = std::min<int64_t>(i0 + be, s1);
+        if (lo < hi)
+          segs.push_back(Seg{j, (int)(lo - i0), (int)(hi - lo), (int)P.sets[G.sets[j]].sl->n_slices});
       }
       for (const Seg& g : segs) {
-        const double2* O = c2(sl[g.k].ovl) + (int64_t)p * nn;
-        MS_TRY(launch_epilogue(ctx, n, g.m, O, first ? nullptr : wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
-                               kq + g.a * sk, sk, mm + g.a * sM, ldm, sM));
-        MS_TRY(launch_tcols(ctx, n, n_o, g.m, chk + (int64_t)g.k * n_oc, yb + g.a * sY, ldy, sY, n, kq + g.a * sk,
-                            pq + g.a * sk, sk, first ? 1 : 0, mm + g.a * sM, ldm, sM));
+        const ms_slices* sl = P.sets[G.sets[g.j]].sl;
+        const int64_t off = (int64_t)g.a * sk + (int64_t)(G.nsmax - g.ns) * n;
+        MS_TRY(launch_wavevectors(ctx, n, g.ns + 2, g.m, sl->eps, P.en + g0 + g.a, sl->dz, P.kb + off, P.pb + off,
+                                  sk));
       }
-      MS_TRY(getrf_aug(ctx, mm, n, ldm, sM, be, piv, point_status + i0, 1));
-      MS_TRY(trsm_upper_aug(ctx, mm, n, ldm, sM, be, yb, ldy, sY, point_status + i0, 1));
-    }
-    for (const Seg& g : segs) {
-      const double* eps_l = sl[g.k].eps;
-      const double* eps_r = sl[g.k].eps + (int64_t)(ns + 1) * n;
-      MS_TRY(launch_batch_T(ctx, n, (int)chs[g.k].size(), g.m, chk + (int64_t)g.k * n_oc, en + i0 + g.a, eps_l,
-                            eps_r, yb + g.a * sY, ldy, sY, T + i0 + g.a, R + i0 + g.a, n_open + i0 + g.a,
-                            point_status + i0 + g.a));
+      const int smax = segs.front().ns;   // the longest set of the sub-batch comes first
+      for (int s = 0; s <= smax; ++s) {
+        int act = 0;                      // instances still folding: a prefix of the sub-batch
+        for (const Seg& g : segs)
+          if (g.ns >= s) act = g.a + g.m;
+        const int64_t q = G.nsmax - s;    // row of slice p = ns - s in every set
+        const double2* kp = P.kb + q * n;
+        const double2* kq = P.kb + (q + 1) * n;
+        const double2* pq = P.pb + (q + 1) * n;
+        const bool first = (s == 0);
+        if (!first) {
+          MS_TRY(launch_prologue(ctx, n, act, P.yb, d.ldy, sY, kq, pq, sk, P.aop, fp32));
+          for (const Seg& g : segs) {
+            if (g.ns < s) break;
+            // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
+            // (no per-energy row padding of the last tile); O^T is shared
+            const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
+            GemmArgs gm;
+            gm.M = 2 * n * g.m; gm.N = n; gm.K = n;
+            gm.A = static_cast<char*>(P.aop) + (size_t)g.a * 2 * nn * d.asz; gm.lda = n; gm.sA = 0; gm.opA = OP_N;
+            gm.B = O; gm.ldb = n; gm.sB = 0; gm.opB = OP_T;
+            gm.C = P.wg + (int64_t)g.a * 2 * nn; gm.ldc = n; gm.sC = 0;
+            gm.batch = 1;
+            gm.prof = PC_IFACE_GEMM;
+            if (fp32) {
+              MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(P.oc)));
+              gm.B = P.oc;
+              MS_TRY(cgemm32(ctx, gm));
+            } else {
+              MS_TRY(zgemm(ctx, gm));
+            }
+          }
+        }
+        for (const Seg& g : segs) {
+          if (g.ns < s) break;
+          const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
+          MS_TRY(launch_epilogue(ctx, n, g.m, O, first ? nullptr : P.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
+                                 kq + g.a * sk, sk, P.mm + g.a * sM, d.ldm, sM));
+          MS_TRY(launch_tcols(ctx, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, P.yb + g.a * sY, d.ldy, sY, n,
+                              kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, P.mm + g.a * sM, d.ldm, sM));
+        }
+        MS_TRY(getrf_aug(ctx, P.mm, n, d.ldm, sM, act, P.piv, P.st + g0, 1));
+        MS_TRY(trsm_upper_aug(ctx, P.mm, n, d.ldm, sM, act, P.yb, d.ldy, sY, P.st + g0, 1));
+      }
+      for (const Seg& g : segs) {
+        const ms_slices* sl = P.sets[G.sets[g.j]].sl;
+        const double* eps_l = sl->eps;
+        const double* eps_r = sl->eps + (int64_t)(g.ns + 1) * n;
+        const int64_t o = g0 + g.a;
+        MS_TRY(launch_batch_T(ctx, n, G.n_ch[g.j], g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, P.en + o, eps_l, eps_r,
+                              P.yb + g.a * sY, d.ldy, sY, P.t + o, P.r + o, P.no + o, P.st + o));
+      }
     }
   }
+  return launch_scatter_results(ctx, P.ni, P.perm, P.t, P.r, P.no, P.st, T, R, n_open, status);
+}
+
+// plan + enqueue; with `graph` the plan's tables and every scratch buffer come from the
+// graph's own workspace and the enqueue is captured (on the context's capture stream) into
+// one hipGraph, which is launched on the context's stream and kept for ms_graph_replay
+ms_status fold_run(ms_ctx ctx, FoldPlan& P, const double* energies, ms_prec prec, bool graph, double* T, double* R,
+                   int64_t* n_open, int32_t* point_status) {
+  if (!graph) {
+    MS_TRY(fold_plan(ctx, energies, prec, P));
+    return fold_enqueue(ctx, P, T, R, n_open, point_status);
+  }
+  if (ctx->graph) {   // its workspace is about to be reused
+    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    MS_HIP(ctx, hipGraphExecDestroy(ctx->graph));
+    ctx->graph = nullptr;
+  }
+  if (!ctx->cap_stream) MS_HIP(ctx, hipStreamCreate(&ctx->cap_stream));
+  ctx->use_gws = true;
+  ms_status s = fold_plan(ctx, energies, prec, P);
+  if (s != MS_OK) {
+    ctx->use_gws = false;
+    return s;
+  }
+  const hipStream_t main = ctx->stream;
+  // Graphs of up to about 93k kernels (folds of N_G 200-800 with up to 390 slices) have been
+  // captured, instantiated and replayed; a capture of 213k kernels ended the process during
+  // the capture or instantiation, so one capture holds at most MAX_GRAPH_KERNELS (less if
+  // MS_GRAPH_MAX_KERNELS says so).
+  ctx->cap_limit = MAX_GRAPH_KERNELS;
+  if (const char* env = getenv("MS_GRAPH_MAX_KERNELS"))
+    ctx->cap_limit = std::max<int64_t>(1, std::min<int64_t>(MAX_GRAPH_KERNELS, atoll(env)));
+  ctx->cap_kernels = 0;
+  const hipError_t eb = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    ctx->use_gws = false;
+    return hip_fail(ctx, eb, "hipStreamBeginCapture");
+  }
+  ctx->stream = ctx->cap_stream;
+  ctx->capturing = true;
+  s = fold_enqueue(ctx, P, T, R, n_open, point_status);
+  ctx->capturing = false;
+  ctx->use_gws = false;
+  ctx->stream = main;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (s != MS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return hip_fail(ctx, e2, "hipGraphInstantiate");
+  ctx->graph = x;
+  MS_HIP(ctx, hipGraphLaunch(x, ctx->stream));
   return MS_OK;
 }
 
@@ -749,7 +952,9 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
     return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
   if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
   MS_TRY(check_energies(ctx, n_e, energies));
-  return fold_multi(ctx, 1, slices, n_e, energies, prec, T, R, n_open, point_status);
+  FoldPlan P;
+  P.sets.push_back(FoldSet{slices, 0, n_e});
+  return fold_run(ctx, P, energies, prec, false, T, R, n_open, point_status);
 }
 
 ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices, int64_t n_e,
@@ -768,7 +973,41 @@ ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices
   }
   if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
   MS_TRY(check_energies(ctx, n_k * n_e, energies));
-  return fold_multi(ctx, (int)n_k, slices, n_e, energies, prec, T, R, n_open, point_status);
+  FoldPlan P;
+  for (int64_t k = 0; k < n_k; ++k) P.sets.push_back(FoldSet{slices + k, k * n_e, n_e});
+  return fold_run(ctx, P, energies, prec, false, T, R, n_open, point_status);
+}
+
+ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* sets, const int64_t* n_e,
+                                 const double* energies, ms_prec prec, int32_t flags, double* T, double* R,
+                                 int64_t* n_open, int32_t* point_status) {
+  if (!ctx) return MS_ERR_ARG;
+  if (n_sets < 0) return fail(ctx, MS_ERR_ARG, "n_sets must be >= 0");
+  if (n_sets == 0) return MS_OK;
+  if (bad_ptr(sets) || bad_ptr(n_e)) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (flags & ~(int32_t)MS_FOLD_GRAPH) return fail(ctx, MS_ERR_ARG, "unknown flags 0x%x", (unsigned)flags);
+  if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
+  FoldPlan P;
+  int64_t total = 0;
+  for (int64_t k = 0; k < n_sets; ++k) {
+    MS_TRY(check_slices(ctx, sets + k));
+    if (n_e[k] < 0) return fail(ctx, MS_ERR_ARG, "n_e[%lld] < 0", (long long)k);
+    P.sets.push_back(FoldSet{sets + k, total, n_e[k]});
+    total += n_e[k];
+  }
+  if (total == 0) return MS_OK;
+  if (bad_ptr(energies) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open) || bad_ptr(point_status))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  MS_TRY(check_energies(ctx, total, energies));
+  return fold_run(ctx, P, energies, prec, (flags & MS_FOLD_GRAPH) != 0, T, R, n_open, point_status);
+}
+
+ms_status ms_graph_replay(ms_ctx ctx) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!ctx->graph) return fail(ctx, MS_ERR_ARG, "no captured graph on this context");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  MS_HIP(ctx, hipGraphLaunch(ctx->graph, ctx->stream));
+  return MS_OK;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -29,15 +29,33 @@ __device__ __forceinline__ double2 prop(double2 k, double dz) {
 
 // kbuf[e][p][i], pbuf[e][p][i] for p = 0..nrows-1 (nrows = n_slices + 2)
 __global__ void k_wavevectors(int n, int nrows, const double* eps, const double* energies, const double* dz,
-                              double2* kbuf, double2* pbuf) {
+                              double2* kbuf, double2* pbuf, int64_t sk) {
   const int64_t e = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)nrows * n) return;
   const int p = (int)(idx / n);
   const double2 k = kz(energies[e], eps[idx]);
   const double d = (p >= 1 && p <= nrows - 2) ? dz[p - 1] : 0.0;
-  kbuf[e * nrows * n + idx] = k;
-  pbuf[e * nrows * n + idx] = prop(k, d);
+  kbuf[e * sk + idx] = k;
+  pbuf[e * sk + idx] = prop(k, d);
+}
+
+__global__ void k_fill_i32(int64_t count, int32_t* v, int32_t value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) v[i] = value;
+}
+
+// results of instance i (fold order) to the caller's position perm[i]
+__global__ void k_scatter_results(int64_t count, const int64_t* perm, const double* t, const double* r,
+                                  const int64_t* no, const int32_t* st, double* T, double* R, int64_t* n_open,
+                                  int32_t* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int64_t j = perm[i];
+  T[j] = t[i];
+  R[j] = r[i];
+  n_open[j] = no[i];
+  status[j] = st[i];
 }
 
 __device__ __forceinline__ void put(double2* d, double2 v) { *d = v; }
@@ -357,10 +375,26 @@ inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); 
 }  // namespace
 
 ms_status launch_wavevectors(ms_ctx ctx, int n, int nrows, int n_e, const double* eps, const double* energies_dev,
-                             const double* dz, double2* kbuf, double2* pbuf) {
+                             const double* dz, double2* kbuf, double2* pbuf, int64_t sk) {
+  if (sk <= 0) sk = (int64_t)nrows * n;
   hipLaunchKernelGGL(k_wavevectors, dim3(blocks((int64_t)nrows * n), n_e), dim3(256), 0, ctx->stream, n, nrows, eps,
-                     energies_dev, dz, kbuf, pbuf);
+                     energies_dev, dz, kbuf, pbuf, sk);
   return check_launch(ctx, "wavevectors");
+}
+
+ms_status launch_fill_i32(ms_ctx ctx, int64_t count, int32_t* v, int32_t value) {
+  if (count <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, ctx->stream, count, v, value);
+  return check_launch(ctx, "fill");
+}
+
+ms_status launch_scatter_results(ms_ctx ctx, int64_t count, const int64_t* perm, const double* t, const double* r,
+                                 const int64_t* no, const int32_t* st, double* T, double* R, int64_t* n_open,
+                                 int32_t* status) {
+  if (count <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_scatter_results, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, ctx->stream, count, perm,
+                     t, r, no, st, T, R, n_open, status);
+  return check_launch(ctx, "scatter results");
 }
 
 ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t ldy, int64_t sY, const double2* kq,

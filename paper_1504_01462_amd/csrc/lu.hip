@@ -646,6 +646,22 @@ void trailing(ms_ctx ctx, double2* A, int ncols, int64_t strideA, int batch, int
 }
 }  // namespace
 
+// workspace of the LU (slots 30, 31) and of the back substitution (slot 32)
+static size_t lu_tbuf_bytes(int ncols, int batch) {
+  return (size_t)batch * 2 * SWAP_MAX * (size_t)ncols * sizeof(double2);
+}
+static size_t lu_linv_bytes(int batch) { return (size_t)batch * 64 * 64 * sizeof(double2); }
+static size_t trsm_dinv_bytes(int n, int batch) {
+  return (size_t)batch * ((n + 63) / 64) * 64 * 64 * sizeof(double2);
+}
+
+ms_status lu_reserve(ms_ctx ctx, int n, int ncols, int batch) {
+  void* p = nullptr;
+  MS_TRY(workspace(ctx, 30, lu_tbuf_bytes(ncols, batch), &p));
+  MS_TRY(workspace(ctx, 31, lu_linv_bytes(batch), &p));
+  return workspace(ctx, 32, trsm_dinv_bytes(n, batch), &p);
+}
+
 // Two-level right-looking LU.  An outer panel [J0, J1) of up to 128 columns is
 // factored as sub-panels of nb columns touching only its own columns (panel
 // kernel, interchanges + unit-lower solve, update G1 of the outer panel's
@@ -662,15 +678,16 @@ ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, i
   constexpr int OUTER = SWAP_MAX;   // 128-column outer panels: rank-128 trailing updates
   void *tbuf = nullptr, *linv = nullptr;
   const int64_t sT = (int64_t)2 * OUTER * ncols;   // block rows, then the touched rows below
-  MS_TRY(workspace(ctx, 30, (size_t)batch * sT * sizeof(double2), &tbuf));
-  MS_TRY(workspace(ctx, 31, (size_t)batch * 64 * 64 * sizeof(double2), &linv));
+  MS_TRY(workspace(ctx, 30, lu_tbuf_bytes(ncols, batch), &tbuf));
+  MS_TRY(workspace(ctx, 31, lu_linv_bytes(batch), &linv));
 
   // Look-ahead: the panels are factored on a second stream.  After outer panel k,
   // the main stream first updates only the columns of panel k+1 (G3a), which the
   // panel stream then factors while the main stream updates the rest (G3b).
   ms_ctx cp = ctx;
   bool lookahead = false;
-  if (const char* env = getenv("MS_LU_LOOKAHEAD")) lookahead = n > OUTER && ncols > n && atoi(env) != 0;
+  if (const char* env = getenv("MS_LU_LOOKAHEAD"))
+    lookahead = n > OUTER && ncols > n && atoi(env) != 0 && !ctx->capturing;
   hipEvent_t ev_panel = nullptr, ev_next = nullptr;
   if (lookahead) {
     MS_TRY(child(ctx, 0, &cp));
@@ -803,7 +820,7 @@ ms_status trsm_upper_aug(ms_ctx ctx, const double2* A, int n, int ncols, int64_t
   if (batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "trsm batch %d > 65535", batch);
   const int nblk = (n + 63) / 64;
   void* dinv = nullptr;
-  MS_TRY(workspace(ctx, 32, (size_t)batch * nblk * 64 * 64 * sizeof(double2), &dinv));
+  MS_TRY(workspace(ctx, 32, trsm_dinv_bytes(n, batch), &dinv));
   Prof prof(ctx, PC_TRSM, 4.0 * (double)n * n * nrhs * batch, 16.0 * batch * ((double)n * n / 2 + 2.0 * n * nrhs));
   hipLaunchKernelGGL(k_upper_block_inverse, dim3(nblk, batch), dim3(64), 0, ctx->stream, A, n, ncols, strideA, nblk,
                      static_cast<double2*>(dinv), status, sst);

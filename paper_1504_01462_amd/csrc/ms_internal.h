@@ -47,6 +47,16 @@ struct ms_ctx_s {
   std::vector<hipEvent_t> lu_ev;    // look-ahead events of the LU (reused)
   int jacobi_n = -1;                // n of the round-robin schedule held in workspace slot 10
   void* jacobi_pairs = nullptr;
+  bool capturing = false;           // launches go into a hipGraph: no allocation, sync or timing
+  hipStream_t cap_stream = nullptr; // stream the captures are recorded on
+  hipGraphExec_t graph = nullptr;   // the last captured fold, replayable
+  int64_t cap_kernels = 0;          // kernels recorded by the open capture
+  int64_t cap_limit = 0;            // most kernels one capture may hold
+  // workspace owned by the captured graph (its tables and scratch), so that later calls on
+  // the context, which use `ws`, neither overwrite nor free what a replay reads
+  std::vector<void*> gws;
+  std::vector<size_t> gws_size;
+  bool use_gws = false;
 };
 
 namespace ms {
@@ -146,7 +156,14 @@ ms_status launch_minmax(ms_ctx ctx, int64_t count, const int32_t* v, int32_t* ou
 // copy `bytes` of host data to device memory and wait (the host buffer may be temporary)
 ms_status upload(ms_ctx ctx, void* dst, const void* src, size_t bytes);
 
+// k and P of rows [0, nrows) for n_e energies; instance e writes kbuf + e * sk (sk <= 0: nrows * n)
 ms_status launch_wavevectors(ms_ctx ctx, int n, int nrows, int n_e, const double* eps, const double* energies_dev,
-                             const double* dz_rows, double2* kbuf, double2* pbuf);
+                             const double* dz_rows, double2* kbuf, double2* pbuf, int64_t sk = 0);
+ms_status launch_fill_i32(ms_ctx ctx, int64_t count, int32_t* v, int32_t value);
+ms_status launch_scatter_results(ms_ctx ctx, int64_t count, const int64_t* perm, const double* t, const double* r,
+                                 const int64_t* no, const int32_t* st, double* T, double* R, int64_t* n_open,
+                                 int32_t* status);
+// workspace of getrf_aug and trsm_upper_aug for `batch` matrices, grown ahead (before a capture)
+ms_status lu_reserve(ms_ctx ctx, int n, int ncols, int batch);
 
 }  // namespace ms

@@ -91,3 +91,34 @@ def test_config3_slices_sampled_against_oracle(ms, full):
         assert np.max(np.abs(o - u.conj().T @ un)) < 1e-12, p
     del s
     torch.cuda.empty_cache()
+
+
+def test_uneven_instances_config4_sample(ms, full):
+    """Instances of the uneven workload at their real sizes (N_G 200 / 450 / 800 with 150-390
+    slices, one energy each), folded in one captured graph: every instance equals its own
+    ms_transmission_batch, conserves current, the FP32 form stays near it, and the cheapest
+    instance matches the oracle."""
+    import oracle as orc
+    ctx = full["ctx"]
+    inst = msgen.config4_instances()
+    pick = [3, 7, 10, 6, 12, 13]                    # n_g 200, 450, 200, 800, 200, 450
+    inps, sets, es = [], [], []
+    for i in pick:
+        j = inst[i]["junction"]
+        inp = msgen.junction_inputs(j, j.kpars[inst[i]["k_index"]])
+        inps.append(inp)
+        sets.append(ms.prepare_from_inputs(ctx, inp))
+        es.append([inst[i]["energy"]])
+    T, R, no, st = (x.cpu().numpy() for x in ms.ms_transmission_uneven(ctx, sets, es, "fp64", graph=True))
+    T32 = ms.ms_transmission_uneven(ctx, sets, es, "fp32", graph=True)[0].cpu().numpy()
+    ctx.sync()
+    assert np.all(st == 0)
+    assert np.max(np.abs(T + R - no)) < 1e-8
+    for k, s in enumerate(sets):
+        t1 = ms.ms_transmission_batch(ctx, s, es[k], "fp64")[0].cpu().numpy()
+        ctx.sync()
+        assert abs(T[k] - t1[0]) < 1e-11, k
+    assert np.max(np.abs(T32 - T)) < 1e-3
+    k = pick.index(12)                              # n_g = 200, 248 slices
+    ref = orc.transmission(orc.prepare(inps[k]), es[k][0])
+    assert abs(T[k] - ref["T"]) < 1e-10 and int(no[k]) == ref["n_open"]

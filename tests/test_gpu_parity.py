@@ -402,3 +402,112 @@ def test_transmission_multi_argument_errors(ms, ctx, c1):
         ms.ms_transmission_multi(ctx, [a, b], np.ones((2, 3)) * 0.5)
     with pytest.raises(ms.MSError):
         ms.ms_transmission_multi(ctx, [a, a], np.array([[0.5, np.nan], [0.5, 0.6]]))
+
+
+# ------------------------------------------------------------------ uneven slice sets -----
+def _uneven_sets(ms, ctx):
+    """Slice sets of two basis sizes (37 and 21 plane waves) and four slice counts, each
+    with its own energies (the cell of config1, k_par off the symmetry point)."""
+    out = []
+    for n_g, ns, es in ((37, 24, [0.3, 0.9]), (21, 9, [0.5]), (37, 5, [0.2, 0.6, 1.4]), (21, 13, [0.75, 2.5])):
+        j = msgen.config1()
+        j.dz = np.full(ns, 6.0 / ns)
+        inp = msgen.junction_inputs(j, (0.07, -0.11), n_g)
+        out.append((inp, ms.prepare_from_inputs(ctx, inp), np.array(es)))
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_transmission_uneven_matches_batch_and_oracle(ms, ctx, graph):
+    sets = _uneven_sets(ms, ctx)
+    T, R, no, st = ms.ms_transmission_uneven(ctx, [s for _, s, _ in sets], [e for _, _, e in sets], "fp64",
+                                             graph=graph)
+    ctx.sync()
+    Tn, Rn, non, stn = (_np(x) for x in (T, R, no, st))
+    assert np.all(stn == 0)
+    off = 0
+    for inp, s, es in sets:
+        sl = slice(off, off + len(es))
+        t1, r1, n1, s1 = (_np(x) for x in ms.ms_transmission_batch(ctx, s, es, "fp64"))
+        ctx.sync()
+        assert np.all(s1 == 0)
+        assert np.max(np.abs(Tn[sl] - t1)) < 1e-12 and np.max(np.abs(Rn[sl] - r1)) < 1e-12
+        assert np.array_equal(non[sl], n1)
+        prep = orc.prepare(inp)
+        for i, e in enumerate(es):
+            ref = orc.transmission(prep, e)
+            assert abs(Tn[off + i] - ref["T"]) < 1e-10 and abs(Rn[off + i] - ref["R"]) < 1e-10
+            assert non[off + i] == ref["n_open"]
+        off += len(es)
+    if graph:
+        # every replay of the captured graph rewrites the same outputs, with eager work between
+        ref_t, ref_r = T.clone(), R.clone()
+        for _ in range(3):
+            T.zero_()
+            R.fill_(-1.0)
+            torch.cuda.synchronize()
+            ms.ms_graph_replay(ctx)
+            ctx.sync()
+            assert torch.equal(T, ref_t) and torch.equal(R, ref_r)
+            assert torch.all(st == 0)
+
+
+def test_transmission_uneven_fp32_form(ms, ctx):
+    sets = _uneven_sets(ms, ctx)
+    args = ([s for _, s, _ in sets], [e for _, _, e in sets])
+    T64 = _np(ms.ms_transmission_uneven(ctx, *args, "fp64")[0])
+    T32, R32, no32, st32 = (_np(x) for x in ms.ms_transmission_uneven(ctx, *args, "fp32", graph=True))
+    ctx.sync()
+    assert np.all(st32 == 0)
+    assert np.max(np.abs(T32 - T64)) < 1e-5
+    assert np.max(np.abs(T32 + R32 - no32)) < 1e-4
+
+
+def test_transmission_uneven_errors_and_empty(ms, ctx, c1):
+    import ctypes
+    _, inp, _ = c1
+    s = ms.prepare_from_inputs(ctx, inp)
+    # a set with no energies is skipped; the others are computed
+    T, R, no, st = ms.ms_transmission_uneven(ctx, [s, s], [[], [0.4]])
+    ctx.sync()
+    assert T.shape == (1,) and int(_np(st)[0]) == 0
+    ref = _np(ms.ms_transmission_batch(ctx, s, [0.4])[0])
+    assert abs(_np(T)[0] - ref[0]) < 1e-13
+    arr = (ms.MsSlices * 1)(s.c)
+    ne = np.array([1], dtype=np.int64)
+    e = np.array([0.4])
+    out = [torch.empty(1, dtype=dt, device="cuda") for dt in (torch.float64, torch.float64, torch.int64, torch.int32)]
+    ptrs = [ctypes.c_void_p(x.data_ptr()) for x in out]
+    rc = ms.lib.ms_transmission_uneven(ctx.handle, 1, arr, ne.ctypes.data_as(ctypes.c_void_p),
+                                       e.ctypes.data_as(ctypes.c_void_p), 0, 2, *ptrs)
+    assert rc == ms.MS_ERR_ARG                       # unknown flag
+    ne[0] = -1
+    rc = ms.lib.ms_transmission_uneven(ctx.handle, 1, arr, ne.ctypes.data_as(ctypes.c_void_p),
+                                       e.ctypes.data_as(ctypes.c_void_p), 0, 0, *ptrs)
+    assert rc == ms.MS_ERR_ARG                       # negative count
+    fresh = ms.Context(0)
+    try:
+        with pytest.raises(ms.MSError) as ei:
+            ms.ms_graph_replay(fresh)
+        assert ei.value.status == ms.MS_ERR_ARG
+    finally:
+        fresh.close()
+
+
+def test_transmission_uneven_graph_budget(ms, ctx):
+    """A fold needing more kernels than one graph may hold fails before anything is
+    launched, and the context keeps working (direct and captured calls)."""
+    import os
+    sets = _uneven_sets(ms, ctx)
+    args = ([s for _, s, _ in sets], [e for _, _, e in sets])
+    os.environ["MS_GRAPH_MAX_KERNELS"] = "50"
+    try:
+        with pytest.raises(ms.MSError) as ei:
+            ms.ms_transmission_uneven(ctx, *args, "fp64", graph=True)
+        assert ei.value.status == ms.MS_ERR_UNSUPPORTED
+    finally:
+        os.environ.pop("MS_GRAPH_MAX_KERNELS", None)
+    T1 = _np(ms.ms_transmission_uneven(ctx, *args, "fp64")[0])
+    T2 = _np(ms.ms_transmission_uneven(ctx, *args, "fp64", graph=True)[0])
+    ctx.sync()
+    assert np.array_equal(T1, T2)
