@@ -182,7 +182,7 @@ def uneven_measure(ms, ctx, count, log, replays=2):
     N_G drawn from {200, 450, 800, 1200}, 100-400 slices and one (E, k_par) each.  Their
     slice eigenproblems and overlaps are prepared instance by instance (timed), then all
     instances are folded in one call, in the FP32-MFMA form and in FP64 (timed; |dT| between
-    the forms per instance).  The instances with N_G <= 450 are also folded in one captured
+    the forms per instance), with GEMM tile edges chosen per basis size by ms_autotune.  The instances with N_G <= 450 are also folded in one captured
     hipGraph, whose replays are timed and checked against the direct call: a graph holds at
     most 96000 kernels, which the whole set (about 213000) exceeds."""
     import torch
@@ -209,6 +209,17 @@ def uneven_measure(ms, ctx, count, log, replays=2):
     prep_s = time.perf_counter() - t0
     log(f"uneven: {count} instances prepared in {prep_s:.2f} s")
     es = [[x["e"]] for x in staged]
+    # GEMM tile edges per basis size, timed on synthetic systems of the group's batch
+    tuned = {}
+    t0 = time.perf_counter()
+    for n_g in sorted({x["n_g"] for x in staged}):
+        nb = sum(1 for x in staged if x["n_g"] == n_g)
+        choice, times = ms.ms_autotune(ctx, n_g, 8, nb)
+        tuned[str(n_g)] = dict(batch=nb, choice=choice, lu_ms=[round(v, 3) for v in times[:4]],
+                               iface_ms=[round(v, 3) for v in times[4:]])
+    tune_s = time.perf_counter() - t0
+    log(f"uneven: autotuned {len(tuned)} basis sizes in {tune_s:.2f} s: "
+        + ", ".join(f"{k}: {v['choice']}" for k, v in tuned.items()))
     out = {}
     for prec in ("fp32", "fp64"):
         ms.ms_transmission_uneven(ctx, bufs, es, prec)          # warm: workspace
@@ -232,6 +243,7 @@ def uneven_measure(ms, ctx, count, log, replays=2):
         "n_g_mix": mix,
         "slices_total": int(sum(x["ns"] for x in staged)),
         "prepare_s": round(prep_s, 4),
+        "autotune": {"seconds": round(tune_s, 3), "per_n_g": tuned},
         "fold_s": {"fp32": round(d32["s"], 4), "fp64": round(d64["s"], 4)},
         "instances_per_s_fold": {"fp32": round(count / d32["s"], 3), "fp64": round(count / d64["s"], 3)},
         "instances_per_s_end_to_end": {"fp32": round(count / (prep_s + d32["s"]), 3),

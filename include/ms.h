@@ -235,6 +235,30 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
                                  const double* energies, ms_prec prec, int32_t flags, double* T, double* R,
                                  int64_t* n_open, int32_t* point_status);
 
+/* Tile edges of the fold's complex GEMMs for one basis size: 64 (64 x 64 tiles, 4 waves) or
+ * 128 (128 x 128 tiles, 8 waves); 0 = the default rule (128 for the LU's trailing update and
+ * for products of at least 128 x 128, else 64).  Roles: the interface product (Sec. II, the
+ * star product with the accumulated right part), the LU's rank-128 trailing update, and its
+ * in-panel and U12 products.  Both shapes accumulate every element in the same order, so the
+ * edges change run time only, never a result. */
+typedef struct {
+  int32_t iface, lu_update, lu_inner;
+} ms_tiles;
+
+/* Use `tiles` for every fold group of basis size n_g on this context.
+ * Errors: MS_ERR_ARG (n_g < 1, an edge other than 0, 64, 128, NULL). */
+ms_status ms_set_tiles(ms_ctx ctx, int64_t n_g, const ms_tiles* tiles);
+
+/* Autotuner: for basis size n_g, n_open open channels and `batch` systems per fold step
+ * (at most 64 are used), time on the device the LU factorisation + back substitution of
+ * synthetic augmented systems (n_g x (2 n_g + n_open), dominant diagonal) with each pair of
+ * (trailing-update, in-panel) edges and the stacked interface product with each edge, best
+ * of two runs each; record the fastest per role for n_g (as ms_set_tiles) and return them in
+ * `chosen`.  times_ms (optional, host [6]): LU 64/64, 64/128, 128/64, 128/128, interface 64,
+ * interface 128.  Waits for the stream.  Workspace: about batch (5 n_g^2 + n_g n_open) c128.
+ * Errors: MS_ERR_ARG, MS_ERR_UNSUPPORTED (inside a capture), MS_ERR_ALLOC, MS_ERR_HIP. */
+ms_status ms_autotune(ms_ctx ctx, int64_t n_g, int64_t n_open, int64_t batch, ms_tiles* chosen, double* times_ms);
+
 /* Launch the graph captured by the last ms_transmission_uneven(..., MS_FOLD_GRAPH, ...) on
  * this context again, on the context's stream: the same slice data, energies, channel
  * lists and output buffers (their contents may have changed; the sizes may not).

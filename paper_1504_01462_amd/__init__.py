@@ -62,6 +62,14 @@ _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_uneven", [_vp, _i64, ctypes.POINTER(MsSlices), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_graph_replay", [_vp])
+
+
+class MsTiles(ctypes.Structure):
+    _fields_ = [("iface", _i32), ("lu_update", _i32), ("lu_inner", _i32)]
+
+
+_sig("ms_set_tiles", [_vp, _i64, ctypes.POINTER(MsTiles)])
+_sig("ms_autotune", [_vp, _i64, _i64, _i64, ctypes.POINTER(MsTiles), _vp])
 _sig("ms_kpar_average", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 _sig("ms_mixed_doubling", [_vp, ctypes.POINTER(MsSlices), _f64, _f64, ctypes.POINTER(MsSmat), ctypes.POINTER(_i32)])
 _sig("ms_debug_profile", [_vp, ctypes.c_uint32])
@@ -285,6 +293,23 @@ def ms_graph_replay(ctx: Context):
     _check(ctx.handle, lib.ms_graph_replay(ctx.handle))
 
 
+def ms_set_tiles(ctx: Context, n_g: int, iface: int = 0, lu_update: int = 0, lu_inner: int = 0):
+    """GEMM tile edges (64, 128, or 0 = default rule) for folds of basis size n_g."""
+    t = MsTiles(iface, lu_update, lu_inner)
+    _check(ctx.handle, lib.ms_set_tiles(ctx.handle, int(n_g), ctypes.byref(t)))
+
+
+def ms_autotune(ctx: Context, n_g: int, n_open: int, batch: int):
+    """Time both tile edges per GEMM role on synthetic systems of basis size n_g and keep the
+    fastest for later folds of that size.  Returns (choice dict, times in ms: LU 64/64,
+    64/128, 128/64, 128/128, interface 64, interface 128)."""
+    t = MsTiles()
+    times = np.zeros(6, dtype=np.float64)
+    _check(ctx.handle, lib.ms_autotune(ctx.handle, int(n_g), int(n_open), int(batch), ctypes.byref(t),
+                                       times.ctypes.data_as(ctypes.c_void_p)))
+    return dict(iface=t.iface, lu_update=t.lu_update, lu_inner=t.lu_inner), times.tolist()
+
+
 def ms_kpar_average(ctx: Context, T: torch.Tensor, n_open: torch.Tensor):
     """T, n_open: [n_k][n_e] device tensors -> (tbar [n_e], per_channel [n_e])."""
     n_k, n_e = T.shape
@@ -391,6 +416,6 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
            "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
-           "MS_FOLD_GRAPH", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
+           "MS_FOLD_GRAPH", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

@@ -649,6 +649,11 @@ struct FoldGroup {          // the sets of one n_g, longest first
   std::vector<int64_t> set_inst0;   // first instance of each set (fold order)
   int64_t inst0 = 0, ni = 0;        // the group's instances [inst0, inst0 + ni)
   int64_t ch0 = 0;                  // channel table [sets][n_oc] at ch0 of the channel buffer
+  ms_ctx run = nullptr;             // context (stream, workspace) the group is enqueued on
+  double cost = 0.0;                // n^3 x fold steps x instances, for placing groups on streams
+  double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
+  void *aop = nullptr, *oc = nullptr;
+  int32_t* piv = nullptr;
 };
 
 struct FoldPlan {
@@ -663,9 +668,7 @@ struct FoldPlan {
   double* r = nullptr;
   int64_t* no = nullptr;
   int32_t* st = nullptr;
-  double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
-  void *aop = nullptr, *oc = nullptr;
-  int32_t* piv = nullptr;
+  int n_run = 0;                   // internal streams the groups are spread over (0: all on ctx)
 };
 
 struct FoldDims {
@@ -689,6 +692,16 @@ FoldDims fold_dims(const FoldGroup& G, bool fp32) {
   return d;
 }
 
+// the reusable fork/join events of the context (created outside any capture)
+ms_status sync_events(ms_ctx ctx, size_t count) {
+  while (ctx->sync_ev.size() < count) {
+    hipEvent_t e = nullptr;
+    MS_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->sync_ev.push_back(e);
+  }
+  return MS_OK;
+}
+
 ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& P) {
   MS_HIP(ctx, hipSetDevice(ctx->device));
   P.fp32 = prec == MS_PREC_FP32_MFMA;
@@ -707,7 +720,6 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
   std::vector<int32_t> chh;
   std::vector<double> enh;
   std::vector<int64_t> permh;
-  size_t need_k = 0, need_aop = 0, need_wg = 0, need_m = 0, need_y = 0, need_piv = 0, need_oc = 0;
   std::vector<double> er;
   for (FoldGroup& G : P.groups) {
     std::stable_sort(G.sets.begin(), G.sets.end(),
@@ -745,19 +757,90 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
       P.ni += fs.ne;
     }
     G.ni = P.ni - G.inst0;
-    const FoldDims d = fold_dims(G, P.fp32);
-    int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, (int64_t)(BATCH_BUDGET / d.per_e)));
-    G.nbi = (int)std::min<int64_t>(nbi, 65535);
-    need_k = std::max(need_k, (size_t)G.nbi * d.sk * sizeof(double2));
-    need_aop = std::max(need_aop, (size_t)G.nbi * 2 * d.nn * d.asz);
-    need_wg = std::max(need_wg, (size_t)G.nbi * 2 * d.nn * sizeof(double2));
-    need_m = std::max(need_m, (size_t)G.nbi * d.sM * sizeof(double2));
-    need_y = std::max(need_y, (size_t)G.nbi * d.sY * sizeof(double2));
-    need_piv = std::max(need_piv, (size_t)G.nbi * G.n * sizeof(int32_t));
-    if (P.fp32) need_oc = std::max(need_oc, (size_t)d.nn * sizeof(float2));
-    MS_TRY(lu_reserve(ctx, G.n, d.ldm, G.nbi));
+    for (int k : G.sets) G.cost += (double)G.n * G.n * G.n * (P.sets[k].sl->n_slices + 1) * P.sets[k].ne;
   }
   if (P.ni == 0) return MS_OK;
+  // Groups of different n_g are independent: with several, they are spread over up to
+  // three internal contexts (own stream and workspace), heaviest first onto the least
+  // loaded, and run concurrently (MS_FOLD_GROUP_STREAMS=0 keeps them on the caller's stream).
+  {
+    bool spread = P.groups.size() > 1;
+    if (const char* env = getenv("MS_FOLD_GROUP_STREAMS")) spread = spread && atoi(env) != 0;
+    P.n_run = spread ? (int)std::min<size_t>(3, P.groups.size()) : 0;
+    std::vector<int> order(P.groups.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.groups[a].cost > P.groups[b].cost; });
+    std::vector<double> load(std::max(1, P.n_run), 0.0);
+    for (int gi : order) {
+      FoldGroup& G = P.groups[gi];
+      if (P.n_run == 0) {
+        G.run = ctx;
+        continue;
+      }
+      const int r = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[r] += G.cost;
+      MS_TRY(child(ctx, r, &G.run));
+      G.run->tiles = ctx->tiles;
+      G.run->use_gws = ctx->use_gws;
+    }
+    if (P.n_run > 0) MS_TRY(sync_events(ctx, 1 + P.n_run));
+  }
+  // each group's scratch comes from its runner's workspace; a runner that serves several
+  // groups (one after the other on its stream) is first grown to the largest need per slot,
+  // so no later request moves a buffer an earlier group already holds
+  const int slots[7] = {WS_K, WS_P, WS_AOP, WS_WG, WS_M, WS_Y, WS_PIV};
+  auto needs = [&](FoldGroup& G, size_t* nd) {
+    const FoldDims d = fold_dims(G, P.fp32);
+    const int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, (int64_t)(BATCH_BUDGET / d.per_e)));
+    G.nbi = (int)std::min<int64_t>(nbi, 65535);
+    nd[0] = nd[1] = (size_t)G.nbi * d.sk * sizeof(double2);
+    nd[2] = (size_t)G.nbi * 2 * d.nn * d.asz;
+    nd[3] = (size_t)G.nbi * 2 * d.nn * sizeof(double2);
+    nd[4] = (size_t)G.nbi * d.sM * sizeof(double2);
+    nd[5] = (size_t)G.nbi * d.sY * sizeof(double2);
+    nd[6] = (size_t)G.nbi * G.n * sizeof(int32_t);
+    return d;
+  };
+  for (FoldGroup& G : P.groups) {   // pass 1: grow every runner to its groups' largest needs
+    size_t nd[7];
+    const FoldDims d = needs(G, nd);
+    void* v;
+    for (int i = 0; i < 7; ++i) {
+      size_t most = nd[i];
+      for (FoldGroup& H : P.groups)
+        if (H.run == G.run) {
+          size_t nh[7];
+          needs(H, nh);
+          most = std::max(most, nh[i]);
+        }
+      MS_TRY(workspace(G.run, slots[i], most, &v));
+    }
+    if (P.fp32) {
+      size_t most = (size_t)d.nn * sizeof(float2);
+      for (const FoldGroup& H : P.groups)
+        if (H.run == G.run) most = std::max(most, (size_t)H.n * H.n * sizeof(float2));
+      MS_TRY(workspace(G.run, WS_OC, most, &v));
+    }
+    MS_TRY(lu_reserve(G.run, G.n, d.ldm, G.nbi));
+  }
+  for (FoldGroup& G : P.groups) {   // pass 2: take the pointers (no slot grows any more)
+    ms_ctx c = G.run;
+    void* v;
+    MS_TRY(workspace(c, WS_K, 1, &v));
+    G.kb = c2(v);
+    MS_TRY(workspace(c, WS_P, 1, &v));
+    G.pb = c2(v);
+    MS_TRY(workspace(c, WS_AOP, 1, &G.aop));
+    MS_TRY(workspace(c, WS_WG, 1, &v));
+    G.wg = c2(v);
+    MS_TRY(workspace(c, WS_M, 1, &v));
+    G.mm = c2(v);
+    MS_TRY(workspace(c, WS_Y, 1, &v));
+    G.yb = c2(v);
+    MS_TRY(workspace(c, WS_PIV, 1, &v));
+    G.piv = (int32_t*)v;
+    if (P.fp32) MS_TRY(workspace(c, WS_OC, 1, &G.oc));
+  }
   void *chd, *end, *pmd, *v;
   MS_TRY(workspace(ctx, WS_CH, chh.size() * sizeof(int32_t), &chd));
   MS_TRY(upload(ctx, chd, chh.data(), chh.size() * sizeof(int32_t)));
@@ -776,102 +859,125 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
   P.no = (int64_t*)v;
   MS_TRY(workspace(ctx, WS_RST, P.ni * sizeof(int32_t), &v));
   P.st = (int32_t*)v;
-  MS_TRY(workspace(ctx, WS_K, need_k, &v));
-  P.kb = c2(v);
-  MS_TRY(workspace(ctx, WS_P, need_k, &v));
-  P.pb = c2(v);
-  MS_TRY(workspace(ctx, WS_AOP, need_aop, &P.aop));
-  MS_TRY(workspace(ctx, WS_WG, need_wg, &v));
-  P.wg = c2(v);
-  MS_TRY(workspace(ctx, WS_M, need_m, &v));
-  P.mm = c2(v);
-  MS_TRY(workspace(ctx, WS_Y, need_y, &v));
-  P.yb = c2(v);
-  MS_TRY(workspace(ctx, WS_PIV, need_piv, &v));
-  P.piv = (int32_t*)v;
-  if (P.fp32) MS_TRY(workspace(ctx, WS_OC, need_oc, &P.oc));
+  return MS_OK;
+}
+
+// the kernels of one group, on its runner's stream
+ms_status enqueue_group(ms_ctx c, const FoldPlan& P, const FoldGroup& G) {
+  const bool fp32 = P.fp32;
+  const int n = G.n, n_o = G.n_o;
+  const FoldDims d = fold_dims(G, fp32);
+  const int64_t nn = d.nn, sk = d.sk, sM = d.sM, sY = d.sY;
+  for (int64_t i0 = 0; i0 < G.ni; i0 += G.nbi) {
+    const int be = (int)std::min<int64_t>(G.nbi, G.ni - i0);
+    const int64_t g0 = G.inst0 + i0;   // fold-order index of local instance 0
+    struct Seg { int j, a, m, ns; };   // group set j owns local instances [a, a + m)
+    std::vector<Seg> segs;
+    for (int j = 0; j < (int)G.sets.size(); ++j) {
+      const int64_t s0 = G.set_inst0[j] - G.inst0, s1 = s0 + P.sets[G.sets[j]].ne;
+      const int64_t lo = std::max<int64_t>(i0, s0), hi = std::min<int64_t>(i0 + be, s1);
+      if (lo < hi) segs.push_back(Seg{j, (int)(lo - i0), (int)(hi - lo), (int)P.sets[G.sets[j]].sl->n_slices});
+    }
+    for (const Seg& g : segs) {
+      const ms_slices* sl = P.sets[G.sets[g.j]].sl;
+      const int64_t off = (int64_t)g.a * sk + (int64_t)(G.nsmax - g.ns) * n;
+      MS_TRY(launch_wavevectors(c, n, g.ns + 2, g.m, sl->eps, P.en + g0 + g.a, sl->dz, G.kb + off, G.pb + off, sk));
+    }
+    const int smax = segs.front().ns;   // the longest set of the sub-batch comes first
+    for (int s = 0; s <= smax; ++s) {
+      int act = 0;                      // instances still folding: a prefix of the sub-batch
+      for (const Seg& g : segs)
+        if (g.ns >= s) act = g.a + g.m;
+      const int64_t q = G.nsmax - s;    // row of slice p = ns - s in every set
+      const double2* kp = G.kb + q * n;
+      const double2* kq = G.kb + (q + 1) * n;
+      const double2* pq = G.pb + (q + 1) * n;
+      const bool first = (s == 0);
+      if (!first) {
+        MS_TRY(launch_prologue(c, n, act, G.yb, d.ldy, sY, kq, pq, sk, G.aop, fp32));
+        for (const Seg& g : segs) {
+          if (g.ns < s) break;
+          // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
+          // (no per-energy row padding of the last tile); O^T is shared
+          const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
+          GemmArgs gm;
+          gm.M = 2 * n * g.m; gm.N = n; gm.K = n;
+          gm.A = static_cast<char*>(G.aop) + (size_t)g.a * 2 * nn * d.asz; gm.lda = n; gm.sA = 0; gm.opA = OP_N;
+          gm.B = O; gm.ldb = n; gm.sB = 0; gm.opB = OP_T;
+          gm.C = G.wg + (int64_t)g.a * 2 * nn; gm.ldc = n; gm.sC = 0;
+          gm.batch = 1;
+          gm.prof = PC_IFACE_GEMM;
+          if (fp32) {
+            MS_TRY(launch_to_c64(c, nn, O, static_cast<float2*>(G.oc)));
+            gm.B = G.oc;
+            MS_TRY(cgemm32(c, gm));
+          } else {
+            MS_TRY(zgemm(c, gm));
+          }
+        }
+      }
+      for (const Seg& g : segs) {
+        if (g.ns < s) break;
+        const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
+        MS_TRY(launch_epilogue(c, n, g.m, O, first ? nullptr : G.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
+                               kq + g.a * sk, sk, G.mm + g.a * sM, d.ldm, sM));
+        MS_TRY(launch_tcols(c, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, G.yb + g.a * sY, d.ldy, sY, n,
+                            kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, G.mm + g.a * sM, d.ldm, sM));
+      }
+      MS_TRY(getrf_aug(c, G.mm, n, d.ldm, sM, act, G.piv, P.st + g0, 1));
+      MS_TRY(trsm_upper_aug(c, G.mm, n, d.ldm, sM, act, G.yb, d.ldy, sY, P.st + g0, 1));
+    }
+    for (const Seg& g : segs) {
+      const ms_slices* sl = P.sets[G.sets[g.j]].sl;
+      const double* eps_l = sl->eps;
+      const double* eps_r = sl->eps + (int64_t)(g.ns + 1) * n;
+      const int64_t o = g0 + g.a;
+      MS_TRY(launch_batch_T(c, n, G.n_ch[g.j], g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, P.en + o, eps_l, eps_r,
+                            G.yb + g.a * sY, d.ldy, sY, P.t + o, P.r + o, P.no + o, P.st + o));
+    }
+  }
   return MS_OK;
 }
 
 ms_status fold_enqueue(ms_ctx ctx, const FoldPlan& P, double* T, double* R, int64_t* n_open, int32_t* status) {
   if (P.ni == 0) return MS_OK;
   MS_TRY(launch_fill_i32(ctx, P.ni, P.st, 0));
-  const bool fp32 = P.fp32;
-  for (const FoldGroup& G : P.groups) {
-    const int n = G.n, n_o = G.n_o;
-    const FoldDims d = fold_dims(G, fp32);
-    const int64_t nn = d.nn, sk = d.sk, sM = d.sM, sY = d.sY;
-    for (int64_t i0 = 0; i0 < G.ni; i0 += G.nbi) {
-      const int be = (int)std::min<int64_t>(G.nbi, G.ni - i0);
-      const int64_t g0 = G.inst0 + i0;   // fold-order index of local instance 0
-      struct Seg { int j, a, m, ns; };   // group set j owns local instances [a, a + m)
-      std::vector<Seg> segs;
-      for (int j = 0; j < (int)G.sets.size(); ++j) {
-        const int64_t s0 = G.set_inst0[j] - G.inst0, s1 = s0 + P.sets[G.sets[j]].ne;
-        const int64_t lo = std::max<int64_t>(i0, s0), hi = std::min<int64_t>(i0 + be, s1);
-        if (lo < hi)
-          segs.push_back(Seg{j, (int)(lo - i0), (int)(hi - lo), (int)P.sets[G.sets[j]].sl->n_slices});
-      }
-      for (const Seg& g : segs) {
-        const ms_slices* sl = P.sets[G.sets[g.j]].sl;
-        const int64_t off = (int64_t)g.a * sk + (int64_t)(G.nsmax - g.ns) * n;
-        MS_TRY(launch_wavevectors(ctx, n, g.ns + 2, g.m, sl->eps, P.en + g0 + g.a, sl->dz, P.kb + off, P.pb + off,
-                                  sk));
-      }
-      const int smax = segs.front().ns;   // the longest set of the sub-batch comes first
-      for (int s = 0; s <= smax; ++s) {
-        int act = 0;                      // instances still folding: a prefix of the sub-batch
-        for (const Seg& g : segs)
-          if (g.ns >= s) act = g.a + g.m;
-        const int64_t q = G.nsmax - s;    // row of slice p = ns - s in every set
-        const double2* kp = P.kb + q * n;
-        const double2* kq = P.kb + (q + 1) * n;
-        const double2* pq = P.pb + (q + 1) * n;
-        const bool first = (s == 0);
-        if (!first) {
-          MS_TRY(launch_prologue(ctx, n, act, P.yb, d.ldy, sY, kq, pq, sk, P.aop, fp32));
-          for (const Seg& g : segs) {
-            if (g.ns < s) break;
-            // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
-            // (no per-energy row padding of the last tile); O^T is shared
-            const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
-            GemmArgs gm;
-            gm.M = 2 * n * g.m; gm.N = n; gm.K = n;
-            gm.A = static_cast<char*>(P.aop) + (size_t)g.a * 2 * nn * d.asz; gm.lda = n; gm.sA = 0; gm.opA = OP_N;
-            gm.B = O; gm.ldb = n; gm.sB = 0; gm.opB = OP_T;
-            gm.C = P.wg + (int64_t)g.a * 2 * nn; gm.ldc = n; gm.sC = 0;
-            gm.batch = 1;
-            gm.prof = PC_IFACE_GEMM;
-            if (fp32) {
-              MS_TRY(launch_to_c64(ctx, nn, O, static_cast<float2*>(P.oc)));
-              gm.B = P.oc;
-              MS_TRY(cgemm32(ctx, gm));
-            } else {
-              MS_TRY(zgemm(ctx, gm));
-            }
-          }
-        }
-        for (const Seg& g : segs) {
-          if (g.ns < s) break;
-          const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
-          MS_TRY(launch_epilogue(ctx, n, g.m, O, first ? nullptr : P.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
-                                 kq + g.a * sk, sk, P.mm + g.a * sM, d.ldm, sM));
-          MS_TRY(launch_tcols(ctx, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, P.yb + g.a * sY, d.ldy, sY, n,
-                              kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, P.mm + g.a * sM, d.ldm, sM));
-        }
-        MS_TRY(getrf_aug(ctx, P.mm, n, d.ldm, sM, act, P.piv, P.st + g0, 1));
-        MS_TRY(trsm_upper_aug(ctx, P.mm, n, d.ldm, sM, act, P.yb, d.ldy, sY, P.st + g0, 1));
-      }
-      for (const Seg& g : segs) {
-        const ms_slices* sl = P.sets[G.sets[g.j]].sl;
-        const double* eps_l = sl->eps;
-        const double* eps_r = sl->eps + (int64_t)(g.ns + 1) * n;
-        const int64_t o = g0 + g.a;
-        MS_TRY(launch_batch_T(ctx, n, G.n_ch[g.j], g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, P.en + o, eps_l, eps_r,
-                              P.yb + g.a * sY, d.ldy, sY, P.t + o, P.r + o, P.no + o, P.st + o));
-      }
-    }
+  std::vector<ms_ctx> runners;   // internal contexts in use, each forked from and joined to ctx
+  for (const FoldGroup& G : P.groups)
+    if (G.run != ctx && std::find(runners.begin(), runners.end(), G.run) == runners.end()) runners.push_back(G.run);
+  if (!runners.empty()) {
+    MS_HIP(ctx, hipEventRecord(ctx->sync_ev[0], ctx->stream));
+    for (ms_ctx c : runners) MS_HIP(ctx, hipStreamWaitEvent(c->stream, ctx->sync_ev[0], 0));
   }
+  ms_status s = MS_OK;
+  for (const FoldGroup& G : P.groups) {
+    ms_ctx c = G.run;
+    c->tile_n = G.n;   // GEMM tiles of the group's basis size
+    if (c != ctx) {   // the runner counts against what is left of the graph's budget
+      c->capturing = ctx->capturing;
+      c->cap_limit = ctx->cap_limit - ctx->cap_kernels;
+      c->cap_kernels = 0;
+    }
+    s = enqueue_group(c, P, G);
+    c->tile_n = 0;
+    if (c != ctx) {
+      c->capturing = false;
+      ctx->cap_kernels += c->cap_kernels;
+      if (s == MS_OK && ctx->capturing && ctx->cap_kernels > ctx->cap_limit)
+        s = fail(ctx, MS_ERR_UNSUPPORTED,
+                 "the fold needs more than %lld kernels in one graph; split the sets over several calls "
+                 "or call without MS_FOLD_GRAPH", (long long)ctx->cap_limit);
+      if (s != MS_OK && !c->last_error.empty()) ctx->last_error = c->last_error;
+    }
+    if (s != MS_OK) break;
+  }
+  // join every runner back into the caller's stream (also after an error, so a capture
+  // can be ended), after all groups have been enqueued
+  for (size_t i = 0; i < runners.size(); ++i) {
+    MS_HIP(ctx, hipEventRecord(ctx->sync_ev[1 + i], runners[i]->stream));
+    MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->sync_ev[1 + i], 0));
+  }
+  MS_TRY(s);
   return launch_scatter_results(ctx, P.ni, P.perm, P.t, P.r, P.no, P.st, T, R, n_open, status);
 }
 
@@ -894,6 +1000,7 @@ ms_status fold_run(ms_ctx ctx, FoldPlan& P, const double* energies, ms_prec prec
   ms_status s = fold_plan(ctx, energies, prec, P);
   if (s != MS_OK) {
     ctx->use_gws = false;
+    for (ms_ctx k : ctx->kids) k->use_gws = false;
     return s;
   }
   const hipStream_t main = ctx->stream;
@@ -908,6 +1015,7 @@ ms_status fold_run(ms_ctx ctx, FoldPlan& P, const double* energies, ms_prec prec
   const hipError_t eb = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
   if (eb != hipSuccess) {
     ctx->use_gws = false;
+    for (ms_ctx k : ctx->kids) k->use_gws = false;
     return hip_fail(ctx, eb, "hipStreamBeginCapture");
   }
   ctx->stream = ctx->cap_stream;
@@ -915,6 +1023,7 @@ ms_status fold_run(ms_ctx ctx, FoldPlan& P, const double* energies, ms_prec prec
   s = fold_enqueue(ctx, P, T, R, n_open, point_status);
   ctx->capturing = false;
   ctx->use_gws = false;
+  for (ms_ctx k : ctx->kids) k->use_gws = false;
   ctx->stream = main;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);

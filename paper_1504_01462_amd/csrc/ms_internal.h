@@ -50,6 +50,12 @@ struct ms_ctx_s {
   bool capturing = false;           // launches go into a hipGraph: no allocation, sync or timing
   hipStream_t cap_stream = nullptr; // stream the captures are recorded on
   hipGraphExec_t graph = nullptr;   // the last captured fold, replayable
+  // GEMM tile edges (64 or 128; 0 = default rule) chosen per basis size for the interface
+  // product, the LU's rank-128 update and its in-panel / U12 products, and the basis size of
+  // the fold group being enqueued (0 outside a fold)
+  struct Tiles { int64_t n; int iface, lu_update, lu_inner; };
+  std::vector<Tiles> tiles;
+  int64_t tile_n = 0;
   int64_t cap_kernels = 0;          // kernels recorded by the open capture
   int64_t cap_limit = 0;            // most kernels one capture may hold
   // workspace owned by the captured graph (its tables and scratch), so that later calls on

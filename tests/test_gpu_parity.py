@@ -511,3 +511,32 @@ def test_transmission_uneven_graph_budget(ms, ctx):
     T2 = _np(ms.ms_transmission_uneven(ctx, *args, "fp64", graph=True)[0])
     ctx.sync()
     assert np.array_equal(T1, T2)
+
+
+def test_tile_choice_and_autotune_do_not_change_results(ms, ctx):
+    """Any GEMM tile edges (set by hand or by the autotuner) give bit-identical T and R:
+    both tile shapes accumulate every element in the same order."""
+    sets = _uneven_sets(ms, ctx)
+    args = ([s for _, s, _ in sets], [e for _, _, e in sets])
+    T0, R0 = (_np(x) for x in ms.ms_transmission_uneven(ctx, *args, "fp64")[:2])
+    try:
+        for tiles in ((64, 64, 64), (128, 128, 128), (64, 128, 64), (128, 64, 128)):
+            for n in (37, 21):
+                ms.ms_set_tiles(ctx, n, *tiles)
+            T, R = (_np(x) for x in ms.ms_transmission_uneven(ctx, *args, "fp64")[:2])
+            ctx.sync()
+            assert np.array_equal(T, T0) and np.array_equal(R, R0), tiles
+        choice, times = ms.ms_autotune(ctx, 37, 3, 5)
+        assert set(choice.values()) <= {64, 128} and all(t > 0 for t in times)
+        T = _np(ms.ms_transmission_uneven(ctx, *args, "fp64")[0])
+        ctx.sync()
+        assert np.array_equal(T, T0)
+    finally:
+        for n in (37, 21):
+            ms.ms_set_tiles(ctx, n)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_set_tiles(ctx, 37, iface=96)
+    assert ei.value.status == ms.MS_ERR_ARG
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_autotune(ctx, 37, 40, 5)            # more open channels than plane waves
+    assert ei.value.status == ms.MS_ERR_ARG
