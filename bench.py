@@ -52,6 +52,8 @@ def parse():
                     help="skip the timing of the mixed-recurrence doubling (ms_mixed_doubling)")
     ap.add_argument("--roofline-kernel", default="iface_gemm",
                     help="profiler category reported in 'roofline' ('auto': the largest summed time in the warmup)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default GEMM tile rule instead of timing both edges first")
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
                          "captured graph after the main measurement; 0 skips it")
@@ -121,10 +123,10 @@ def cpu_baseline(name, budget_s):
                        "extrapolated, not a full point")}
 
 
-def measured_traffic(cat, flops_per_launch, form):
+def measured_traffic(cat, flops_per_launch, form, tile=128):
     """HBM bytes per launch of the roofline kernel from the committed rocprofv3 counter
-    summary, or None when it covers another kernel, launch shape or form, or when the
-    kernel source has changed since the counters were taken."""
+    summary, or None when it covers another kernel, tile shape, launch shape or form, or
+    when the kernel source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{cat}_config3_counters.txt")
     if form != "fp64" or not os.path.exists(path):
@@ -140,6 +142,8 @@ def measured_traffic(cat, flops_per_launch, form):
             return None
         n = 1200
         if abs(flops_per_launch - 8.0 * 2 * n * n * n * int(kv["batch"])) > 1.0:
+            return None
+        if int(kv.get("tile", "128")) != tile:
             return None
         return float(kv["traffic_bytes"])
     except (KeyError, ValueError, OSError):
@@ -177,10 +181,10 @@ def mixed_doubling_measure(ms, ctx, st, buf, results, log):
                      "3 1/3 N^3 per interface for the fused fold")}
 
 
-def uneven_measure(ms, ctx, count, log, replays=2):
+def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3):
     """The uneven workload: the first `count` seeded instances of the bilayer junction with
     N_G drawn from {200, 450, 800, 1200}, 100-400 slices and one (E, k_par) each.  Their
-    slice eigenproblems and overlaps are prepared instance by instance (timed), then all
+    slice eigenproblems and overlaps are prepared on `prep_streams` contexts (timed), then all
     instances are folded in one call, in the FP32-MFMA form and in FP64 (timed; |dT| between
     the forms per instance), with GEMM tile edges chosen per basis size by ms_autotune.  The instances with N_G <= 450 are also folded in one captured
     hipGraph, whose replays are timed and checked against the direct call: a graph holds at
@@ -201,13 +205,26 @@ def uneven_measure(ms, ctx, count, log, replays=2):
             dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
             bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
     bufs = [ms.Slices.empty(x["n_g"], x["ns"], x["dz"], dev) for x in staged]
+    # the instances' slice eigenproblems are independent: spread them over contexts on
+    # separate streams (heaviest first onto the least loaded)
+    pctx = [ctx] + [ms.Context(0, stream=torch.cuda.Stream()) for _ in range(prep_streams - 1)]
+    load = [0.0] * len(pctx)
+    place = [0] * len(staged)
+    for i in sorted(range(len(staged)), key=lambda i: -staged[i]["ns"] * staged[i]["n_g"] ** 3):
+        r = min(range(len(pctx)), key=lambda r: load[r])
+        load[r] += staged[i]["ns"] * staged[i]["n_g"] ** 3
+        place[i] = r
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for b, x in zip(bufs, staged):
-        ms.ms_slices_prepare(ctx, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
+    for i, (b, x) in enumerate(zip(bufs, staged)):
+        c = pctx[place[i]]
+        with torch.cuda.stream(c.stream):
+            ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
-    log(f"uneven: {count} instances prepared in {prep_s:.2f} s")
+    for c in pctx[1:]:
+        c.close()
+    log(f"uneven: {count} instances prepared in {prep_s:.2f} s on {len(pctx)} streams")
     es = [[x["e"]] for x in staged]
     # GEMM tile edges per basis size, timed on synthetic systems of the group's batch
     tuned = {}
@@ -243,6 +260,7 @@ def uneven_measure(ms, ctx, count, log, replays=2):
         "n_g_mix": mix,
         "slices_total": int(sum(x["ns"] for x in staged)),
         "prepare_s": round(prep_s, 4),
+        "prepare_streams": prep_streams,
         "autotune": {"seconds": round(tune_s, 3), "per_n_g": tuned},
         "fold_s": {"fp32": round(d32["s"], 4), "fp64": round(d64["s"], 4)},
         "instances_per_s_fold": {"fp32": round(count / d32["s"], 3), "fp64": round(count / d64["s"], 3)},
@@ -339,6 +357,14 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     log(f"inputs staged: {len(staged)} steps of {args.config}, {kps} k_par per step")
+    tuned_main = None
+    if args.autotune:   # GEMM tile edges for this basis size and batch (never changes a result)
+        t0 = time.perf_counter()
+        choice, times = ms.ms_autotune(ctx, j0.n_g, min(j0.n_g, 13), kps * n_e)
+        tuned_main = dict(seconds=round(time.perf_counter() - t0, 3), choice=choice,
+                          lu_ms=[round(v, 3) for v in times[:4]], iface_ms=[round(v, 3) for v in times[4:]])
+        log(f"autotune n_g={j0.n_g}, batch {kps * n_e}: {choice} (LU ms {tuned_main['lu_ms']}, "
+            f"interface ms {tuned_main['iface_ms']})")
 
     def run(steps, prec):
         """One step: the slice eigenproblems and overlaps of each of its k_par, the fused fold
@@ -423,8 +449,11 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by_per / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if launches else None
-    roof["traffic"] = measured_traffic(cat, fl_per, head)
+    iface_tile = (tuned_main["choice"]["iface"] if tuned_main else 0) or 128
+    roof["traffic"] = measured_traffic(cat, fl_per, head, iface_tile if cat == "iface_gemm" else 128)
     roof["kernel"] = cat
+    if cat == "iface_gemm":
+        roof["tile"] = f"{iface_tile}x{iface_tile}"
     roof["avg_launch_ms"] = avg_s * 1e3
     roof["launches"] = launches
     roof["note"] = ("per-launch durations from HIP events that bracket the kernel's own execution "
@@ -449,6 +478,7 @@ def main():
                    "headline_form": head},
         "forms": out_forms,
         "roofline": roof,
+        "autotune": tuned_main,
     }
     if args.next3 and args.config == "config3":
         line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)

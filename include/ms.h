@@ -236,8 +236,8 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
                                  int64_t* n_open, int32_t* point_status);
 
 /* Tile edges of the fold's complex GEMMs for one basis size: 64 (64 x 64 tiles, 4 waves) or
- * 128 (128 x 128 tiles, 8 waves); 0 = the default rule (128 for the LU's trailing update and
- * for products of at least 128 x 128, else 64).  Roles: the interface product (Sec. II, the
+ * 128 (128 x 128 tiles, 8 waves); 0 = the default rule (64 for the LU's products, 128 for the
+ * interface product when it is at least 128 x 128, else 64).  Roles: the interface product (Sec. II, the
  * star product with the accumulated right part), the LU's rank-128 trailing update, and its
  * in-panel and U12 products.  Both shapes accumulate every element in the same order, so the
  * edges change run time only, never a result. */

@@ -282,8 +282,9 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
             true);
   // Tile edge: the tuned choice for the fold group's basis size (ms_autotune / ms_set_tiles),
-  // else 128 x 128 (8 waves) for the LU's trailing update and for products of at least 128 x
-  // 128, 64 x 64 (4 waves) otherwise.  Both tile shapes accumulate every element in the same
+  // else 64 x 64 (4 waves, two workgroups per CU) for the LU's products, which timed faster at
+  // every basis size (200-1200) and batch (3-64) tried, and for products smaller than 128 x
+  // 128, 128 x 128 (8 waves) otherwise.  Both tile shapes accumulate every element in the same
   // order, so the choice never changes a result.
   static const int tile_env = [] {   // MS_GEMM_TILE=64: 64 x 64 tiles everywhere
     const char* e = getenv("MS_GEMM_TILE");
@@ -296,7 +297,8 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
         tile = g.prof == PC_IFACE_GEMM ? t.iface
                                        : (g.prof == PC_LU_UPDATE ? t.lu_update : (g.prof == PC_LU_INNER ? t.lu_inner : 0));
   if (tile_env == 64) tile = 64;
-  if (tile == 0) tile = (g.prof == PC_LU_UPDATE || (g.M >= 128 && g.N >= 128)) ? 128 : 64;
+  if (tile == 0)
+    tile = (g.prof != PC_LU_UPDATE && g.prof != PC_LU_INNER && g.M >= 128 && g.N >= 128) ? 128 : 64;
   const bool big = tile == 128;
   if (g.prof == PC_LU_UPDATE)
     return big ? launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof);
