@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
                          "captured graph after the main measurement; 0 skips it")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="measure only the uneven workload (--uneven instances) and print its JSON line")
     ap.add_argument("--no-event-profile", action="store_true",
                     help="record no HIP events around launches (no roofline figure; for external profilers)")
     return ap.parse_args()
@@ -181,126 +183,165 @@ def mixed_doubling_measure(ms, ctx, st, buf, results, log):
                      "3 1/3 N^3 per interface for the fused fold")}
 
 
-def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3):
+def uneven_inputs(i):
+    """Seeded inputs of uneven instance i (host arrays; no GPU)."""
+    import msgen
+    it = msgen.config4_instances()[i]
+    j = it["junction"]
+    inp = msgen.junction_inputs(j, j.kpars[it["k_index"]])
+    return dict(n_g=j.n_g, ns=len(j.dz), e=float(it["energy"]),
+                miller=np.ascontiguousarray(inp["miller"], dtype=np.int32),
+                q=np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), vq=np.ascontiguousarray(inp["vq"]),
+                dz=np.ascontiguousarray(inp["dz"]), bvec=np.asarray(inp["bvec"]).reshape(4),
+                kpar=np.asarray(inp["kpar"]))
+
+
+def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=64e9, host_inputs=None):
     """The uneven workload: the first `count` seeded instances of the bilayer junction with
-    N_G drawn from {200, 450, 800, 1200}, 100-400 slices and one (E, k_par) each.  Their
-    slice eigenproblems and overlaps are prepared on `prep_streams` contexts (timed), then all
-    instances are folded in one call, in the FP32-MFMA form and in FP64 (timed; |dT| between
-    the forms per instance), with GEMM tile edges chosen per basis size by ms_autotune.  The instances with N_G <= 450 are also folded in one captured
-    hipGraph, whose replays are timed and checked against the direct call: a graph holds at
-    most 96000 kernels, which the whole set (about 213000) exceeds."""
+    N_G drawn from {200, 450, 800, 1200}, 100-400 slices and one (E, k_par) each, taken in
+    chunks of consecutive instances whose overlaps fit `chunk_bytes` of HBM.  Per chunk the
+    slice eigenproblems and overlaps are prepared on `prep_streams` contexts (timed), then
+    all instances of the chunk are folded in one call, in the FP32-MFMA form and in FP64
+    (timed; |dT| between the forms per instance), with GEMM tile edges chosen per basis size
+    by ms_autotune.  The first chunk's instances with N_G <= 450 are also folded in one
+    captured hipGraph, whose replays are timed and checked against the direct call (a graph
+    holds at most 96000 kernels, which the first 16 instances together, about 213000, exceed)."""
     import torch
     import msgen
     dev = ctx.device
     inst = msgen.config4_instances()[:count]
-    staged = []
-    for it in inst:
-        j = it["junction"]
-        inp = msgen.junction_inputs(j, j.kpars[it["k_index"]])
-        staged.append(dict(
-            n_g=j.n_g, ns=len(j.dz), e=float(it["energy"]),
-            miller=torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev),
-            q=torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev),
-            vq=torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev),
-            dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
-            bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
-    bufs = [ms.Slices.empty(x["n_g"], x["ns"], x["dz"], dev) for x in staged]
-    # the instances' slice eigenproblems are independent: spread them over contexts on
-    # separate streams (heaviest first onto the least loaded)
+    chunks, cur, acc = [], [], 0.0
+    for i, it in enumerate(inst):
+        nb = (len(it["junction"].dz) + 1) * it["junction"].n_g ** 2 * 16.0
+        if cur and acc + nb > chunk_bytes:
+            chunks.append(cur)
+            cur, acc = [], 0.0
+        cur.append(i)
+        acc += nb
+    chunks.append(cur)
     pctx = [ctx] + [ms.Context(0, stream=torch.cuda.Stream()) for _ in range(prep_streams - 1)]
-    load = [0.0] * len(pctx)
-    place = [0] * len(staged)
-    for i in sorted(range(len(staged)), key=lambda i: -staged[i]["ns"] * staged[i]["n_g"] ** 3):
-        r = min(range(len(pctx)), key=lambda r: load[r])
-        load[r] += staged[i]["ns"] * staged[i]["n_g"] ** 3
-        place[i] = r
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i, (b, x) in enumerate(zip(bufs, staged)):
-        c = pctx[place[i]]
-        with torch.cuda.stream(c.stream):
-            ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
-    torch.cuda.synchronize()
-    prep_s = time.perf_counter() - t0
-    for c in pctx[1:]:
-        c.close()
-    log(f"uneven: {count} instances prepared in {prep_s:.2f} s on {len(pctx)} streams")
-    es = [[x["e"]] for x in staged]
-    # GEMM tile edges per basis size, timed on synthetic systems of the group's batch
-    tuned = {}
-    t0 = time.perf_counter()
-    for n_g in sorted({x["n_g"] for x in staged}):
-        nb = sum(1 for x in staged if x["n_g"] == n_g)
-        choice, times = ms.ms_autotune(ctx, n_g, 8, nb)
-        tuned[str(n_g)] = dict(batch=nb, choice=choice, lu_ms=[round(v, 3) for v in times[:4]],
-                               iface_ms=[round(v, 3) for v in times[4:]])
-    tune_s = time.perf_counter() - t0
-    log(f"uneven: autotuned {len(tuned)} basis sizes in {tune_s:.2f} s: "
-        + ", ".join(f"{k}: {v['choice']}" for k, v in tuned.items()))
-    out = {}
-    for prec in ("fp32", "fp64"):
-        ms.ms_transmission_uneven(ctx, bufs, es, prec)          # warm: workspace
+    n_gs = sorted({it["junction"].n_g for it in inst})
+    tuned, tune_s = {}, 0.0
+    tot = dict(prep=0.0, fp32=0.0, fp64=0.0)
+    res_T = {"fp32": np.zeros(count), "fp64": np.zeros(count)}
+    res_R64, res_no64 = np.zeros(count), np.zeros(count, dtype=np.int64)
+    bad = 0
+    graph = None
+    for ci, chunk in enumerate(chunks):
+        staged = []
+        for i in chunk:
+            h = host_inputs[i] if host_inputs is not None else uneven_inputs(i)
+            staged.append(dict(h, miller=torch.as_tensor(h["miller"], device=dev),
+                               q=torch.as_tensor(h["q"], device=dev), vq=torch.as_tensor(h["vq"], device=dev),
+                               dz=torch.as_tensor(h["dz"], device=dev)))
+        bufs = [ms.Slices.empty(x["n_g"], x["ns"], x["dz"], dev) for x in staged]
+        # the instances' slice eigenproblems are independent: spread them over contexts on
+        # separate streams (heaviest first onto the least loaded)
+        load = [0.0] * len(pctx)
+        place = [0] * len(staged)
+        for i in sorted(range(len(staged)), key=lambda i: -staged[i]["ns"] * staged[i]["n_g"] ** 3):
+            r = min(range(len(pctx)), key=lambda r: load[r])
+            load[r] += staged[i]["ns"] * staged[i]["n_g"] ** 3
+            place[i] = r
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        T, R, no, st = ms.ms_transmission_uneven(ctx, bufs, es, prec)
+        for i, (b, x) in enumerate(zip(bufs, staged)):
+            c = pctx[place[i]]
+            with torch.cuda.stream(c.stream):
+                ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        out[prec] = dict(T=T.cpu().numpy(), R=R.cpu().numpy(), no=no.cpu().numpy(), st=st.cpu().numpy(), s=dt)
-        log(f"uneven {prec}: {count} instances folded in {dt:.2f} s")
-    d32, d64 = out["fp32"], out["fp64"]
-    dT = np.abs(d32["T"] - d64["T"])
+        prep_s = time.perf_counter() - t0
+        tot["prep"] += prep_s
+        if ci == 0:   # GEMM tile edges per basis size, timed on synthetic systems of a chunk's batch
+            t0 = time.perf_counter()
+            for n_g in n_gs:
+                nb = max(1, max(sum(1 for i in ch if inst[i]["junction"].n_g == n_g) for ch in chunks))
+                choice, times = ms.ms_autotune(ctx, n_g, 8, nb)
+                tuned[str(n_g)] = dict(batch=nb, choice=choice, lu_ms=[round(v, 3) for v in times[:4]],
+                                       iface_ms=[round(v, 3) for v in times[4:]])
+            tune_s = time.perf_counter() - t0
+            log(f"uneven: autotuned {len(tuned)} basis sizes in {tune_s:.2f} s: "
+                + ", ".join(f"{k}: {v['choice']}" for k, v in tuned.items()))
+        es = [[x["e"]] for x in staged]
+        for prec in ("fp32", "fp64"):
+            if len(chunks) == 1:
+                ms.ms_transmission_uneven(ctx, bufs, es, prec)          # warm: workspace
+                torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T, R, no, st = ms.ms_transmission_uneven(ctx, bufs, es, prec)
+            torch.cuda.synchronize()
+            tot[prec] += time.perf_counter() - t0
+            res_T[prec][chunk] = T.cpu().numpy()
+            bad += int(np.sum(st.cpu().numpy() != 0))
+            if prec == "fp64":
+                res_R64[chunk] = R.cpu().numpy()
+                res_no64[chunk] = no.cpu().numpy()
+        log(f"uneven chunk {ci + 1}/{len(chunks)}: {len(chunk)} instances, prepare {prep_s:.2f} s, "
+            f"folds so far fp32 {tot['fp32']:.2f} s / fp64 {tot['fp64']:.2f} s")
+        small = [i for i, x in enumerate(staged) if x["n_g"] <= 450]
+        if ci == 0 and small:
+            sb, se = [bufs[i] for i in small], [es[i] for i in small]
+            t0 = time.perf_counter()
+            Tg = ms.ms_transmission_uneven(ctx, sb, se, "fp32", graph=True)[0]
+            torch.cuda.synchronize()
+            first_s = time.perf_counter() - t0
+            ts = []
+            for _ in range(replays):
+                Tg.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ms.ms_graph_replay(ctx)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            ms.ms_transmission_uneven(ctx, sb, se, "fp32")           # the same instances, no graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Te = ms.ms_transmission_uneven(ctx, sb, se, "fp32")[0]
+            torch.cuda.synchronize()
+            eager_s = time.perf_counter() - t0
+            graph = {
+                "instances": len(small), "which": [chunk[i] for i in small], "form": "fp32",
+                "capture_and_first_launch_s": round(first_s, 4),
+                "replay_s": round(min(ts), 4),
+                "direct_call_s": round(eager_s, 4),
+                "max_abs_T_replay_minus_direct": float(np.max(np.abs(Tg.cpu().numpy() - Te.cpu().numpy()))),
+            }
+            log(f"uneven graph ({len(small)} instances): capture+launch {first_s:.2f} s, replay {min(ts):.3f} s, "
+                f"direct {eager_s:.3f} s")
+        del bufs, staged
+        torch.cuda.empty_cache()
+    for c in pctx[1:]:
+        c.close()
+    dT = np.abs(res_T["fp32"] - res_T["fp64"])
     mix = {}
-    for x in staged:
-        mix[str(x["n_g"])] = mix.get(str(x["n_g"]), 0) + 1
+    for it in inst:
+        mix[str(it["junction"].n_g)] = mix.get(str(it["junction"].n_g), 0) + 1
     res = {
         "workload": "uneven instances of the bilayer-gap junction (hexagonal 2x2 cell, 16 bohr): "
                     "N_G in {200, 450, 800, 1200}, 100-400 slices, one (E, k_par) each, seeded; "
                     f"the first {count} of 512",
         "instances": count,
+        "chunks": len(chunks),
         "n_g_mix": mix,
-        "slices_total": int(sum(x["ns"] for x in staged)),
-        "prepare_s": round(prep_s, 4),
+        "slices_total": int(sum(len(it["junction"].dz) for it in inst)),
+        "prepare_s": round(tot["prep"], 4),
         "prepare_streams": prep_streams,
         "autotune": {"seconds": round(tune_s, 3), "per_n_g": tuned},
-        "fold_s": {"fp32": round(d32["s"], 4), "fp64": round(d64["s"], 4)},
-        "instances_per_s_fold": {"fp32": round(count / d32["s"], 3), "fp64": round(count / d64["s"], 3)},
-        "instances_per_s_end_to_end": {"fp32": round(count / (prep_s + d32["s"]), 3),
-                                       "fp64": round(count / (prep_s + d64["s"]), 3)},
-        "abs_dT_fp32_vs_fp64": [float(f"{v:.3g}") for v in dT],
+        "fold_s": {"fp32": round(tot["fp32"], 4), "fp64": round(tot["fp64"], 4)},
+        "instances_per_s_fold": {"fp32": round(count / tot["fp32"], 3), "fp64": round(count / tot["fp64"], 3)},
+        "instances_per_s_end_to_end": {"fp32": round(count / (tot["prep"] + tot["fp32"]), 3),
+                                       "fp64": round(count / (tot["prep"] + tot["fp64"]), 3)},
         "max_abs_dT_fp32_vs_fp64": float(dT.max()),
-        "max_abs_R_plus_T_minus_Nopen_fp64": float(np.max(np.abs(d64["T"] + d64["R"] - d64["no"]))),
-        "bad_points": int(np.sum(d32["st"] != 0) + np.sum(d64["st"] != 0)),
+        "max_abs_R_plus_T_minus_Nopen_fp64": float(np.max(np.abs(res_T["fp64"] + res_R64 - res_no64))),
+        "bad_points": bad,
     }
-    small = [i for i, x in enumerate(staged) if x["n_g"] <= 450]
-    if small:
-        sb, se = [bufs[i] for i in small], [es[i] for i in small]
-        t0 = time.perf_counter()
-        Tg = ms.ms_transmission_uneven(ctx, sb, se, "fp32", graph=True)[0]
-        torch.cuda.synchronize()
-        first_s = time.perf_counter() - t0
-        ts = []
-        for _ in range(replays):
-            Tg.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ms.ms_graph_replay(ctx)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        ms.ms_transmission_uneven(ctx, sb, se, "fp32")           # the same instances, no graph
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        Te = ms.ms_transmission_uneven(ctx, sb, se, "fp32")[0]
-        torch.cuda.synchronize()
-        eager_s = time.perf_counter() - t0
-        res["graph"] = {
-            "instances": len(small), "which": small, "form": "fp32",
-            "capture_and_first_launch_s": round(first_s, 4),
-            "replay_s": round(min(ts), 4),
-            "direct_call_s": round(eager_s, 4),
-            "max_abs_T_replay_minus_direct": float(np.max(np.abs(Tg.cpu().numpy() - Te.cpu().numpy()))),
-        }
-        log(f"uneven graph ({len(small)} instances): capture+launch {first_s:.2f} s, replay {min(ts):.3f} s, "
-            f"direct {eager_s:.3f} s")
+    if count <= 32:
+        res["abs_dT_fp32_vs_fp64"] = [float(f"{v:.3g}") for v in dT]
+    else:
+        res["abs_dT_fp32_vs_fp64_quantiles"] = {q: float(f"{np.quantile(dT, float(q)):.3g}")
+                                                for q in ("0.5", "0.9", "0.99", "1.0")}
+    if graph:
+        res["graph"] = graph
     return res
 
 
@@ -311,10 +352,27 @@ def main():
         print("bench.py measures one GPU only: every box of this build has a single MI355X and the path "
               "shards over (E, k_par) points without communication; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    host_inputs = None
+    if args.uneven_only:
+        # generate the seeded inputs in worker processes, before this process loads the GPU
+        # library or touches the GPU; the pool and its workers are gone before that
+        from concurrent.futures import ProcessPoolExecutor
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+            host_inputs = list(pool.map(uneven_inputs, range(max(1, args.uneven)), chunksize=4))
+        print(f"[bench] uneven inputs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     import torch
     import msgen
     import paper_1504_01462_amd as ms
 
+    if args.uneven_only:
+        n_u = max(1, args.uneven)
+        ctx = ms.Context(0)
+        u = uneven_measure(ms, ctx, n_u, lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
+                           host_inputs=host_inputs)
+        ctx.close()
+        print(json.dumps({"uneven_batch": u, "n_gpus": 1, "data": "synthetic"}), flush=True)
+        return
     combos, make, desc = workload(args.config)
     # a step takes kps consecutive k_par of one junction (one batch of kps x n_e points)
     kps = max(1, args.kpar_per_step)
