@@ -41,7 +41,7 @@ __all__ = [
     "transfer_matrix", "smatrix_from_transfer", "identity_smatrix", "star", "cascade",
     "recurrence2_cascade", "interface_smatrices", "iter_interface_smatrices", "transmission_from_smatrix",
     "transmission", "global_system", "transfer_product", "born_reflection",
-    "LEAD_THRESHOLD", "kpar_average",
+    "LEAD_THRESHOLD", "kpar_average", "slice_amplitudes", "dT_dV", "dT_dV_real",
 ]
 
 LEAD_THRESHOLD = 1e-10
@@ -440,3 +440,119 @@ def kpar_average(t_k, n_open_k):
     tot = n.sum(axis=0)
     per = np.where(tot > 0, t_k.sum(axis=0) / np.where(tot > 0, tot, 1.0), 0.0)
     return tbar, per
+
+
+# --------------------------------------------------------------------------------------
+# First variation of T with respect to the slice potentials
+# --------------------------------------------------------------------------------------
+
+def slice_amplitudes(prep: dict, energy: float, a0, bn1):
+    """(A^p, B^p) for p = 0..N+1 of the solution with incoming amplitudes A^0 = a0 (left
+    lead) and B^{N+1} = bn1 (right lead), columns = several solutions.  From the left
+    cascade L = S(0,p) and the right cascade R = S(p,N+1) (Sec. II.A, Eq. smm2):
+    A^p = L11 A^0 + L12 B^p and B^p = R21 A^p + R22 B^{N+1}, i.e.
+    (I - L12 R21) A^p = L11 A^0 + L12 R22 B^{N+1}."""
+    smats = interface_smatrices(prep, energy)
+    n, ns = prep["n"], prep["n_slices"]
+    left = [identity_smatrix(n)]
+    for s_ in smats:
+        left.append(star(left[-1], s_))                 # left[p] = S(0,p)
+    right = [identity_smatrix(n)]
+    for s_ in reversed(smats):
+        right.append(star(s_, right[-1]))              # right[k] = S(N+1-k, N+1)
+    right = right[::-1]                                 # right[p] = S(p, N+1)
+    out = []
+    for p in range(ns + 2):
+        lp, rp_ = left[p], right[p]
+        f = np.eye(n, dtype=np.complex128) - lp["rp"] @ rp_["r"]
+        a = np.linalg.solve(f, lp["t"] @ a0 + lp["rp"] @ (rp_["tp"] @ bn1))
+        b = rp_["r"] @ a + rp_["tp"] @ bn1
+        out.append((a, b))
+    return out, left[-1]
+
+
+def _exp_integral(kappa, width):
+    """int_{-w}^{0} e^{i kappa s} ds, elementwise (w >= 0)."""
+    x = 1j * kappa * width
+    small = np.abs(x) < 1e-8
+    safe = np.where(small, 1.0, kappa)
+    val = (1.0 - np.exp(-x)) / (1j * safe)
+    return np.where(small, width * (1.0 - 0.5 * x), val)
+
+
+def dT_dV(prep: dict, energy: float, q_of_ij, n_q: int) -> np.ndarray:
+    """g[p][Q] (slices p = 1..N as rows 0..N-1) with dT = 2 Re sum_{p,Q} g[p][Q] dV^p(Q) to
+    first order, for any perturbation dV of the slice potentials' Fourier coefficients
+    (H^p_ab = |k+G_a|^2 delta_ab + V^p(G_a - G_b)).
+
+    Derivation (not in the paper; the sliced model as in Sec. II): with the Wronskian
+    W[f, g] = f^dagger g' - f'^dagger g, dW/dz = f^dagger dH g when f solves the unperturbed
+    equation and g the perturbed one.  Taking g = psi_j (incident from the left in open
+    channel j: A^0 = e_j, B^{N+1} = 0) and f = phi_i (outgoing only into the right lead's open
+    channel i: the open rows of B^0 vanish, those of A^{N+1} equal e_i, the incoming
+    amplitudes only on open channels) gives dt_ij = (1/(2 i k_i)) int phi_i^dagger dH psi_j dz,
+    and dT = sum_ij (k_i/k_j) 2 Re(conj(t_ij) dt_ij).  Inside slice p both are
+    U^p [A e^{ik(z-z_p)} + B e^{-ik(z-z_p)}], so the z integral is a sum of exponential
+    integrals over the slice."""
+    n, ns = prep["n"], prep["n_slices"]
+    _lead_check(energy, prep["eps"][0])
+    _lead_check(energy, prep["eps"][-1])
+    kl = wavevectors(energy, prep["eps"][0])
+    kr = wavevectors(energy, prep["eps"][-1])
+    ol = np.where(np.asarray(prep["eps"][0]) < energy)[0]
+    orr = np.where(np.asarray(prep["eps"][-1]) < energy)[0]
+    g = np.zeros((ns, n_q), dtype=np.complex128)
+    if ol.size == 0 or orr.size == 0:
+        return g
+    # in-states psi_j
+    a0 = np.zeros((n, ol.size), dtype=np.complex128)
+    a0[ol, np.arange(ol.size)] = 1.0
+    amp_in, whole = slice_amplitudes(prep, energy, a0, np.zeros_like(a0))
+    t = whole["t"][np.ix_(orr, ol)]
+    # out-states phi_i: solve [r_OO t'_OR; t_RO r'_RR] [x; y] = [0; e_i] on the open channels
+    sys_ = np.block([[whole["r"][np.ix_(ol, ol)], whole["tp"][np.ix_(ol, orr)]],
+                     [whole["t"][np.ix_(orr, ol)], whole["rp"][np.ix_(orr, orr)]]])
+    rhs = np.zeros((ol.size + orr.size, orr.size), dtype=np.complex128)
+    rhs[ol.size + np.arange(orr.size), np.arange(orr.size)] = 1.0
+    xy = np.linalg.solve(sys_, rhs)
+    fa0 = np.zeros((n, orr.size), dtype=np.complex128)
+    fa0[ol, :] = xy[:ol.size]
+    fb = np.zeros((n, orr.size), dtype=np.complex128)
+    fb[orr, :] = xy[ol.size:]
+    amp_out, _ = slice_amplitudes(prep, energy, fa0, fb)
+    # weights w_ij = (k_i / k_j) conj(t_ij) / (2 i k_i) = conj(t_ij) / (2 i k_j)
+    w = np.conj(t) / (2j * kl[ol][None, :])                    # (i in orr, j in ol)
+    q = np.asarray(q_of_ij)
+    for p in range(1, ns + 1):
+        k = wavevectors(energy, prep["eps"][p])
+        width = prep["dz"][p]
+        a_j, b_j = amp_in[p]
+        c_i, d_i = amp_out[p]
+        kc = np.conj(k)[:, None]
+        km = k[None, :]
+        m = (_exp_integral(km - kc, width) * (c_i.conj() @ w @ a_j.T)
+             + _exp_integral(-km - kc, width) * (c_i.conj() @ w @ b_j.T)
+             + _exp_integral(km + kc, width) * (d_i.conj() @ w @ a_j.T)
+             + _exp_integral(-km + kc, width) * (d_i.conj() @ w @ b_j.T))
+        u = prep["u"][p]
+        kmat = u.conj() @ m @ u.T                                # K_ab = sum_nm conj(U_an) M_nm U_bm
+        g[p - 1] = np.bincount(q.ravel(), weights=kmat.real.ravel(), minlength=n_q) + \
+            1j * np.bincount(q.ravel(), weights=kmat.imag.ravel(), minlength=n_q)
+    return g
+
+
+def dT_dV_real(g: np.ndarray, q_miller) -> tuple:
+    """The gradient with respect to real parameters on a half-set of Q (V(-Q) = conj V(Q)
+    keeps H Hermitian): for each Q with its partner -Q, dT/dRe V(Q) = 2 Re(g(Q) + g(-Q)) and
+    dT/dIm V(Q) = 2 Im(g(-Q) - g(Q)); for Q = -Q only the real part, 2 Re g(Q).  Returns
+    (index of Q, index of -Q, d/dRe, d/dIm) arrays over the half-set."""
+    qm = np.asarray(q_miller)
+    index = {tuple(v): i for i, v in enumerate(qm.tolist())}
+    partner = np.array([index[tuple((-v).tolist())] for v in qm])
+    keep = np.arange(len(qm)) <= partner
+    qi = np.where(keep)[0]
+    qj = partner[qi]
+    self_ = qi == qj
+    d_re = 2.0 * np.real(g[:, qi] + np.where(self_[None, :], 0.0, g[:, qj]))
+    d_im = np.where(self_[None, :], 0.0, 2.0 * np.imag(g[:, qj] - g[:, qi]))
+    return qi, qj, d_re, d_im

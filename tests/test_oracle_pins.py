@@ -394,3 +394,75 @@ def test_kpar_average():
     assert np.allclose(per1, tx.sum(0) / nx.sum(0), rtol=1e-15) and np.allclose(per1, per2, rtol=1e-15)
     tb, pc = orc.kpar_average(np.zeros((2, 3)), np.zeros((2, 3), dtype=int))
     assert np.all(tb == 0) and np.all(pc == 0)
+
+
+# ---------------------------------------------------------------- dT/dV (first variation) --
+def test_dT_dV_square_barrier_closed_form():
+    """z-only barrier: d/dV0 of the textbook T(E; V0) (the closed form differentiated by
+    central differences) equals the first-variation gradient summed over the barrier's
+    slices at Q = 0."""
+    j, inp = _c1(n_slices=12, slab=3.0)
+    v0 = 0.5
+    vz = np.zeros(12)
+    vz[2:10] = v0
+    inp = _with_vq(inp, _const_vq(inp, vz))
+    prep = orc.prepare(inp)
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    for e in (0.45, 1.0, 3.5):
+        g = orc.dT_dV(prep, e, inp["q_of_ij"], inp["vq"].shape[1])
+        grad = float(2.0 * np.real(np.sum(g[2:10, q0])))
+        h = 1e-6
+        closed = lambda v: sum(_barrier_closed(e - kk, v, 2.0) for kk in prep["kin"] if kk < e)
+        ref = (closed(v0 + h) - closed(v0 - h)) / (2 * h)
+        assert abs(grad - ref) < 1e-8 * max(1.0, abs(ref)), (e, grad, ref)
+        # a z-only potential keeps the channels decoupled (t diagonal), so a first-order
+        # change of T comes only from the diagonal of dH, which is carried by Q = 0
+        others = np.delete(g, q0, axis=1)
+        assert np.max(np.abs(others)) < 1e-12 * max(1.0, np.max(np.abs(g[:, q0])))
+
+
+def test_dT_dV_matches_central_differences():
+    """Coupled channels (config1 wells, 13 plane waves, k_par off symmetry, 5 open
+    channels): dT/dRe V^p(Q) and dT/dIm V^p(Q) with V(-Q) = conj V(Q) kept, against
+    central differences of T (h = 1e-6) on 8 seeded coefficients."""
+    j, inp = _c1(kpar=(0.07, -0.11), n_g=13, n_slices=6)
+    prep = orc.prepare(inp)
+    e = 2.3
+    g = orc.dT_dV(prep, e, inp["q_of_ij"], inp["vq"].shape[1])
+    qi, qj, dre, dim = orc.dT_dV_real(g, inp["q_miller"])
+    rng = np.random.default_rng(20)
+    h = 1e-6
+    checked = 0
+    for _ in range(8):
+        p, c = int(rng.integers(0, 6)), int(rng.integers(0, len(qi)))
+        for part in ("re", "im"):
+            if part == "im" and qi[c] == qj[c]:
+                continue
+            vals = []
+            for sgn in (1, -1):
+                vq = inp["vq"].copy()
+                d = h * (1 if part == "re" else 1j) * sgn
+                vq[p, qi[c]] += d
+                if qj[c] != qi[c]:
+                    vq[p, qj[c]] += np.conj(d)
+                vals.append(orc.transmission(orc.prepare(_with_vq(inp, vq)), e)["T"])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = dre[p, c] if part == "re" else dim[p, c]
+            assert abs(fd - an) < 2e-8 + 1e-5 * abs(an), (p, c, part, fd, an)
+            checked += 1
+    assert checked >= 12
+
+
+def test_dT_dV_born_limit():
+    """Weak potential (lambda V, lambda -> 0): t = diag(e^{ikL}) + O(lambda), so to first
+    order dT is the diagonal Born transmission change, whose real part vanishes (current
+    conservation); the gradient must be O(lambda) while T - N_open = O(lambda^2)."""
+    j, inp = _c1(n_slices=8)
+    e = 1.7
+    grads = []
+    for lam in (1e-3, 2e-3):
+        ii = _with_vq(inp, inp["vq"] * lam)
+        prep = orc.prepare(ii)
+        g = orc.dT_dV(prep, e, ii["q_of_ij"], ii["vq"].shape[1])
+        grads.append(np.max(np.abs(np.real(g))))
+    assert grads[1] / grads[0] == pytest.approx(2.0, rel=1e-2)
