@@ -16,7 +16,8 @@ The steps run twice, in FP64 and in the FP32-MFMA form, over the same
 also solved with the paper's mixed transfer/scattering doubling, and the first
 instances of the uneven workload (N_G from 200 to 1200, 100-400 slices, one point
 each) are folded in one call, the small ones also in a captured hipGraph
-(`uneven_batch`).
+(`uneven_batch`), and the gradient dT/dV of every slice coefficient is timed at two
+energies of the adjoint workload (`adjoint`).
 
     python bench.py [--steps K] [--warmup W] [--config config3|config2|config1]
 Prints one JSON line.
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
                          "captured graph after the main measurement; 0 skips it")
+    ap.add_argument("--adjoint", type=int, default=2,
+                    help="energies of the adjoint workload (dT/dV at N_G = 1200) to time; 0 skips it")
     ap.add_argument("--uneven-only", action="store_true",
                     help="measure only the uneven workload (--uneven instances) and print its JSON line")
     ap.add_argument("--no-event-profile", action="store_true",
@@ -345,6 +348,61 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
     return res
 
 
+def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
+    """The adjoint workload: dT/dV^p(Q) for every slice and Fourier coefficient of the
+    side-contact junction at gap 6.3 bohr, k_par = 0 (N_G = 1200, 400 slices, checkpoints every
+    20 planes), at `n_e` of its 16 energies; seconds per energy, and the derivative with
+    respect to Re V^p(0) on three slices against central differences of T (h = 1e-5)."""
+    import torch
+    import msgen
+    j = msgen.config5()
+    inp = msgen.junction_inputs(j, j.kpars[0])
+    dev = ctx.device
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
+    times, grads = [], []
+    for i in idx:
+        e = float(j.energies[i])
+        t0 = time.perf_counter()
+        g, tr, no = ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], 20)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        grads.append((e, g.cpu().numpy(), tr.cpu().numpy(), int(no.cpu().numpy()[0])))
+        log(f"adjoint: E = {e:.4f} Ry, T = {grads[-1][2][0]:.6f}, {times[-1]:.2f} s")
+    e, g, tr, _ = grads[0]
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    h, rel = 1e-5, []
+    for p in fd_slices:
+        vals = []
+        for sgn in (1, -1):
+            vq = inp["vq"].copy()
+            vq[p, q0] += sgn * h
+            sp = ms.prepare_from_inputs(ctx, dict(inp, vq=vq))
+            vals.append(float(ms.ms_transmission_batch(ctx, sp, [e])[0].cpu().numpy()[0]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = float(2.0 * np.real(g[p, q0]))
+        rel.append(abs(fd - an) / max(abs(an), 1e-12))
+    n, ns = j.n_g, len(j.dz)
+    flop = 8.0 * (3 * 31.0 / 3 + 8 + 7.0 / 3) * n ** 3 * (ns + 1)
+    return {
+        "workload": "dT/dV^p(Q) of the side-contact junction at gap 6.3 bohr, k_par = 0: N_G = 1200, "
+                    f"400 slices, {inp['vq'].shape[1]} Fourier coefficients per slice, checkpoints every 20 planes",
+        "energies": [float(x[0]) for x in grads],
+        "prepare_with_eigenvectors_s": round(prep_s, 3),
+        "seconds_per_energy": [round(x, 3) for x in times],
+        "gradient_entries_per_energy": int(ns * inp["vq"].shape[1]),
+        "approx_flop_per_energy": flop,
+        "approx_tflops": round(flop / np.mean(times) / 1e12, 2),
+        "fd_check": {"coefficient": "Re V^p(Q=0)", "slices": list(fd_slices), "h": h,
+                     "max_rel_diff": float(max(rel))},
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -540,6 +598,10 @@ def main():
     }
     if args.next3 and args.config == "config3":
         line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)
+    if args.adjoint > 0 and args.config == "config3":
+        bufs.clear()
+        torch.cuda.empty_cache()
+        line["adjoint"] = adjoint_measure(ms, ctx, args.adjoint, log)
     if args.uneven > 0:
         bufs.clear()                        # the main workload's slice buffers
         torch.cuda.empty_cache()

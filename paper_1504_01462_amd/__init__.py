@@ -62,6 +62,7 @@ _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_uneven", [_vp, _i64, ctypes.POINTER(MsSlices), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_graph_replay", [_vp])
+_sig("ms_dT_dV", [_vp, ctypes.POINTER(MsSlices), _f64, _vp, _i64, _i64, _vp, _vp, _vp])
 
 
 class MsTiles(ctypes.Structure):
@@ -293,6 +294,41 @@ def ms_graph_replay(ctx: Context):
     _check(ctx.handle, lib.ms_graph_replay(ctx.handle))
 
 
+def ms_dT_dV(ctx: Context, slices: Slices, energy: float, q_of_ij: torch.Tensor, n_q: int, checkpoint: int = 0):
+    """g [n_slices][n_q] complex128 with dT = 2 Re sum g dV^p(Q), plus (T, R) and n_open at
+    this energy; `slices` must hold the eigenvectors (with_evec=True)."""
+    g = torch.empty((slices.n_slices, int(n_q)), dtype=torch.complex128, device=ctx.device)
+    tr = torch.empty(2, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(1, dtype=torch.int64, device=ctx.device)
+    _check(ctx.handle, lib.ms_dT_dV(ctx.handle, ctypes.byref(slices.c), float(energy),
+                                    _ptr(q_of_ij, torch.int32, "q_of_ij"), int(n_q), int(checkpoint), _ptr(g),
+                                    _ptr(tr), _ptr(no)))
+    return g, tr, no
+
+
+class Transmission(torch.autograd.Function):
+    """T(E, k_par) as a differentiable function of the slice potentials vq [n_slices][n_q]
+    (complex128, device).  forward: a1-a3 (with eigenvectors) and the right-cascade
+    checkpoints' run of ms_dT_dV, which also yields T; backward: the gradient it computed,
+    in PyTorch's convention for complex inputs of a real output (dL/dRe + i dL/dIm =
+    2 conj(g) dL/dT, treating every vq entry as independent).
+
+        T = Transmission.apply(vq, ctx, miller, bvec, kpar, q_of_ij, dz, energy, checkpoint)
+    """
+
+    @staticmethod
+    def forward(fctx, vq, ctx, miller, bvec, kpar, q_of_ij, dz, energy, checkpoint=0):
+        s = ms_slices_prepare(ctx, miller, bvec, kpar, q_of_ij, vq.detach(), dz, with_evec=True)
+        g, tr, _ = ms_dT_dV(ctx, s, energy, q_of_ij, vq.shape[1], checkpoint)
+        fctx.save_for_backward(g)
+        return tr[0].clone()
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (g,) = fctx.saved_tensors
+        return (2.0 * grad_out * g.conj(),) + (None,) * 8
+
+
 def ms_set_tiles(ctx: Context, n_g: int, iface: int = 0, lu_update: int = 0, lu_inner: int = 0):
     """GEMM tile edges (64, 128, or 0 = default rule) for folds of basis size n_g."""
     t = MsTiles(iface, lu_update, lu_inner)
@@ -416,6 +452,6 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
            "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
-           "MS_FOLD_GRAPH", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
+           "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

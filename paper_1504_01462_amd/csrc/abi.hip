@@ -145,7 +145,10 @@ enum {
   WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
   WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V,
   WS_MD_A = 33, WS_MD_B, WS_MD_INV, WS_MD_T, WS_MD_NRM,
-  WS_PERM, WS_RT, WS_RR, WS_RNO, WS_RST
+  WS_PERM, WS_RT, WS_RR, WS_RNO, WS_RST,
+  // first variation of T
+  WS_GSEG, WS_GCK, WS_GRS, WS_GL, WS_GK, WS_GP, WS_GCH, WS_GOS, WS_GX, WS_GFA, WS_GFB, WS_GAUG, WS_GY,
+  WS_GT1, WS_GBP, WS_GBF, WS_GP1, WS_GP2, WS_GMC, WS_GYG, WS_GKC, WS_GPIV, WS_GEN, WS_GA2, WS_GB2
 };
 
 constexpr int MAX_N = 4096;
@@ -556,6 +559,211 @@ ms_status star(ms_ctx ctx, int n, Blocks a, Blocks b, Blocks out) {
 Blocks blocks_of(const ms_smat& s) { return Blocks{c2(s.t), c2(s.rp), c2(s.r), c2(s.tp)}; }
 
 }  // namespace
+
+// ------------------------------------------------------------------------------------------
+// First variation of T with respect to the slice potentials.
+//
+// dt_ij = (1/(2 i k_i)) int phi_i^dagger dH psi_j dz (psi_j: incident from the left in open
+// channel j; phi_i: outgoing only into the right lead's open channel i), dT = sum_ij (k_i/k_j)
+// 2 Re(conj(t_ij) dt_ij).  Both states' amplitudes (A^p, B^p) at the reference plane of slice p
+// come from the left cascade L = S(0,p) and the right cascade R = S(p,N+1):
+// (I - L12 R21) A^p = L11 A^0 + L12 R22 B^{N+1}, B^p = R21 A^p + R22 B^{N+1}.  The right
+// cascades are swept once from the right lead, kept at every `ck`-th plane and recomputed
+// segment by segment while the left cascade is swept from the left lead.
+namespace {
+
+struct GradCtx {
+  ms_ctx ctx;
+  const ms_slices* sl;
+  double energy;
+  int n;
+  int64_t nn;
+};
+
+ms_status slice_smats_into(const GradCtx& G, int p0, int p1, double2* seg) {   // S(p,p+1), p in [p0,p1)
+  std::vector<ms_smat> out(p1 - p0);
+  for (int i = 0; i < p1 - p0; ++i) {
+    double2* b = seg + (int64_t)i * 4 * G.nn;
+    out[i] = ms_smat{G.n, b, b + G.nn, b + 2 * G.nn, b + 3 * G.nn};
+  }
+  return ms_slice_smatrix(G.ctx, G.sl, G.energy, p0, p1, out.data());
+}
+
+Blocks blk(double2* base, int64_t nn) { return Blocks{base, base + nn, base + 2 * nn, base + 3 * nn}; }
+
+ms_status copy_blocks(ms_ctx ctx, const double2* src, double2* dst, int64_t nn) {
+  MS_HIP(ctx, hipMemcpyAsync(dst, src, 4 * nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  return MS_OK;
+}
+
+}  // namespace
+
+ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
+                   int64_t checkpoint, void* grad, double* t_r, int64_t* n_open) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (bad_ptr(slices->evec)) return fail(ctx, MS_ERR_ARG, "slices->evec (the eigenvectors) is required");
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  if (bad_ptr(q_of_ij) || bad_ptr(grad) || bad_ptr(t_r) || bad_ptr(n_open))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n_q < 1) return fail(ctx, MS_ERR_ARG, "n_q must be >= 1");
+  if (checkpoint < 0) return fail(ctx, MS_ERR_ARG, "checkpoint must be >= 0");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
+  const int64_t nn = (int64_t)n * n;
+  const int ck = checkpoint > 0 ? (int)std::min<int64_t>(checkpoint, ns + 1)
+                                : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
+  GradCtx G{ctx, slices, energy, n, nn};
+  const size_t B4 = 4 * nn * sizeof(double2);
+  {   // every q_of_ij value must index the gradient's n_q columns (they are scatter targets)
+    void* mm;
+    MS_TRY(workspace(ctx, WS_MISC, 4 * sizeof(int32_t), &mm));
+    MS_TRY(launch_minmax(ctx, nn, q_of_ij, (int32_t*)mm));
+    int32_t qr[2] = {0, 0};
+    MS_HIP(ctx, hipMemcpyAsync(qr, mm, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (qr[0] < 0 || qr[1] >= n_q)
+      return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
+  }
+  // host copies: thicknesses and the two leads' channel energies
+  std::vector<double> dzh(ns), el(n), er(n);
+  MS_HIP(ctx, hipMemcpyAsync(dzh.data(), slices->dz, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(el.data(), slices->eps, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(er.data(), slices->eps + (int64_t)(ns + 1) * n, n * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  std::vector<int32_t> chan;
+  for (int i = 0; i < n; ++i)
+    if (el[i] < energy) chan.push_back(i);
+  const int nl = (int)chan.size();
+  for (int i = 0; i < n; ++i)
+    if (er[i] < energy) chan.push_back(i);
+  const int nr = (int)chan.size() - nl;
+  MS_HIP(ctx, hipMemsetAsync(grad, 0, (size_t)ns * n_q * sizeof(double2), ctx->stream));
+  void *seg, *cks, *rseg, *lb, *kb, *pb, *chd, *en, *v;
+  const int nck = (ns + 1) / ck + 1;            // planes 0, ck, 2 ck, ... <= ns
+  MS_TRY(workspace(ctx, WS_GSEG, (size_t)(ck + 1) * B4, &seg));
+  MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * B4, &cks));
+  MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 1) * B4, &rseg));
+  MS_TRY(workspace(ctx, WS_GL, 2 * B4, &lb));
+  MS_TRY(workspace(ctx, WS_GK, (size_t)nrows * n * sizeof(double2), &kb));
+  MS_TRY(workspace(ctx, WS_GP, (size_t)nrows * n * sizeof(double2), &pb));
+  MS_TRY(workspace(ctx, WS_GCH, std::max<size_t>(1, chan.size()) * sizeof(int32_t), &chd));
+  MS_TRY(workspace(ctx, WS_GEN, sizeof(double), &en));
+  if (!chan.empty()) MS_TRY(upload(ctx, chd, chan.data(), chan.size() * sizeof(int32_t)));
+  MS_TRY(upload(ctx, en, &energy, sizeof(double)));
+  MS_TRY(launch_wavevectors(ctx, n, nrows, 1, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb)));
+  const int32_t* ol = (const int32_t*)chd;
+  const int32_t* orr = ol + nl;
+
+  // 1. right sweep R_p = S(p,p+1) * R_{p+1} from R_ns = S(ns,ns+1); R_p kept when p % ck == 0
+  double2* segp = c2(seg);
+  double2* ckp = c2(cks);
+  double2* racc[2] = {c2(rseg), c2(rseg) + 4 * nn};   // ping-pong (rseg has >= 2 slots)
+  int cur = 0;
+  for (int hi = ns; hi >= 0; hi -= (ck + 1)) {
+    const int lo = std::max(0, hi - ck);
+    MS_TRY(slice_smats_into(G, lo, hi + 1, segp));
+    for (int p = hi; p >= lo; --p) {
+      double2* sp = segp + (int64_t)(p - lo) * 4 * nn;
+      if (p == ns) {
+        MS_TRY(copy_blocks(ctx, sp, racc[cur], nn));
+      } else {
+        MS_TRY(star(ctx, n, blk(sp, nn), blk(racc[cur], nn), blk(racc[cur ^ 1], nn)));
+        cur ^= 1;
+      }
+      if (p % ck == 0) MS_TRY(copy_blocks(ctx, racc[cur], ckp + (int64_t)(p / ck) * 4 * nn, nn));
+    }
+  }
+  // 2. the whole S = R_0: T, R, N_open
+  const Blocks whole = blk(ckp, nn);
+  MS_TRY(launch_whole_T(ctx, n, energy, whole.t, whole.r, slices->eps, slices->eps + (int64_t)(ns + 1) * n, t_r,
+                        t_r + 1, n_open, ctx->d_status));
+  if (nl == 0 || nr == 0) return MS_OK;       // no open channel: dT = 0
+  // 3. incoming amplitudes of the out-states: [r_OO t'_OR; t_RO r'_RR] [x; y] = [0; e_i]
+  const int m = nl + nr;
+  void *os, *xs, *fa, *fbv, *pv;
+  MS_TRY(workspace(ctx, WS_GOS, (size_t)m * (m + nr) * sizeof(double2), &os));
+  MS_TRY(workspace(ctx, WS_GX, (size_t)m * nr * sizeof(double2), &xs));
+  MS_TRY(workspace(ctx, WS_GFA, (size_t)n * nr * sizeof(double2), &fa));
+  MS_TRY(workspace(ctx, WS_GFB, (size_t)n * nr * sizeof(double2), &fbv));
+  MS_TRY(workspace(ctx, WS_GPIV, (size_t)n * sizeof(int32_t), &pv));
+  MS_TRY(launch_grad_open_system(ctx, n, nl, nr, ol, orr, whole.t, whole.rp, whole.r, whole.tp, c2(os)));
+  MS_TRY(getrf_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, (int32_t*)pv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, c2(xs), nr, (int64_t)m * nr,
+                        ctx->d_status, 0));
+  MS_TRY(launch_grad_incoming(ctx, n, nl, nr, ol, orr, c2(xs), c2(fa), c2(fbv)));
+  // 4. segments of planes [lo, hi], lo >= 1: recompute R_p there, sweep L_p, add each slice
+  const int w = nl + nr, ldaug = n + w;
+  void *aug, *ys, *t1, *bps, *bph, *p1, *p2, *mc, *yg, *kc;
+  MS_TRY(workspace(ctx, WS_GAUG, (size_t)n * ldaug * sizeof(double2), &aug));
+  MS_TRY(workspace(ctx, WS_GY, (size_t)n * w * sizeof(double2), &ys));
+  MS_TRY(workspace(ctx, WS_GT1, (size_t)n * nr * sizeof(double2), &t1));
+  MS_TRY(workspace(ctx, WS_GBP, (size_t)n * nl * sizeof(double2), &bps));
+  MS_TRY(workspace(ctx, WS_GBF, (size_t)n * nr * sizeof(double2), &bph));
+  MS_TRY(workspace(ctx, WS_GP1, (size_t)n * nl * sizeof(double2), &p1));
+  MS_TRY(workspace(ctx, WS_GP2, (size_t)n * nl * sizeof(double2), &p2));
+  MS_TRY(workspace(ctx, WS_GMC, nn * sizeof(double2), &mc));
+  MS_TRY(workspace(ctx, WS_GYG, nn * sizeof(double2), &yg));
+  MS_TRY(workspace(ctx, WS_GKC, nn * sizeof(double2), &kc));
+  double2* lbuf[2] = {c2(lb), c2(lb) + 4 * nn};
+  int lc = 0;
+  const double2* kl = c2(kb);   // left lead row
+  for (int lo = 1; lo <= ns; lo = (lo / ck + 1) * ck) {
+    const int hi = std::min(ns, (lo / ck + 1) * ck - 1);
+    // interfaces S(p,p+1), p in [lo-1, hi]: seg[i] = S(lo-1+i, lo+i)
+    MS_TRY(slice_smats_into(G, lo - 1, hi + 1, segp));
+    // R_p for p = hi..lo into rseg[p - lo]: R_hi from the checkpoint at hi + 1 (or S(ns,ns+1))
+    double2* rs = c2(rseg);
+    for (int p = hi; p >= lo; --p) {
+      double2* sp = segp + (int64_t)(p - lo + 1) * 4 * nn;
+      double2* dst = rs + (int64_t)(p - lo) * 4 * nn;
+      if (p == ns) {
+        MS_TRY(copy_blocks(ctx, sp, dst, nn));
+      } else {
+        const double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * 4 * nn : dst + 4 * nn;
+        MS_TRY(star(ctx, n, blk(sp, nn), blk(const_cast<double2*>(right), nn), blk(dst, nn)));
+      }
+    }
+    for (int p = lo; p <= hi; ++p) {
+      // L_p = L_{p-1} * S(p-1,p)  (L_1 = S(0,1))
+      double2* sprev = segp + (int64_t)(p - lo) * 4 * nn;
+      if (p == 1) {
+        MS_TRY(copy_blocks(ctx, sprev, lbuf[lc], nn));
+      } else {
+        MS_TRY(star(ctx, n, blk(lbuf[lc], nn), blk(sprev, nn), blk(lbuf[lc ^ 1], nn)));
+        lc ^= 1;
+      }
+      const Blocks L = blk(lbuf[lc], nn);
+      const Blocks R = blk(rs + (int64_t)(p - lo) * 4 * nn, nn);
+      // [I - L12 R21 | L11[:, ol] | L11 fa0 + L12 (R22 fb)]
+      MS_TRY(launch_eye(ctx, n, ldaug, c2(aug)));
+      MS_TRY(gemm(ctx, n, n, n, L.rp, n, OP_N, R.r, n, OP_N, aug, ldaug, MONE, ONE));
+      MS_TRY(launch_gather_cols(ctx, n, nl, ol, L.t, n, c2(aug) + n, ldaug));
+      MS_TRY(gemm(ctx, n, nr, n, R.tp, n, OP_N, fbv, nr, OP_N, t1, nr, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, nr, n, L.t, n, OP_N, fa, nr, OP_N, c2(aug) + n + nl, ldaug, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, nr, n, L.rp, n, OP_N, t1, nr, OP_N, c2(aug) + n + nl, ldaug, ONE, ONE));
+      MS_TRY(getrf_aug(ctx, c2(aug), n, ldaug, (int64_t)n * ldaug, 1, (int32_t*)pv, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, c2(aug), n, ldaug, (int64_t)n * ldaug, 1, c2(ys), w, (int64_t)n * w, ctx->d_status,
+                            0));
+      const double2* apsi = c2(ys);          // n x nl, ld w
+      const double2* aphi = c2(ys) + nl;     // n x nr, ld w
+      // B^p: psi: R21 a; phi: R21 a + R22 fb
+      MS_TRY(gemm(ctx, n, nl, n, R.r, n, OP_N, apsi, w, OP_N, bps, nl, ONE, ZERO));
+      MS_HIP(ctx, hipMemcpyAsync(bph, t1, (size_t)n * nr * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+      MS_TRY(gemm(ctx, n, nr, n, R.r, n, OP_N, aphi, w, OP_N, bph, nr, ONE, ONE));
+      // slice p: conj(M), then conj(K) = U conj(M) U^dagger, then g[q(a,b)] += K_ab
+      MS_TRY(launch_grad_p(ctx, n, nl, nr, aphi, w, c2(bph), nr, whole.t, ol, orr, kl, c2(p1), c2(p2)));
+      MS_TRY(launch_grad_m(ctx, n, nl, c2(kb) + (int64_t)p * n, dzh[p - 1], c2(p1), c2(p2), apsi, w, c2(bps), nl,
+                           c2(mc)));
+      const double2* U = c2(slices->evec) + (int64_t)(p - 1) * nn;
+      MS_TRY(gemm(ctx, n, n, n, mc, n, OP_N, U, n, OP_C, yg, n, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, n, n, U, n, OP_N, yg, n, OP_N, kc, n, ONE, ZERO));
+      MS_TRY(launch_grad_scatter(ctx, nn, q_of_ij, c2(kc), static_cast<double*>(grad) + 2 * (int64_t)(p - 1) * n_q));
+    }
+  }
+  return MS_OK;
+}
 
 ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec prec, ms_smat* whole) {
   if (!ctx) return MS_ERR_ARG;

@@ -14,6 +14,7 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 // k = sqrt(E - eps) on the branch Im k >= 0;  P = exp(i k dz)
 __device__ __forceinline__ double2 kz(double e, double eps) {
@@ -372,6 +373,127 @@ __global__ __launch_bounds__(256) void k_norm1(int n, const double2* A, int64_t 
 
 inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+// ---- first variation of T (gradient with respect to the slice potentials) -------------
+
+// The open-channel system of the out-states: rows/cols [0, nl) are the left lead's open
+// channels ol, [nl, nl + nr) the right lead's orr.  aug = [[r_OO, tp_OR], [t_RO, rp_RR] | 0; I]
+// (row-major, ld = 2 nl + 2 nr... width w = nl + nr + nr).
+__global__ void k_grad_open_system(int n, int nl, int nr, const int32_t* ol, const int32_t* orr, const double2* t,
+                                   const double2* rp, const double2* r, const double2* tp, double2* aug) {
+  const int m = nl + nr, w = m + nr;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * w) return;
+  const int i = idx / w, j = idx % w;
+  double2 v = make_double2(0.0, 0.0);
+  if (j < m) {
+    const bool top = i < nl, left = j < nl;
+    const int gi = top ? ol[i] : orr[i - nl];
+    const int gj = left ? ol[j] : orr[j - nl];
+    const double2* blk = top ? (left ? r : tp) : (left ? t : rp);
+    v = blk[(int64_t)gi * n + gj];
+  } else if (i >= nl && (i - nl) == (j - m)) {
+    v = make_double2(1.0, 0.0);
+  }
+  aug[idx] = v;
+}
+
+// dst[:, c] = src[:, idx[c]] for c < nc (n rows; row-major, leading dims lds, ldd); idx < 0: zero
+__global__ void k_gather_cols(int n, int nc, const int32_t* idx, const double2* src, int64_t lds, double2* dst,
+                              int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nc) return;
+  const int i = (int)(e / nc), c = (int)(e % nc);
+  const int s = idx[c];
+  dst[(int64_t)i * ldd + c] = s >= 0 ? src[(int64_t)i * lds + s] : make_double2(0.0, 0.0);
+}
+
+// the out-states' incoming amplitudes: fa0[ol[a], c] = x[a][c], fb[orr[b], c] = x[nl + b][c],
+// every other entry 0 (n x nr each, row-major)
+__global__ void k_grad_incoming(int n, int nl, int nr, const int32_t* ol, const int32_t* orr, const double2* x,
+                                double2* fa0, double2* fb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nr) return;
+  const int row = (int)(e / nr), c = (int)(e % nr);
+  double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
+  for (int a = 0; a < nl; ++a)
+    if (ol[a] == row) va = x[(int64_t)a * nr + c];
+  for (int b = 0; b < nr; ++b)
+    if (orr[b] == row) vb = x[(int64_t)(nl + b) * nr + c];
+  fa0[e] = va;
+  fb[e] = vb;
+}
+
+// int_{-w}^{0} e^{i kappa s} ds
+__device__ __forceinline__ double2 exp_integral(double2 kap, double w) {
+  const double2 x = make_double2(-kap.y * w, kap.x * w);       // i kappa w
+  if (x.x * x.x + x.y * x.y < 1e-16) return make_double2(w * (1.0 - 0.5 * x.x), -0.5 * w * x.y);
+  const double em = exp(-x.x);                                 // e^{-x}
+  const double2 one_minus = make_double2(1.0 - em * cos(-x.y), -em * sin(-x.y));
+  const double2 ik = make_double2(-kap.y, kap.x);
+  return cdiv(one_minus, ik);
+}
+
+// conj(M) of one slice, n x n row-major:
+//   M_nm = sum_j P1_nj (a_mj E(k_m - k*_n) + b_mj E(-k_m - k*_n)) + P2_nj (a_mj E(k_m + k*_n) + b_mj E(-k_m + k*_n))
+// with P1 = conj(C) w, P2 = conj(D) w (n x nl), a, b the in-states' amplitudes (n x nl),
+// k the slice's wavevectors, w its thickness.
+__global__ void k_grad_m(int n, int nl, const double2* k, double width, const double2* p1, const double2* p2,
+                         const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int row = (int)(e / n), col = (int)(e % n);
+  const double2 kn = cconj(k[row]), km = k[col];
+  const double2 e1 = exp_integral(make_double2(km.x - kn.x, km.y - kn.y), width);
+  const double2 e2 = exp_integral(make_double2(-km.x - kn.x, -km.y - kn.y), width);
+  const double2 e3 = exp_integral(make_double2(km.x + kn.x, km.y + kn.y), width);
+  const double2 e4 = exp_integral(make_double2(-km.x + kn.x, -km.y + kn.y), width);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int j = 0; j < nl; ++j) {
+    const double2 aj = a[(int64_t)col * lda + j], bj = b[(int64_t)col * ldb + j];
+    const double2 u = cadd(cmul(aj, e1), cmul(bj, e2));
+    const double2 v = cadd(cmul(aj, e3), cmul(bj, e4));
+    acc = cadd(acc, cadd(cmul(p1[(int64_t)row * nl + j], u), cmul(p2[(int64_t)row * nl + j], v)));
+  }
+  mc[e] = cconj(acc);
+}
+
+// P = conj(C) w: P_nj = sum_i conj(C_ni) w_ij, w_ij = conj(t_ij) / (2 i k_j)  (i in orr, j in ol)
+__global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d, int64_t ldd,
+                         const double2* whole_t, const int32_t* ol, const int32_t* orr, const double2* kl, double2* p1,
+                         double2* p2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * nl) return;
+  const int row = (int)(e / nl), j = (int)(e % nl);
+  const double2 kj = kl[ol[j]];
+  const double2 den = make_double2(-2.0 * kj.y, 2.0 * kj.x);   // 2 i k_j
+  double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+  for (int i = 0; i < nr; ++i) {
+    const double2 w = cdiv(cconj(whole_t[(int64_t)orr[i] * n + ol[j]]), den);
+    s1 = cadd(s1, cmul(cconj(c[(int64_t)row * ldc + i]), w));
+    s2 = cadd(s2, cmul(cconj(d[(int64_t)row * ldd + i]), w));
+  }
+  p1[e] = s1;
+  p2[e] = s2;
+}
+
+// the first n columns of an n-row matrix (leading dim ld) set to the identity
+__global__ void k_eye(int n, int64_t ld, double2* dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  dst[(int64_t)i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// g[q(a,b)] += conj(Kc_ab)
+__global__ void k_grad_scatter(int64_t nn, const int32_t* q, const double2* kc, double* g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const int64_t qi = q[e];
+  const double2 v = kc[e];
+  atomicAdd(g + 2 * qi, v.x);
+  atomicAdd(g + 2 * qi + 1, -v.y);
+}
+
 }  // namespace
 
 ms_status launch_wavevectors(ms_ctx ctx, int n, int nrows, int n_e, const double* eps, const double* energies_dev,
@@ -498,6 +620,55 @@ ms_status launch_axpby(ms_ctx ctx, int64_t nn, int nb, double alpha, const doubl
 ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, int64_t s, double* out) {
   hipLaunchKernelGGL(k_norm1, dim3(nb), dim3(256), 0, ctx->stream, n, A, ld, s, out);
   return check_launch(ctx, "1-norm");
+}
+
+
+ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
+                                  const double2* t, const double2* rp, const double2* r, const double2* tp,
+                                  double2* aug) {
+  const int total = (nl + nr) * (nl + 2 * nr);
+  hipLaunchKernelGGL(k_grad_open_system, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, n, nl, nr, ol, orr, t,
+                     rp, r, tp, aug);
+  return check_launch(ctx, "gradient open system");
+}
+
+ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, const double2* src, int64_t lds,
+                             double2* dst, int64_t ldd) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(blocks((int64_t)n * nc)), dim3(256), 0, ctx->stream, n, nc, idx, src, lds,
+                     dst, ldd);
+  return check_launch(ctx, "gather columns");
+}
+
+ms_status launch_grad_incoming(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
+                               const double2* x, double2* fa0, double2* fb) {
+  hipLaunchKernelGGL(k_grad_incoming, dim3(blocks((int64_t)n * nr)), dim3(256), 0, ctx->stream, n, nl, nr, ol, orr,
+                     x, fa0, fb);
+  return check_launch(ctx, "gradient incoming amplitudes");
+}
+
+ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d,
+                        int64_t ldd, const double2* whole_t, const int32_t* ol, const int32_t* orr, const double2* kl,
+                        double2* p1, double2* p2) {
+  hipLaunchKernelGGL(k_grad_p, dim3(blocks((int64_t)n * nl)), dim3(256), 0, ctx->stream, n, nl, nr, c, ldc, d, ldd,
+                     whole_t, ol, orr, kl, p1, p2);
+  return check_launch(ctx, "gradient weights");
+}
+
+ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, double width, const double2* p1,
+                        const double2* p2, const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc) {
+  hipLaunchKernelGGL(k_grad_m, dim3(blocks((int64_t)n * n)), dim3(256), 0, ctx->stream, n, nl, k, width, p1, p2, a, lda,
+                     b, ldb, mc);
+  return check_launch(ctx, "gradient slice integrals");
+}
+
+ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst) {
+  hipLaunchKernelGGL(k_eye, dim3(blocks((int64_t)n * n)), dim3(256), 0, ctx->stream, n, ld, dst);
+  return check_launch(ctx, "identity");
+}
+
+ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, double* g) {
+  hipLaunchKernelGGL(k_grad_scatter, dim3(blocks(nn)), dim3(256), 0, ctx->stream, nn, q, kc, g);
+  return check_launch(ctx, "gradient scatter");
 }
 
 }  // namespace ms

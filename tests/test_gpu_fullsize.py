@@ -122,3 +122,34 @@ def test_uneven_instances_config4_sample(ms, full):
     k = pick.index(12)                              # n_g = 200, 248 slices
     ref = orc.transmission(orc.prepare(inps[k]), es[k][0])
     assert abs(T[k] - ref["T"]) < 1e-10 and int(no[k]) == ref["n_open"]
+
+
+def test_dT_dV_full_size_central_differences(ms, full):
+    """The adjoint workload's geometry at full size (config3 gap 6.3, k_par = 0, N_G = 1200,
+    400 slices, checkpoints every 20 planes): three slice coefficients' derivatives against
+    central differences of the batch path's T (h = 1e-5), and T itself."""
+    import torch
+    ctx = full["ctx"]
+    j = msgen.config5()
+    inp = msgen.junction_inputs(j, j.kpars[0])
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device="cuda")
+    e = float(j.energies[8])
+    g, tr, no = ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], 20)
+    T0 = ms.ms_transmission_batch(ctx, s, [e])[0].cpu().numpy()[0]
+    ctx.sync()
+    g = g.cpu().numpy()
+    assert abs(tr.cpu().numpy()[0] - T0) < 1e-9
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    h = 1e-5
+    for p in (37, 200, 371):
+        vals = []
+        for sgn in (1, -1):
+            vq = inp["vq"].copy()
+            vq[p, q0] += sgn * h
+            sp = ms.prepare_from_inputs(ctx, dict(inp, vq=vq))
+            vals.append(ms.ms_transmission_batch(ctx, sp, [e])[0].cpu().numpy()[0])
+            ctx.sync()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = 2.0 * np.real(g[p, q0])
+        assert abs(fd - an) < 1e-6 + 1e-4 * abs(an), (p, fd, an)

@@ -540,3 +540,101 @@ def test_tile_choice_and_autotune_do_not_change_results(ms, ctx):
     with pytest.raises(ms.MSError) as ei:
         ms.ms_autotune(ctx, 37, 40, 5)            # more open channels than plane waves
     assert ei.value.status == ms.MS_ERR_ARG
+
+
+# ------------------------------------------------------------------ dT/dV -----------------
+def _grad_case(ms, ctx, n_g, ns, kpar):
+    j = msgen.config1()
+    j.dz = np.full(ns, 6.0 / ns)
+    inp = msgen.junction_inputs(j, kpar, n_g)
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device="cuda")
+    return inp, s, q
+
+
+@pytest.mark.parametrize("n_g,ns,e", [(13, 6, 2.3), (21, 9, 1.1), (37, 24, 0.7)])
+def test_dT_dV_matches_oracle(ms, ctx, n_g, ns, e):
+    """The gradient of every slice coefficient against the oracle's first variation, with
+    the right cascades kept at every plane, every 4th, the default spacing and only at the
+    left lead (all recomputed)."""
+    inp, s, q = _grad_case(ms, ctx, n_g, ns, (0.07, -0.11))
+    prep = orc.prepare(inp)
+    ref = orc.dT_dV(prep, e, inp["q_of_ij"], inp["vq"].shape[1])
+    out = orc.transmission(prep, e)
+    scale = np.max(np.abs(ref))
+    for ck in (1, 4, 0, ns + 1):
+        g, tr, no = ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], ck)
+        ctx.sync()
+        g = _np(g)
+        assert np.max(np.abs(g - ref)) < 1e-10 * scale, (ck, np.max(np.abs(g - ref)), scale)
+        assert abs(_np(tr)[0] - out["T"]) < 1e-10 and int(_np(no)[0]) == out["n_open"]
+
+
+def test_dT_dV_central_differences_on_gpu(ms, ctx):
+    """d T / d Re V^p(Q) and d Im, with V(-Q) = conj V(Q) kept, against central differences
+    of the GPU's own T (h = 1e-6) on 6 seeded coefficients of the config1 cell (37 plane
+    waves, 24 slices)."""
+    inp, s, q = _grad_case(ms, ctx, 37, 24, (0.0, 0.0))
+    e = 0.7
+    g = _np(ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1])[0])
+    ctx.sync()
+    qi, qj, dre, dim = orc.dT_dV_real(g, inp["q_miller"])
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for _ in range(6):
+        p, c = int(rng.integers(0, 24)), int(rng.integers(0, len(qi)))
+        for part in ("re", "im"):
+            if part == "im" and qi[c] == qj[c]:
+                continue
+            vals = []
+            for sgn in (1, -1):
+                vq = inp["vq"].copy()
+                d = h * (1 if part == "re" else 1j) * sgn
+                vq[p, qi[c]] += d
+                if qj[c] != qi[c]:
+                    vq[p, qj[c]] += np.conj(d)
+                sp = ms.prepare_from_inputs(ctx, dict(inp, vq=vq))
+                vals.append(float(_np(ms.ms_transmission_batch(ctx, sp, [e])[0])[0]))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = dre[p, c] if part == "re" else dim[p, c]
+            assert abs(fd - an) < 5e-8 + 1e-5 * abs(an), (p, c, part, fd, an)
+
+
+def test_transmission_autograd(ms, ctx):
+    """torch.autograd: T from the Function equals the batch path's T, and vq.grad is
+    2 conj(g) (PyTorch's convention for complex inputs of a real output)."""
+    inp, s, q = _grad_case(ms, ctx, 21, 9, (0.07, -0.11))
+    e = 1.1
+    dev = torch.device("cuda")
+    vq = torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev).requires_grad_(True)
+    miller = torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev)
+    dz = torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev)
+    T = ms.Transmission.apply(vq, ctx, miller, np.asarray(inp["bvec"]).reshape(4), inp["kpar"], q, dz, e, 3)
+    (3.0 * T).backward()
+    ref_T = float(_np(ms.ms_transmission_batch(ctx, s, [e])[0])[0])
+    g = _np(ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1])[0])
+    ctx.sync()
+    assert abs(float(T.item()) - ref_T) < 1e-12
+    assert np.max(np.abs(_np(vq.grad) - 6.0 * np.conj(g))) < 1e-12 * max(1.0, np.max(np.abs(g)))
+
+
+def test_dT_dV_argument_errors(ms, ctx, c1):
+    _, inp, _ = c1
+    s = ms.prepare_from_inputs(ctx, inp)             # no eigenvectors kept
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device="cuda")
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_dT_dV(ctx, s, 0.5, q, inp["vq"].shape[1])
+    assert ei.value.status == ms.MS_ERR_ARG
+    s2 = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_dT_dV(ctx, s2, float("nan"), q, inp["vq"].shape[1])
+    assert ei.value.status == ms.MS_ERR_ARG
+
+
+def test_dT_dV_rejects_out_of_range_q(ms, ctx, c1):
+    _, inp, _ = c1
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device="cuda")
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_dT_dV(ctx, s, 0.5, q, int(inp["q_of_ij"].max()))      # n_q one too small
+    assert ei.value.status == ms.MS_ERR_ARG
