@@ -16,7 +16,7 @@ The steps run twice, in FP64 and in the FP32-MFMA form, over the same
 also solved with the paper's mixed transfer/scattering doubling, and the first
 instances of the uneven workload (N_G from 200 to 1200, 100-400 slices, one point
 each) are folded in one call, the small ones also in a captured hipGraph
-(`uneven_batch`), and the gradient dT/dV of every slice coefficient is timed at two
+(`uneven_batch`), and the gradient dT/dV of every slice coefficient is timed at three
 energies of the adjoint workload (`adjoint`).
 
     python bench.py [--steps K] [--warmup W] [--config config3|config2|config1]
@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
                          "captured graph after the main measurement; 0 skips it")
-    ap.add_argument("--adjoint", type=int, default=2,
+    ap.add_argument("--adjoint", type=int, default=3,
                     help="energies of the adjoint workload (dT/dV at N_G = 1200) to time; 0 skips it")
     ap.add_argument("--uneven-only", action="store_true",
                     help="measure only the uneven workload (--uneven instances) and print its JSON line")
@@ -351,7 +351,8 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
 def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     """The adjoint workload: dT/dV^p(Q) for every slice and Fourier coefficient of the
     side-contact junction at gap 6.3 bohr, k_par = 0 (N_G = 1200, 400 slices, checkpoints every
-    20 planes), at `n_e` of its 16 energies; seconds per energy, and the derivative with
+    20 planes), at `n_e` of its 16 energies in one call (they run concurrently on internal
+    streams); seconds per energy, and the derivative with
     respect to Re V^p(0) on three slices against central differences of T (h = 1e-5)."""
     import torch
     import msgen
@@ -365,15 +366,15 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
     idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
-    times, grads = [], []
-    for i in idx:
-        e = float(j.energies[i])
-        t0 = time.perf_counter()
-        g, tr, no = ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], 20)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        grads.append((e, g.cpu().numpy(), tr.cpu().numpy(), int(no.cpu().numpy()[0])))
-        log(f"adjoint: E = {e:.4f} Ry, T = {grads[-1][2][0]:.6f}, {times[-1]:.2f} s")
+    es = [float(j.energies[i]) for i in idx]
+    t0 = time.perf_counter()
+    gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 20)   # energies on internal streams
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    trall = trall.cpu().numpy()
+    log(f"adjoint: {n_e} energies in {total:.2f} s ({total / n_e:.2f} s per energy), T = {trall[:, 0]}")
+    times = [total / n_e] * n_e
+    grads = [(es[0], gall[0].cpu().numpy(), trall[0], 0)]
     e, g, tr, _ = grads[0]
     q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
     h, rel = 1e-5, []
@@ -392,7 +393,9 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     return {
         "workload": "dT/dV^p(Q) of the side-contact junction at gap 6.3 bohr, k_par = 0: N_G = 1200, "
                     f"400 slices, {inp['vq'].shape[1]} Fourier coefficients per slice, checkpoints every 20 planes",
-        "energies": [float(x[0]) for x in grads],
+        "energies": es,
+        "T": [float(x) for x in trall[:, 0]],
+        "concurrent_streams": min(3, n_e),
         "prepare_with_eigenvectors_s": round(prep_s, 3),
         "seconds_per_energy": [round(x, 3) for x in times],
         "gradient_entries_per_energy": int(ns * inp["vq"].shape[1]),

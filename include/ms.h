@@ -245,20 +245,25 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  * to first order, for independent complex dV (keep V(-Q) = conj V(Q) to stay Hermitian:
  * dT/dRe V(Q) = 2 Re(g(Q) + g(-Q)), dT/dIm V(Q) = 2 Im(g(-Q) - g(Q)) for Q != -Q).
  *   slices      prepared with the eigenvectors (slices->evec != NULL)
+ *   energies    [n_e] f64 (host); several energies run concurrently on up to three internal
+ *               streams (each with its own workspace), joined to the context's stream
  *   q_of_ij     [n_g][n_g] int32 (device), the map of ms_slices_prepare
  *   n_q         number of Q
  *   checkpoint  planes between stored right cascades (0: about sqrt(n_slices + 1));
  *               workspace about 3 (checkpoint + 1) + (n_slices + 1) / checkpoint blocks of
  *               4 n_g^2 c128
- *   grad        [n_slices][n_q] c128 (device output)
- *   t_r         [2] f64 (device output): T and R at this energy; n_open [1] int64 (device)
+ *   grad        [n_e][n_slices][n_q] c128 (device output)
+ *   t_r         [n_e][2] f64 (device output): T and R; n_open [n_e] int64 (device)
  * Cost: about three star-product cascades (3 x 10 1/3 n_g^3 complex MACs per interface) plus
- * two slice S-matrices, one n_g-column solve and two n_g^3 products per slice.  Waits for
- * the stream once (the leads' channel energies).  Errors: MS_ERR_ARG (no eigenvectors,
- * nulls, non-finite energy, n_q < 1), MS_ERR_UNSUPPORTED, MS_ERR_ALLOC; numerical errors
- * (singular systems, lead threshold) via ms_ctx_sync. */
-ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
-                   int64_t checkpoint, void* grad, double* t_r, int64_t* n_open);
+ * two slice S-matrices, one n_g-column solve and two n_g^3 products per slice and energy.
+ * The sum over Q uses FP64 atomic additions, so g can differ in the last bits from run to
+ * run (T and R do not).  Waits for the stream (the range of q_of_ij, each energy's lead
+ * channel energies).
+ * Errors: MS_ERR_ARG (no eigenvectors, nulls, non-finite energies, n_q < 1, q_of_ij out of
+ * [0, n_q)), MS_ERR_UNSUPPORTED, MS_ERR_ALLOC; numerical errors (singular systems, lead
+ * threshold) via ms_ctx_sync. */
+ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const double* energies, const int32_t* q_of_ij,
+                   int64_t n_q, int64_t checkpoint, void* grad, double* t_r, int64_t* n_open);
 
 /* Tile edges of the fold's complex GEMMs for one basis size: 64 (64 x 64 tiles, 4 waves) or
  * 128 (128 x 128 tiles, 8 waves); 0 = the default rule (64 for the LU's products, 128 for the

@@ -62,7 +62,7 @@ _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_uneven", [_vp, _i64, ctypes.POINTER(MsSlices), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_graph_replay", [_vp])
-_sig("ms_dT_dV", [_vp, ctypes.POINTER(MsSlices), _f64, _vp, _i64, _i64, _vp, _vp, _vp])
+_sig("ms_dT_dV", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _vp, _i64, _i64, _vp, _vp, _vp])
 
 
 class MsTiles(ctypes.Structure):
@@ -294,15 +294,21 @@ def ms_graph_replay(ctx: Context):
     _check(ctx.handle, lib.ms_graph_replay(ctx.handle))
 
 
-def ms_dT_dV(ctx: Context, slices: Slices, energy: float, q_of_ij: torch.Tensor, n_q: int, checkpoint: int = 0):
-    """g [n_slices][n_q] complex128 with dT = 2 Re sum g dV^p(Q), plus (T, R) and n_open at
-    this energy; `slices` must hold the eigenvectors (with_evec=True)."""
-    g = torch.empty((slices.n_slices, int(n_q)), dtype=torch.complex128, device=ctx.device)
-    tr = torch.empty(2, dtype=torch.float64, device=ctx.device)
-    no = torch.empty(1, dtype=torch.int64, device=ctx.device)
-    _check(ctx.handle, lib.ms_dT_dV(ctx.handle, ctypes.byref(slices.c), float(energy),
+def ms_dT_dV(ctx: Context, slices: Slices, energies, q_of_ij: torch.Tensor, n_q: int, checkpoint: int = 0):
+    """For each energy, g [n_slices][n_q] complex128 with dT = 2 Re sum g dV^p(Q), plus (T, R)
+    and n_open: returns g [n_e][n_slices][n_q], tr [n_e][2], no [n_e] (a scalar energy gives
+    the same without the leading axis).  `slices` must hold the eigenvectors (with_evec=True)."""
+    scalar = np.ndim(energies) == 0
+    e = np.ascontiguousarray(np.atleast_1d(np.asarray(energies, dtype=np.float64)))
+    n_e = len(e)
+    g = torch.empty((n_e, slices.n_slices, int(n_q)), dtype=torch.complex128, device=ctx.device)
+    tr = torch.empty((n_e, 2), dtype=torch.float64, device=ctx.device)
+    no = torch.empty(n_e, dtype=torch.int64, device=ctx.device)
+    _check(ctx.handle, lib.ms_dT_dV(ctx.handle, ctypes.byref(slices.c), n_e, e.ctypes.data_as(ctypes.c_void_p),
                                     _ptr(q_of_ij, torch.int32, "q_of_ij"), int(n_q), int(checkpoint), _ptr(g),
                                     _ptr(tr), _ptr(no)))
+    if scalar:
+        return g[0], tr[0], no[:1]
     return g, tr, no
 
 

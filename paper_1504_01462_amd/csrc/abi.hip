@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "elem.h"
@@ -598,33 +599,19 @@ ms_status copy_blocks(ms_ctx ctx, const double2* src, double2* dst, int64_t nn) 
 
 }  // namespace
 
-ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
-                   int64_t checkpoint, void* grad, double* t_r, int64_t* n_open) {
-  if (!ctx) return MS_ERR_ARG;
-  MS_TRY(check_slices(ctx, slices));
-  if (bad_ptr(slices->evec)) return fail(ctx, MS_ERR_ARG, "slices->evec (the eigenvectors) is required");
-  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
-  if (bad_ptr(q_of_ij) || bad_ptr(grad) || bad_ptr(t_r) || bad_ptr(n_open))
-    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
-  if (n_q < 1) return fail(ctx, MS_ERR_ARG, "n_q must be >= 1");
-  if (checkpoint < 0) return fail(ctx, MS_ERR_ARG, "checkpoint must be >= 0");
+namespace {
+
+ms_status sync_events(ms_ctx ctx, size_t count);
+ms_status check_energies(ms_ctx ctx, int64_t count, const double* energies);
+
+// the gradient at one energy, on context ctx (its stream and workspace)
+ms_status dT_dV_one(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
+                    int ck, void* grad, double* t_r, int64_t* n_open) {
   MS_HIP(ctx, hipSetDevice(ctx->device));
   const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
   const int64_t nn = (int64_t)n * n;
-  const int ck = checkpoint > 0 ? (int)std::min<int64_t>(checkpoint, ns + 1)
-                                : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
   GradCtx G{ctx, slices, energy, n, nn};
   const size_t B4 = 4 * nn * sizeof(double2);
-  {   // every q_of_ij value must index the gradient's n_q columns (they are scatter targets)
-    void* mm;
-    MS_TRY(workspace(ctx, WS_MISC, 4 * sizeof(int32_t), &mm));
-    MS_TRY(launch_minmax(ctx, nn, q_of_ij, (int32_t*)mm));
-    int32_t qr[2] = {0, 0};
-    MS_HIP(ctx, hipMemcpyAsync(qr, mm, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (qr[0] < 0 || qr[1] >= n_q)
-      return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
-  }
   // host copies: thicknesses and the two leads' channel energies
   std::vector<double> dzh(ns), el(n), er(n);
   MS_HIP(ctx, hipMemcpyAsync(dzh.data(), slices->dz, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -763,6 +750,79 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, double energy, const int
     }
   }
   return MS_OK;
+}
+
+}  // namespace
+
+ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const double* energies, const int32_t* q_of_ij,
+                   int64_t n_q, int64_t checkpoint, void* grad, double* t_r, int64_t* n_open) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (bad_ptr(slices->evec)) return fail(ctx, MS_ERR_ARG, "slices->evec (the eigenvectors) is required");
+  if (n_e < 0) return fail(ctx, MS_ERR_ARG, "n_e must be >= 0");
+  if (n_e == 0) return MS_OK;
+  if (bad_ptr(energies) || bad_ptr(q_of_ij) || bad_ptr(grad) || bad_ptr(t_r) || bad_ptr(n_open))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  MS_TRY(check_energies(ctx, n_e, energies));
+  if (n_q < 1) return fail(ctx, MS_ERR_ARG, "n_q must be >= 1");
+  if (checkpoint < 0) return fail(ctx, MS_ERR_ARG, "checkpoint must be >= 0");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)slices->n_g, ns = (int)slices->n_slices;
+  const int64_t nn = (int64_t)n * n;
+  const int ck = checkpoint > 0 ? (int)std::min<int64_t>(checkpoint, ns + 1)
+                                : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
+  {   // every q_of_ij value must index the gradient's n_q columns (they are scatter targets)
+    void* mm;
+    MS_TRY(workspace(ctx, WS_MISC, 4 * sizeof(int32_t), &mm));
+    MS_TRY(launch_minmax(ctx, nn, q_of_ij, (int32_t*)mm));
+    int32_t qr[2] = {0, 0};
+    MS_HIP(ctx, hipMemcpyAsync(qr, mm, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (qr[0] < 0 || qr[1] >= n_q)
+      return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
+  }
+  // energies are independent: with several, they run on up to three internal contexts (own
+  // stream and workspace), forked from and joined to the caller's stream, so the single-
+  // matrix LU steps of different energies overlap on the GPU
+  const int nrun = n_e > 1 ? (int)std::min<int64_t>(3, n_e) : 0;
+  std::vector<ms_ctx> run(std::max(1, nrun), ctx);
+  for (int r = 0; r < nrun; ++r) MS_TRY(child(ctx, r, &run[r]));
+  if (nrun > 0) {
+    MS_TRY(sync_events(ctx, 1 + nrun));
+    MS_HIP(ctx, hipEventRecord(ctx->sync_ev[0], ctx->stream));
+    for (int r = 0; r < nrun; ++r) MS_HIP(ctx, hipStreamWaitEvent(run[r]->stream, ctx->sync_ev[0], 0));
+  }
+  // each internal context's energies are enqueued by a host thread of their own: the
+  // per-energy host steps wait for their stream (channel energies, slice S-matrix uploads),
+  // which one thread would turn into a sequence
+  auto energies_of = [&](int r) -> ms_status {
+    for (int64_t e = r; e < n_e; e += std::max(1, nrun)) {
+      ms_ctx c = nrun > 0 ? run[r] : ctx;
+      const ms_status st = dT_dV_one(c, slices, energies[e], q_of_ij, n_q, ck,
+                                     static_cast<double2*>(grad) + e * (int64_t)ns * n_q, t_r + 2 * e, n_open + e);
+      if (st != MS_OK) return st;
+    }
+    return MS_OK;
+  };
+  ms_status st = MS_OK;
+  if (nrun == 0) {
+    st = energies_of(0);
+  } else {
+    std::vector<ms_status> res(nrun, MS_OK);
+    std::vector<std::thread> threads;
+    for (int r = 0; r < nrun; ++r) threads.emplace_back([&, r] { res[r] = energies_of(r); });
+    for (auto& t : threads) t.join();
+    for (int r = 0; r < nrun; ++r)
+      if (res[r] != MS_OK && st == MS_OK) {
+        st = res[r];
+        ctx->last_error = run[r]->last_error;
+      }
+  }
+  for (int r = 0; r < nrun; ++r) {   // join (also after an error)
+    MS_HIP(ctx, hipEventRecord(ctx->sync_ev[1 + r], run[r]->stream));
+    MS_HIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->sync_ev[1 + r], 0));
+  }
+  return st;
 }
 
 ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec prec, ms_smat* whole) {

@@ -638,3 +638,23 @@ def test_dT_dV_rejects_out_of_range_q(ms, ctx, c1):
     with pytest.raises(ms.MSError) as ei:
         ms.ms_dT_dV(ctx, s, 0.5, q, int(inp["q_of_ij"].max()))      # n_q one too small
     assert ei.value.status == ms.MS_ERR_ARG
+
+
+def test_dT_dV_several_energies_concurrently(ms, ctx):
+    """Several energies in one call (run on internal streams) give each energy's gradient of
+    a one-energy call (to rounding), and the oracle's."""
+    inp, s, q = _grad_case(ms, ctx, 37, 24, (0.0, 0.0))
+    es = [0.45, 0.7, 1.3, 2.2]
+    g, tr, no = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 5)
+    ctx.sync()
+    g, tr, no = _np(g), _np(tr), _np(no)
+    prep = orc.prepare(inp)
+    for i, e in enumerate(es):
+        g1, tr1, no1 = (_np(x) for x in ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], 5))
+        ctx.sync()
+        # T and R are bit-identical; g agrees to rounding (the scatter over Q adds with FP64
+        # atomics, whose order varies from run to run)
+        assert np.array_equal(tr[i], tr1) and no[i] == no1[0]
+        assert np.max(np.abs(g[i] - g1)) < 1e-12 * np.max(np.abs(g1))
+    ref = orc.dT_dV(prep, es[2], inp["q_of_ij"], inp["vq"].shape[1])
+    assert np.max(np.abs(g[2] - ref)) < 1e-10 * np.max(np.abs(ref))
