@@ -239,7 +239,7 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
                                dz=torch.as_tensor(h["dz"], device=dev)))
         bufs = [ms.Slices.empty(x["n_g"], x["ns"], x["dz"], dev) for x in staged]
         # the instances' slice eigenproblems are independent: spread them over contexts on
-        # separate streams (heaviest first onto the least loaded)
+        # separate streams (heaviest first onto the least loaded), one host thread each
         load = [0.0] * len(pctx)
         place = [0] * len(staged)
         for i in sorted(range(len(staged)), key=lambda i: -staged[i]["ns"] * staged[i]["n_g"] ** 3):
@@ -248,10 +248,16 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
             place[i] = r
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i, (b, x) in enumerate(zip(bufs, staged)):
-            c = pctx[place[i]]
-            with torch.cuda.stream(c.stream):
-                ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
+
+        def prepare_on(r):   # one host thread per context: each preparation waits for its stream
+            for i, (b, x) in enumerate(zip(bufs, staged)):
+                if place[i] == r:
+                    c = pctx[r]
+                    ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
+
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=len(pctx)) as pool:
+            list(pool.map(prepare_on, range(len(pctx))))
         torch.cuda.synchronize()
         prep_s = time.perf_counter() - t0
         tot["prep"] += prep_s
