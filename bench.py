@@ -395,7 +395,9 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
         an = float(2.0 * np.real(g[p, q0]))
         rel.append(abs(fd - an) / max(abs(an), 1e-12))
     n, ns = j.n_g, len(j.dz)
-    flop = 8.0 * (3 * 31.0 / 3 + 8 + 7.0 / 3) * n ** 3 * (ns + 1)
+    # per interface: three reduced star products (4 1/3 n^3 complex MACs each), two slice
+    # S-matrices (4 n^3 each), and per slice I - L12 R21, its LU and conj(U) M U^T (3 1/3 n^3)
+    flop = 8.0 * (3 * 13.0 / 3 + 8 + 10.0 / 3) * n ** 3 * (ns + 1)
     return {
         "workload": "dT/dV^p(Q) of the side-contact junction at gap 6.3 bohr, k_par = 0: N_G = 1200, "
                     f"400 slices, {inp['vq'].shape[1]} Fourier coefficients per slice, checkpoints every 20 planes",

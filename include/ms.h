@@ -250,12 +250,15 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  *   q_of_ij     [n_g][n_g] int32 (device), the map of ms_slices_prepare
  *   n_q         number of Q
  *   checkpoint  planes between stored right cascades (0: about sqrt(n_slices + 1));
- *               workspace about 3 (checkpoint + 1) + (n_slices + 1) / checkpoint blocks of
- *               4 n_g^2 c128
+ *               workspace per energy in flight about 4 (checkpoint + 1) + (n_slices + 1) /
+ *               checkpoint + checkpoint + 12 blocks of n_g^2 c128
  *   grad        [n_e][n_slices][n_q] c128 (device output)
  *   t_r         [n_e][2] f64 (device output): T and R; n_open [n_e] int64 (device)
- * Cost: about three star-product cascades (3 x 10 1/3 n_g^3 complex MACs per interface) plus
- * two slice S-matrices, one n_g-column solve and two n_g^3 products per slice and energy.
+ * The cascades carry only what the amplitudes need (S(p,N+1): r, the open columns of t', the
+ * open rows of t, the open block of r'; S(0,p): r', the open columns of t).  Cost per
+ * interface and energy: three such star products (4 1/3 n_g^3 complex MACs each), two slice
+ * S-matrices (4 n_g^3 each) and, per slice, I - L12 R21, its LU and conj(U) M U^T
+ * (3 1/3 n_g^3): about 24 1/3 n_g^3.
  * The sum over Q uses FP64 atomic additions, so g can differ in the last bits from run to
  * run (T and R do not).  Waits for the stream (the range of q_of_ij, each energy's lead
  * channel energies).

@@ -592,17 +592,93 @@ ms_status slice_smats_into(const GradCtx& G, int p0, int p1, double2* seg) {   /
 
 Blocks blk(double2* base, int64_t nn) { return Blocks{base, base + nn, base + 2 * nn, base + 3 * nn}; }
 
-ms_status copy_blocks(ms_ctx ctx, const double2* src, double2* dst, int64_t nn) {
-  MS_HIP(ctx, hipMemcpyAsync(dst, src, 4 * nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  return MS_OK;
-}
-
 }  // namespace
 
 namespace {
 
 ms_status sync_events(ms_ctx ctx, size_t count);
 ms_status check_energies(ms_ctx ctx, int64_t count, const double* energies);
+
+// Reduced cascade states (row-major, c128):
+//   right, R = S(p, N+1): r (n x n), tpc = t'[:, orr] (n x nr), trow = t[orr, :] (nr x n),
+//                         rpo = r'[orr, orr] (nr x nr)
+//   left,  L = S(0, p):   rp = r' (n x n), ltc = t[:, ol] (n x nl)
+// which is all the amplitudes and the whole S's open blocks need.  Their star products with
+// a slice S cost 4 1/3 n^3 complex MACs instead of 10 1/3 for all four blocks.
+struct RState {
+  double2 *r, *tpc, *trow, *rpo;
+};
+struct LState {
+  double2 *rp, *ltc;
+};
+
+RState rstate(double2* base, int n, int nr) {
+  const int64_t nn = (int64_t)n * n;
+  return RState{base, base + nn, base + nn + (int64_t)n * nr, base + nn + 2 * (int64_t)n * nr};
+}
+int64_t rstate_size(int n, int nr) { return (int64_t)n * n + 2 * (int64_t)n * nr + (int64_t)nr * nr; }
+LState lstate(double2* base, int n) { return LState{base, base + (int64_t)n * n}; }
+
+struct GradWork {   // scratch of the reduced star products and the per-slice solve
+  double2 *aug, *w, *tmp, *thin;
+  int32_t* piv;
+};
+
+// out = a * b with a = S(p,p+1) (full blocks), b = S(p+1,N+1) (reduced); F = I - rp_a r_b,
+// W = F^-1 [t_a | rp_a tpc_b]:  r = r_a + tp_a r_b W_t,  tpc = tp_a (tpc_b + r_b W_x),
+// trow = trow_b W_t,  rpo = rpo_b + trow_b W_x.
+ms_status rstar(ms_ctx ctx, int n, int nr, Blocks a, RState b, RState out, const GradWork& g) {
+  const int64_t nn = (int64_t)n * n;
+  const int ld = 2 * n + nr, wl = n + nr;
+  MS_TRY(launch_eye(ctx, n, ld, g.aug));
+  MS_TRY(gemm(ctx, n, n, n, a.rp, n, OP_N, b.r, n, OP_N, g.aug, ld, MONE, ONE));
+  MS_TRY(launch_gather2(ctx, n, n, nullptr, nullptr, a.t, n, g.aug + n, ld));
+  if (nr > 0) MS_TRY(gemm(ctx, n, nr, n, a.rp, n, OP_N, b.tpc, nr, OP_N, g.aug + 2 * n, ld, ONE, ZERO));
+  MS_TRY(getrf_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.piv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.w, wl, (int64_t)n * wl, ctx->d_status, 0));
+  const double2* wt = g.w;
+  const double2* wx = g.w + n;
+  MS_TRY(gemm(ctx, n, n, n, b.r, n, OP_N, wt, wl, OP_N, g.tmp, n, ONE, ZERO));
+  MS_HIP(ctx, hipMemcpyAsync(out.r, a.r, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(gemm(ctx, n, n, n, a.tp, n, OP_N, g.tmp, n, OP_N, out.r, n, ONE, ONE));
+  if (nr > 0) {
+    MS_HIP(ctx, hipMemcpyAsync(g.thin, b.tpc, (size_t)n * nr * sizeof(double2), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    MS_TRY(gemm(ctx, n, nr, n, b.r, n, OP_N, wx, wl, OP_N, g.thin, nr, ONE, ONE));
+    MS_TRY(gemm(ctx, n, nr, n, a.tp, n, OP_N, g.thin, nr, OP_N, out.tpc, nr, ONE, ZERO));
+    MS_TRY(gemm(ctx, nr, n, n, b.trow, n, OP_N, wt, wl, OP_N, out.trow, n, ONE, ZERO));
+    MS_HIP(ctx, hipMemcpyAsync(out.rpo, b.rpo, (size_t)nr * nr * sizeof(double2), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+    MS_TRY(gemm(ctx, nr, nr, n, b.trow, n, OP_N, wx, wl, OP_N, out.rpo, nr, ONE, ONE));
+  }
+  return MS_OK;
+}
+
+// out = a * b with a = S(0,p) (reduced), b = S(p,p+1) (full blocks); F = I - rp_a r_b,
+// W = F^-1 [rp_a | ltc_a]:  rp = rp_b + (t_b W_rp) tp_b,  ltc = t_b W_l.
+ms_status lstar(ms_ctx ctx, int n, int nl, LState a, Blocks b, LState out, const GradWork& g) {
+  const int64_t nn = (int64_t)n * n;
+  const int ld = 2 * n + nl, wl = n + nl;
+  MS_TRY(launch_eye(ctx, n, ld, g.aug));
+  MS_TRY(gemm(ctx, n, n, n, a.rp, n, OP_N, b.r, n, OP_N, g.aug, ld, MONE, ONE));
+  MS_TRY(launch_gather2(ctx, n, n, nullptr, nullptr, a.rp, n, g.aug + n, ld));
+  if (nl > 0) MS_TRY(launch_gather2(ctx, n, nl, nullptr, nullptr, a.ltc, nl, g.aug + 2 * n, ld));
+  MS_TRY(getrf_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.piv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.w, wl, (int64_t)n * wl, ctx->d_status, 0));
+  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, g.w, wl, OP_N, g.tmp, n, ONE, ZERO));
+  MS_HIP(ctx, hipMemcpyAsync(out.rp, b.rp, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(gemm(ctx, n, n, n, g.tmp, n, OP_N, b.tp, n, OP_N, out.rp, n, ONE, ONE));
+  if (nl > 0) MS_TRY(gemm(ctx, n, nl, n, b.t, n, OP_N, g.w + n, wl, OP_N, out.ltc, nl, ONE, ZERO));
+  return MS_OK;
+}
+
+// the reduced right state of one slice S(p,p+1) (the cascade's first factor, p = N)
+ms_status rstate_of(ms_ctx ctx, int n, int nr, const int32_t* orr, Blocks s, RState out) {
+  MS_HIP(ctx, hipMemcpyAsync(out.r, s.r, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(launch_gather2(ctx, n, nr, nullptr, orr, s.tp, n, out.tpc, nr));
+  MS_TRY(launch_gather2(ctx, nr, n, orr, nullptr, s.t, n, out.trow, n));
+  return launch_gather2(ctx, nr, nr, orr, orr, s.rp, n, out.rpo, nr);
+}
 
 // the gradient at one energy, on context ctx (its stream and workspace)
 ms_status dT_dV_one(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
@@ -627,73 +703,84 @@ ms_status dT_dV_one(ms_ctx ctx, const ms_slices* slices, double energy, const in
     if (er[i] < energy) chan.push_back(i);
   const int nr = (int)chan.size() - nl;
   MS_HIP(ctx, hipMemsetAsync(grad, 0, (size_t)ns * n_q * sizeof(double2), ctx->stream));
-  void *seg, *cks, *rseg, *lb, *kb, *pb, *chd, *en, *v;
+  const int64_t rsz = rstate_size(n, nr), lsz = nn + (int64_t)n * nl;
   const int nck = (ns + 1) / ck + 1;            // planes 0, ck, 2 ck, ... <= ns
+  const int wmax = std::max(nl, nr);
+  void *seg, *cks, *rseg, *lb, *kb, *pb, *chd, *en, *aug, *w, *tmp, *thin, *tf, *pv;
   MS_TRY(workspace(ctx, WS_GSEG, (size_t)(ck + 1) * B4, &seg));
-  MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * B4, &cks));
-  MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 1) * B4, &rseg));
-  MS_TRY(workspace(ctx, WS_GL, 2 * B4, &lb));
+  MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * rsz * sizeof(double2), &cks));
+  MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 2) * rsz * sizeof(double2), &rseg));
+  MS_TRY(workspace(ctx, WS_GL, 2 * (size_t)lsz * sizeof(double2), &lb));
   MS_TRY(workspace(ctx, WS_GK, (size_t)nrows * n * sizeof(double2), &kb));
   MS_TRY(workspace(ctx, WS_GP, (size_t)nrows * n * sizeof(double2), &pb));
   MS_TRY(workspace(ctx, WS_GCH, std::max<size_t>(1, chan.size()) * sizeof(int32_t), &chd));
   MS_TRY(workspace(ctx, WS_GEN, sizeof(double), &en));
+  MS_TRY(workspace(ctx, WS_GAUG, (size_t)n * (2 * n + wmax) * sizeof(double2), &aug));
+  MS_TRY(workspace(ctx, WS_GY, (size_t)n * (n + wmax) * sizeof(double2), &w));
+  MS_TRY(workspace(ctx, WS_GT1, nn * sizeof(double2), &tmp));
+  MS_TRY(workspace(ctx, WS_GBF, (size_t)n * std::max(1, wmax) * sizeof(double2), &thin));
+  MS_TRY(workspace(ctx, WS_GMC, nn * sizeof(double2), &tf));
+  MS_TRY(workspace(ctx, WS_GPIV, (size_t)n * sizeof(int32_t), &pv));
   if (!chan.empty()) MS_TRY(upload(ctx, chd, chan.data(), chan.size() * sizeof(int32_t)));
   MS_TRY(upload(ctx, en, &energy, sizeof(double)));
   MS_TRY(launch_wavevectors(ctx, n, nrows, 1, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb)));
   const int32_t* ol = (const int32_t*)chd;
   const int32_t* orr = ol + nl;
+  const GradWork gw{c2(aug), c2(w), c2(tmp), c2(thin), (int32_t*)pv};
 
-  // 1. right sweep R_p = S(p,p+1) * R_{p+1} from R_ns = S(ns,ns+1); R_p kept when p % ck == 0
+  // 1. right sweep R_p = S(p,p+1) * R_{p+1} from R_ns = S(ns,ns+1) (reduced); R_p kept when p % ck == 0
   double2* segp = c2(seg);
   double2* ckp = c2(cks);
-  double2* racc[2] = {c2(rseg), c2(rseg) + 4 * nn};   // ping-pong (rseg has >= 2 slots)
+  double2* racc[2] = {c2(rseg), c2(rseg) + rsz};
   int cur = 0;
   for (int hi = ns; hi >= 0; hi -= (ck + 1)) {
     const int lo = std::max(0, hi - ck);
     MS_TRY(slice_smats_into(G, lo, hi + 1, segp));
     for (int p = hi; p >= lo; --p) {
-      double2* sp = segp + (int64_t)(p - lo) * 4 * nn;
+      const Blocks sp = blk(segp + (int64_t)(p - lo) * 4 * nn, nn);
       if (p == ns) {
-        MS_TRY(copy_blocks(ctx, sp, racc[cur], nn));
+        MS_TRY(rstate_of(ctx, n, nr, orr, sp, rstate(racc[cur], n, nr)));
       } else {
-        MS_TRY(star(ctx, n, blk(sp, nn), blk(racc[cur], nn), blk(racc[cur ^ 1], nn)));
+        MS_TRY(rstar(ctx, n, nr, sp, rstate(racc[cur], n, nr), rstate(racc[cur ^ 1], n, nr), gw));
         cur ^= 1;
       }
-      if (p % ck == 0) MS_TRY(copy_blocks(ctx, racc[cur], ckp + (int64_t)(p / ck) * 4 * nn, nn));
+      if (p % ck == 0)
+        MS_HIP(ctx, hipMemcpyAsync(ckp + (int64_t)(p / ck) * rsz, racc[cur], rsz * sizeof(double2),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
     }
   }
-  // 2. the whole S = R_0: T, R, N_open
-  const Blocks whole = blk(ckp, nn);
-  MS_TRY(launch_whole_T(ctx, n, energy, whole.t, whole.r, slices->eps, slices->eps + (int64_t)(ns + 1) * n, t_r,
+  // 2. the whole S = R_0 (its open blocks): T, R, N_open
+  const RState whole = rstate(ckp, n, nr);
+  MS_HIP(ctx, hipMemsetAsync(tf, 0, nn * sizeof(double2), ctx->stream));
+  MS_TRY(launch_scatter_rows(ctx, nr, n, orr, whole.trow, c2(tf)));   // t with its open rows
+  MS_TRY(launch_whole_T(ctx, n, energy, c2(tf), whole.r, slices->eps, slices->eps + (int64_t)(ns + 1) * n, t_r,
                         t_r + 1, n_open, ctx->d_status));
   if (nl == 0 || nr == 0) return MS_OK;       // no open channel: dT = 0
   // 3. incoming amplitudes of the out-states: [r_OO t'_OR; t_RO r'_RR] [x; y] = [0; e_i]
   const int m = nl + nr;
-  void *os, *xs, *fa, *fbv, *pv;
+  void *os, *xs;
   MS_TRY(workspace(ctx, WS_GOS, (size_t)m * (m + nr) * sizeof(double2), &os));
   MS_TRY(workspace(ctx, WS_GX, (size_t)m * nr * sizeof(double2), &xs));
-  MS_TRY(workspace(ctx, WS_GFA, (size_t)n * nr * sizeof(double2), &fa));
-  MS_TRY(workspace(ctx, WS_GFB, (size_t)n * nr * sizeof(double2), &fbv));
-  MS_TRY(workspace(ctx, WS_GPIV, (size_t)n * sizeof(int32_t), &pv));
-  MS_TRY(launch_grad_open_system(ctx, n, nl, nr, ol, orr, whole.t, whole.rp, whole.r, whole.tp, c2(os)));
+  MS_TRY(launch_grad_open_system(ctx, n, nl, nr, ol, whole.r, whole.tpc, whole.trow, whole.rpo, c2(os)));
   MS_TRY(getrf_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, (int32_t*)pv, ctx->d_status, 0));
   MS_TRY(trsm_upper_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, c2(xs), nr, (int64_t)m * nr,
                         ctx->d_status, 0));
-  MS_TRY(launch_grad_incoming(ctx, n, nl, nr, ol, orr, c2(xs), c2(fa), c2(fbv)));
+  const double2* xtop = c2(xs);                       // incoming from the left on ol (nl x nr)
+  const double2* xbot = c2(xs) + (int64_t)nl * nr;    // incoming from the right on orr (nr x nr)
   // 4. segments of planes [lo, hi], lo >= 1: recompute R_p there, sweep L_p, add each slice
-  const int w = nl + nr, ldaug = n + w;
-  void *aug, *ys, *t1, *bps, *bph, *p1, *p2, *mc, *yg, *kc;
-  MS_TRY(workspace(ctx, WS_GAUG, (size_t)n * ldaug * sizeof(double2), &aug));
-  MS_TRY(workspace(ctx, WS_GY, (size_t)n * w * sizeof(double2), &ys));
-  MS_TRY(workspace(ctx, WS_GT1, (size_t)n * nr * sizeof(double2), &t1));
+  const int wa = nl + nr, ldaug = n + wa;
+  void *aug2, *ys, *t1, *bps, *bph, *p1, *p2, *mc, *yg, *kc;
+  MS_TRY(workspace(ctx, WS_GA2, (size_t)n * ldaug * sizeof(double2), &aug2));
+  MS_TRY(workspace(ctx, WS_GB2, (size_t)n * wa * sizeof(double2), &ys));
+  MS_TRY(workspace(ctx, WS_GFA, (size_t)n * nr * sizeof(double2), &t1));
   MS_TRY(workspace(ctx, WS_GBP, (size_t)n * nl * sizeof(double2), &bps));
-  MS_TRY(workspace(ctx, WS_GBF, (size_t)n * nr * sizeof(double2), &bph));
+  MS_TRY(workspace(ctx, WS_GFB, (size_t)n * nr * sizeof(double2), &bph));
   MS_TRY(workspace(ctx, WS_GP1, (size_t)n * nl * sizeof(double2), &p1));
   MS_TRY(workspace(ctx, WS_GP2, (size_t)n * nl * sizeof(double2), &p2));
-  MS_TRY(workspace(ctx, WS_GMC, nn * sizeof(double2), &mc));
   MS_TRY(workspace(ctx, WS_GYG, nn * sizeof(double2), &yg));
   MS_TRY(workspace(ctx, WS_GKC, nn * sizeof(double2), &kc));
-  double2* lbuf[2] = {c2(lb), c2(lb) + 4 * nn};
+  mc = tf;   // t with its open rows is no longer needed
+  double2* lbuf[2] = {c2(lb), c2(lb) + lsz};
   int lc = 0;
   const double2* kl = c2(kb);   // left lead row
   for (int lo = 1; lo <= ns; lo = (lo / ck + 1) * ck) {
@@ -703,45 +790,47 @@ ms_status dT_dV_one(ms_ctx ctx, const ms_slices* slices, double energy, const in
     // R_p for p = hi..lo into rseg[p - lo]: R_hi from the checkpoint at hi + 1 (or S(ns,ns+1))
     double2* rs = c2(rseg);
     for (int p = hi; p >= lo; --p) {
-      double2* sp = segp + (int64_t)(p - lo + 1) * 4 * nn;
-      double2* dst = rs + (int64_t)(p - lo) * 4 * nn;
+      const Blocks sp = blk(segp + (int64_t)(p - lo + 1) * 4 * nn, nn);
+      double2* dst = rs + (int64_t)(p - lo) * rsz;
       if (p == ns) {
-        MS_TRY(copy_blocks(ctx, sp, dst, nn));
+        MS_TRY(rstate_of(ctx, n, nr, orr, sp, rstate(dst, n, nr)));
       } else {
-        const double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * 4 * nn : dst + 4 * nn;
-        MS_TRY(star(ctx, n, blk(sp, nn), blk(const_cast<double2*>(right), nn), blk(dst, nn)));
+        double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * rsz : dst + rsz;
+        MS_TRY(rstar(ctx, n, nr, sp, rstate(right, n, nr), rstate(dst, n, nr), gw));
       }
     }
     for (int p = lo; p <= hi; ++p) {
       // L_p = L_{p-1} * S(p-1,p)  (L_1 = S(0,1))
-      double2* sprev = segp + (int64_t)(p - lo) * 4 * nn;
+      const Blocks sprev = blk(segp + (int64_t)(p - lo) * 4 * nn, nn);
       if (p == 1) {
-        MS_TRY(copy_blocks(ctx, sprev, lbuf[lc], nn));
+        const LState l1 = lstate(lbuf[lc], n);
+        MS_HIP(ctx, hipMemcpyAsync(l1.rp, sprev.rp, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+        MS_TRY(launch_gather2(ctx, n, nl, nullptr, ol, sprev.t, n, l1.ltc, nl));
       } else {
-        MS_TRY(star(ctx, n, blk(lbuf[lc], nn), blk(sprev, nn), blk(lbuf[lc ^ 1], nn)));
+        MS_TRY(lstar(ctx, n, nl, lstate(lbuf[lc], n), sprev, lstate(lbuf[lc ^ 1], n), gw));
         lc ^= 1;
       }
-      const Blocks L = blk(lbuf[lc], nn);
-      const Blocks R = blk(rs + (int64_t)(p - lo) * 4 * nn, nn);
-      // [I - L12 R21 | L11[:, ol] | L11 fa0 + L12 (R22 fb)]
-      MS_TRY(launch_eye(ctx, n, ldaug, c2(aug)));
-      MS_TRY(gemm(ctx, n, n, n, L.rp, n, OP_N, R.r, n, OP_N, aug, ldaug, MONE, ONE));
-      MS_TRY(launch_gather_cols(ctx, n, nl, ol, L.t, n, c2(aug) + n, ldaug));
-      MS_TRY(gemm(ctx, n, nr, n, R.tp, n, OP_N, fbv, nr, OP_N, t1, nr, ONE, ZERO));
-      MS_TRY(gemm(ctx, n, nr, n, L.t, n, OP_N, fa, nr, OP_N, c2(aug) + n + nl, ldaug, ONE, ZERO));
-      MS_TRY(gemm(ctx, n, nr, n, L.rp, n, OP_N, t1, nr, OP_N, c2(aug) + n + nl, ldaug, ONE, ONE));
-      MS_TRY(getrf_aug(ctx, c2(aug), n, ldaug, (int64_t)n * ldaug, 1, (int32_t*)pv, ctx->d_status, 0));
-      MS_TRY(trsm_upper_aug(ctx, c2(aug), n, ldaug, (int64_t)n * ldaug, 1, c2(ys), w, (int64_t)n * w, ctx->d_status,
-                            0));
-      const double2* apsi = c2(ys);          // n x nl, ld w
-      const double2* aphi = c2(ys) + nl;     // n x nr, ld w
+      const LState L = lstate(lbuf[lc], n);
+      const RState R = rstate(rs + (int64_t)(p - lo) * rsz, n, nr);
+      // [I - L12 R21 | L11[:, ol] | L11[:, ol] x_top + L12 (R22[:, orr] x_bot)]
+      MS_TRY(launch_eye(ctx, n, ldaug, c2(aug2)));
+      MS_TRY(gemm(ctx, n, n, n, L.rp, n, OP_N, R.r, n, OP_N, aug2, ldaug, MONE, ONE));
+      MS_TRY(launch_gather2(ctx, n, nl, nullptr, nullptr, L.ltc, nl, c2(aug2) + n, ldaug));
+      MS_TRY(gemm(ctx, n, nr, nr, R.tpc, nr, OP_N, xbot, nr, OP_N, t1, nr, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, nr, nl, L.ltc, nl, OP_N, xtop, nr, OP_N, c2(aug2) + n + nl, ldaug, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, nr, n, L.rp, n, OP_N, t1, nr, OP_N, c2(aug2) + n + nl, ldaug, ONE, ONE));
+      MS_TRY(getrf_aug(ctx, c2(aug2), n, ldaug, (int64_t)n * ldaug, 1, (int32_t*)pv, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, c2(aug2), n, ldaug, (int64_t)n * ldaug, 1, c2(ys), wa, (int64_t)n * wa,
+                            ctx->d_status, 0));
+      const double2* apsi = c2(ys);          // n x nl, ld wa
+      const double2* aphi = c2(ys) + nl;     // n x nr, ld wa
       // B^p: psi: R21 a; phi: R21 a + R22 fb
-      MS_TRY(gemm(ctx, n, nl, n, R.r, n, OP_N, apsi, w, OP_N, bps, nl, ONE, ZERO));
+      MS_TRY(gemm(ctx, n, nl, n, R.r, n, OP_N, apsi, wa, OP_N, bps, nl, ONE, ZERO));
       MS_HIP(ctx, hipMemcpyAsync(bph, t1, (size_t)n * nr * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-      MS_TRY(gemm(ctx, n, nr, n, R.r, n, OP_N, aphi, w, OP_N, bph, nr, ONE, ONE));
+      MS_TRY(gemm(ctx, n, nr, n, R.r, n, OP_N, aphi, wa, OP_N, bph, nr, ONE, ONE));
       // slice p: conj(M), then conj(K) = U conj(M) U^dagger, then g[q(a,b)] += K_ab
-      MS_TRY(launch_grad_p(ctx, n, nl, nr, aphi, w, c2(bph), nr, whole.t, ol, orr, kl, c2(p1), c2(p2)));
-      MS_TRY(launch_grad_m(ctx, n, nl, c2(kb) + (int64_t)p * n, dzh[p - 1], c2(p1), c2(p2), apsi, w, c2(bps), nl,
+      MS_TRY(launch_grad_p(ctx, n, nl, nr, aphi, wa, c2(bph), nr, whole.trow, ol, kl, c2(p1), c2(p2)));
+      MS_TRY(launch_grad_m(ctx, n, nl, c2(kb) + (int64_t)p * n, dzh[p - 1], c2(p1), c2(p2), apsi, wa, c2(bps), nl,
                            c2(mc)));
       const double2* U = c2(slices->evec) + (int64_t)(p - 1) * nn;
       MS_TRY(gemm(ctx, n, n, n, mc, n, OP_N, U, n, OP_C, yg, n, ONE, ZERO));

@@ -35,16 +35,16 @@ ms_status launch_axpby(ms_ctx ctx, int64_t nn, int nb, double alpha, const doubl
 ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, int64_t s, double* out);
 
 // first variation of T with respect to the slice potentials
-ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
-                                  const double2* t, const double2* rp, const double2* r, const double2* tp,
-                                  double2* aug);
+ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const double2* r,
+                                  const double2* tpc, const double2* trow, const double2* rpo, double2* aug);
+ms_status launch_gather2(ms_ctx ctx, int nrow, int ncol, const int32_t* rows, const int32_t* cols,
+                         const double2* src, int64_t lds, double2* dst, int64_t ldd);
+ms_status launch_scatter_rows(ms_ctx ctx, int nrow, int n, const int32_t* rows, const double2* src, double2* dst);
 ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, const double2* src, int64_t lds,
                              double2* dst, int64_t ldd);
-ms_status launch_grad_incoming(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
-                               const double2* x, double2* fa0, double2* fb);
 ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d,
-                        int64_t ldd, const double2* whole_t, const int32_t* ol, const int32_t* orr, const double2* kl,
-                        double2* p1, double2* p2);
+                        int64_t ldd, const double2* trow, const int32_t* ol, const double2* kl, double2* p1,
+                        double2* p2);
 ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, double width, const double2* p1,
                         const double2* p2, const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc);
 ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst);

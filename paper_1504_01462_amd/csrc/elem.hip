@@ -375,26 +375,44 @@ inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); 
 
 // ---- first variation of T (gradient with respect to the slice potentials) -------------
 
-// The open-channel system of the out-states: rows/cols [0, nl) are the left lead's open
-// channels ol, [nl, nl + nr) the right lead's orr.  aug = [[r_OO, tp_OR], [t_RO, rp_RR] | 0; I]
-// (row-major, ld = 2 nl + 2 nr... width w = nl + nr + nr).
-__global__ void k_grad_open_system(int n, int nl, int nr, const int32_t* ol, const int32_t* orr, const double2* t,
-                                   const double2* rp, const double2* r, const double2* tp, double2* aug) {
+// The open-channel system of the out-states, from the reduced whole S: r (n x n), tpc = t'[:, orr]
+// (n x nr), trow = t[orr, :] (nr x n), rpo = r'[orr, orr] (nr x nr).  Rows/cols [0, nl) are the
+// left lead's open channels ol, [nl, nl + nr) the right lead's.  aug = [[r_OO, t'_OR], [t_RO,
+// r'_RR] | 0; I] (row-major, width nl + 2 nr).
+__global__ void k_grad_open_system(int n, int nl, int nr, const int32_t* ol, const double2* r, const double2* tpc,
+                                   const double2* trow, const double2* rpo, double2* aug) {
   const int m = nl + nr, w = m + nr;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * w) return;
   const int i = idx / w, j = idx % w;
   double2 v = make_double2(0.0, 0.0);
   if (j < m) {
-    const bool top = i < nl, left = j < nl;
-    const int gi = top ? ol[i] : orr[i - nl];
-    const int gj = left ? ol[j] : orr[j - nl];
-    const double2* blk = top ? (left ? r : tp) : (left ? t : rp);
-    v = blk[(int64_t)gi * n + gj];
+    if (i < nl && j < nl) v = r[(int64_t)ol[i] * n + ol[j]];
+    else if (i < nl) v = tpc[(int64_t)ol[i] * nr + (j - nl)];
+    else if (j < nl) v = trow[(int64_t)(i - nl) * n + ol[j]];
+    else v = rpo[(int64_t)(i - nl) * nr + (j - nl)];
   } else if (i >= nl && (i - nl) == (j - m)) {
     v = make_double2(1.0, 0.0);
   }
   aug[idx] = v;
+}
+
+// dst[i][j] = src[rows ? rows[i] : i][cols ? cols[j] : j] for i < nrow, j < ncol
+__global__ void k_gather2(int nrow, int ncol, const int32_t* rows, const int32_t* cols, const double2* src,
+                          int64_t lds, double2* dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nrow * ncol) return;
+  const int i = (int)(e / ncol), j = (int)(e % ncol);
+  const int si = rows ? rows[i] : i, sj = cols ? cols[j] : j;
+  dst[(int64_t)i * ldd + j] = src[(int64_t)si * lds + sj];
+}
+
+// dst[rows[i]][:] = src[i][:] (n columns) for i < nrow; the other rows of dst are left as they are
+__global__ void k_scatter_rows(int nrow, int n, const int32_t* rows, const double2* src, double2* dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nrow * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  dst[(int64_t)rows[i] * n + j] = src[e];
 }
 
 // dst[:, c] = src[:, idx[c]] for c < nc (n rows; row-major, leading dims lds, ldd); idx < 0: zero
@@ -405,22 +423,6 @@ __global__ void k_gather_cols(int n, int nc, const int32_t* idx, const double2* 
   const int i = (int)(e / nc), c = (int)(e % nc);
   const int s = idx[c];
   dst[(int64_t)i * ldd + c] = s >= 0 ? src[(int64_t)i * lds + s] : make_double2(0.0, 0.0);
-}
-
-// the out-states' incoming amplitudes: fa0[ol[a], c] = x[a][c], fb[orr[b], c] = x[nl + b][c],
-// every other entry 0 (n x nr each, row-major)
-__global__ void k_grad_incoming(int n, int nl, int nr, const int32_t* ol, const int32_t* orr, const double2* x,
-                                double2* fa0, double2* fb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * nr) return;
-  const int row = (int)(e / nr), c = (int)(e % nr);
-  double2 va = make_double2(0.0, 0.0), vb = make_double2(0.0, 0.0);
-  for (int a = 0; a < nl; ++a)
-    if (ol[a] == row) va = x[(int64_t)a * nr + c];
-  for (int b = 0; b < nr; ++b)
-    if (orr[b] == row) vb = x[(int64_t)(nl + b) * nr + c];
-  fa0[e] = va;
-  fb[e] = vb;
 }
 
 // int_{-w}^{0} e^{i kappa s} ds
@@ -457,10 +459,10 @@ __global__ void k_grad_m(int n, int nl, const double2* k, double width, const do
   mc[e] = cconj(acc);
 }
 
-// P = conj(C) w: P_nj = sum_i conj(C_ni) w_ij, w_ij = conj(t_ij) / (2 i k_j)  (i in orr, j in ol)
+// P = conj(C) w: P_nj = sum_i conj(C_ni) w_ij, w_ij = conj(t_ij) / (2 i k_j)  (i in orr, j in ol;
+// trow = the open rows t[orr, :] of the whole S)
 __global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d, int64_t ldd,
-                         const double2* whole_t, const int32_t* ol, const int32_t* orr, const double2* kl, double2* p1,
-                         double2* p2) {
+                         const double2* trow, const int32_t* ol, const double2* kl, double2* p1, double2* p2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * nl) return;
   const int row = (int)(e / nl), j = (int)(e % nl);
@@ -468,7 +470,7 @@ __global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, c
   const double2 den = make_double2(-2.0 * kj.y, 2.0 * kj.x);   // 2 i k_j
   double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
   for (int i = 0; i < nr; ++i) {
-    const double2 w = cdiv(cconj(whole_t[(int64_t)orr[i] * n + ol[j]]), den);
+    const double2 w = cdiv(cconj(trow[(int64_t)i * n + ol[j]]), den);
     s1 = cadd(s1, cmul(cconj(c[(int64_t)row * ldc + i]), w));
     s2 = cadd(s2, cmul(cconj(d[(int64_t)row * ldd + i]), w));
   }
@@ -623,13 +625,27 @@ ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, 
 }
 
 
-ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
-                                  const double2* t, const double2* rp, const double2* r, const double2* tp,
-                                  double2* aug) {
+ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const double2* r,
+                                  const double2* tpc, const double2* trow, const double2* rpo, double2* aug) {
   const int total = (nl + nr) * (nl + 2 * nr);
-  hipLaunchKernelGGL(k_grad_open_system, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, n, nl, nr, ol, orr, t,
-                     rp, r, tp, aug);
+  hipLaunchKernelGGL(k_grad_open_system, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, n, nl, nr, ol, r, tpc,
+                     trow, rpo, aug);
   return check_launch(ctx, "gradient open system");
+}
+
+ms_status launch_gather2(ms_ctx ctx, int nrow, int ncol, const int32_t* rows, const int32_t* cols,
+                         const double2* src, int64_t lds, double2* dst, int64_t ldd) {
+  if ((int64_t)nrow * ncol <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_gather2, dim3(blocks((int64_t)nrow * ncol)), dim3(256), 0, ctx->stream, nrow, ncol, rows, cols,
+                     src, lds, dst, ldd);
+  return check_launch(ctx, "gather");
+}
+
+ms_status launch_scatter_rows(ms_ctx ctx, int nrow, int n, const int32_t* rows, const double2* src, double2* dst) {
+  if ((int64_t)nrow * n <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(blocks((int64_t)nrow * n)), dim3(256), 0, ctx->stream, nrow, n, rows, src,
+                     dst);
+  return check_launch(ctx, "scatter rows");
 }
 
 ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, const double2* src, int64_t lds,
@@ -639,18 +655,11 @@ ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, cons
   return check_launch(ctx, "gather columns");
 }
 
-ms_status launch_grad_incoming(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const int32_t* orr,
-                               const double2* x, double2* fa0, double2* fb) {
-  hipLaunchKernelGGL(k_grad_incoming, dim3(blocks((int64_t)n * nr)), dim3(256), 0, ctx->stream, n, nl, nr, ol, orr,
-                     x, fa0, fb);
-  return check_launch(ctx, "gradient incoming amplitudes");
-}
-
 ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d,
-                        int64_t ldd, const double2* whole_t, const int32_t* ol, const int32_t* orr, const double2* kl,
-                        double2* p1, double2* p2) {
+                        int64_t ldd, const double2* trow, const int32_t* ol, const double2* kl, double2* p1,
+                        double2* p2) {
   hipLaunchKernelGGL(k_grad_p, dim3(blocks((int64_t)n * nl)), dim3(256), 0, ctx->stream, n, nl, nr, c, ldc, d, ldd,
-                     whole_t, ol, orr, kl, p1, p2);
+                     trow, ol, kl, p1, p2);
   return check_launch(ctx, "gradient weights");
 }
 
