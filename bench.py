@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
                          "captured graph after the main measurement; 0 skips it")
-    ap.add_argument("--adjoint", type=int, default=3,
+    ap.add_argument("--adjoint", type=int, default=8,
                     help="energies of the adjoint workload (dT/dV at N_G = 1200) to time; 0 skips it")
     ap.add_argument("--uneven-only", action="store_true",
                     help="measure only the uneven workload (--uneven instances) and print its JSON line")
@@ -357,8 +357,8 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
 def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     """The adjoint workload: dT/dV^p(Q) for every slice and Fourier coefficient of the
     side-contact junction at gap 6.3 bohr, k_par = 0 (N_G = 1200, 400 slices, checkpoints every
-    20 planes), at `n_e` of its 16 energies in one call (they run concurrently on internal
-    streams); seconds per energy, and the derivative with
+    20 planes), at `n_e` of its 16 energies in one call (split over three streams, each
+    stream's energies batched through every launch); seconds per energy, and the derivative with
     respect to Re V^p(0) on three slices against central differences of T (h = 1e-5)."""
     import torch
     import msgen
@@ -374,7 +374,7 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
     es = [float(j.energies[i]) for i in idx]
     t0 = time.perf_counter()
-    gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 20)   # energies on internal streams
+    gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 20)   # energies batched
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     trall = trall.cpu().numpy()
@@ -404,6 +404,7 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
         "energies": es,
         "T": [float(x) for x in trall[:, 0]],
         "concurrent_streams": min(3, n_e),
+        "energies_per_batch": -(-n_e // min(3, n_e)),
         "prepare_with_eigenvectors_s": round(prep_s, 3),
         "seconds_per_energy": [round(x, 3) for x in times],
         "gradient_entries_per_energy": int(ns * inp["vq"].shape[1]),

@@ -245,12 +245,12 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  * to first order, for independent complex dV (keep V(-Q) = conj V(Q) to stay Hermitian:
  * dT/dRe V(Q) = 2 Re(g(Q) + g(-Q)), dT/dIm V(Q) = 2 Im(g(-Q) - g(Q)) for Q != -Q).
  *   slices      prepared with the eigenvectors (slices->evec != NULL)
- *   energies    [n_e] f64 (host); several energies run concurrently on up to three internal
- *               streams (each with its own workspace), joined to the context's stream
+ *   energies    [n_e] f64 (host); the energies go through every launch together, in
+ *               batches of at most 16 and of as many as half the free device memory holds
  *   q_of_ij     [n_g][n_g] int32 (device), the map of ms_slices_prepare
  *   n_q         number of Q
  *   checkpoint  planes between stored right cascades (0: about sqrt(n_slices + 1));
- *               workspace per energy in flight about 4 (checkpoint + 1) + (n_slices + 1) /
+ *               workspace per energy of a batch about 4 (checkpoint + 1) + (n_slices + 1) /
  *               checkpoint + checkpoint + 12 blocks of n_g^2 c128
  *   grad        [n_e][n_slices][n_q] c128 (device output)
  *   t_r         [n_e][2] f64 (device output): T and R; n_open [n_e] int64 (device)
@@ -260,8 +260,8 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  * S-matrices (4 n_g^3 each) and, per slice, I - L12 R21, its LU and conj(U) M U^T
  * (3 1/3 n_g^3): about 24 1/3 n_g^3.
  * The sum over Q uses FP64 atomic additions, so g can differ in the last bits from run to
- * run (T and R do not).  Waits for the stream (the range of q_of_ij, each energy's lead
- * channel energies).
+ * run (T and R do not).  Waits for the stream (the range of q_of_ij, the lead channel
+ * energies, each slice S-matrix segment).
  * Errors: MS_ERR_ARG (no eigenvectors, nulls, non-finite energies, n_q < 1, q_of_ij out of
  * [0, n_q)), MS_ERR_UNSUPPORTED, MS_ERR_ALLOC; numerical errors (singular systems, lead
  * threshold) via ms_ctx_sync. */

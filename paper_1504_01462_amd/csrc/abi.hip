@@ -573,269 +573,341 @@ Blocks blocks_of(const ms_smat& s) { return Blocks{c2(s.t), c2(s.rp), c2(s.r), c
 // segment by segment while the left cascade is swept from the left lead.
 namespace {
 
-struct GradCtx {
-  ms_ctx ctx;
-  const ms_slices* sl;
-  double energy;
-  int n;
-  int64_t nn;
+ms_status check_energies(ms_ctx ctx, int64_t count, const double* energies);
+ms_status sync_events(ms_ctx ctx, size_t count);
+
+struct GradHost {   // the slices' thicknesses and the two leads' channel energies, on the host
+  std::vector<double> dz, el, er;
 };
 
-ms_status slice_smats_into(const GradCtx& G, int p0, int p1, double2* seg) {   // S(p,p+1), p in [p0,p1)
-  std::vector<ms_smat> out(p1 - p0);
-  for (int i = 0; i < p1 - p0; ++i) {
-    double2* b = seg + (int64_t)i * 4 * G.nn;
-    out[i] = ms_smat{G.n, b, b + G.nn, b + 2 * G.nn, b + 3 * G.nn};
-  }
-  return ms_slice_smatrix(G.ctx, G.sl, G.energy, p0, p1, out.data());
+ms_status grad_host(ms_ctx ctx, const ms_slices* sl, GradHost* h) {
+  const int n = (int)sl->n_g, ns = (int)sl->n_slices;
+  h->dz.resize(ns);
+  h->el.resize(n);
+  h->er.resize(n);
+  MS_HIP(ctx, hipMemcpyAsync(h->dz.data(), sl->dz, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(h->el.data(), sl->eps, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(h->er.data(), sl->eps + (int64_t)(ns + 1) * n, n * sizeof(double),
+                             hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return MS_OK;
+}
+
+int open_count(const std::vector<double>& eps, double energy) {
+  int c = 0;
+  for (double x : eps) c += x < energy;
+  return c;
 }
 
 Blocks blk(double2* base, int64_t nn) { return Blocks{base, base + nn, base + 2 * nn, base + 3 * nn}; }
 
-}  // namespace
+// The energies of one batch go through every launch together: matrix b of a batched operand
+// sits b * stride elements after matrix 0.  Channel tables are padded with -1 to the batch's
+// largest open counts NL, NR; padded columns of the reduced states stay zero throughout.
+struct Batch {
+  ms_ctx ctx;
+  int nb;
+};
 
-namespace {
+ms_status gemmb(const Batch& B, int M, int N, int K, const double2* A, int64_t lda, int64_t sA, const double2* X,
+                int64_t ldx, int64_t sX, int opX, double2* C, int64_t ldc, int64_t sC, double2 alpha, double2 beta) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.sA = sA;
+  g.B = X; g.ldb = ldx; g.sB = sX; g.opB = opX;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.alpha = alpha; g.beta = beta;
+  g.batch = B.nb;
+  return zgemm(B.ctx, g);
+}
 
-ms_status sync_events(ms_ctx ctx, size_t count);
-ms_status check_energies(ms_ctx ctx, int64_t count, const double* energies);
+ms_status copyb(const Batch& B, int nrow, int ncol, const double2* src, int64_t lds, int64_t ss, double2* dst,
+                int64_t ldd, int64_t sd) {
+  return launch_gather2(B.ctx, nrow, ncol, nullptr, nullptr, src, lds, dst, ldd, B.nb, 0, 0, ss, sd);
+}
 
-// Reduced cascade states (row-major, c128):
-//   right, R = S(p, N+1): r (n x n), tpc = t'[:, orr] (n x nr), trow = t[orr, :] (nr x n),
-//                         rpo = r'[orr, orr] (nr x nr)
-//   left,  L = S(0, p):   rp = r' (n x n), ltc = t[:, ol] (n x nl)
+// Reduced cascade states (row-major, c128), one per energy, `s` elements apart:
+//   right, R = S(p, N+1): r (n x n), tpc = t'[:, orr] (n x NR), trow = t[orr, :] (NR x n),
+//                         rpo = r'[orr, orr] (NR x NR)
+//   left,  L = S(0, p):   rp = r' (n x n), ltc = t[:, ol] (n x NL)
 // which is all the amplitudes and the whole S's open blocks need.  Their star products with
 // a slice S cost 4 1/3 n^3 complex MACs instead of 10 1/3 for all four blocks.
 struct RState {
   double2 *r, *tpc, *trow, *rpo;
+  int64_t s;
 };
 struct LState {
   double2 *rp, *ltc;
+  int64_t s;
 };
 
+int64_t rstate_size(int n, int nr) { return (int64_t)n * n + 2 * (int64_t)n * nr + (int64_t)nr * nr; }
 RState rstate(double2* base, int n, int nr) {
   const int64_t nn = (int64_t)n * n;
-  return RState{base, base + nn, base + nn + (int64_t)n * nr, base + nn + 2 * (int64_t)n * nr};
+  return RState{base, base + nn, base + nn + (int64_t)n * nr, base + nn + 2 * (int64_t)n * nr, rstate_size(n, nr)};
 }
-int64_t rstate_size(int n, int nr) { return (int64_t)n * n + 2 * (int64_t)n * nr + (int64_t)nr * nr; }
-LState lstate(double2* base, int n) { return LState{base, base + (int64_t)n * n}; }
+int64_t lstate_size(int n, int nl) { return (int64_t)n * n + (int64_t)n * nl; }
+LState lstate(double2* base, int n, int nl) { return LState{base, base + (int64_t)n * n, lstate_size(n, nl)}; }
 
-struct GradWork {   // scratch of the reduced star products and the per-slice solve
+struct GradWork {   // scratch of the reduced star products, per energy: aug, w, tmp, thin, piv
   double2 *aug, *w, *tmp, *thin;
+  int64_t sg, sw, st;   // strides of aug, w and thin (tmp: n * n)
   int32_t* piv;
 };
 
-// out = a * b with a = S(p,p+1) (full blocks), b = S(p+1,N+1) (reduced); F = I - rp_a r_b,
-// W = F^-1 [t_a | rp_a tpc_b]:  r = r_a + tp_a r_b W_t,  tpc = tp_a (tpc_b + r_b W_x),
-// trow = trow_b W_t,  rpo = rpo_b + trow_b W_x.
-ms_status rstar(ms_ctx ctx, int n, int nr, Blocks a, RState b, RState out, const GradWork& g) {
+// out = a * b with a = S(p,p+1) (full blocks, energies sa apart), b = S(p+1,N+1) (reduced);
+// F = I - rp_a r_b, W = F^-1 [t_a | rp_a tpc_b]:  r = r_a + tp_a r_b W_t,
+// tpc = tp_a (tpc_b + r_b W_x), trow = trow_b W_t,  rpo = rpo_b + trow_b W_x.
+ms_status rstar(const Batch& B, int n, int nr, Blocks a, int64_t sa, RState b, RState out, const GradWork& g) {
+  ms_ctx ctx = B.ctx;
   const int64_t nn = (int64_t)n * n;
   const int ld = 2 * n + nr, wl = n + nr;
-  MS_TRY(launch_eye(ctx, n, ld, g.aug));
-  MS_TRY(gemm(ctx, n, n, n, a.rp, n, OP_N, b.r, n, OP_N, g.aug, ld, MONE, ONE));
-  MS_TRY(launch_gather2(ctx, n, n, nullptr, nullptr, a.t, n, g.aug + n, ld));
-  if (nr > 0) MS_TRY(gemm(ctx, n, nr, n, a.rp, n, OP_N, b.tpc, nr, OP_N, g.aug + 2 * n, ld, ONE, ZERO));
-  MS_TRY(getrf_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.piv, ctx->d_status, 0));
-  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.w, wl, (int64_t)n * wl, ctx->d_status, 0));
+  MS_TRY(launch_eye(ctx, n, ld, g.aug, B.nb, g.sg));
+  MS_TRY(gemmb(B, n, n, n, a.rp, n, sa, b.r, n, b.s, OP_N, g.aug, ld, g.sg, MONE, ONE));
+  MS_TRY(copyb(B, n, n, a.t, n, sa, g.aug + n, ld, g.sg));
+  if (nr > 0) MS_TRY(gemmb(B, n, nr, n, a.rp, n, sa, b.tpc, nr, b.s, OP_N, g.aug + 2 * n, ld, g.sg, ONE, ZERO));
+  MS_TRY(getrf_aug(ctx, g.aug, n, ld, g.sg, B.nb, g.piv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, g.sg, B.nb, g.w, wl, g.sw, ctx->d_status, 0));
   const double2* wt = g.w;
   const double2* wx = g.w + n;
-  MS_TRY(gemm(ctx, n, n, n, b.r, n, OP_N, wt, wl, OP_N, g.tmp, n, ONE, ZERO));
-  MS_HIP(ctx, hipMemcpyAsync(out.r, a.r, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(gemm(ctx, n, n, n, a.tp, n, OP_N, g.tmp, n, OP_N, out.r, n, ONE, ONE));
+  MS_TRY(gemmb(B, n, n, n, b.r, n, b.s, wt, wl, g.sw, OP_N, g.tmp, n, nn, ONE, ZERO));
+  MS_TRY(copyb(B, n, n, a.r, n, sa, out.r, n, out.s));
+  MS_TRY(gemmb(B, n, n, n, a.tp, n, sa, g.tmp, n, nn, OP_N, out.r, n, out.s, ONE, ONE));
   if (nr > 0) {
-    MS_HIP(ctx, hipMemcpyAsync(g.thin, b.tpc, (size_t)n * nr * sizeof(double2), hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    MS_TRY(gemm(ctx, n, nr, n, b.r, n, OP_N, wx, wl, OP_N, g.thin, nr, ONE, ONE));
-    MS_TRY(gemm(ctx, n, nr, n, a.tp, n, OP_N, g.thin, nr, OP_N, out.tpc, nr, ONE, ZERO));
-    MS_TRY(gemm(ctx, nr, n, n, b.trow, n, OP_N, wt, wl, OP_N, out.trow, n, ONE, ZERO));
-    MS_HIP(ctx, hipMemcpyAsync(out.rpo, b.rpo, (size_t)nr * nr * sizeof(double2), hipMemcpyDeviceToDevice,
-                               ctx->stream));
-    MS_TRY(gemm(ctx, nr, nr, n, b.trow, n, OP_N, wx, wl, OP_N, out.rpo, nr, ONE, ONE));
+    MS_TRY(copyb(B, n, nr, b.tpc, nr, b.s, g.thin, nr, g.st));
+    MS_TRY(gemmb(B, n, nr, n, b.r, n, b.s, wx, wl, g.sw, OP_N, g.thin, nr, g.st, ONE, ONE));
+    MS_TRY(gemmb(B, n, nr, n, a.tp, n, sa, g.thin, nr, g.st, OP_N, out.tpc, nr, out.s, ONE, ZERO));
+    MS_TRY(gemmb(B, nr, n, n, b.trow, n, b.s, wt, wl, g.sw, OP_N, out.trow, n, out.s, ONE, ZERO));
+    MS_TRY(copyb(B, nr, nr, b.rpo, nr, b.s, out.rpo, nr, out.s));
+    MS_TRY(gemmb(B, nr, nr, n, b.trow, n, b.s, wx, wl, g.sw, OP_N, out.rpo, nr, out.s, ONE, ONE));
   }
   return MS_OK;
 }
 
-// out = a * b with a = S(0,p) (reduced), b = S(p,p+1) (full blocks); F = I - rp_a r_b,
-// W = F^-1 [rp_a | ltc_a]:  rp = rp_b + (t_b W_rp) tp_b,  ltc = t_b W_l.
-ms_status lstar(ms_ctx ctx, int n, int nl, LState a, Blocks b, LState out, const GradWork& g) {
+// out = a * b with a = S(0,p) (reduced), b = S(p,p+1) (full blocks, energies sb apart);
+// F = I - rp_a r_b, W = F^-1 [rp_a | ltc_a]:  rp = rp_b + (t_b W_rp) tp_b,  ltc = t_b W_l.
+ms_status lstar(const Batch& B, int n, int nl, LState a, Blocks b, int64_t sb, LState out, const GradWork& g) {
+  ms_ctx ctx = B.ctx;
   const int64_t nn = (int64_t)n * n;
   const int ld = 2 * n + nl, wl = n + nl;
-  MS_TRY(launch_eye(ctx, n, ld, g.aug));
-  MS_TRY(gemm(ctx, n, n, n, a.rp, n, OP_N, b.r, n, OP_N, g.aug, ld, MONE, ONE));
-  MS_TRY(launch_gather2(ctx, n, n, nullptr, nullptr, a.rp, n, g.aug + n, ld));
-  if (nl > 0) MS_TRY(launch_gather2(ctx, n, nl, nullptr, nullptr, a.ltc, nl, g.aug + 2 * n, ld));
-  MS_TRY(getrf_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.piv, ctx->d_status, 0));
-  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, (int64_t)n * ld, 1, g.w, wl, (int64_t)n * wl, ctx->d_status, 0));
-  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, g.w, wl, OP_N, g.tmp, n, ONE, ZERO));
-  MS_HIP(ctx, hipMemcpyAsync(out.rp, b.rp, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(gemm(ctx, n, n, n, g.tmp, n, OP_N, b.tp, n, OP_N, out.rp, n, ONE, ONE));
-  if (nl > 0) MS_TRY(gemm(ctx, n, nl, n, b.t, n, OP_N, g.w + n, wl, OP_N, out.ltc, nl, ONE, ZERO));
+  MS_TRY(launch_eye(ctx, n, ld, g.aug, B.nb, g.sg));
+  MS_TRY(gemmb(B, n, n, n, a.rp, n, a.s, b.r, n, sb, OP_N, g.aug, ld, g.sg, MONE, ONE));
+  MS_TRY(copyb(B, n, n, a.rp, n, a.s, g.aug + n, ld, g.sg));
+  if (nl > 0) MS_TRY(copyb(B, n, nl, a.ltc, nl, a.s, g.aug + 2 * n, ld, g.sg));
+  MS_TRY(getrf_aug(ctx, g.aug, n, ld, g.sg, B.nb, g.piv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, g.aug, n, ld, g.sg, B.nb, g.w, wl, g.sw, ctx->d_status, 0));
+  MS_TRY(gemmb(B, n, n, n, b.t, n, sb, g.w, wl, g.sw, OP_N, g.tmp, n, nn, ONE, ZERO));
+  MS_TRY(copyb(B, n, n, b.rp, n, sb, out.rp, n, out.s));
+  MS_TRY(gemmb(B, n, n, n, g.tmp, n, nn, b.tp, n, sb, OP_N, out.rp, n, out.s, ONE, ONE));
+  if (nl > 0) MS_TRY(gemmb(B, n, nl, n, b.t, n, sb, g.w + n, wl, g.sw, OP_N, out.ltc, nl, out.s, ONE, ZERO));
   return MS_OK;
 }
 
-// the reduced right state of one slice S(p,p+1) (the cascade's first factor, p = N)
-ms_status rstate_of(ms_ctx ctx, int n, int nr, const int32_t* orr, Blocks s, RState out) {
-  MS_HIP(ctx, hipMemcpyAsync(out.r, s.r, (size_t)n * n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(launch_gather2(ctx, n, nr, nullptr, orr, s.tp, n, out.tpc, nr));
-  MS_TRY(launch_gather2(ctx, nr, n, orr, nullptr, s.t, n, out.trow, n));
-  return launch_gather2(ctx, nr, nr, orr, orr, s.rp, n, out.rpo, nr);
+// the reduced right state of one slice S(p,p+1) (the cascade's first factor, p = N);
+// ort: [nb][nr] right-lead channel table
+ms_status rstate_of(const Batch& B, int n, int nr, const int32_t* ort, Blocks s, int64_t ss, RState out) {
+  MS_TRY(copyb(B, n, n, s.r, n, ss, out.r, n, out.s));
+  MS_TRY(launch_gather2(B.ctx, n, nr, nullptr, ort, s.tp, n, out.tpc, nr, B.nb, 0, nr, ss, out.s));
+  MS_TRY(launch_gather2(B.ctx, nr, n, ort, nullptr, s.t, n, out.trow, n, B.nb, nr, 0, ss, out.s));
+  return launch_gather2(B.ctx, nr, nr, ort, ort, s.rp, n, out.rpo, nr, B.nb, nr, nr, ss, out.s);
 }
 
-// the gradient at one energy, on context ctx (its stream and workspace)
-ms_status dT_dV_one(ms_ctx ctx, const ms_slices* slices, double energy, const int32_t* q_of_ij, int64_t n_q,
-                    int ck, void* grad, double* t_r, int64_t* n_open) {
-  MS_HIP(ctx, hipSetDevice(ctx->device));
+// channel counts of an energy batch and the bytes of device memory it needs
+struct GradDims {
+  int NL = 0, NR = 0;
+};
+GradDims grad_dims(const GradHost& h, int nb, const double* energy) {
+  GradDims d;
+  for (int e = 0; e < nb; ++e) {
+    d.NL = std::max(d.NL, open_count(h.el, energy[e]));
+    d.NR = std::max(d.NR, open_count(h.er, energy[e]));
+  }
+  return d;
+}
+int64_t grad_elems_per_energy(int n, int ns, int ck, GradDims d) {   // c128 elements
+  const int64_t nn = (int64_t)n * n, rsz = rstate_size(n, d.NR), lsz = lstate_size(n, d.NL);
+  const int64_t wmax = std::max(1, std::max(d.NL, d.NR)), m = d.NL + d.NR, wa = m;
+  const int64_t nck = (ns + 1) / ck + 1;
+  return (ck + 1) * 4 * nn + nck * rsz + (ck + 2) * rsz + 2 * lsz + 2 * (int64_t)(ns + 2) * n +
+         n * (2 * n + wmax) + n * (n + wmax) + nn + n * wmax + nn + m * (m + d.NR) + m * d.NR + n * (n + wa) +
+         n * wa + 2 * n * (int64_t)d.NR + 3 * n * (int64_t)d.NL + 2 * nn;
+}
+
+// the gradient at nb energies, all on ctx's stream; grad: [nb][ns][n_q] c128
+ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, int nb, const double* energy,
+                      const int32_t* q_of_ij, int64_t n_q, int ck, double2* grad, double* t_r, int64_t* n_open) {
   const int n = (int)slices->n_g, ns = (int)slices->n_slices, nrows = ns + 2;
-  const int64_t nn = (int64_t)n * n;
-  GradCtx G{ctx, slices, energy, n, nn};
-  const size_t B4 = 4 * nn * sizeof(double2);
-  // host copies: thicknesses and the two leads' channel energies
-  std::vector<double> dzh(ns), el(n), er(n);
-  MS_HIP(ctx, hipMemcpyAsync(dzh.data(), slices->dz, ns * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(el.data(), slices->eps, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(er.data(), slices->eps + (int64_t)(ns + 1) * n, n * sizeof(double),
-                             hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  std::vector<int32_t> chan;
-  for (int i = 0; i < n; ++i)
-    if (el[i] < energy) chan.push_back(i);
-  const int nl = (int)chan.size();
-  for (int i = 0; i < n; ++i)
-    if (er[i] < energy) chan.push_back(i);
-  const int nr = (int)chan.size() - nl;
-  MS_HIP(ctx, hipMemsetAsync(grad, 0, (size_t)ns * n_q * sizeof(double2), ctx->stream));
-  const int64_t rsz = rstate_size(n, nr), lsz = nn + (int64_t)n * nl;
+  const int64_t nn = (int64_t)n * n, s4 = 4 * nn;
+  const Batch B{ctx, nb};
+  const GradDims dims = grad_dims(h, nb, energy);
+  const int NL = dims.NL, NR = dims.NR;
+  // channel tables: ol [nb][NL] then orr [nb][NR], padded with -1
+  std::vector<int32_t> tab((size_t)nb * (NL + NR), -1);
+  for (int e = 0; e < nb; ++e) {
+    int c = 0;
+    for (int i = 0; i < n; ++i)
+      if (h.el[i] < energy[e]) tab[(size_t)e * NL + c++] = i;
+    c = 0;
+    for (int i = 0; i < n; ++i)
+      if (h.er[i] < energy[e]) tab[(size_t)nb * NL + (size_t)e * NR + c++] = i;
+  }
+  MS_HIP(ctx, hipMemsetAsync(grad, 0, (size_t)nb * ns * n_q * sizeof(double2), ctx->stream));
+  const int64_t rsz = rstate_size(n, NR), lsz = lstate_size(n, NL);
   const int nck = (ns + 1) / ck + 1;            // planes 0, ck, 2 ck, ... <= ns
-  const int wmax = std::max(nl, nr);
+  const int wmax = std::max(1, std::max(NL, NR));
+  const size_t E = sizeof(double2);
   void *seg, *cks, *rseg, *lb, *kb, *pb, *chd, *en, *aug, *w, *tmp, *thin, *tf, *pv;
-  MS_TRY(workspace(ctx, WS_GSEG, (size_t)(ck + 1) * B4, &seg));
-  MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * rsz * sizeof(double2), &cks));
-  MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 2) * rsz * sizeof(double2), &rseg));
-  MS_TRY(workspace(ctx, WS_GL, 2 * (size_t)lsz * sizeof(double2), &lb));
-  MS_TRY(workspace(ctx, WS_GK, (size_t)nrows * n * sizeof(double2), &kb));
-  MS_TRY(workspace(ctx, WS_GP, (size_t)nrows * n * sizeof(double2), &pb));
-  MS_TRY(workspace(ctx, WS_GCH, std::max<size_t>(1, chan.size()) * sizeof(int32_t), &chd));
-  MS_TRY(workspace(ctx, WS_GEN, sizeof(double), &en));
-  MS_TRY(workspace(ctx, WS_GAUG, (size_t)n * (2 * n + wmax) * sizeof(double2), &aug));
-  MS_TRY(workspace(ctx, WS_GY, (size_t)n * (n + wmax) * sizeof(double2), &w));
-  MS_TRY(workspace(ctx, WS_GT1, nn * sizeof(double2), &tmp));
-  MS_TRY(workspace(ctx, WS_GBF, (size_t)n * std::max(1, wmax) * sizeof(double2), &thin));
-  MS_TRY(workspace(ctx, WS_GMC, nn * sizeof(double2), &tf));
-  MS_TRY(workspace(ctx, WS_GPIV, (size_t)n * sizeof(int32_t), &pv));
-  if (!chan.empty()) MS_TRY(upload(ctx, chd, chan.data(), chan.size() * sizeof(int32_t)));
-  MS_TRY(upload(ctx, en, &energy, sizeof(double)));
-  MS_TRY(launch_wavevectors(ctx, n, nrows, 1, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb)));
-  const int32_t* ol = (const int32_t*)chd;
-  const int32_t* orr = ol + nl;
-  const GradWork gw{c2(aug), c2(w), c2(tmp), c2(thin), (int32_t*)pv};
+  MS_TRY(workspace(ctx, WS_GSEG, (size_t)(ck + 1) * nb * s4 * E, &seg));
+  MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * nb * rsz * E, &cks));
+  MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 2) * nb * rsz * E, &rseg));
+  MS_TRY(workspace(ctx, WS_GL, 2 * (size_t)nb * lsz * E, &lb));
+  MS_TRY(workspace(ctx, WS_GK, (size_t)nb * nrows * n * E, &kb));
+  MS_TRY(workspace(ctx, WS_GP, (size_t)nb * nrows * n * E, &pb));
+  MS_TRY(workspace(ctx, WS_GCH, std::max<size_t>(1, tab.size()) * sizeof(int32_t), &chd));
+  MS_TRY(workspace(ctx, WS_GEN, (size_t)nb * sizeof(double), &en));
+  MS_TRY(workspace(ctx, WS_GAUG, (size_t)nb * n * (2 * n + wmax) * E, &aug));
+  MS_TRY(workspace(ctx, WS_GY, (size_t)nb * n * (n + wmax) * E, &w));
+  MS_TRY(workspace(ctx, WS_GT1, (size_t)nb * nn * E, &tmp));
+  MS_TRY(workspace(ctx, WS_GBF, (size_t)nb * n * wmax * E, &thin));
+  MS_TRY(workspace(ctx, WS_GMC, (size_t)nb * nn * E, &tf));
+  MS_TRY(workspace(ctx, WS_GPIV, (size_t)nb * std::max(n, NL + NR) * sizeof(int32_t), &pv));
+  if (!tab.empty()) MS_TRY(upload(ctx, chd, tab.data(), tab.size() * sizeof(int32_t)));
+  MS_TRY(upload(ctx, en, energy, nb * sizeof(double)));
+  const int64_t sk = (int64_t)nrows * n;
+  MS_TRY(launch_wavevectors(ctx, n, nrows, nb, slices->eps, (const double*)en, slices->dz, c2(kb), c2(pb), sk));
+  const int32_t* olt = (const int32_t*)chd;
+  const int32_t* ort = olt + (int64_t)nb * NL;
+  const GradWork gw{c2(aug), c2(w), c2(tmp), c2(thin), (int64_t)n * (2 * n + wmax), (int64_t)n * (n + wmax),
+                    (int64_t)n * wmax, (int32_t*)pv};
+  double2* segp = c2(seg);
+  // S(p,p+1) for p in [p0,p1) and every energy: slot i = p - p0 holds energy e at (i nb + e) 4 n^2
+  auto smats = [&](int p0, int p1) -> ms_status {
+    std::vector<ms_smat> out(p1 - p0);
+    for (int e = 0; e < nb; ++e) {
+      for (int i = 0; i < p1 - p0; ++i) {
+        double2* b = segp + ((int64_t)i * nb + e) * s4;
+        out[i] = ms_smat{n, b, b + nn, b + 2 * nn, b + 3 * nn};
+      }
+      MS_TRY(ms_slice_smatrix(ctx, slices, energy[e], p0, p1, out.data()));
+    }
+    return MS_OK;
+  };
+  auto slot = [&](int i) { return blk(segp + (int64_t)i * nb * s4, nn); };
 
   // 1. right sweep R_p = S(p,p+1) * R_{p+1} from R_ns = S(ns,ns+1) (reduced); R_p kept when p % ck == 0
-  double2* segp = c2(seg);
   double2* ckp = c2(cks);
-  double2* racc[2] = {c2(rseg), c2(rseg) + rsz};
+  double2* racc[2] = {c2(rseg), c2(rseg) + (int64_t)nb * rsz};
   int cur = 0;
   for (int hi = ns; hi >= 0; hi -= (ck + 1)) {
     const int lo = std::max(0, hi - ck);
-    MS_TRY(slice_smats_into(G, lo, hi + 1, segp));
+    MS_TRY(smats(lo, hi + 1));
     for (int p = hi; p >= lo; --p) {
-      const Blocks sp = blk(segp + (int64_t)(p - lo) * 4 * nn, nn);
+      const Blocks sp = slot(p - lo);
       if (p == ns) {
-        MS_TRY(rstate_of(ctx, n, nr, orr, sp, rstate(racc[cur], n, nr)));
+        MS_TRY(rstate_of(B, n, NR, ort, sp, s4, rstate(racc[cur], n, NR)));
       } else {
-        MS_TRY(rstar(ctx, n, nr, sp, rstate(racc[cur], n, nr), rstate(racc[cur ^ 1], n, nr), gw));
+        MS_TRY(rstar(B, n, NR, sp, s4, rstate(racc[cur], n, NR), rstate(racc[cur ^ 1], n, NR), gw));
         cur ^= 1;
       }
       if (p % ck == 0)
-        MS_HIP(ctx, hipMemcpyAsync(ckp + (int64_t)(p / ck) * rsz, racc[cur], rsz * sizeof(double2),
+        MS_HIP(ctx, hipMemcpyAsync(ckp + (int64_t)(p / ck) * nb * rsz, racc[cur], (size_t)nb * rsz * E,
                                    hipMemcpyDeviceToDevice, ctx->stream));
     }
   }
-  // 2. the whole S = R_0 (its open blocks): T, R, N_open
-  const RState whole = rstate(ckp, n, nr);
-  MS_HIP(ctx, hipMemsetAsync(tf, 0, nn * sizeof(double2), ctx->stream));
-  MS_TRY(launch_scatter_rows(ctx, nr, n, orr, whole.trow, c2(tf)));   // t with its open rows
-  MS_TRY(launch_whole_T(ctx, n, energy, c2(tf), whole.r, slices->eps, slices->eps + (int64_t)(ns + 1) * n, t_r,
-                        t_r + 1, n_open, ctx->d_status));
-  if (nl == 0 || nr == 0) return MS_OK;       // no open channel: dT = 0
+  // 2. the whole S = R_0 (its open blocks): T, R, N_open of each energy
+  const RState whole = rstate(ckp, n, NR);
+  MS_HIP(ctx, hipMemsetAsync(tf, 0, (size_t)nb * nn * E, ctx->stream));
+  for (int e = 0; e < nb; ++e) {
+    double2* te = c2(tf) + e * nn;
+    MS_TRY(launch_scatter_rows(ctx, NR, n, ort + (int64_t)e * NR, whole.trow + e * rsz, te));   // t, open rows
+    MS_TRY(launch_whole_T(ctx, n, energy[e], te, whole.r + e * rsz, slices->eps,
+                          slices->eps + (int64_t)(ns + 1) * n, t_r + 2 * e, t_r + 2 * e + 1, n_open + e,
+                          ctx->d_status));
+  }
+  if (NL == 0 || NR == 0) return MS_OK;       // no open channel at any energy: dT = 0
   // 3. incoming amplitudes of the out-states: [r_OO t'_OR; t_RO r'_RR] [x; y] = [0; e_i]
-  const int m = nl + nr;
+  //    (padded channels: identity rows and zero right-hand sides)
+  const int m = NL + NR, mw = m + NR;
   void *os, *xs;
-  MS_TRY(workspace(ctx, WS_GOS, (size_t)m * (m + nr) * sizeof(double2), &os));
-  MS_TRY(workspace(ctx, WS_GX, (size_t)m * nr * sizeof(double2), &xs));
-  MS_TRY(launch_grad_open_system(ctx, n, nl, nr, ol, whole.r, whole.tpc, whole.trow, whole.rpo, c2(os)));
-  MS_TRY(getrf_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, (int32_t*)pv, ctx->d_status, 0));
-  MS_TRY(trsm_upper_aug(ctx, c2(os), m, m + nr, (int64_t)m * (m + nr), 1, c2(xs), nr, (int64_t)m * nr,
-                        ctx->d_status, 0));
-  const double2* xtop = c2(xs);                       // incoming from the left on ol (nl x nr)
-  const double2* xbot = c2(xs) + (int64_t)nl * nr;    // incoming from the right on orr (nr x nr)
+  MS_TRY(workspace(ctx, WS_GOS, (size_t)nb * m * mw * E, &os));
+  MS_TRY(workspace(ctx, WS_GX, (size_t)nb * m * NR * E, &xs));
+  MS_TRY(launch_grad_open_system(ctx, n, NL, NR, olt, ort, whole.r, whole.tpc, whole.trow, whole.rpo, rsz, c2(os),
+                                 nb));
+  MS_TRY(getrf_aug(ctx, c2(os), m, mw, (int64_t)m * mw, nb, (int32_t*)pv, ctx->d_status, 0));
+  MS_TRY(trsm_upper_aug(ctx, c2(os), m, mw, (int64_t)m * mw, nb, c2(xs), NR, (int64_t)m * NR, ctx->d_status, 0));
+  const int64_t sx = (int64_t)m * NR;
+  const double2* xtop = c2(xs);                       // incoming from the left on ol (NL x NR)
+  const double2* xbot = c2(xs) + (int64_t)NL * NR;    // incoming from the right on orr (NR x NR)
   // 4. segments of planes [lo, hi], lo >= 1: recompute R_p there, sweep L_p, add each slice
-  const int wa = nl + nr, ldaug = n + wa;
-  void *aug2, *ys, *t1, *bps, *bph, *p1, *p2, *mc, *yg, *kc;
-  MS_TRY(workspace(ctx, WS_GA2, (size_t)n * ldaug * sizeof(double2), &aug2));
-  MS_TRY(workspace(ctx, WS_GB2, (size_t)n * wa * sizeof(double2), &ys));
-  MS_TRY(workspace(ctx, WS_GFA, (size_t)n * nr * sizeof(double2), &t1));
-  MS_TRY(workspace(ctx, WS_GBP, (size_t)n * nl * sizeof(double2), &bps));
-  MS_TRY(workspace(ctx, WS_GFB, (size_t)n * nr * sizeof(double2), &bph));
-  MS_TRY(workspace(ctx, WS_GP1, (size_t)n * nl * sizeof(double2), &p1));
-  MS_TRY(workspace(ctx, WS_GP2, (size_t)n * nl * sizeof(double2), &p2));
-  MS_TRY(workspace(ctx, WS_GYG, nn * sizeof(double2), &yg));
-  MS_TRY(workspace(ctx, WS_GKC, nn * sizeof(double2), &kc));
-  mc = tf;   // t with its open rows is no longer needed
-  double2* lbuf[2] = {c2(lb), c2(lb) + lsz};
+  const int wa = NL + NR, ldaug = n + wa;
+  const int64_t sa2 = (int64_t)n * ldaug, sy = (int64_t)n * wa, snr = (int64_t)n * NR, snl = (int64_t)n * NL;
+  void *aug2, *ys, *t1, *bps, *bph, *p1, *p2, *yg, *kc;
+  MS_TRY(workspace(ctx, WS_GA2, (size_t)nb * sa2 * E, &aug2));
+  MS_TRY(workspace(ctx, WS_GB2, (size_t)nb * sy * E, &ys));
+  MS_TRY(workspace(ctx, WS_GFA, (size_t)nb * snr * E, &t1));
+  MS_TRY(workspace(ctx, WS_GBP, (size_t)nb * snl * E, &bps));
+  MS_TRY(workspace(ctx, WS_GFB, (size_t)nb * snr * E, &bph));
+  MS_TRY(workspace(ctx, WS_GP1, (size_t)nb * snl * E, &p1));
+  MS_TRY(workspace(ctx, WS_GP2, (size_t)nb * snl * E, &p2));
+  MS_TRY(workspace(ctx, WS_GYG, (size_t)nb * nn * E, &yg));
+  MS_TRY(workspace(ctx, WS_GKC, (size_t)nb * nn * E, &kc));
+  double2* mc = c2(tf);   // t with its open rows is no longer needed
+  double2* lbuf[2] = {c2(lb), c2(lb) + (int64_t)nb * lsz};
   int lc = 0;
-  const double2* kl = c2(kb);   // left lead row
   for (int lo = 1; lo <= ns; lo = (lo / ck + 1) * ck) {
     const int hi = std::min(ns, (lo / ck + 1) * ck - 1);
-    // interfaces S(p,p+1), p in [lo-1, hi]: seg[i] = S(lo-1+i, lo+i)
-    MS_TRY(slice_smats_into(G, lo - 1, hi + 1, segp));
-    // R_p for p = hi..lo into rseg[p - lo]: R_hi from the checkpoint at hi + 1 (or S(ns,ns+1))
+    // interfaces S(p,p+1), p in [lo-1, hi]: slot i = S(lo-1+i, lo+i)
+    MS_TRY(smats(lo - 1, hi + 1));
+    // R_p for p = hi..lo into rseg slot p - lo: R_hi from the checkpoint at hi + 1 (or S(ns,ns+1))
     double2* rs = c2(rseg);
     for (int p = hi; p >= lo; --p) {
-      const Blocks sp = blk(segp + (int64_t)(p - lo + 1) * 4 * nn, nn);
-      double2* dst = rs + (int64_t)(p - lo) * rsz;
+      const Blocks sp = slot(p - lo + 1);
+      double2* dst = rs + (int64_t)(p - lo) * nb * rsz;
       if (p == ns) {
-        MS_TRY(rstate_of(ctx, n, nr, orr, sp, rstate(dst, n, nr)));
+        MS_TRY(rstate_of(B, n, NR, ort, sp, s4, rstate(dst, n, NR)));
       } else {
-        double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * rsz : dst + rsz;
-        MS_TRY(rstar(ctx, n, nr, sp, rstate(right, n, nr), rstate(dst, n, nr), gw));
+        double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * nb * rsz : dst + (int64_t)nb * rsz;
+        MS_TRY(rstar(B, n, NR, sp, s4, rstate(right, n, NR), rstate(dst, n, NR), gw));
       }
     }
     for (int p = lo; p <= hi; ++p) {
       // L_p = L_{p-1} * S(p-1,p)  (L_1 = S(0,1))
-      const Blocks sprev = blk(segp + (int64_t)(p - lo) * 4 * nn, nn);
+      const Blocks sprev = slot(p - lo);
       if (p == 1) {
-        const LState l1 = lstate(lbuf[lc], n);
-        MS_HIP(ctx, hipMemcpyAsync(l1.rp, sprev.rp, nn * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-        MS_TRY(launch_gather2(ctx, n, nl, nullptr, ol, sprev.t, n, l1.ltc, nl));
+        const LState l1 = lstate(lbuf[lc], n, NL);
+        MS_TRY(copyb(B, n, n, sprev.rp, n, s4, l1.rp, n, l1.s));
+        MS_TRY(launch_gather2(ctx, n, NL, nullptr, olt, sprev.t, n, l1.ltc, NL, nb, 0, NL, s4, l1.s));
       } else {
-        MS_TRY(lstar(ctx, n, nl, lstate(lbuf[lc], n), sprev, lstate(lbuf[lc ^ 1], n), gw));
+        MS_TRY(lstar(B, n, NL, lstate(lbuf[lc], n, NL), sprev, s4, lstate(lbuf[lc ^ 1], n, NL), gw));
         lc ^= 1;
       }
-      const LState L = lstate(lbuf[lc], n);
-      const RState R = rstate(rs + (int64_t)(p - lo) * rsz, n, nr);
+      const LState L = lstate(lbuf[lc], n, NL);
+      const RState R = rstate(rs + (int64_t)(p - lo) * nb * rsz, n, NR);
       // [I - L12 R21 | L11[:, ol] | L11[:, ol] x_top + L12 (R22[:, orr] x_bot)]
-      MS_TRY(launch_eye(ctx, n, ldaug, c2(aug2)));
-      MS_TRY(gemm(ctx, n, n, n, L.rp, n, OP_N, R.r, n, OP_N, aug2, ldaug, MONE, ONE));
-      MS_TRY(launch_gather2(ctx, n, nl, nullptr, nullptr, L.ltc, nl, c2(aug2) + n, ldaug));
-      MS_TRY(gemm(ctx, n, nr, nr, R.tpc, nr, OP_N, xbot, nr, OP_N, t1, nr, ONE, ZERO));
-      MS_TRY(gemm(ctx, n, nr, nl, L.ltc, nl, OP_N, xtop, nr, OP_N, c2(aug2) + n + nl, ldaug, ONE, ZERO));
-      MS_TRY(gemm(ctx, n, nr, n, L.rp, n, OP_N, t1, nr, OP_N, c2(aug2) + n + nl, ldaug, ONE, ONE));
-      MS_TRY(getrf_aug(ctx, c2(aug2), n, ldaug, (int64_t)n * ldaug, 1, (int32_t*)pv, ctx->d_status, 0));
-      MS_TRY(trsm_upper_aug(ctx, c2(aug2), n, ldaug, (int64_t)n * ldaug, 1, c2(ys), wa, (int64_t)n * wa,
-                            ctx->d_status, 0));
-      const double2* apsi = c2(ys);          // n x nl, ld wa
-      const double2* aphi = c2(ys) + nl;     // n x nr, ld wa
+      MS_TRY(launch_eye(ctx, n, ldaug, c2(aug2), nb, sa2));
+      MS_TRY(gemmb(B, n, n, n, L.rp, n, L.s, R.r, n, R.s, OP_N, c2(aug2), ldaug, sa2, MONE, ONE));
+      MS_TRY(copyb(B, n, NL, L.ltc, NL, L.s, c2(aug2) + n, ldaug, sa2));
+      MS_TRY(gemmb(B, n, NR, NR, R.tpc, NR, R.s, xbot, NR, sx, OP_N, c2(t1), NR, snr, ONE, ZERO));
+      MS_TRY(gemmb(B, n, NR, NL, L.ltc, NL, L.s, xtop, NR, sx, OP_N, c2(aug2) + n + NL, ldaug, sa2, ONE, ZERO));
+      MS_TRY(gemmb(B, n, NR, n, L.rp, n, L.s, c2(t1), NR, snr, OP_N, c2(aug2) + n + NL, ldaug, sa2, ONE, ONE));
+      MS_TRY(getrf_aug(ctx, c2(aug2), n, ldaug, sa2, nb, (int32_t*)pv, ctx->d_status, 0));
+      MS_TRY(trsm_upper_aug(ctx, c2(aug2), n, ldaug, sa2, nb, c2(ys), wa, sy, ctx->d_status, 0));
+      const double2* apsi = c2(ys);          // n x NL, ld wa
+      const double2* aphi = c2(ys) + NL;     // n x NR, ld wa
       // B^p: psi: R21 a; phi: R21 a + R22 fb
-      MS_TRY(gemm(ctx, n, nl, n, R.r, n, OP_N, apsi, wa, OP_N, bps, nl, ONE, ZERO));
-      MS_HIP(ctx, hipMemcpyAsync(bph, t1, (size_t)n * nr * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-      MS_TRY(gemm(ctx, n, nr, n, R.r, n, OP_N, aphi, wa, OP_N, bph, nr, ONE, ONE));
+      MS_TRY(gemmb(B, n, NL, n, R.r, n, R.s, apsi, wa, sy, OP_N, c2(bps), NL, snl, ONE, ZERO));
+      MS_TRY(copyb(B, n, NR, c2(t1), NR, snr, c2(bph), NR, snr));
+      MS_TRY(gemmb(B, n, NR, n, R.r, n, R.s, aphi, wa, sy, OP_N, c2(bph), NR, snr, ONE, ONE));
       // slice p: conj(M), then conj(K) = U conj(M) U^dagger, then g[q(a,b)] += K_ab
-      MS_TRY(launch_grad_p(ctx, n, nl, nr, aphi, wa, c2(bph), nr, whole.trow, ol, kl, c2(p1), c2(p2)));
-      MS_TRY(launch_grad_m(ctx, n, nl, c2(kb) + (int64_t)p * n, dzh[p - 1], c2(p1), c2(p2), apsi, wa, c2(bps), nl,
-                           c2(mc)));
+      MS_TRY(launch_grad_p(ctx, n, NL, NR, aphi, wa, sy, c2(bph), NR, snr, whole.trow, rsz, olt, NL, c2(kb), sk,
+                           c2(p1), c2(p2), snl, nb));
+      MS_TRY(launch_grad_m(ctx, n, NL, c2(kb) + (int64_t)p * n, sk, h.dz[p - 1], c2(p1), c2(p2), snl, apsi, wa, sy,
+                           c2(bps), NL, snl, mc, nn, nb));
       const double2* U = c2(slices->evec) + (int64_t)(p - 1) * nn;
-      MS_TRY(gemm(ctx, n, n, n, mc, n, OP_N, U, n, OP_C, yg, n, ONE, ZERO));
-      MS_TRY(gemm(ctx, n, n, n, U, n, OP_N, yg, n, OP_N, kc, n, ONE, ZERO));
-      MS_TRY(launch_grad_scatter(ctx, nn, q_of_ij, c2(kc), static_cast<double*>(grad) + 2 * (int64_t)(p - 1) * n_q));
+      MS_TRY(gemmb(B, n, n, n, mc, n, nn, U, n, 0, OP_C, c2(yg), n, nn, ONE, ZERO));
+      MS_TRY(gemmb(B, n, n, n, U, n, 0, c2(yg), n, nn, OP_N, c2(kc), n, nn, ONE, ZERO));
+      MS_TRY(launch_grad_scatter(ctx, nn, q_of_ij, c2(kc), nn, reinterpret_cast<double*>(grad) + 2 * (int64_t)(p - 1) * n_q,
+                                 2 * (int64_t)ns * n_q, nb));
     }
   }
   return MS_OK;
@@ -870,26 +942,36 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
     if (qr[0] < 0 || qr[1] >= n_q)
       return fail(ctx, MS_ERR_ARG, "q_of_ij values span [%d,%d], outside [0,%lld)", qr[0], qr[1], (long long)n_q);
   }
-  // energies are independent: with several, they run on up to three internal contexts (own
-  // stream and workspace), forked from and joined to the caller's stream, so the single-
-  // matrix LU steps of different energies overlap on the GPU
+  GradHost h;
+  MS_TRY(grad_host(ctx, slices, &h));
+  // Energies are split over up to three internal contexts (own stream and workspace, forked
+  // from and joined to the caller's stream, each driven by a host thread of its own, since the
+  // segments' host steps wait for their stream); each context's energies go through every
+  // launch together, as many per batch as its share of half the free device memory holds
+  // (at most 16).  One energy alone leaves most of the chip idle in its single-matrix LU and
+  // GEMM steps: the streams overlap one energy's LU with another's GEMMs, the batches fill both.
   const int nrun = n_e > 1 ? (int)std::min<int64_t>(3, n_e) : 0;
-  std::vector<ms_ctx> run(std::max(1, nrun), ctx);
+  const int64_t R = std::max(1, nrun);
+  size_t free_b = 0, total_b = 0;
+  MS_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
+  const GradDims all = grad_dims(h, (int)n_e, energies);
+  const int64_t per_e = grad_elems_per_energy(n, ns, ck, all) * (int64_t)sizeof(double2);
+  const int64_t fit = std::max<int64_t>(1, (int64_t)(free_b / 2) / R / std::max<int64_t>(1, per_e));
+  std::vector<ms_ctx> run(R, ctx);
   for (int r = 0; r < nrun; ++r) MS_TRY(child(ctx, r, &run[r]));
   if (nrun > 0) {
     MS_TRY(sync_events(ctx, 1 + nrun));
     MS_HIP(ctx, hipEventRecord(ctx->sync_ev[0], ctx->stream));
     for (int r = 0; r < nrun; ++r) MS_HIP(ctx, hipStreamWaitEvent(run[r]->stream, ctx->sync_ev[0], 0));
   }
-  // each internal context's energies are enqueued by a host thread of their own: the
-  // per-energy host steps wait for their stream (channel energies, slice S-matrix uploads),
-  // which one thread would turn into a sequence
-  auto energies_of = [&](int r) -> ms_status {
-    for (int64_t e = r; e < n_e; e += std::max(1, nrun)) {
-      ms_ctx c = nrun > 0 ? run[r] : ctx;
-      const ms_status st = dT_dV_one(c, slices, energies[e], q_of_ij, n_q, ck,
-                                     static_cast<double2*>(grad) + e * (int64_t)ns * n_q, t_r + 2 * e, n_open + e);
-      if (st != MS_OK) return st;
+  auto energies_of = [&](int r) -> ms_status {   // context r: energies [r n_e / R, (r+1) n_e / R)
+    const int64_t eb = r * n_e / R, cnt = (r + 1) * n_e / R - eb;
+    const int64_t cap = std::min<int64_t>({cnt, 16, fit});
+    const int64_t nbat = (cnt + cap - 1) / cap;
+    for (int64_t b = 0; b < nbat; ++b) {   // batches of near-equal size
+      const int64_t e0 = eb + b * cnt / nbat, e1 = eb + (b + 1) * cnt / nbat;
+      MS_TRY(dT_dV_batch(run[r], slices, h, (int)(e1 - e0), energies + e0, q_of_ij, n_q, ck,
+                         static_cast<double2*>(grad) + e0 * (int64_t)ns * n_q, t_r + 2 * e0, n_open + e0));
     }
     return MS_OK;
   };

@@ -34,20 +34,26 @@ ms_status launch_axpby(ms_ctx ctx, int64_t nn, int nb, double alpha, const doubl
                        const double2* c, int64_t s_c, double2* out, int64_t s_o);
 ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, int64_t s, double* out);
 
-// first variation of T with respect to the slice potentials
-ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const double2* r,
-                                  const double2* tpc, const double2* trow, const double2* rpo, double2* aug);
+// first variation of T with respect to the slice potentials (batched over energies: every
+// pointer of batch entry b is advanced by b times its stride)
+ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* olt, const int32_t* ort,
+                                  const double2* r, const double2* tpc, const double2* trow, const double2* rpo,
+                                  int64_t s_st, double2* aug, int batch);
 ms_status launch_gather2(ms_ctx ctx, int nrow, int ncol, const int32_t* rows, const int32_t* cols,
-                         const double2* src, int64_t lds, double2* dst, int64_t ldd);
+                         const double2* src, int64_t lds, double2* dst, int64_t ldd, int batch = 1, int64_t s_rows = 0,
+                         int64_t s_cols = 0, int64_t s_src = 0, int64_t s_dst = 0);
 ms_status launch_scatter_rows(ms_ctx ctx, int nrow, int n, const int32_t* rows, const double2* src, double2* dst);
 ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, const double2* src, int64_t lds,
                              double2* dst, int64_t ldd);
-ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d,
-                        int64_t ldd, const double2* trow, const int32_t* ol, const double2* kl, double2* p1,
-                        double2* p2);
-ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, double width, const double2* p1,
-                        const double2* p2, const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc);
-ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst);
-ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, double* g);
+ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, int64_t s_c,
+                        const double2* d, int64_t ldd, int64_t s_d, const double2* trow, int64_t s_trow,
+                        const int32_t* ol, int64_t s_ol, const double2* kl, int64_t s_kl, double2* p1, double2* p2,
+                        int64_t s_p, int batch);
+ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, int64_t s_k, double width, const double2* p1,
+                        const double2* p2, int64_t s_p, const double2* a, int64_t lda, int64_t s_a, const double2* b,
+                        int64_t ldb, int64_t s_b, double2* mc, int64_t s_m, int batch);
+ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst, int batch = 1, int64_t s_dst = 0);
+ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, int64_t s_kc, double* g,
+                              int64_t s_g, int batch);
 
 }  // namespace ms

@@ -378,33 +378,50 @@ inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); 
 // The open-channel system of the out-states, from the reduced whole S: r (n x n), tpc = t'[:, orr]
 // (n x nr), trow = t[orr, :] (nr x n), rpo = r'[orr, orr] (nr x nr).  Rows/cols [0, nl) are the
 // left lead's open channels ol, [nl, nl + nr) the right lead's.  aug = [[r_OO, t'_OR], [t_RO,
-// r'_RR] | 0; I] (row-major, width nl + 2 nr).
-__global__ void k_grad_open_system(int n, int nl, int nr, const int32_t* ol, const double2* r, const double2* tpc,
-                                   const double2* trow, const double2* rpo, double2* aug) {
+// r'_RR] | 0; I] (row-major, width nl + 2 nr).  blockIdx.y = energy b: channel tables olt, ort
+// hold [b][nl] and [b][nr] entries, -1 for padding (an identity row and column, zero right-hand
+// side); the states of energy b are b * s_st elements after energy 0's.
+__global__ void k_grad_open_system(int n, int nl, int nr, const int32_t* olt, const int32_t* ort, const double2* r,
+                                   const double2* tpc, const double2* trow, const double2* rpo, int64_t s_st,
+                                   double2* aug) {
   const int m = nl + nr, w = m + nr;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * w) return;
+  const int64_t b = blockIdx.y;
+  const int32_t* ol = olt + b * nl;
+  const int32_t* orr = ort + b * nr;
+  r += b * s_st;
+  tpc += b * s_st;
+  trow += b * s_st;
+  rpo += b * s_st;
   const int i = idx / w, j = idx % w;
+  const bool row_open = i < nl ? ol[i] >= 0 : orr[i - nl] >= 0;
   double2 v = make_double2(0.0, 0.0);
   if (j < m) {
-    if (i < nl && j < nl) v = r[(int64_t)ol[i] * n + ol[j]];
+    const bool col_open = j < nl ? ol[j] >= 0 : orr[j - nl] >= 0;
+    if (!row_open || !col_open) v = make_double2(i == j ? 1.0 : 0.0, 0.0);   // padding
+    else if (i < nl && j < nl) v = r[(int64_t)ol[i] * n + ol[j]];
     else if (i < nl) v = tpc[(int64_t)ol[i] * nr + (j - nl)];
     else if (j < nl) v = trow[(int64_t)(i - nl) * n + ol[j]];
     else v = rpo[(int64_t)(i - nl) * nr + (j - nl)];
-  } else if (i >= nl && (i - nl) == (j - m)) {
+  } else if (row_open && i >= nl && (i - nl) == (j - m)) {
     v = make_double2(1.0, 0.0);
   }
-  aug[idx] = v;
+  aug[b * m * w + idx] = v;
 }
 
-// dst[i][j] = src[rows ? rows[i] : i][cols ? cols[j] : j] for i < nrow, j < ncol
-__global__ void k_gather2(int nrow, int ncol, const int32_t* rows, const int32_t* cols, const double2* src,
-                          int64_t lds, double2* dst, int64_t ldd) {
+// dst[i][j] = src[rows ? rows[i] : i][cols ? cols[j] : j] for i < nrow, j < ncol (an index
+// of -1 gives 0); blockIdx.y = batch entry b, every pointer advanced by its stride times b
+__global__ void k_gather2(int nrow, int ncol, const int32_t* rows, int64_t s_rows, const int32_t* cols,
+                          int64_t s_cols, const double2* src, int64_t lds, int64_t s_src, double2* dst, int64_t ldd,
+                          int64_t s_dst) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nrow * ncol) return;
+  const int64_t b = blockIdx.y;
   const int i = (int)(e / ncol), j = (int)(e % ncol);
-  const int si = rows ? rows[i] : i, sj = cols ? cols[j] : j;
-  dst[(int64_t)i * ldd + j] = src[(int64_t)si * lds + sj];
+  const int si = rows ? rows[b * s_rows + i] : i, sj = cols ? cols[b * s_cols + j] : j;
+  dst[b * s_dst + (int64_t)i * ldd + j] =
+      (si < 0 || sj < 0) ? make_double2(0.0, 0.0) : src[b * s_src + (int64_t)si * lds + sj];
 }
 
 // dst[rows[i]][:] = src[i][:] (n columns) for i < nrow; the other rows of dst are left as they are
@@ -412,6 +429,7 @@ __global__ void k_scatter_rows(int nrow, int n, const int32_t* rows, const doubl
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nrow * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
+  if (rows[i] < 0) return;   // a padded row
   dst[(int64_t)rows[i] * n + j] = src[e];
 }
 
@@ -439,10 +457,18 @@ __device__ __forceinline__ double2 exp_integral(double2 kap, double w) {
 //   M_nm = sum_j P1_nj (a_mj E(k_m - k*_n) + b_mj E(-k_m - k*_n)) + P2_nj (a_mj E(k_m + k*_n) + b_mj E(-k_m + k*_n))
 // with P1 = conj(C) w, P2 = conj(D) w (n x nl), a, b the in-states' amplitudes (n x nl),
 // k the slice's wavevectors, w its thickness.
-__global__ void k_grad_m(int n, int nl, const double2* k, double width, const double2* p1, const double2* p2,
-                         const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc) {
+__global__ void k_grad_m(int n, int nl, const double2* kall, int64_t s_k, double width, const double2* p1all,
+                         const double2* p2all, int64_t s_p, const double2* aall, int64_t lda, int64_t s_a,
+                         const double2* ball, int64_t ldb, int64_t s_b, double2* mcall, int64_t s_m) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * n) return;
+  const int64_t bb = blockIdx.y;
+  const double2* k = kall + bb * s_k;
+  const double2* p1 = p1all + bb * s_p;
+  const double2* p2 = p2all + bb * s_p;
+  const double2* a = aall + bb * s_a;
+  const double2* b = ball + bb * s_b;
+  double2* mc = mcall + bb * s_m;
   const int row = (int)(e / n), col = (int)(e % n);
   const double2 kn = cconj(k[row]), km = k[col];
   const double2 e1 = exp_integral(make_double2(km.x - kn.x, km.y - kn.y), width);
@@ -459,39 +485,47 @@ __global__ void k_grad_m(int n, int nl, const double2* k, double width, const do
   mc[e] = cconj(acc);
 }
 
-// P = conj(C) w: P_nj = sum_i conj(C_ni) w_ij, w_ij = conj(t_ij) / (2 i k_j)  (i in orr, j in ol;
-// trow = the open rows t[orr, :] of the whole S)
-__global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d, int64_t ldd,
-                         const double2* trow, const int32_t* ol, const double2* kl, double2* p1, double2* p2) {
+// P = conj(C) w: P_nj = sum_i conj(C_ni) w_ij, w_ij = conj(t_ij) / (2 i k_j)  (i over the right
+// lead's open channels, j over the left lead's: ol[j] < 0 or a padded row i (trow = 0 there)
+// contribute nothing; trow = the open rows t[orr, :] of the whole S).  blockIdx.y = energy b.
+__global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, int64_t s_c, const double2* d,
+                         int64_t ldd, int64_t s_d, const double2* trow, int64_t s_trow, const int32_t* ol, int64_t s_ol,
+                         const double2* kl, int64_t s_kl, double2* p1, double2* p2, int64_t s_p) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * nl) return;
+  const int64_t b = blockIdx.y;
   const int row = (int)(e / nl), j = (int)(e % nl);
-  const double2 kj = kl[ol[j]];
-  const double2 den = make_double2(-2.0 * kj.y, 2.0 * kj.x);   // 2 i k_j
+  const int oj = ol[b * s_ol + j];
   double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
-  for (int i = 0; i < nr; ++i) {
-    const double2 w = cdiv(cconj(trow[(int64_t)i * n + ol[j]]), den);
-    s1 = cadd(s1, cmul(cconj(c[(int64_t)row * ldc + i]), w));
-    s2 = cadd(s2, cmul(cconj(d[(int64_t)row * ldd + i]), w));
+  if (oj >= 0) {
+    const double2 kj = kl[b * s_kl + oj];
+    const double2 den = make_double2(-2.0 * kj.y, 2.0 * kj.x);   // 2 i k_j
+    for (int i = 0; i < nr; ++i) {
+      const double2 w = cdiv(cconj(trow[b * s_trow + (int64_t)i * n + oj]), den);
+      s1 = cadd(s1, cmul(cconj(c[b * s_c + (int64_t)row * ldc + i]), w));
+      s2 = cadd(s2, cmul(cconj(d[b * s_d + (int64_t)row * ldd + i]), w));
+    }
   }
-  p1[e] = s1;
-  p2[e] = s2;
+  p1[b * s_p + e] = s1;
+  p2[b * s_p + e] = s2;
 }
 
 // the first n columns of an n-row matrix (leading dim ld) set to the identity
-__global__ void k_eye(int n, int64_t ld, double2* dst) {
+__global__ void k_eye(int n, int64_t ld, double2* dst, int64_t s_dst) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
-  dst[(int64_t)i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  dst[blockIdx.y * s_dst + (int64_t)i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
 }
 
 // g[q(a,b)] += conj(Kc_ab)
-__global__ void k_grad_scatter(int64_t nn, const int32_t* q, const double2* kc, double* g) {
+__global__ void k_grad_scatter(int64_t nn, const int32_t* q, const double2* kcall, int64_t s_kc, double* gall,
+                               int64_t s_g) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nn) return;
   const int64_t qi = q[e];
-  const double2 v = kc[e];
+  const double2 v = kcall[blockIdx.y * s_kc + e];
+  double* g = gall + blockIdx.y * s_g;
   atomicAdd(g + 2 * qi, v.x);
   atomicAdd(g + 2 * qi + 1, -v.y);
 }
@@ -625,19 +659,21 @@ ms_status launch_norm1(ms_ctx ctx, int n, int nb, const double2* A, int64_t ld, 
 }
 
 
-ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* ol, const double2* r,
-                                  const double2* tpc, const double2* trow, const double2* rpo, double2* aug) {
+ms_status launch_grad_open_system(ms_ctx ctx, int n, int nl, int nr, const int32_t* olt, const int32_t* ort,
+                                  const double2* r, const double2* tpc, const double2* trow, const double2* rpo,
+                                  int64_t s_st, double2* aug, int batch) {
   const int total = (nl + nr) * (nl + 2 * nr);
-  hipLaunchKernelGGL(k_grad_open_system, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, n, nl, nr, ol, r, tpc,
-                     trow, rpo, aug);
+  hipLaunchKernelGGL(k_grad_open_system, dim3((total + 255) / 256, batch), dim3(256), 0, ctx->stream, n, nl, nr, olt,
+                     ort, r, tpc, trow, rpo, s_st, aug);
   return check_launch(ctx, "gradient open system");
 }
 
 ms_status launch_gather2(ms_ctx ctx, int nrow, int ncol, const int32_t* rows, const int32_t* cols,
-                         const double2* src, int64_t lds, double2* dst, int64_t ldd) {
-  if ((int64_t)nrow * ncol <= 0) return MS_OK;
-  hipLaunchKernelGGL(k_gather2, dim3(blocks((int64_t)nrow * ncol)), dim3(256), 0, ctx->stream, nrow, ncol, rows, cols,
-                     src, lds, dst, ldd);
+                         const double2* src, int64_t lds, double2* dst, int64_t ldd, int batch, int64_t s_rows,
+                         int64_t s_cols, int64_t s_src, int64_t s_dst) {
+  if ((int64_t)nrow * ncol <= 0 || batch <= 0) return MS_OK;
+  hipLaunchKernelGGL(k_gather2, dim3(blocks((int64_t)nrow * ncol), batch), dim3(256), 0, ctx->stream, nrow, ncol, rows,
+                     s_rows, cols, s_cols, src, lds, s_src, dst, ldd, s_dst);
   return check_launch(ctx, "gather");
 }
 
@@ -655,28 +691,31 @@ ms_status launch_gather_cols(ms_ctx ctx, int n, int nc, const int32_t* idx, cons
   return check_launch(ctx, "gather columns");
 }
 
-ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, const double2* d,
-                        int64_t ldd, const double2* trow, const int32_t* ol, const double2* kl, double2* p1,
-                        double2* p2) {
-  hipLaunchKernelGGL(k_grad_p, dim3(blocks((int64_t)n * nl)), dim3(256), 0, ctx->stream, n, nl, nr, c, ldc, d, ldd,
-                     trow, ol, kl, p1, p2);
+ms_status launch_grad_p(ms_ctx ctx, int n, int nl, int nr, const double2* c, int64_t ldc, int64_t s_c,
+                        const double2* d, int64_t ldd, int64_t s_d, const double2* trow, int64_t s_trow,
+                        const int32_t* ol, int64_t s_ol, const double2* kl, int64_t s_kl, double2* p1, double2* p2,
+                        int64_t s_p, int batch) {
+  hipLaunchKernelGGL(k_grad_p, dim3(blocks((int64_t)n * nl), batch), dim3(256), 0, ctx->stream, n, nl, nr, c, ldc, s_c,
+                     d, ldd, s_d, trow, s_trow, ol, s_ol, kl, s_kl, p1, p2, s_p);
   return check_launch(ctx, "gradient weights");
 }
 
-ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, double width, const double2* p1,
-                        const double2* p2, const double2* a, int64_t lda, const double2* b, int64_t ldb, double2* mc) {
-  hipLaunchKernelGGL(k_grad_m, dim3(blocks((int64_t)n * n)), dim3(256), 0, ctx->stream, n, nl, k, width, p1, p2, a, lda,
-                     b, ldb, mc);
+ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, int64_t s_k, double width, const double2* p1,
+                        const double2* p2, int64_t s_p, const double2* a, int64_t lda, int64_t s_a, const double2* b,
+                        int64_t ldb, int64_t s_b, double2* mc, int64_t s_m, int batch) {
+  hipLaunchKernelGGL(k_grad_m, dim3(blocks((int64_t)n * n), batch), dim3(256), 0, ctx->stream, n, nl, k, s_k, width, p1,
+                     p2, s_p, a, lda, s_a, b, ldb, s_b, mc, s_m);
   return check_launch(ctx, "gradient slice integrals");
 }
 
-ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst) {
-  hipLaunchKernelGGL(k_eye, dim3(blocks((int64_t)n * n)), dim3(256), 0, ctx->stream, n, ld, dst);
+ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst, int batch, int64_t s_dst) {
+  hipLaunchKernelGGL(k_eye, dim3(blocks((int64_t)n * n), batch), dim3(256), 0, ctx->stream, n, ld, dst, s_dst);
   return check_launch(ctx, "identity");
 }
 
-ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, double* g) {
-  hipLaunchKernelGGL(k_grad_scatter, dim3(blocks(nn)), dim3(256), 0, ctx->stream, nn, q, kc, g);
+ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, int64_t s_kc, double* g,
+                              int64_t s_g, int batch) {
+  hipLaunchKernelGGL(k_grad_scatter, dim3(blocks(nn), batch), dim3(256), 0, ctx->stream, nn, q, kc, s_kc, g, s_g);
   return check_launch(ctx, "gradient scatter");
 }
 
