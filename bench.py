@@ -23,10 +23,12 @@ energies of the adjoint workload (`adjoint`).
 Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -60,6 +62,8 @@ def parse():
                          "captured graph after the main measurement; 0 skips it")
     ap.add_argument("--adjoint", type=int, default=8,
                     help="energies of the adjoint workload (dT/dV at N_G = 1200) to time; 0 skips it")
+    ap.add_argument("--overlap", action="store_true",
+                    help="prepare the next step's slices on a second stream while the current step folds")
     ap.add_argument("--uneven-only", action="store_true",
                     help="measure only the uneven workload (--uneven instances) and print its JSON line")
     ap.add_argument("--no-event-profile", action="store_true",
@@ -255,7 +259,6 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
                     c = pctx[r]
                     ms.ms_slices_prepare(c, x["miller"], x["bvec"], x["kpar"], x["q"], x["vq"], x["dz"], out=b)
 
-        from concurrent.futures import ThreadPoolExecutor
         with ThreadPoolExecutor(max_workers=len(pctx)) as pool:
             list(pool.map(prepare_on, range(len(pctx))))
         torch.cuda.synchronize()
@@ -476,7 +479,13 @@ def main():
         staged.append(dict(j=j, key=key, iks=list(iks), ks=ks))
     j0 = staged[0]["j"]
     n_e, n_k = len(j0.energies), len(j0.kpars)
-    bufs = [ms.Slices.empty(j0.n_g, j0.n_slices, staged[0]["ks"][0]["dz"], dev) for _ in range(kps)]
+    # two sets of slice buffers: with --overlap the next step's slices are prepared into one set
+    # (on a second context and stream) while the current step folds the other
+    bufsets = [[ms.Slices.empty(j0.n_g, j0.n_slices, staged[0]["ks"][0]["dz"], dev) for _ in range(kps)]
+               for _ in range(2 if args.overlap else 1)]
+    bufs = bufsets[0]
+    sp = torch.cuda.Stream(dev) if args.overlap else None   # default priority
+    ctx_p = ms.Context(0, stream=sp) if args.overlap else None
     t_store = torch.zeros((n_k, n_e), dtype=torch.float64, device=dev)
     no_store = torch.zeros((n_k, n_e), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
@@ -494,23 +503,57 @@ def main():
         log(f"autotune n_g={j0.n_g}, batch {kps * n_e}: {choice} (LU ms {tuned_main['lu_ms']}, "
             f"interface ms {tuned_main['iface_ms']})")
 
+    def fold(i, st, prec, bset, outs):
+        m = len(st["ks"])
+        es = np.tile(np.asarray(st["j"].energies, dtype=np.float64), (m, 1))
+        T, R, no, status = ms.ms_transmission_multi(ctx, bset[:m], es, prec)
+        for r, ik in enumerate(st["iks"]):
+            t_store[ik].copy_(T[r])
+            no_store[ik].copy_(no[r])
+        ms.ms_kpar_average(ctx, t_store, no_store)
+        outs.append((T.reshape(-1), R.reshape(-1), no.reshape(-1), status.reshape(-1)))
+
     def run(steps, prec):
         """One step: the slice eigenproblems and overlaps of each of its k_par, the fused fold
-        over all their energies in one batch, T and R, the k_par average -- all on the current
-        stream, one after the other."""
+        over all their energies in one batch, T and R, the k_par average.  Without --overlap all
+        on the current stream, one after the other; with it, step i+1's slices are prepared on a
+        second context and stream (enqueued by a worker thread, since the preparation's host
+        steps wait for its stream) while step i folds, ordered by events: a fold waits for its
+        slices, a preparation for the fold that last read its buffer set."""
         outs = []
-        for i, st in enumerate(steps):
-            m = len(st["ks"])
-            for b, kk in zip(bufs, st["ks"]):
-                ms.ms_slices_prepare(ctx, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"], out=b)
-            es = np.tile(np.asarray(st["j"].energies, dtype=np.float64), (m, 1))
-            T, R, no, status = ms.ms_transmission_multi(ctx, bufs[:m], es, prec)
-            for r, ik in enumerate(st["iks"]):
-                t_store[ik].copy_(T[r])
-                no_store[ik].copy_(no[r])
-            ms.ms_kpar_average(ctx, t_store, no_store)
-            outs.append((T.reshape(-1), R.reshape(-1), no.reshape(-1), status.reshape(-1)))
-            log(f"{prec} step {i + 1}/{len(steps)} enqueued")
+        if not args.overlap:
+            for i, st in enumerate(steps):
+                for b, kk in zip(bufs, st["ks"]):
+                    ms.ms_slices_prepare(ctx, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"],
+                                         out=b)
+                fold(i, st, prec, bufs, outs)
+                log(f"{prec} step {i + 1}/{len(steps)} enqueued")
+            return outs
+        main = torch.cuda.current_stream(dev)
+        ev_prep = [torch.cuda.Event() for _ in steps]
+        ev_fold = [torch.cuda.Event() for _ in steps]
+        start = torch.cuda.Event()
+        start.record(main)
+
+        def prep(i):
+            with torch.cuda.stream(sp):
+                sp.wait_event(ev_fold[i - 2] if i >= 2 else start)
+                for b, kk in zip(bufsets[i % 2], steps[i]["ks"]):
+                    ms.ms_slices_prepare(ctx_p, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"],
+                                         out=b)
+                ev_prep[i].record(sp)
+
+        with ThreadPoolExecutor(1) as pool:
+            fut = pool.submit(prep, 0)
+            for i, st in enumerate(steps):
+                fut.result()
+                if i + 1 < len(steps):
+                    fut = pool.submit(prep, i + 1)
+                main.wait_event(ev_prep[i])
+                fold(i, st, prec, bufsets[i % 2], outs)
+                ev_fold[i].record(main)
+                log(f"{prec} step {i + 1}/{len(steps)} enqueued")
+            fut.result()
         return outs
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -551,7 +594,8 @@ def main():
     for prec, r in results.items():
         d = dict(points_per_s=r["points"] / r["seconds"], ms_per_step=1e3 * r["seconds"] / args.steps,
                  max_abs_R_plus_T_minus_Nopen=float(np.max(np.abs(r["T"] + r["R"] - r["NO"]))),
-                 bad_points=int(np.sum(r["ST"] != 0)))
+                 bad_points=int(np.sum(r["ST"] != 0)),
+                 T_sha1=hashlib.sha1(np.ascontiguousarray(r["T"]).tobytes()).hexdigest()[:16])
         if prec != forms[0]:
             d["max_abs_dT_vs_" + forms[0]] = float(np.max(np.abs(r["T"] - base["T"])))
         d["warmup_kernel_ms_per_step"] = {c: round(v[0] / max(1, args.warmup), 3)
@@ -601,7 +645,7 @@ def main():
         "dtype": "c64-mfma+f64" if head == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {desc}", "n_g": j0.n_g, "n_slices": j0.n_slices,
-                   "energies_per_kpar": n_e, "kpar_per_step": kps,
+                   "energies_per_kpar": n_e, "kpar_per_step": kps, "prepare_overlapped": bool(args.overlap),
                    "steps_over": [[str(st["key"]), st["iks"]] for st in staged],
                    "headline_form": head},
         "forms": out_forms,
@@ -610,12 +654,16 @@ def main():
     }
     if args.next3 and args.config == "config3":
         line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)
+    if ctx_p is not None:
+        ctx_p.close()                       # the preparation context's workspace
     if args.adjoint > 0 and args.config == "config3":
-        bufs.clear()
+        for bs in bufsets:
+            bs.clear()
         torch.cuda.empty_cache()
         line["adjoint"] = adjoint_measure(ms, ctx, args.adjoint, log)
     if args.uneven > 0:
-        bufs.clear()                        # the main workload's slice buffers
+        for bs in bufsets:                  # the main workload's slice buffers
+            bs.clear()
         torch.cuda.empty_cache()
         line["uneven_batch"] = uneven_measure(ms, ctx, args.uneven, log)
     if not args.no_cpu_baseline:
