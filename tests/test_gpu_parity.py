@@ -641,8 +641,8 @@ def test_dT_dV_rejects_out_of_range_q(ms, ctx, c1):
 
 
 def test_dT_dV_several_energies_concurrently(ms, ctx):
-    """Several energies in one call (run on internal streams) give each energy's gradient of
-    a one-energy call (to rounding), and the oracle's."""
+    """Several energies in one call (split over internal streams, batched within each) give
+    each energy's gradient of a one-energy call (to rounding), and the oracle's."""
     inp, s, q = _grad_case(ms, ctx, 37, 24, (0.0, 0.0))
     es = [0.45, 0.7, 1.3, 2.2]
     g, tr, no = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 5)
@@ -658,3 +658,32 @@ def test_dT_dV_several_energies_concurrently(ms, ctx):
         assert np.max(np.abs(g[i] - g1)) < 1e-12 * np.max(np.abs(g1))
     ref = orc.dT_dV(prep, es[2], inp["q_of_ij"], inp["vq"].shape[1])
     assert np.max(np.abs(g[2] - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_dT_dV_batches_with_uneven_open_counts(ms, ctx):
+    """Seven energies in one call: the three internal streams take energies [0, 2), [2, 4) and
+    [4, 7), each stream's energies batched through every launch with its channel tables padded
+    to the batch's largest open counts.  Open counts differ inside every batch, so padded
+    channels occur in each; every energy matches a one-energy call (T, R, N_open bitwise, g to
+    rounding) and, for three of them, the oracle."""
+    inp, s, q = _grad_case(ms, ctx, 37, 24, (0.0, 0.0))
+    es = [1.2, 2.0, 0.7, 3.5, 2.6, 1.0, 4.0]
+    prep = orc.prepare(inp)
+    opn = [int(np.sum(np.asarray(prep["eps"][0]) < e)) for e in es]
+    for b0, b1 in ((0, 2), (2, 4), (4, 7)):
+        assert len(set(opn[b0:b1])) > 1, opn
+    n_q = inp["vq"].shape[1]
+    g, tr, no = ms.ms_dT_dV(ctx, s, es, q, n_q, 5)
+    ctx.sync()
+    g, tr, no = _np(g), _np(tr), _np(no)
+    assert [int(x) for x in no] == opn
+    for i, e in enumerate(es):
+        g1, tr1, no1 = (_np(x) for x in ms.ms_dT_dV(ctx, s, e, q, n_q, 5))
+        ctx.sync()
+        assert np.array_equal(tr[i], tr1) and no[i] == no1[0], (e, tr[i], tr1)
+        assert np.max(np.abs(g[i] - g1)) < 1e-12 * np.max(np.abs(g1)), e
+    for i in (1, 3, 6):
+        ref = orc.dT_dV(prep, es[i], inp["q_of_ij"], n_q)
+        out = orc.transmission(prep, es[i])
+        assert np.max(np.abs(g[i] - ref)) < 1e-10 * np.max(np.abs(ref)), es[i]
+        assert abs(tr[i][0] - out["T"]) < 1e-10
