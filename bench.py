@@ -359,10 +359,11 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
 
 def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     """The adjoint workload: dT/dV^p(Q) for every slice and Fourier coefficient of the
-    side-contact junction at gap 6.3 bohr, k_par = 0 (N_G = 1200, 400 slices, checkpoints every
-    20 planes), at `n_e` of its 16 energies in one call (split over three streams, each
-    stream's energies batched through every launch); seconds per energy, and the derivative with
-    respect to Re V^p(0) on three slices against central differences of T (h = 1e-5)."""
+    side-contact junction at gap 6.3 bohr, k_par = 0 (N_G = 1200, 400 slices, the right
+    cascade of every plane kept), at `n_e` of its 16 energies in one call (split over three
+    streams, each stream's energies batched through every launch); seconds per energy, and the
+    derivative with respect to Re V^p(0) on three slices against central differences of T
+    (h = 1e-5)."""
     import torch
     import msgen
     j = msgen.config5()
@@ -377,7 +378,7 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
     es = [float(j.energies[i]) for i in idx]
     t0 = time.perf_counter()
-    gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 20)   # energies batched
+    gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 1)   # every plane kept
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     trall = trall.cpu().numpy()
@@ -400,10 +401,11 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     n, ns = j.n_g, len(j.dz)
     # per interface: three reduced star products (4 1/3 n^3 complex MACs each), two slice
     # S-matrices (4 n^3 each), and per slice I - L12 R21, its LU and conj(U) M U^T (3 1/3 n^3)
-    flop = 8.0 * (3 * 13.0 / 3 + 8 + 10.0 / 3) * n ** 3 * (ns + 1)
+    flop = 8.0 * (2 * 13.0 / 3 + 8 + 10.0 / 3) * n ** 3 * (ns + 1)   # two star products per plane
     return {
         "workload": "dT/dV^p(Q) of the side-contact junction at gap 6.3 bohr, k_par = 0: N_G = 1200, "
-                    f"400 slices, {inp['vq'].shape[1]} Fourier coefficients per slice, checkpoints every 20 planes",
+                    f"400 slices, {inp['vq'].shape[1]} Fourier coefficients per slice, the right cascade of "
+                    "every plane kept",
         "energies": es,
         "T": [float(x) for x in trall[:, 0]],
         "concurrent_streams": min(3, n_e),

@@ -249,16 +249,20 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  *               batches of at most 16 and of as many as half the free device memory holds
  *   q_of_ij     [n_g][n_g] int32 (device), the map of ms_slices_prepare
  *   n_q         number of Q
- *   checkpoint  planes between stored right cascades (0: about sqrt(n_slices + 1));
- *               workspace per energy of a batch about 4 (checkpoint + 1) + (n_slices + 1) /
- *               checkpoint + checkpoint + 12 blocks of n_g^2 c128
+ *   checkpoint  planes between stored right cascades; those between are recomputed segment
+ *               by segment (1: every plane kept, none recomputed; 0: 1 when that fits the
+ *               energies in flight into half the free device memory, else about
+ *               sqrt(n_slices + 1)); workspace per energy of a batch about 4 (L + 1) +
+ *               (n_slices + 1) / checkpoint + checkpoint + 12 blocks of n_g^2 c128, L =
+ *               checkpoint (16 when checkpoint is 1)
  *   grad        [n_e][n_slices][n_q] c128 (device output)
  *   t_r         [n_e][2] f64 (device output): T and R; n_open [n_e] int64 (device)
  * The cascades carry only what the amplitudes need (S(p,N+1): r, the open columns of t', the
  * open rows of t, the open block of r'; S(0,p): r', the open columns of t).  Cost per
- * interface and energy: three such star products (4 1/3 n_g^3 complex MACs each), two slice
- * S-matrices (4 n_g^3 each) and, per slice, I - L12 R21, its LU and conj(U) M U^T
- * (3 1/3 n_g^3): about 24 1/3 n_g^3.
+ * interface and energy: two such star products (4 1/3 n_g^3 complex MACs each), a third to
+ * recompute the right cascade where it is not stored, two slice S-matrices (4 n_g^3 each)
+ * and, per slice, I - L12 R21, its LU and conj(U) M U^T (3 1/3 n_g^3): about 20 n_g^3 with
+ * every plane kept, about 24 1/3 n_g^3 otherwise.
  * The sum over Q uses FP64 atomic additions, so g can differ in the last bits from run to
  * run (T and R do not).  Waits for the stream (the range of q_of_ij, the lead channel
  * energies, each slice S-matrix segment).

@@ -714,21 +714,24 @@ ms_status rstate_of(const Batch& B, int n, int nr, const int32_t* ort, Blocks s,
 
 // channel counts of an energy batch and the bytes of device memory it needs
 struct GradDims {
-  int NL = 0, NR = 0;
+  int NL, NR;
 };
 GradDims grad_dims(const GradHost& h, int nb, const double* energy) {
-  GradDims d;
+  GradDims d{0, 0};
   for (int e = 0; e < nb; ++e) {
     d.NL = std::max(d.NL, open_count(h.el, energy[e]));
     d.NR = std::max(d.NR, open_count(h.er, energy[e]));
   }
   return d;
 }
+// planes per segment of slice S-matrices: the checkpoint spacing (the right cascades of a
+// segment are recomputed from the checkpoint above it), or 16 when every plane is kept
+int seg_planes(int ck) { return ck == 1 ? 16 : ck; }
 int64_t grad_elems_per_energy(int n, int ns, int ck, GradDims d) {   // c128 elements
   const int64_t nn = (int64_t)n * n, rsz = rstate_size(n, d.NR), lsz = lstate_size(n, d.NL);
   const int64_t wmax = std::max(1, std::max(d.NL, d.NR)), m = d.NL + d.NR, wa = m;
   const int64_t nck = (ns + 1) / ck + 1;
-  return (ck + 1) * 4 * nn + nck * rsz + (ck + 2) * rsz + 2 * lsz + 2 * (int64_t)(ns + 2) * n +
+  return (seg_planes(ck) + 1) * 4 * nn + nck * rsz + (ck + 2) * rsz + 2 * lsz + 2 * (int64_t)(ns + 2) * n +
          n * (2 * n + wmax) + n * (n + wmax) + nn + n * wmax + nn + m * (m + d.NR) + m * d.NR + n * (n + wa) +
          n * wa + 2 * n * (int64_t)d.NR + 3 * n * (int64_t)d.NL + 2 * nn;
 }
@@ -757,7 +760,8 @@ ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, in
   const int wmax = std::max(1, std::max(NL, NR));
   const size_t E = sizeof(double2);
   void *seg, *cks, *rseg, *lb, *kb, *pb, *chd, *en, *aug, *w, *tmp, *thin, *tf, *pv;
-  MS_TRY(workspace(ctx, WS_GSEG, (size_t)(ck + 1) * nb * s4 * E, &seg));
+  const int L = seg_planes(ck);
+  MS_TRY(workspace(ctx, WS_GSEG, (size_t)(L + 1) * nb * s4 * E, &seg));
   MS_TRY(workspace(ctx, WS_GCK, (size_t)nck * nb * rsz * E, &cks));
   MS_TRY(workspace(ctx, WS_GRS, (size_t)(ck + 2) * nb * rsz * E, &rseg));
   MS_TRY(workspace(ctx, WS_GL, 2 * (size_t)nb * lsz * E, &lb));
@@ -798,8 +802,8 @@ ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, in
   double2* ckp = c2(cks);
   double2* racc[2] = {c2(rseg), c2(rseg) + (int64_t)nb * rsz};
   int cur = 0;
-  for (int hi = ns; hi >= 0; hi -= (ck + 1)) {
-    const int lo = std::max(0, hi - ck);
+  for (int hi = ns; hi >= 0; hi -= (L + 1)) {   // chunks of up to L + 1 slice S-matrices
+    const int lo = std::max(0, hi - L);
     MS_TRY(smats(lo, hi + 1));
     for (int p = hi; p >= lo; --p) {
       const Blocks sp = slot(p - lo);
@@ -854,21 +858,32 @@ ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, in
   double2* mc = c2(tf);   // t with its open rows is no longer needed
   double2* lbuf[2] = {c2(lb), c2(lb) + (int64_t)nb * lsz};
   int lc = 0;
-  for (int lo = 1; lo <= ns; lo = (lo / ck + 1) * ck) {
-    const int hi = std::min(ns, (lo / ck + 1) * ck - 1);
-    // interfaces S(p,p+1), p in [lo-1, hi]: slot i = S(lo-1+i, lo+i)
-    MS_TRY(smats(lo - 1, hi + 1));
-    // R_p for p = hi..lo into rseg slot p - lo: R_hi from the checkpoint at hi + 1 (or S(ns,ns+1))
+  // segments [lo, hi]: with checkpoints every ck > 1 planes, hi + 1 is a checkpoint (or hi = ns);
+  // with every plane kept (ck = 1), L planes each
+  std::vector<double2*> rptr(L);
+  for (int lo = 1; lo <= ns;) {
+    const int hi = ck == 1 ? std::min(ns, lo + L - 1) : std::min(ns, (lo / ck + 1) * ck - 1);
+    bool recompute = false;   // a plane of the segment without a stored right cascade
+    for (int p = lo; p <= hi; ++p) recompute = recompute || p % ck != 0;
+    // interfaces S(p,p+1), p in [lo-1, hi] (p < hi without a recompute): slot i = S(lo-1+i, lo+i)
+    MS_TRY(smats(lo - 1, recompute ? hi + 1 : hi));
+    // R_p for p = hi..lo: stored ones from their checkpoint, the others recomputed into rseg
+    // slot p - lo from the one above (R_hi from the checkpoint at hi + 1, or S(ns,ns+1))
     double2* rs = c2(rseg);
     for (int p = hi; p >= lo; --p) {
+      if (p % ck == 0) {
+        rptr[p - lo] = ckp + (int64_t)(p / ck) * nb * rsz;
+        continue;
+      }
       const Blocks sp = slot(p - lo + 1);
       double2* dst = rs + (int64_t)(p - lo) * nb * rsz;
       if (p == ns) {
         MS_TRY(rstate_of(B, n, NR, ort, sp, s4, rstate(dst, n, NR)));
       } else {
-        double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * nb * rsz : dst + (int64_t)nb * rsz;
+        double2* right = (p == hi) ? ckp + (int64_t)((hi + 1) / ck) * nb * rsz : rptr[p + 1 - lo];
         MS_TRY(rstar(B, n, NR, sp, s4, rstate(right, n, NR), rstate(dst, n, NR), gw));
       }
+      rptr[p - lo] = dst;
     }
     for (int p = lo; p <= hi; ++p) {
       // L_p = L_{p-1} * S(p-1,p)  (L_1 = S(0,1))
@@ -882,7 +897,7 @@ ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, in
         lc ^= 1;
       }
       const LState L = lstate(lbuf[lc], n, NL);
-      const RState R = rstate(rs + (int64_t)(p - lo) * nb * rsz, n, NR);
+      const RState R = rstate(rptr[p - lo], n, NR);
       // [I - L12 R21 | L11[:, ol] | L11[:, ol] x_top + L12 (R22[:, orr] x_bot)]
       MS_TRY(launch_eye(ctx, n, ldaug, c2(aug2), nb, sa2));
       MS_TRY(gemmb(B, n, n, n, L.rp, n, L.s, R.r, n, R.s, OP_N, c2(aug2), ldaug, sa2, MONE, ONE));
@@ -909,6 +924,7 @@ ms_status dT_dV_batch(ms_ctx ctx, const ms_slices* slices, const GradHost& h, in
       MS_TRY(launch_grad_scatter(ctx, nn, q_of_ij, c2(kc), nn, reinterpret_cast<double*>(grad) + 2 * (int64_t)(p - 1) * n_q,
                                  2 * (int64_t)ns * n_q, nb));
     }
+    lo = hi + 1;
   }
   return MS_OK;
 }
@@ -930,8 +946,6 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
   MS_HIP(ctx, hipSetDevice(ctx->device));
   const int n = (int)slices->n_g, ns = (int)slices->n_slices;
   const int64_t nn = (int64_t)n * n;
-  const int ck = checkpoint > 0 ? (int)std::min<int64_t>(checkpoint, ns + 1)
-                                : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
   {   // every q_of_ij value must index the gradient's n_q columns (they are scatter targets)
     void* mm;
     MS_TRY(workspace(ctx, WS_MISC, 4 * sizeof(int32_t), &mm));
@@ -955,6 +969,14 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
   size_t free_b = 0, total_b = 0;
   MS_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
   const GradDims all = grad_dims(h, (int)n_e, energies);
+  // checkpoint 0: every plane's right cascade kept (none recomputed) when that fits the energies
+  // in flight into half the free device memory, else about sqrt(N_s + 1) planes apart
+  int ck = (int)std::min<int64_t>(checkpoint, ns + 1);
+  if (checkpoint == 0) {
+    const int64_t inflight = std::min<int64_t>(n_e, 16 * R);
+    const int64_t all_planes = grad_elems_per_energy(n, ns, 1, all) * (int64_t)sizeof(double2) * inflight;
+    ck = all_planes <= (int64_t)(free_b / 2) ? 1 : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
+  }
   const int64_t per_e = grad_elems_per_energy(n, ns, ck, all) * (int64_t)sizeof(double2);
   const int64_t fit = std::max<int64_t>(1, (int64_t)(free_b / 2) / R / std::max<int64_t>(1, per_e));
   std::vector<ms_ctx> run(R, ctx);
