@@ -377,6 +377,8 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     prep_s = time.perf_counter() - t0
     idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
     es = [float(j.energies[i]) for i in idx]
+    free_gb = torch.cuda.mem_get_info(dev)[0] / 1e9
+    log(f"adjoint: {free_gb:.0f} GB of device memory free before the call")
     t0 = time.perf_counter()
     gall, trall, _ = ms.ms_dT_dV(ctx, s, es, q, inp["vq"].shape[1], 1)   # every plane kept
     torch.cuda.synchronize()
@@ -662,7 +664,10 @@ def main():
         for bs in bufsets:
             bs.clear()
         torch.cuda.empty_cache()
-        line["adjoint"] = adjoint_measure(ms, ctx, args.adjoint, log)
+        actx = ms.Context(0)                # its own context: the gradient's workspace is freed after
+        line["adjoint"] = adjoint_measure(ms, actx, args.adjoint, log)
+        actx.close()
+        torch.cuda.empty_cache()
     if args.uneven > 0:
         for bs in bufsets:                  # the main workload's slice buffers
             bs.clear()

@@ -246,12 +246,12 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
  * dT/dRe V(Q) = 2 Re(g(Q) + g(-Q)), dT/dIm V(Q) = 2 Im(g(-Q) - g(Q)) for Q != -Q).
  *   slices      prepared with the eigenvectors (slices->evec != NULL)
  *   energies    [n_e] f64 (host); the energies go through every launch together, in
- *               batches of at most 16 and of as many as half the free device memory holds
+ *               batches of at most 16 and of as many as 3/4 of the free device memory holds
  *   q_of_ij     [n_g][n_g] int32 (device), the map of ms_slices_prepare
  *   n_q         number of Q
  *   checkpoint  planes between stored right cascades; those between are recomputed segment
  *               by segment (1: every plane kept, none recomputed; 0: 1 when that fits the
- *               energies in flight into half the free device memory, else about
+ *               energies in flight into 3/4 of the free device memory, else about
  *               sqrt(n_slices + 1)); workspace per energy of a batch about 4 (L + 1) +
  *               (n_slices + 1) / checkpoint + checkpoint + 12 blocks of n_g^2 c128, L =
  *               checkpoint (16 when checkpoint is 1)

@@ -961,7 +961,7 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
   // Energies are split over up to three internal contexts (own stream and workspace, forked
   // from and joined to the caller's stream, each driven by a host thread of its own, since the
   // segments' host steps wait for their stream); each context's energies go through every
-  // launch together, as many per batch as its share of half the free device memory holds
+  // launch together, as many per batch as its share of 3/4 of the free device memory holds
   // (at most 16).  One energy alone leaves most of the chip idle in its single-matrix LU and
   // GEMM steps: the streams overlap one energy's LU with another's GEMMs, the batches fill both.
   const int nrun = n_e > 1 ? (int)std::min<int64_t>(3, n_e) : 0;
@@ -970,15 +970,16 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
   MS_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
   const GradDims all = grad_dims(h, (int)n_e, energies);
   // checkpoint 0: every plane's right cascade kept (none recomputed) when that fits the energies
-  // in flight into half the free device memory, else about sqrt(N_s + 1) planes apart
+  // in flight into 3/4 of the free device memory, else about sqrt(N_s + 1) planes apart
+  const int64_t budget = (int64_t)(free_b / 4) * 3;
   int ck = (int)std::min<int64_t>(checkpoint, ns + 1);
   if (checkpoint == 0) {
     const int64_t inflight = std::min<int64_t>(n_e, 16 * R);
     const int64_t all_planes = grad_elems_per_energy(n, ns, 1, all) * (int64_t)sizeof(double2) * inflight;
-    ck = all_planes <= (int64_t)(free_b / 2) ? 1 : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
+    ck = all_planes <= budget ? 1 : std::max(1, (int)std::lround(std::sqrt((double)(ns + 1))));
   }
   const int64_t per_e = grad_elems_per_energy(n, ns, ck, all) * (int64_t)sizeof(double2);
-  const int64_t fit = std::max<int64_t>(1, (int64_t)(free_b / 2) / R / std::max<int64_t>(1, per_e));
+  const int64_t fit = std::max<int64_t>(1, budget / R / std::max<int64_t>(1, per_e));
   std::vector<ms_ctx> run(R, ctx);
   for (int r = 0; r < nrun; ++r) MS_TRY(child(ctx, r, &run[r]));
   if (nrun > 0) {
