@@ -6,4 +6,8 @@ it; the library and its binding never do.  It shares no code with the HIP
 path: both consume the same seeded inputs (``msgen``) and nothing else.
 """
 from .transport import *  # noqa: F401,F403
-from .transport import __all__  # noqa: F401
+from .transport import __all__ as _t_all
+from .bands import *  # noqa: F401,F403
+from .bands import __all__ as _b_all
+
+__all__ = list(_t_all) + list(_b_all)

@@ -1,0 +1,133 @@
+"""Complex band structure of a periodic electrode cell and its folding from the
+transverse primitive cell to a supercell (App. B: generalized Bloch conditions,
+Eq. cmp, and the band-folding relations that close the appendix).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.  Built from the same
+steps as ``transport`` (slice eigenpairs, interface S-matrices, star products);
+no blocking or reordering beyond the appendix's equations.
+
+Model: local potential only, so no non-local sphere crosses a cell boundary
+(N_crosl = N_crosr = 0) and the unknowns of Eq. cmp are 2N plane-wave-slice
+amplitudes.  The cell holds slices 1..M (the periodic electrode's unit cell
+along z, a3 along z so a3_perp = 0); slice M+1 is the next cell's slice 1.
+Reference planes as in ``transport``: z_p is the right end of slice p, so
+z_{M+1} = z_1 + d with d the cell length.
+
+The Bloch conditions (Eqs. bc1, bc2) on the wave and its z-derivative say
+that the amplitudes in slice M+1 are lam = e^{i k d} times those in slice 1:
+A^{M+1} = lam A^1, B^{M+1} = lam B^1.  The cell's S-matrix S = S(1, M+1)
+gives [A^{M+1}; B^1] = S [A^1; B^{M+1}] (Eq. smm3_0 without the C terms).
+Taking the cell's incoming amplitudes X = [A^1; B^{M+1}] as the unknowns
+(the choice of App. B), the two block rows read
+
+    lam A^1 = S11 A^1 + S12 B^{M+1}
+    B^{M+1} = lam (S21 A^1 + S22 B^{M+1})
+
+i.e.  P X = lam Q X  with  P = [[S11, S12], [0, I]],  Q = [[I, 0], [S21, S22]],
+the generalized eigenproblem of Eq. cmp.  |lam| = 1: propagating Bloch
+states; |lam| < 1: evanescent states decaying towards +z; |lam| > 1: decaying
+towards -z.
+
+Readings (listed in the design notes): the cell's first slice is repeated as
+slice M+1 so that both Bloch planes are reference planes of the same slice
+basis; k = -i log(lam) / d on the principal branch (Re k in (-pi/d, pi/d]).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .transport import (LEAD_THRESHOLD, ThresholdError, cascade, interface_smatrix, overlap,
+                        wavevectors)
+
+__all__ = ["cell_smatrix", "bloch_pencil", "complex_bands", "mode_flux", "fold_indices", "fold_mode"]
+
+
+def _cell_slices(prep: dict):
+    """Slices 1..M of a prepared cell (``transport.prepare``; its lead entries are unused)."""
+    m = prep["n_slices"]
+    if m < 1:
+        raise ValueError("the cell needs at least one slice")
+    return [prep["eps"][p] for p in range(1, m + 1)], [prep["u"][p] for p in range(1, m + 1)], \
+        [float(prep["dz"][p]) for p in range(1, m + 1)]
+
+
+def cell_smatrix(prep: dict, energy: float) -> dict:
+    """S(1, M+1) of one electrode cell: the interfaces 1|2, ..., M-1|M and M|1' (slice 1
+    of the next cell, thickness dz_1), joined by star products (Eq. recurrence1)."""
+    eps, us, dz = _cell_slices(prep)
+    for e in eps:
+        if np.min(np.abs(energy - np.asarray(e))) < LEAD_THRESHOLD:
+            raise ThresholdError("energy on a slice channel threshold (k = 0)")
+    ks = [wavevectors(energy, e) for e in eps]
+    m = len(eps)
+    smats = []
+    for p in range(m):
+        q = (p + 1) % m                       # the next slice; after slice M, slice 1 again
+        smats.append(interface_smatrix(overlap(us[p], us[q]), ks[p], ks[q], dz[q]))
+    return cascade(smats)
+
+
+def bloch_pencil(s: dict):
+    """P, Q of Eq. cmp from the cell's S-matrix blocks (S11, S12, S21, S22) = (t, rp, r, tp)."""
+    n = s["t"].shape[0]
+    eye = np.eye(n, dtype=np.complex128)
+    zero = np.zeros((n, n), dtype=np.complex128)
+    p = np.block([[s["t"], s["rp"]], [zero, eye]])
+    q = np.block([[eye, zero], [s["r"], s["tp"]]])
+    return p, q
+
+
+def complex_bands(prep: dict, energy: float) -> dict:
+    """Eq. cmp at one energy: lam [2N], X [2N][2N] (columns [A^1; B^{M+1}], unit 2-norm),
+    k = -i log(lam) / d, the cell length d, and the pencil (P, Q)."""
+    s = cell_smatrix(prep, energy)
+    p, q = bloch_pencil(s)
+    lam, x = sla.eig(p, q)
+    x = x / np.linalg.norm(x, axis=0)[None, :]
+    d = float(np.sum(_cell_slices(prep)[2]))
+    return dict(lam=lam, x=x, k=-1j * np.log(lam) / d, d=d, p=p, q=q)
+
+
+def mode_flux(prep: dict, energy: float, lam: complex, x: np.ndarray) -> float:
+    """Probability current of one mode (H = -nabla^2, per cell area) at the reference plane of
+    slice 1: sum over its channels of 2 k (|A|^2 - |B|^2) (real k) or 4 kappa Im(conj(A) B)
+    (k = i kappa), with B^1 = B^{M+1} / lam; the slice eigenstates are orthonormal, so the
+    channels do not mix."""
+    eps = _cell_slices(prep)[0][0]
+    k = wavevectors(energy, eps)
+    n = k.size
+    a, b = x[:n], x[n:] / lam
+    real = np.abs(k.imag) <= np.abs(k.real)
+    j = np.sum(2.0 * k.real[real] * (np.abs(a[real]) ** 2 - np.abs(b[real]) ** 2))
+    j += np.sum(4.0 * k.imag[~real] * np.imag(np.conj(a[~real]) * b[~real]))
+    return float(j)
+
+
+def fold_indices(miller_prim, c, mk, miller_super) -> np.ndarray:
+    """Position in the supercell basis of each primitive plane wave k_perp + m b1 + n b2 with
+    k_perp = K_perp + m^k B1 + n^k B2, b1 = c11 B1 + c12 B2, b2 = c21 B1 + c22 B2: the wave
+    is K_perp + (m^k + m c11 + n c21) B1 + (n^k + m c12 + n c22) B2 (App. B).  Raises if a
+    folded wave is not in the supercell basis."""
+    mp = np.asarray(miller_prim, dtype=np.int64)
+    c = np.asarray(c, dtype=np.int64).reshape(2, 2)
+    big = np.stack([mk[0] + mp[:, 0] * c[0, 0] + mp[:, 1] * c[1, 0],
+                    mk[1] + mp[:, 0] * c[0, 1] + mp[:, 1] * c[1, 1]], axis=1)
+    where = {tuple(v): i for i, v in enumerate(np.asarray(miller_super, dtype=np.int64))}
+    try:
+        return np.array([where[tuple(v)] for v in big], dtype=np.int64)
+    except KeyError as e:
+        raise ValueError(f"folded plane wave {e} is not in the supercell basis")
+
+
+def fold_mode(x_prim: np.ndarray, u1_prim, u1_super, idx: np.ndarray, n_super: int) -> np.ndarray:
+    """A primitive-cell mode [A^1; B^{M+1}] (slice-1 eigenbasis of the primitive cell) as the
+    supercell's unknowns: both halves to plane-wave coefficients (U^1 a), re-indexed by
+    ``fold_indices``, then to the supercell's slice-1 eigenbasis (U^1_super^dagger)."""
+    n = x_prim.shape[0] // 2
+    out = np.zeros(2 * n_super, dtype=np.complex128)
+    for h in range(2):
+        pw = np.zeros(n_super, dtype=np.complex128)
+        pw[idx] = u1_prim @ x_prim[h * n:(h + 1) * n]
+        out[h * n_super:(h + 1) * n_super] = u1_super.conj().T @ pw
+    return out
