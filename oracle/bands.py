@@ -40,7 +40,11 @@ import scipy.linalg as sla
 from .transport import (LEAD_THRESHOLD, ThresholdError, cascade, interface_smatrix, overlap,
                         wavevectors)
 
-__all__ = ["cell_smatrix", "bloch_pencil", "complex_bands", "mode_flux", "fold_indices", "fold_mode"]
+__all__ = ["cell_smatrix", "bloch_pencil", "complex_bands", "mode_flux", "flux_matrix", "electrode_modes",
+           "transmission_bands", "fold_indices", "fold_mode", "PROPAGATING_TOL"]
+
+# |lam| within this of 1: a propagating Bloch state
+PROPAGATING_TOL = 1e-8
 
 
 def _cell_slices(prep: dict):
@@ -102,6 +106,93 @@ def mode_flux(prep: dict, energy: float, lam: complex, x: np.ndarray) -> float:
     j = np.sum(2.0 * k.real[real] * (np.abs(a[real]) ** 2 - np.abs(b[real]) ** 2))
     j += np.sum(4.0 * k.imag[~real] * np.imag(np.conj(a[~real]) * b[~real]))
     return float(j)
+
+
+def flux_matrix(k, a_u, b_u, a_v, b_v) -> np.ndarray:
+    """Cross flux J(u_i, v_j) = -i (conj(u) v' - conj(u') v) of two sets of modes given by
+    their channel amplitudes (columns) at a reference plane, where u = a + b and
+    u' = i k (a - b) per channel:  J = (A_u + B_u)^H K (A_v - B_v) + (A_u - B_u)^H K^* (A_v + B_v),
+    K = diag(k).  J(u, u) is ``mode_flux``; Bloch states of different lam on the unit circle
+    carry no cross flux."""
+    k = np.asarray(k)
+    su, du = a_u + b_u, a_u - b_u
+    sv, dv = a_v + b_v, a_v - b_v
+    return su.conj().T @ (k[:, None] * dv) + du.conj().T @ (np.conj(k)[:, None] * sv)
+
+
+def electrode_modes(prep: dict, energy: float) -> dict:
+    """The Bloch states of an electrode cell at one energy, with their amplitudes (a, b) in the
+    slice-1 eigenbasis at slice 1's reference plane (b = B^{M+1} / lam), sorted into
+    right-going (propagating with positive flux, or decaying towards +z: |lam| < 1) and
+    left-going ones (negative flux, or |lam| > 1).  Each set must hold N states."""
+    bands = complex_bands(prep, energy)
+    lam, x = bands["lam"], bands["x"]
+    n = x.shape[0] // 2
+    a, b = x[:n], x[n:] / lam[None, :]
+    k = wavevectors(energy, _cell_slices(prep)[0][0])
+    prop = np.abs(np.abs(lam) - 1.0) < PROPAGATING_TOL
+    flux = np.real(np.diag(flux_matrix(k, a, b, a, b)))
+    right = np.where((prop & (flux > 0)) | (~prop & (np.abs(lam) < 1.0)))[0]
+    left = np.where((prop & (flux < 0)) | (~prop & (np.abs(lam) > 1.0)))[0]
+    if right.size != n or left.size != n:
+        raise ValueError(f"{right.size} right- and {left.size} left-going states, expected {n} each "
+                         "(an energy at a band edge?)")
+    return dict(lam=lam, a=a, b=b, k=k, prop=prop, flux=flux, right=right, left=left, u1=_cell_slices(prep)[1][0])
+
+
+def transmission_bands(left_cell: dict, scatter: dict, right_cell: dict, energy: float) -> dict:
+    """T and R between two periodic electrodes through a scattering region (App. C in the
+    S-matrix form of Sec. II.A).  The left electrode ends with a copy of its cell's slice 1
+    (reference plane: its right end), the scattering region's slices 1..N follow, and the right
+    electrode starts with its cell's slice 1 (reference plane: its right end); the region's
+    S-matrix S = S(L1, R1) joins those two planes.  Left of it the wave is an incident
+    right-going propagating state plus the left-going states (amplitudes rho), right of it the
+    right-going states (amplitudes tau): per incident state,
+
+        T_a tau              = S11 (a_in + R_a rho) + S12 T_b tau
+        b_in + R_b rho       = S21 (a_in + R_a rho) + S22 T_b tau
+
+    (T_a, T_b: the right electrode's right-going states, R_a, R_b: the left electrode's
+    left-going ones).  With incident states j and flux matrices J,
+    T = Tr[(tau_p^H J_out tau_p) J_in^-1] over the propagating transmitted states, R likewise
+    with -J over the propagating reflected ones; T + R = number of incident states."""
+    for cell in (left_cell, right_cell):
+        if not np.allclose(cell["kin"], scatter["kin"], rtol=0, atol=1e-12):
+            raise ValueError("the electrodes and the scattering region need the same transverse basis")
+    lm = electrode_modes(left_cell, energy)
+    rm = electrode_modes(right_cell, energy)
+    eps_s, us, dz = ([scatter["eps"][p] for p in range(1, scatter["n_slices"] + 1)],
+                     [scatter["u"][p] for p in range(1, scatter["n_slices"] + 1)],
+                     [float(scatter["dz"][p]) for p in range(1, scatter["n_slices"] + 1)])
+    le, lu, _ = _cell_slices(left_cell)
+    re_, ru, rdz = _cell_slices(right_cell)
+    eps = [le[0]] + eps_s + [re_[0]]
+    uu = [lu[0]] + us + [ru[0]]
+    ws = [0.0] + dz + [rdz[0]]
+    for e in eps:
+        if np.min(np.abs(energy - np.asarray(e))) < LEAD_THRESHOLD:
+            raise ThresholdError("energy on a slice channel threshold (k = 0)")
+    ks = [wavevectors(energy, e) for e in eps]
+    s = cascade([interface_smatrix(overlap(uu[p], uu[p + 1]), ks[p], ks[p + 1], ws[p + 1])
+                 for p in range(len(eps) - 1)])
+    inc = lm["right"][lm["prop"][lm["right"]]]
+    ta, tb = rm["a"][:, rm["right"]], rm["b"][:, rm["right"]]
+    ra, rb = lm["a"][:, lm["left"]], lm["b"][:, lm["left"]]
+    ia, ib = lm["a"][:, inc], lm["b"][:, inc]
+    m = np.block([[ta - s["rp"] @ tb, -s["t"] @ ra], [-s["tp"] @ tb, rb - s["r"] @ ra]])
+    d = np.vstack([s["t"] @ ia, s["r"] @ ia - ib])
+    y = np.linalg.solve(m, d)
+    n = ta.shape[0]
+    tau, rho = y[:n], y[n:]
+    tp = rm["prop"][rm["right"]]
+    rp = lm["prop"][lm["left"]]
+    j_in = flux_matrix(lm["k"], ia, ib, ia, ib)
+    j_out = flux_matrix(rm["k"], ta[:, tp], tb[:, tp], ta[:, tp], tb[:, tp])
+    j_ref = -flux_matrix(lm["k"], ra[:, rp], rb[:, rp], ra[:, rp], rb[:, rp])
+    jinv = np.linalg.inv(j_in)
+    tt = float(np.real(np.trace(tau[tp].conj().T @ j_out @ tau[tp] @ jinv)))
+    rr = float(np.real(np.trace(rho[rp].conj().T @ j_ref @ rho[rp] @ jinv)))
+    return dict(T=tt, R=rr, n_in=int(inc.size), S=s, tau=tau, rho=rho)
 
 
 def fold_indices(miller_prim, c, mk, miller_super) -> np.ndarray:

@@ -165,3 +165,66 @@ def test_folding_primitive_to_supercell(nmat):
             res = bs["p"] @ xf - bp["lam"][i] * (bs["q"] @ xf)
             assert np.linalg.norm(res) < 1e-10 * max(1.0, abs(bp["lam"][i])), (i, np.linalg.norm(res))
     _match(bs["lam"], want, 1e-9)
+
+
+# ---------------------------------------------------------------- transmission between
+# periodic electrodes (App. C through the region's S-matrix)
+def _with(inp, dz, vq):
+    out = dict(inp)
+    out["dz"] = np.asarray(dz, dtype=np.float64)
+    out["vq"] = np.asarray(vq)
+    return out
+
+
+def test_free_electrodes_reproduce_free_lead_transmission():
+    """Electrode cells of zero potential (one slice and two of other thicknesses): their Bloch
+    states are the free plane waves, so T and R equal those of the free-lead path (itself
+    pinned to closed forms and a second exact route)."""
+    dz = np.array([0.5, 0.7, 0.3, 0.6])
+    inp = _cell_inputs(11, dz)
+    scatter = orc.prepare(inp)
+    zero = np.zeros((1, inp["vq"].shape[1]), dtype=np.complex128)
+    left = orc.prepare(_with(inp, [0.9], zero))
+    right = orc.prepare(_with(inp, [0.4, 0.35], np.zeros((2, inp["vq"].shape[1]))))
+    for e in (0.45, 1.3, 2.2):
+        ref = orc.transmission(scatter, e)
+        got = orc.transmission_bands(left, scatter, right, e)
+        assert got["n_in"] == ref["n_open"]
+        assert abs(got["T"] - ref["T"]) < 1e-10, (e, got["T"], ref["T"])
+        assert abs(got["R"] - ref["R"]) < 1e-10
+
+
+def test_crystal_continued_through_the_region_transmits_perfectly():
+    """A scattering region that continues the electrodes' crystal (their cell's slices 2..M, 1
+    repeated, ending with 2..M): every incident Bloch state is transmitted, T = the number of
+    incident states, R = 0."""
+    dz = np.array([0.5, 0.6, 0.4])
+    inp = _cell_inputs(11, dz)
+    cell = orc.prepare(inp)
+    order = [1, 2, 0, 1, 2, 0, 1, 2]
+    region = orc.prepare(_with(inp, dz[order], inp["vq"][order]))
+    for e in (0.8, 1.7):
+        got = orc.transmission_bands(cell, region, cell, e)
+        assert got["n_in"] >= 1
+        assert abs(got["T"] - got["n_in"]) < 1e-9, (e, got)
+        assert abs(got["R"]) < 1e-9
+
+
+def test_different_electrodes_conserve_flux():
+    """A wells electrode on the left, a z-only crystal on the right, a random region between:
+    T + R equals the number of incident Bloch states, and both lie in [0, n_in]."""
+    dz = np.array([0.5, 0.6, 0.4])
+    inp = _cell_inputs(11, dz)
+    left = orc.prepare(inp)
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    vr = np.zeros((2, inp["vq"].shape[1]), dtype=np.complex128)
+    vr[:, q0] = [0.3, -0.4]
+    right = orc.prepare(_with(inp, [0.45, 0.55], vr))
+    rng = np.random.default_rng(7)
+    dzs = np.array([0.3, 0.5, 0.4, 0.2, 0.6])
+    vq = inp["vq"][rng.integers(0, 3, dzs.size)] * 1.7
+    region = orc.prepare(_with(inp, dzs, vq))
+    for e in (0.9, 1.6, 2.4):
+        got = orc.transmission_bands(left, region, right, e)
+        assert abs(got["T"] + got["R"] - got["n_in"]) < 1e-9, (e, got["T"], got["R"], got["n_in"])
+        assert -1e-12 < got["T"] < got["n_in"] + 1e-12 and got["R"] > -1e-12
