@@ -56,6 +56,13 @@ def test_null_context_is_rejected(lib):
         "ms_transmission": (None, None, ctypes.c_double(0.5), None, None, None, None, None),
         "ms_transmission_batch": (None, None, 1, None, 0, None, None, None, None),
         "ms_kpar_average": (None, 1, 1, None, None, None, None),
+        "ms_mixed_doubling": (None, None, ctypes.c_double(0.5), ctypes.c_double(1e6), None, None),
+        "ms_transmission_multi": (None, 1, None, 1, None, 0, None, None, None, None),
+        "ms_transmission_uneven": (None, 1, None, None, None, 0, 0, None, None, None, None),
+        "ms_graph_replay": (None,),
+        "ms_dT_dV": (None, None, 1, None, None, 1, 0, None, None, None),
+        "ms_set_tiles": (None, 1, None),
+        "ms_autotune": (None, 1, 0, 1, None, None),
         "ms_debug_gemm": (None, 0, 0, 1, 1, 1, None, 1, None, 1, None, 1, None, None, 0),
         "ms_debug_lu_solve": (None, 1, 1, 1, None, None, None),
         "ms_debug_eigh": (None, 1, 1, None, None, None, None),
