@@ -228,3 +228,27 @@ def test_different_electrodes_conserve_flux():
         got = orc.transmission_bands(left, region, right, e)
         assert abs(got["T"] + got["R"] - got["n_in"]) < 1e-9, (e, got["T"], got["R"], got["n_in"])
         assert -1e-12 < got["T"] < got["n_in"] + 1e-12 and got["R"] > -1e-12
+
+
+def test_flux_matrix_diagonal_and_cross_flux():
+    """The flux matrix's diagonal is each state's own flux, and two propagating Bloch states
+    of different lam carry no cross flux (current conservation from cell to cell: J(u, v) is
+    multiplied by conj(lam_u) lam_v per cell, which is not 1)."""
+    dz = np.array([0.5, 0.6, 0.4])
+    inp = _cell_inputs(13, dz)
+    prep = orc.prepare(inp)
+    e = 1.9
+    m = orc.electrode_modes(prep, e)
+    j = orc.flux_matrix(m["k"], m["a"], m["b"], m["a"], m["b"])
+    lam = m["lam"]
+    for i in range(lam.size):
+        assert abs(j[i, i].real - orc.mode_flux(prep, e, lam[i], np.concatenate([m["a"][:, i],
+                                                                                 m["b"][:, i] * lam[i]]))) \
+            < 1e-12 * np.max(np.abs(j))
+    prop = np.where(m["prop"])[0]
+    assert prop.size >= 4
+    scale = np.max(np.abs(np.diag(j)[prop]))
+    for a in prop:
+        for b in prop:
+            if a != b and abs(lam[a] - lam[b]) > 1e-6:
+                assert abs(j[a, b]) < 1e-10 * scale, (lam[a], lam[b], j[a, b])
