@@ -310,6 +310,21 @@ ms_status ms_graph_replay(ms_ctx ctx);
 ms_status ms_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T, const int64_t* n_open,
                           double* tbar, double* per_channel);
 
+/* Electrode cell, first stage of the complex bands (App. B, Eq. cmp; local potential, so no
+ * non-local sphere crosses a cell boundary): the Bloch conditions A^{M+1} = lam A^1,
+ * B^{M+1} = lam B^1 (lam = e^{ikd}) through the cell's S-matrix S = S(1, M+1), with the cell's
+ * incoming amplitudes X = [A^1; B^{M+1}] as unknowns, give P X = lam Q X with
+ *   P = [[S11, S12], [0, I]],  Q = [[I, 0], [S21, S22]]   (2 n_g x 2 n_g).
+ *   cell    prepared (ms_slices_prepare) from the cell's slices 1..M followed by slice 1 again
+ *           (its potential row and thickness repeated: slice M+1 is the next cell's slice 1),
+ *           so n_slices = M + 1 >= 2; the lead entries are unused
+ *   P, Q    [2 n_g][2 n_g] c128 (device outputs, row-major, distinct)
+ * The pencil's eigenvalues lam and eigenvectors (A^1 in the slice-1 eigenbasis, B^{M+1} in
+ * that of the repeated slice) are the electrode's Bloch states; solving it is not part of the
+ * library yet.  Errors: MS_ERR_ARG, MS_ERR_UNSUPPORTED, MS_ERR_ALLOC; singular X via
+ * ms_ctx_sync. */
+ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void* P, void* Q);
+
 #ifdef __cplusplus
 }
 #endif

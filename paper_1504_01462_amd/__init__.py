@@ -57,6 +57,7 @@ _sig("ms_ctx_last_error", [_vp, ctypes.c_char_p, _i64])
 _sig("ms_slices_prepare", [_vp, _i64, _vp, _vp, _vp, _f64, _f64, _i64, _i64, _vp, _vp, ctypes.POINTER(MsSlices)])
 _sig("ms_slice_smatrix", [_vp, ctypes.POINTER(MsSlices), _f64, _i64, _i64, ctypes.POINTER(MsSmat)])
 _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER(MsSmat)])
+_sig("ms_bloch_pencil", [_vp, ctypes.POINTER(MsSlices), ctypes.c_double, _vp, _vp])
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
@@ -206,6 +207,17 @@ def ms_star_cascade(ctx: Context, smats, prec="fp64"):
     w = _smat(whole)
     _check(ctx.handle, lib.ms_star_cascade(ctx.handle, arr, len(smats), _PREC[prec], ctypes.byref(w)))
     return whole
+
+
+def ms_bloch_pencil(ctx: Context, cell: Slices, energy: float):
+    """P, Q [2n][2n] complex128 of an electrode cell's Bloch eigenproblem P X = lam Q X; `cell`
+    holds the cell's slices 1..M followed by slice 1 again."""
+    m = 2 * cell.n_g
+    P = torch.empty((m, m), dtype=torch.complex128, device=ctx.device)
+    Q = torch.empty((m, m), dtype=torch.complex128, device=ctx.device)
+    _check(ctx.handle, lib.ms_bloch_pencil(ctx.handle, ctypes.byref(cell.c), float(energy),
+                                           _ptr(P, torch.complex128, "P"), _ptr(Q, torch.complex128, "Q")))
+    return P, Q
 
 
 def ms_mixed_doubling(ctx: Context, slices: Slices, energy: float, max_cond: float = 1e6):
@@ -456,7 +468,8 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
-           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_mixed_doubling", "ms_transmission",
+           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_mixed_doubling",
+           "ms_transmission",
            "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",

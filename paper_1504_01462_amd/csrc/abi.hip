@@ -149,7 +149,9 @@ enum {
   WS_PERM, WS_RT, WS_RR, WS_RNO, WS_RST,
   // first variation of T
   WS_GSEG, WS_GCK, WS_GRS, WS_GL, WS_GK, WS_GP, WS_GCH, WS_GOS, WS_GX, WS_GFA, WS_GFB, WS_GAUG, WS_GY,
-  WS_GT1, WS_GBP, WS_GBF, WS_GP1, WS_GP2, WS_GMC, WS_GYG, WS_GKC, WS_GPIV, WS_GEN, WS_GA2, WS_GB2
+  WS_GT1, WS_GBP, WS_GBF, WS_GP1, WS_GP2, WS_GMC, WS_GYG, WS_GKC, WS_GPIV, WS_GEN, WS_GA2, WS_GB2,
+  // electrode cells
+  WS_BSEG, WS_BWHOLE
 };
 
 constexpr int MAX_N = 4096;
@@ -1063,6 +1065,33 @@ ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec 
     cur ^= 1;
   }
   return MS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void* P, void* Q) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, cell));
+  if (cell->n_slices < 2) return fail(ctx, MS_ERR_ARG, "the cell needs its M >= 1 slices and slice 1 again");
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  if (bad_ptr(P) || bad_ptr(Q) || P == Q) return fail(ctx, MS_ERR_ARG, "P and Q must be distinct device buffers");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const int n = (int)cell->n_g, m = (int)cell->n_slices - 1;   // the cell's slices 1..m, then slice 1 again
+  const int64_t nn = (int64_t)n * n;
+  void *seg, *whole;
+  MS_TRY(workspace(ctx, WS_BSEG, (size_t)m * 4 * nn * sizeof(double2), &seg));
+  MS_TRY(workspace(ctx, WS_BWHOLE, (size_t)4 * nn * sizeof(double2), &whole));
+  std::vector<ms_smat> s(m);
+  for (int i = 0; i < m; ++i) {
+    double2* b = c2(seg) + (int64_t)i * 4 * nn;
+    s[i] = ms_smat{n, b, b + nn, b + 2 * nn, b + 3 * nn};
+  }
+  // S(p, p+1) for p = 1..m (the last one joins slice m to the next cell's slice 1), then S(1, m+1)
+  MS_TRY(ms_slice_smatrix(ctx, cell, energy, 1, m + 1, s.data()));
+  double2* w = c2(whole);
+  ms_smat ws{n, w, w + nn, w + 2 * nn, w + 3 * nn};
+  MS_TRY(ms_star_cascade(ctx, s.data(), m, MS_PREC_FP64, &ws));
+  return launch_bloch_pencil(ctx, n, w, w + nn, w + 2 * nn, w + 3 * nn, static_cast<double2*>(P),
+                             static_cast<double2*>(Q));
 }
 
 // ------------------------------------------------------------------------------------------

@@ -53,6 +53,9 @@ ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, int64_t s_k
                         const double2* p2, int64_t s_p, const double2* a, int64_t lda, int64_t s_a, const double2* b,
                         int64_t ldb, int64_t s_b, double2* mc, int64_t s_m, int batch);
 ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst, int batch = 1, int64_t s_dst = 0);
+// P, Q of an electrode cell's Bloch eigenproblem from its S-matrix blocks
+ms_status launch_bloch_pencil(ms_ctx ctx, int n, const double2* t, const double2* rp, const double2* r,
+                              const double2* tp, double2* P, double2* Q);
 ms_status launch_grad_scatter(ms_ctx ctx, int64_t nn, const int32_t* q, const double2* kc, int64_t s_kc, double* g,
                               int64_t s_g, int batch);
 

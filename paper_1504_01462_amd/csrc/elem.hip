@@ -511,6 +511,24 @@ __global__ void k_grad_p(int n, int nl, int nr, const double2* c, int64_t ldc, i
 }
 
 // the first n columns of an n-row matrix (leading dim ld) set to the identity
+// P = [[S11, S12], [0, I]], Q = [[I, 0], [S21, S22]] (2n x 2n row-major) from the blocks of a
+// cell S-matrix, (S11, S12, S21, S22) = (t, rp, r, tp)
+__global__ void k_bloch_pencil(int n, const double2* t, const double2* rp, const double2* r, const double2* tp,
+                               double2* P, double2* Q) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = 2 * (int64_t)n;
+  if (e >= m * m) return;
+  const int i = (int)(e / m), j = (int)(e % m);
+  const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+  if (i < n) {
+    P[e] = j < n ? t[(int64_t)i * n + j] : rp[(int64_t)i * n + (j - n)];
+    Q[e] = j < n ? (i == j ? one : zero) : zero;
+  } else {
+    P[e] = j < n ? zero : (i == j ? one : zero);
+    Q[e] = j < n ? r[(int64_t)(i - n) * n + j] : tp[(int64_t)(i - n) * n + (j - n)];
+  }
+}
+
 __global__ void k_eye(int n, int64_t ld, double2* dst, int64_t s_dst) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)n * n) return;
@@ -706,6 +724,13 @@ ms_status launch_grad_m(ms_ctx ctx, int n, int nl, const double2* k, int64_t s_k
   hipLaunchKernelGGL(k_grad_m, dim3(blocks((int64_t)n * n), batch), dim3(256), 0, ctx->stream, n, nl, k, s_k, width, p1,
                      p2, s_p, a, lda, s_a, b, ldb, s_b, mc, s_m);
   return check_launch(ctx, "gradient slice integrals");
+}
+
+ms_status launch_bloch_pencil(ms_ctx ctx, int n, const double2* t, const double2* rp, const double2* r,
+                              const double2* tp, double2* P, double2* Q) {
+  hipLaunchKernelGGL(k_bloch_pencil, dim3(blocks(4 * (int64_t)n * n)), dim3(256), 0, ctx->stream, n, t, rp, r, tp, P,
+                     Q);
+  return check_launch(ctx, "Bloch pencil");
 }
 
 ms_status launch_eye(ms_ctx ctx, int n, int64_t ld, double2* dst, int batch, int64_t s_dst) {

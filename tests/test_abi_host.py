@@ -63,6 +63,7 @@ def test_null_context_is_rejected(lib):
         "ms_dT_dV": (None, None, 1, None, None, 1, 0, None, None, None),
         "ms_set_tiles": (None, 1, None),
         "ms_autotune": (None, 1, 0, 1, None, None),
+        "ms_bloch_pencil": (None, None, ctypes.c_double(0.5), None, None),
         "ms_debug_gemm": (None, 0, 0, 1, 1, 1, None, 1, None, 1, None, 1, None, None, 0),
         "ms_debug_lu_solve": (None, 1, 1, 1, None, None, None),
         "ms_debug_eigh": (None, 1, 1, None, None, None, None),

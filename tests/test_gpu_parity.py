@@ -687,3 +687,45 @@ def test_dT_dV_batches_with_uneven_open_counts(ms, ctx):
         out = orc.transmission(prep, es[i])
         assert np.max(np.abs(g[i] - ref)) < 1e-10 * np.max(np.abs(ref)), es[i]
         assert abs(tr[i][0] - out["T"]) < 1e-10
+
+
+# ------------------------------------------------------------------ electrode cells (App. B) --
+@pytest.mark.parametrize("zonly", [False, True])
+def test_bloch_pencil_eigenvalues_match_oracle(ms, ctx, zonly):
+    """The cell's S(1, M+1) and the pencil of Eq. cmp on the GPU: its eigenvalues (LAPACK on the
+    host, on the GPU's P and Q; they do not depend on the slices' eigenvector gauge) against the
+    oracle's complex bands, for a wells cell and a cell whose potential depends on z only
+    (propagating and evanescent states alike)."""
+    import scipy.linalg as sla
+    j = msgen.config1()
+    dz = np.array([0.5, 0.6, 0.4])
+    j.dz = dz
+    inp = msgen.junction_inputs(j, (0.07, -0.11), 13)
+    if zonly:
+        q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+        vq = np.zeros_like(inp["vq"])
+        vq[:, q0] = [0.0, 0.8, -0.5]
+        inp["vq"] = vq
+    prep = orc.prepare(inp)
+    cell = dict(inp, vq=np.concatenate([inp["vq"], inp["vq"][:1]]), dz=np.concatenate([dz, dz[:1]]))
+    s = ms.prepare_from_inputs(ctx, cell)
+    for e in (0.9, 1.6, 2.7):
+        P, Q = ms.ms_bloch_pencil(ctx, s, e)
+        ctx.sync()
+        lam = list(sla.eigvals(_np(P), _np(Q)))
+        ref = orc.complex_bands(prep, e)["lam"]
+        assert len(lam) == ref.size
+        for w in ref:
+            d = [abs(g - w) / abs(w) for g in lam]
+            i = int(np.argmin(d))
+            assert d[i] < 1e-9, (e, w, lam[i], d[i])
+            lam.pop(i)
+
+
+def test_bloch_pencil_argument_errors(ms, ctx):
+    j = msgen.config1()
+    j.dz = np.array([0.5])
+    inp = msgen.junction_inputs(j, (0.07, -0.11), 9)
+    s = ms.prepare_from_inputs(ctx, inp)      # one slice: the repeated slice 1 is missing
+    with pytest.raises(ms.MSError):
+        ms.ms_bloch_pencil(ctx, s, 0.9)
