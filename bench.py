@@ -426,8 +426,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: every box of this build has a single MI355X and the path "
-              "shards over (E, k_par) points without communication; run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the path shards over (E, k_par) points with no "
+              "communication between GPUs, so it has no multi-GPU step to time; run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     host_inputs = None
     if args.uneven_only:

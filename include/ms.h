@@ -48,7 +48,7 @@ typedef enum {
                            /* or the fused interface matrix)                             */
   MS_ERR_THRESHOLD = 5,    /* |E - lead channel energy| < 1e-10: k = 0 in a lead          */
   MS_ERR_NONFINITE = 6,    /* NaN or Inf met in inputs or results                        */
-  MS_ERR_UNSUPPORTED = 7,  /* size or mode this build does not handle                    */
+  MS_ERR_UNSUPPORTED = 7,  /* size or mode the library does not handle                 */
   MS_ERR_NOCONV = 8        /* slice eigensolver did not reach its tolerance              */
 } ms_status;
 

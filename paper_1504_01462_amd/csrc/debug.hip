@@ -67,7 +67,7 @@ ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, 
   if (!ctx) return MS_ERR_ARG;
   if (!aug || !x || !status) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
   if (n <= 0 || nrhs <= 0 || batch <= 0) return fail(ctx, MS_ERR_ARG, "bad sizes");
-  if (n > 4096 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond this build");
+  if (n > 4096 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond the supported limits");
   MS_HIP(ctx, hipSetDevice(ctx->device));
   void* piv = nullptr;
   MS_TRY(workspace(ctx, 13, (size_t)batch * n * sizeof(int32_t), &piv));
@@ -84,7 +84,7 @@ ms_status ms_debug_eigh(ms_ctx ctx, int64_t n, int64_t batch, const void* h, con
   if (!ctx) return MS_ERR_ARG;
   if (!h || !shift || !eps || !u) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
   if (n <= 0 || batch <= 0) return fail(ctx, MS_ERR_ARG, "bad sizes");
-  if (n > 3000 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond this build");
+  if (n > 3000 || batch > 65535) return fail(ctx, MS_ERR_UNSUPPORTED, "size beyond the supported limits");
   MS_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t nn = n * n;
   void* W = nullptr;
