@@ -41,10 +41,15 @@ from .transport import (LEAD_THRESHOLD, ThresholdError, cascade, interface_smatr
                         wavevectors)
 
 __all__ = ["cell_smatrix", "bloch_pencil", "complex_bands", "mode_flux", "flux_matrix", "electrode_modes",
-           "transmission_bands", "fold_indices", "fold_mode", "PROPAGATING_TOL"]
+           "transmission_bands", "fold_indices", "fold_mode", "PROPAGATING_TOL", "LAM_RANGE"]
 
 # |lam| within this of 1: a propagating Bloch state
 PROPAGATING_TOL = 1e-8
+# Bloch factors outside [1/LAM_RANGE, LAM_RANGE] (evanescent states that change by more than
+# this over one cell) are not resolved in FP64: S22 of the cell is then singular to working
+# precision, Eq. cmp has (numerically) infinite eigenvalues and the states' amplitudes at the
+# cell's first plane vanish, so the matching would be singular
+LAM_RANGE = 1e13
 
 
 def _cell_slices(prep: dict):
@@ -88,6 +93,10 @@ def complex_bands(prep: dict, energy: float) -> dict:
     s = cell_smatrix(prep, energy)
     p, q = bloch_pencil(s)
     lam, x = sla.eig(p, q)
+    mag = np.abs(lam)
+    if not np.all(np.isfinite(lam)) or mag.min() < 1.0 / LAM_RANGE or mag.max() > LAM_RANGE:
+        raise ValueError(f"Bloch factors span [{mag.min():.1e}, {mag.max():.1e}], beyond what FP64 resolves "
+                         f"([{1.0 / LAM_RANGE:.0e}, {LAM_RANGE:.0e}]): a thinner cell or a smaller basis")
     x = x / np.linalg.norm(x, axis=0)[None, :]
     d = float(np.sum(_cell_slices(prep)[2]))
     return dict(lam=lam, x=x, k=-1j * np.log(lam) / d, d=d, p=p, q=q)

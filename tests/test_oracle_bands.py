@@ -252,3 +252,21 @@ def test_flux_matrix_diagonal_and_cross_flux():
         for b in prop:
             if a != b and abs(lam[a] - lam[b]) > 1e-6:
                 assert abs(j[a, b]) < 1e-10 * scale, (lam[a], lam[b], j[a, b])
+
+
+def test_bloch_factor_range_is_checked():
+    """Within the resolved range (N = 61, a 5 bohr cell: |lam| in about [1e-12, 1e12]) flux is
+    conserved to rounding; a cell whose evanescent states change by more than 1e13 per cell
+    (N = 97, 5 bohr) is refused instead of giving a singular matching."""
+    j = msgen.config1()
+    dz = np.full(3, 5.0 / 3)
+    j.dz = dz
+    inp = msgen.junction_inputs(j, KPAR, 61)
+    cell = orc.prepare(inp)
+    rng = np.random.default_rng(3)
+    region = orc.prepare(_with(inp, [0.3, 0.5, 0.4, 0.2], inp["vq"][rng.integers(0, 3, 4)] * 1.3))
+    got = orc.transmission_bands(cell, region, cell, 1.3)
+    assert abs(got["T"] + got["R"] - got["n_in"]) < 1e-11
+    inp = msgen.junction_inputs(j, KPAR, 97)
+    with pytest.raises(ValueError, match="beyond what FP64 resolves"):
+        orc.complex_bands(orc.prepare(inp), 1.3)
