@@ -46,9 +46,10 @@ __all__ = ["cell_smatrix", "bloch_pencil", "complex_bands", "mode_flux", "flux_m
 # |lam| within this of 1: a propagating Bloch state
 PROPAGATING_TOL = 1e-8
 # Bloch factors outside [1/LAM_RANGE, LAM_RANGE] (evanescent states that change by more than
-# this over one cell) are not resolved in FP64: S22 of the cell is then singular to working
-# precision, Eq. cmp has (numerically) infinite eigenvalues and the states' amplitudes at the
-# cell's first plane vanish, so the matching would be singular
+# this over one cell) are not resolved as numbers in FP64: S22 of the cell is then singular to
+# working precision and Eq. cmp has numerically infinite eigenvalues, so ``complex_bands``
+# refuses to list their k.  The states themselves stay well defined when each is read at the
+# plane where it is largest (``electrode_modes``), so the matching does not need the range.
 LAM_RANGE = 1e13
 
 
@@ -87,19 +88,22 @@ def bloch_pencil(s: dict):
     return p, q
 
 
-def complex_bands(prep: dict, energy: float) -> dict:
+def complex_bands(prep: dict, energy: float, check_range: bool = True) -> dict:
     """Eq. cmp at one energy: lam [2N], X [2N][2N] (columns [A^1; B^{M+1}], unit 2-norm),
-    k = -i log(lam) / d, the cell length d, and the pencil (P, Q)."""
+    k = -i log(lam) / d, the cell length d, and the pencil (P, Q).  With check_range, Bloch
+    factors beyond LAM_RANGE raise."""
     s = cell_smatrix(prep, energy)
     p, q = bloch_pencil(s)
     lam, x = sla.eig(p, q)
     mag = np.abs(lam)
-    if not np.all(np.isfinite(lam)) or mag.min() < 1.0 / LAM_RANGE or mag.max() > LAM_RANGE:
+    if check_range and (not np.all(np.isfinite(lam)) or mag.min() < 1.0 / LAM_RANGE or mag.max() > LAM_RANGE):
         raise ValueError(f"Bloch factors span [{mag.min():.1e}, {mag.max():.1e}], beyond what FP64 resolves "
                          f"([{1.0 / LAM_RANGE:.0e}, {LAM_RANGE:.0e}]): a thinner cell or a smaller basis")
     x = x / np.linalg.norm(x, axis=0)[None, :]
     d = float(np.sum(_cell_slices(prep)[2]))
-    return dict(lam=lam, x=x, k=-1j * np.log(lam) / d, d=d, p=p, q=q)
+    with np.errstate(divide="ignore", invalid="ignore"):   # lam of 0 or inf without check_range
+        k = -1j * np.log(lam) / d
+    return dict(lam=lam, x=x, k=k, d=d, p=p, q=q)
 
 
 def mode_flux(prep: dict, energy: float, lam: complex, x: np.ndarray) -> float:
@@ -131,13 +135,21 @@ def flux_matrix(k, a_u, b_u, a_v, b_v) -> np.ndarray:
 
 def electrode_modes(prep: dict, energy: float) -> dict:
     """The Bloch states of an electrode cell at one energy, with their amplitudes (a, b) in the
-    slice-1 eigenbasis at slice 1's reference plane (b = B^{M+1} / lam), sorted into
+    slice-1 eigenbasis at a slice-1 reference plane (plane 1 for |lam| <= 1, plane M+1 for the
+    others: each where it is largest, so that states decaying by more than FP64 spans over one
+    cell stay well defined), sorted into
     right-going (propagating with positive flux, or decaying towards +z: |lam| < 1) and
     left-going ones (negative flux, or |lam| > 1).  Each set must hold N states."""
-    bands = complex_bands(prep, energy)
-    lam, x = bands["lam"], bands["x"]
+    bands = complex_bands(prep, energy, check_range=False)
+    lam, x, p, q = bands["lam"], bands["x"], bands["p"], bands["q"]
     n = x.shape[0] // 2
-    a, b = x[:n], x[n:] / lam[None, :]
+    xt, xb = x[:n], x[n:]
+    # each state where it is largest, through the cell's S-matrix (no division by lam): states
+    # with |lam| <= 1 at plane 1, (A^1, B^1 = S21 A^1 + S22 B^{M+1}); the others at plane M+1,
+    # (A^{M+1} = S11 A^1 + S12 B^{M+1}, B^{M+1}).  Both are slice-1 planes of the electrode.
+    grow = np.abs(lam) > 1.0
+    a = np.where(grow[None, :], p[:n, :n] @ xt + p[:n, n:] @ xb, xt)
+    b = np.where(grow[None, :], xb, q[n:, :n] @ xt + q[n:, n:] @ xb)
     k = wavevectors(energy, _cell_slices(prep)[0][0])
     prop = np.abs(np.abs(lam) - 1.0) < PROPAGATING_TOL
     flux = np.real(np.diag(flux_matrix(k, a, b, a, b)))

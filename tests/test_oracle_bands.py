@@ -254,19 +254,27 @@ def test_flux_matrix_diagonal_and_cross_flux():
                 assert abs(j[a, b]) < 1e-10 * scale, (lam[a], lam[b], j[a, b])
 
 
-def test_bloch_factor_range_is_checked():
-    """Within the resolved range (N = 61, a 5 bohr cell: |lam| in about [1e-12, 1e12]) flux is
-    conserved to rounding; a cell whose evanescent states change by more than 1e13 per cell
-    (N = 97, 5 bohr) is refused instead of giving a singular matching."""
+def test_far_evanescent_states():
+    """A cell whose evanescent states change by far more than FP64 spans per cell (N = 137, a
+    5 bohr cell: S22 singular to working precision, some lam numerically infinite).  The list
+    of k values is refused, but the states read at the plane where each is largest, through
+    the cell's S-matrix, still match exactly: flux is conserved, free electrodes reproduce the
+    free-lead path and a region that continues the crystal transmits perfectly."""
     j = msgen.config1()
     dz = np.full(3, 5.0 / 3)
     j.dz = dz
-    inp = msgen.junction_inputs(j, KPAR, 61)
+    inp = msgen.junction_inputs(j, KPAR, 137)
     cell = orc.prepare(inp)
+    with pytest.raises(ValueError, match="beyond what FP64 resolves"):
+        orc.complex_bands(cell, 1.3)
     rng = np.random.default_rng(3)
     region = orc.prepare(_with(inp, [0.3, 0.5, 0.4, 0.2], inp["vq"][rng.integers(0, 3, 4)] * 1.3))
     got = orc.transmission_bands(cell, region, cell, 1.3)
     assert abs(got["T"] + got["R"] - got["n_in"]) < 1e-11
-    inp = msgen.junction_inputs(j, KPAR, 97)
-    with pytest.raises(ValueError, match="beyond what FP64 resolves"):
-        orc.complex_bands(orc.prepare(inp), 1.3)
+    free = orc.prepare(_with(inp, [5.0], np.zeros((1, inp["vq"].shape[1]))))
+    ref = orc.transmission(region, 1.3)
+    assert abs(orc.transmission_bands(free, region, free, 1.3)["T"] - ref["T"]) < 1e-10
+    order = [1, 2, 0, 1, 2, 0, 1, 2]
+    crystal = orc.prepare(_with(inp, dz[order], inp["vq"][order]))
+    got = orc.transmission_bands(cell, crystal, cell, 1.3)
+    assert abs(got["T"] - got["n_in"]) < 1e-10 and abs(got["R"]) < 1e-10
