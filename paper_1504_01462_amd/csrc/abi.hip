@@ -1077,6 +1077,22 @@ ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void
   MS_HIP(ctx, hipSetDevice(ctx->device));
   const int n = (int)cell->n_g, m = (int)cell->n_slices - 1;   // the cell's slices 1..m, then slice 1 again
   const int64_t nn = (int64_t)n * n;
+  {   // the last slice must repeat the first: same thickness, same channel energies (to rounding)
+    std::vector<double> e1(n), e2(n), dz(m + 1);
+    MS_HIP(ctx, hipMemcpyAsync(e1.data(), cell->eps + n, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(e2.data(), cell->eps + (int64_t)(m + 1) * n, n * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(dz.data(), cell->dz, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double scale = 1.0, diff = 0.0;
+    for (int i = 0; i < n; ++i) {
+      scale = std::max(scale, std::fabs(e1[i]));
+      diff = std::max(diff, std::fabs(e1[i] - e2[i]));
+    }
+    if (dz[0] != dz[m] || !(diff <= 1e-9 * scale))
+      return fail(ctx, MS_ERR_ARG, "the cell's last slice must repeat its first (dz %g vs %g, eps differ by %g)", dz[0],
+                  dz[m], diff);
+  }
   void *seg, *whole;
   MS_TRY(workspace(ctx, WS_BSEG, (size_t)m * 4 * nn * sizeof(double2), &seg));
   MS_TRY(workspace(ctx, WS_BWHOLE, (size_t)4 * nn * sizeof(double2), &whole));

@@ -729,3 +729,8 @@ def test_bloch_pencil_argument_errors(ms, ctx):
     s = ms.prepare_from_inputs(ctx, inp)      # one slice: the repeated slice 1 is missing
     with pytest.raises(ms.MSError):
         ms.ms_bloch_pencil(ctx, s, 0.9)
+    j.dz = np.array([0.5, 0.6, 0.4])
+    inp = msgen.junction_inputs(j, (0.07, -0.11), 9)
+    s = ms.prepare_from_inputs(ctx, inp)      # three different slices: the last does not repeat the first
+    with pytest.raises(ms.MSError, match="repeat its first"):
+        ms.ms_bloch_pencil(ctx, s, 0.9)
