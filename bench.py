@@ -4,20 +4,24 @@
 Workload (default): the side-contact overlap junction -- rectangular 4.65 x 40
 bohr cell, two graphene-like Gaussian-well sheets overlapping 15 bohr along
 the transport direction, N_G = 1200 plane waves, 400 slices of 0.05 bohr,
-free-electron leads, 32 energies at each of 8 k_par for 3 vacuum gaps.  One
-step = two k_par of one gap (64 points): slice Hamiltonians, eigenpairs and
-overlaps (E-independent) of each, the fused slice-S / star-product fold of
-all 64 points in one batch, T and R per point, and the k_par average.
-Inputs are seeded and synthetic, uploaded to HBM before the timed region.
+free-electron leads, 32 energies at each of 8 k_par for 3 vacuum gaps (768
+points).  One step = two k_par of one gap (64 points): slice Hamiltonians,
+eigenpairs and overlaps (E-independent) of each, the fused slice-S /
+star-product fold of all 64 points in one batch, T and R per point, and the
+k_par average.  Successive steps walk through the 12 (gap, k_par pair) groups.
+Inputs are seeded and synthetic, generated once per distinct (gap, k_par) in
+worker processes before the GPU is touched, and resident in HBM before timing.
 
-The steps run twice, in FP64 and in the FP32-MFMA form, over the same
-(gap, k_par) pairs; the FP32 number is the headline only when its largest
-|dT| against the FP64 run stays below 1e-6.  One point of the workload is
-also solved with the paper's mixed transfer/scattering doubling, and the first
-instances of the uneven workload (N_G from 200 to 1200, 100-400 slices, one point
-each) are folded in one call, the small ones also in a captured hipGraph
-(`uneven_batch`), and the gradient dT/dV of every slice coefficient is timed at three
-energies of the adjoint workload (`adjoint`).
+Timing: min(W, 1) untimed warmup steps, then the FP64 form over K steps, or
+over as many as the wall budget `--time-budget` holds (at least one; the line
+reports the steps actually timed in `steps`).  Then the FP32-MFMA form over the
+first timed steps (`--fp32-steps`), with its largest |dT| against the FP64
+results of the same points; its number is the headline only when that stays
+below 1e-6.  Optional legs (each skipped when the process's wall budget
+`--wall-budget` would not hold it): the paper's mixed transfer/scattering
+doubling (`--mixed`), the gradient dT/dV (`--adjoint N`), uneven instances
+(`--uneven N`).  `--all-points` runs every group once in both forms (the
+|dT| chain over the whole workload) with no time budget.
 
     python bench.py [--steps K] [--warmup W] [--config config3|config2|config1]
 Prints one JSON line.
@@ -38,29 +42,40 @@ import numpy as np  # noqa: E402
 METRIC = "(E,k∥) transmission points/s at N_G=1200; FP32-MFMA vs FP64 at |ΔT|<1e-6"
 PEAK = {"fp64": 78.6, "fp32": 157.3}      # dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                          # GB/s
+T_START = time.perf_counter()
+
+
+def elapsed():
+    return time.perf_counter() - T_START
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="config3", choices=["config1", "config2", "config3"])
-    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--time-budget", type=float, default=200.0,
+                    help="seconds of the timed FP64 leg: fewer than --steps are timed when they would not fit")
+    ap.add_argument("--wall-budget", type=float, default=450.0,
+                    help="seconds from start after which optional legs are skipped")
+    ap.add_argument("--fp32-steps", type=int, default=1,
+                    help="timed steps of the FP32-MFMA form (the first timed FP64 steps' points); 0 skips it")
+    ap.add_argument("--all-points", action="store_true",
+                    help="every (gap, k_par pair) group once, in both forms, without time budget")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kpar-per-step", type=int, default=2,
                     help="k_par values of one junction folded together in one batch per step")
-    ap.add_argument("--no-next3", dest="next3", action="store_false",
-                    help="skip the timing of the mixed-recurrence doubling (ms_mixed_doubling)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="also time the paper's mixed-recurrence doubling (ms_mixed_doubling) at one point")
     ap.add_argument("--roofline-kernel", default="iface_gemm",
-                    help="profiler category reported in 'roofline' ('auto': the largest summed time in the warmup)")
+                    help="profiler category reported in 'roofline'")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default GEMM tile rule instead of timing both edges first")
-    ap.add_argument("--uneven", type=int, default=16,
-                    help="instances of the uneven workload (N_G 200-1200, 100-400 slices) folded in one "
-                         "captured graph after the main measurement; 0 skips it")
-    ap.add_argument("--adjoint", type=int, default=8,
+    ap.add_argument("--uneven", type=int, default=0,
+                    help="instances of the uneven workload (N_G 200-1200, 100-400 slices) to fold; 0 skips it")
+    ap.add_argument("--adjoint", type=int, default=0,
                     help="energies of the adjoint workload (dT/dV at N_G = 1200) to time; 0 skips it")
     ap.add_argument("--overlap", action="store_true",
                     help="prepare the next step's slices on a second stream while the current step folds")
@@ -68,10 +83,12 @@ def parse():
                     help="measure only the uneven workload (--uneven instances) and print its JSON line")
     ap.add_argument("--no-event-profile", action="store_true",
                     help="record no HIP events around launches (no roofline figure; for external profilers)")
+    ap.add_argument("--workers", type=int, default=16, help="processes generating the seeded inputs")
     return ap.parse_args()
 
 
 def workload(name):
+    """(groups of (key, [k_par indices]) in step order, junction factory, description)."""
     import msgen
     if name == "config3":
         combos = [(gap, ik) for gap in (6.3, 5.0, 7.5) for ik in range(8)]
@@ -89,15 +106,49 @@ def workload(name):
     return combos, make, desc
 
 
+def step_groups(combos, kps):
+    groups = []
+    for key, ik in combos:
+        if groups and groups[-1][0] == key and len(groups[-1][1]) < kps:
+            groups[-1][1].append(ik)
+        else:
+            groups.append((key, [ik]))
+    return groups
+
+
+def host_inputs_of(task):
+    """Seeded inputs of one (config, key, k_par index) as host arrays (no GPU)."""
+    name, key, ik = task
+    _, make, _ = workload(name)
+    import msgen
+    j = make(key)
+    inp = msgen.junction_inputs(j, j.kpars[ik])
+    return dict(miller=np.ascontiguousarray(inp["miller"], dtype=np.int32),
+                q=np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), vq=np.ascontiguousarray(inp["vq"]),
+                dz=np.ascontiguousarray(inp["dz"]), bvec=np.asarray(inp["bvec"]).reshape(4),
+                kpar=np.asarray(inp["kpar"]))
+
+
+def adjoint_energy_indices(n_total, n_e):
+    """n_e distinct energy indices spread evenly over [0, n_total) (all of them when n_e >= n_total)."""
+    n_e = max(1, min(n_e, n_total))
+    if n_e == 1:
+        return np.array([n_total // 2])
+    return np.round(np.linspace(0, n_total - 1, n_e)).astype(int)
+
+
 def cpu_baseline(name, budget_s):
-    """The oracle, untuned, on a bounded sample of one point of the workload."""
+    """The oracle, untuned, on a bounded sample of one point of the workload: consecutive slice
+    eigenproblems (about a third of the budget) and the interface S-matrices + star products of
+    the chain they form (the rest), scaled to one point."""
     import msgen
     import oracle as orc
+    blas_threads = None
     try:
         from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
     combos, make, _ = workload(name)
     j = make(combos[0][0])
     inp = msgen.junction_inputs(j, j.kpars[combos[0][1]])
@@ -107,7 +158,7 @@ def cpu_baseline(name, budget_s):
     t0 = time.perf_counter()
     n_eig = 0
     us = []
-    while n_eig < 3 and (n_eig == 0 or time.perf_counter() - t0 < 0.35 * budget_s):
+    while n_eig < ns and (n_eig < 2 or time.perf_counter() - t0 < 0.33 * budget_s):
         h = orc.slice_hamiltonians(kin, inp["vq"][n_eig:n_eig + 1], inp["q_of_ij"])
         eps, u = orc.slice_eigen(h)
         us.append((eps[0], u[0]))
@@ -116,7 +167,7 @@ def cpu_baseline(name, budget_s):
     t1 = time.perf_counter()
     acc = orc.identity_smatrix(len(kin))
     n_if = 0
-    while n_if < len(us) - 1 and (n_if == 0 or time.perf_counter() - t1 < 0.6 * budget_s):
+    while n_if < len(us) - 1 and (n_if == 0 or time.perf_counter() - t1 < 0.67 * budget_s):
         o = orc.overlap(us[n_if][1], us[n_if + 1][1])
         s = orc.interface_smatrix(o, orc.wavevectors(e, us[n_if][0]), orc.wavevectors(e, us[n_if + 1][0]),
                                   float(inp["dz"][n_if]))
@@ -125,18 +176,22 @@ def cpu_baseline(name, budget_s):
     t_if = (time.perf_counter() - t1) / max(1, n_if)
     # one point = its share of the E-independent eigenproblems + (n_slices + 1) interfaces
     t_point = t_eig * ns / len(j.energies) + t_if * (ns + 1)
-    return {"value": 1.0 / t_point, "unit": "points/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"{name} first (gap/registry, k_par), E={e:.4f} Ry: {n_eig} slice eigenproblems "
-                       f"({t_eig:.2f} s each) and {n_if} interface S-matrix + star products ({t_if:.2f} s each), "
-                       f"scaled to one point = eigen share over {len(j.energies)} energies + {ns + 1} interfaces; "
-                       "extrapolated, not a full point")}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except Exception:
+        affinity = None
+    return {"value": 1.0 / t_point, "unit": "points/s", "cores": int(blas_threads or affinity or os.cpu_count() or 1),
+            "kind": "oracle", "blas_threads": blas_threads, "host_cpus": os.cpu_count(), "affinity_cpus": affinity,
+            "sample": (f"{name} first (gap/registry, k_par), E={e:.4f} Ry: {n_eig} consecutive slice eigenproblems "
+                       f"({t_eig:.2f} s each) and the {n_if} interface S-matrices + star products between them "
+                       f"({t_if:.2f} s each), scaled to one point = eigen share over {len(j.energies)} energies + "
+                       f"{ns + 1} interfaces (extrapolated from the sample, not a full point)")}
 
 
 def measured_traffic(cat, flops_per_launch, form, tile=128):
     """HBM bytes per launch of the roofline kernel from the committed rocprofv3 counter
     summary, or None when it covers another kernel, tile shape, launch shape or form, or
     when the kernel source has changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{cat}_config3_counters.txt")
     if form != "fp64" or not os.path.exists(path):
         return None
@@ -375,7 +430,7 @@ def adjoint_measure(ms, ctx, n_e, log, fd_slices=(37, 200, 371)):
     s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
     torch.cuda.synchronize()
     prep_s = time.perf_counter() - t0
-    idx = np.linspace(0, len(j.energies) - 1, n_e + 2)[1:-1].round().astype(int)
+    idx = adjoint_energy_indices(len(j.energies), n_e)
     es = [float(j.energies[i]) for i in idx]
     free_gb = torch.cuda.mem_get_info(dev)[0] / 1e9
     log(f"adjoint: {free_gb:.0f} GB of device memory free before the call")
@@ -430,62 +485,62 @@ def main():
               "communication between GPUs, so it has no multi-GPU step to time; run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
-    host_inputs = None
+
+    def log(msg):
+        print(f"[bench {elapsed():6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+    # ---- seeded inputs, generated in worker processes before this process loads the GPU
+    # library or touches the GPU (the pool and its workers are gone before that)
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(args.workers, os.cpu_count() or 1))
+    uneven_host = None
     if args.uneven_only:
-        # generate the seeded inputs in worker processes, before this process loads the GPU
-        # library or touches the GPU; the pool and its workers are gone before that
-        from concurrent.futures import ProcessPoolExecutor
-        t0 = time.perf_counter()
-        with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
-            host_inputs = list(pool.map(uneven_inputs, range(max(1, args.uneven)), chunksize=4))
-        print(f"[bench] uneven inputs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        import msgen  # noqa: F401
+        with ProcessPoolExecutor(max_workers=workers) as pool:
+            uneven_host = list(pool.map(uneven_inputs, range(max(1, args.uneven)), chunksize=4))
+        log(f"uneven inputs generated ({len(uneven_host)} instances)")
+    combos, make, desc = workload(args.config)
+    kps = max(1, args.kpar_per_step)
+    groups = step_groups(combos, kps)
+    warm = min(max(0, args.warmup), 1)
+    if args.all_points:
+        plan = groups[:]                              # every group once, all timed
+        warm = 0
+    else:
+        nmax = max(1, args.steps)
+        plan = [groups[i % len(groups)] for i in range(warm + nmax)]
+    host = {}
+    if not args.uneven_only:
+        tasks = sorted({(args.config, key, ik) for key, iks in plan for ik in iks}, key=str)
+        with ProcessPoolExecutor(max_workers=min(workers, len(tasks))) as pool:
+            for t, h in zip(tasks, pool.map(host_inputs_of, tasks)):
+                host[(t[1], t[2])] = h
+        log(f"inputs generated: {len(tasks)} distinct (key, k_par) of {args.config} in {workers} processes")
+
     import torch
-    import msgen
     import paper_1504_01462_amd as ms
 
     if args.uneven_only:
         n_u = max(1, args.uneven)
         ctx = ms.Context(0)
-        u = uneven_measure(ms, ctx, n_u, lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True),
-                           host_inputs=host_inputs)
+        u = uneven_measure(ms, ctx, n_u, log, host_inputs=uneven_host)
         ctx.close()
         print(json.dumps({"uneven_batch": u, "n_gpus": 1, "data": "synthetic"}), flush=True)
         return
-    combos, make, desc = workload(args.config)
-    # a step takes kps consecutive k_par of one junction (one batch of kps x n_e points)
-    kps = max(1, args.kpar_per_step)
-    groups = []
-    for key, ik in combos:
-        if groups and groups[-1][0] == key and len(groups[-1][1]) < kps:
-            groups[-1][1].append(ik)
-        else:
-            groups.append((key, [ik]))
-    nsteps = args.warmup + args.steps
-    sel = [groups[i % len(groups)] for i in range(nsteps)]
+
     ctx = ms.Context(0)
     dev = ctx.device
-    # seeded inputs, uploaded to HBM before timing
-    cache = {}
-    staged = []
-    for key, iks in sel:
-        if key not in cache:
-            cache[key] = make(key)
-        j = cache[key]
-        ks = []
-        for ik in iks:
-            inp = msgen.junction_inputs(j, j.kpars[ik])
-            ks.append(dict(
-                ik=ik,
-                miller=torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev),
-                q=torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev),
-                vq=torch.as_tensor(np.ascontiguousarray(inp["vq"]), device=dev),
-                dz=torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev),
-                bvec=np.asarray(inp["bvec"]).reshape(4), kpar=np.asarray(inp["kpar"])))
-        staged.append(dict(j=j, key=key, iks=list(iks), ks=ks))
+    juncs = {}
+    dev_in = {}
+    for (key, ik), h in host.items():      # resident in HBM before any timing
+        if key not in juncs:
+            juncs[key] = make(key)
+        dev_in[(key, ik)] = dict(h, miller=torch.as_tensor(h["miller"], device=dev),
+                                 q=torch.as_tensor(h["q"], device=dev), vq=torch.as_tensor(h["vq"], device=dev),
+                                 dz=torch.as_tensor(h["dz"], device=dev))
+    staged = [dict(j=juncs[key], key=key, iks=list(iks), ks=[dev_in[(key, ik)] for ik in iks]) for key, iks in plan]
     j0 = staged[0]["j"]
     n_e, n_k = len(j0.energies), len(j0.kpars)
-    # two sets of slice buffers: with --overlap the next step's slices are prepared into one set
-    # (on a second context and stream) while the current step folds the other
     bufsets = [[ms.Slices.empty(j0.n_g, j0.n_slices, staged[0]["ks"][0]["dz"], dev) for _ in range(kps)]
                for _ in range(2 if args.overlap else 1)]
     bufs = bufsets[0]
@@ -494,21 +549,19 @@ def main():
     t_store = torch.zeros((n_k, n_e), dtype=torch.float64, device=dev)
     no_store = torch.zeros((n_k, n_e), dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
+    log(f"inputs resident: {len(staged)} planned steps of {args.config}, {kps} k_par per step")
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    log(f"inputs staged: {len(staged)} steps of {args.config}, {kps} k_par per step")
     tuned_main = None
     if args.autotune:   # GEMM tile edges for this basis size and batch (never changes a result)
         t0 = time.perf_counter()
         choice, times = ms.ms_autotune(ctx, j0.n_g, min(j0.n_g, 13), kps * n_e)
         tuned_main = dict(seconds=round(time.perf_counter() - t0, 3), choice=choice,
                           lu_ms=[round(v, 3) for v in times[:4]], iface_ms=[round(v, 3) for v in times[4:]])
-        log(f"autotune n_g={j0.n_g}, batch {kps * n_e}: {choice} (LU ms {tuned_main['lu_ms']}, "
-            f"interface ms {tuned_main['iface_ms']})")
+        log(f"autotune n_g={j0.n_g}, batch {kps * n_e}: {choice}")
 
-    def fold(i, st, prec, bset, outs):
+    main_stream = torch.cuda.current_stream(dev)
+
+    def fold(st, prec, bset, outs, evs):
         m = len(st["ks"])
         es = np.tile(np.asarray(st["j"].energies, dtype=np.float64), (m, 1))
         T, R, no, status = ms.ms_transmission_multi(ctx, bset[:m], es, prec)
@@ -516,29 +569,34 @@ def main():
             t_store[ik].copy_(T[r])
             no_store[ik].copy_(no[r])
         ms.ms_kpar_average(ctx, t_store, no_store)
+        if evs is not None:
+            evs.append(torch.cuda.Event(enable_timing=True))
+            evs[-1].record(main_stream)
         outs.append((T.reshape(-1), R.reshape(-1), no.reshape(-1), status.reshape(-1)))
 
-    def run(steps, prec):
+    def run(steps, prec, label):
         """One step: the slice eigenproblems and overlaps of each of its k_par, the fused fold
         over all their energies in one batch, T and R, the k_par average.  Without --overlap all
-        on the current stream, one after the other; with it, step i+1's slices are prepared on a
-        second context and stream (enqueued by a worker thread, since the preparation's host
-        steps wait for its stream) while step i folds, ordered by events: a fold waits for its
-        slices, a preparation for the fold that last read its buffer set."""
-        outs = []
+        on the current stream, one after the other, with stream events between preparation and
+        fold (the E-independent share of each step); with it, step i+1's slices are prepared on a
+        second context and stream while step i folds, ordered by events."""
+        outs, evs = [], []
         if not args.overlap:
+            evs.append(torch.cuda.Event(enable_timing=True))
+            evs[-1].record(main_stream)
             for i, st in enumerate(steps):
                 for b, kk in zip(bufs, st["ks"]):
                     ms.ms_slices_prepare(ctx, kk["miller"], kk["bvec"], kk["kpar"], kk["q"], kk["vq"], kk["dz"],
                                          out=b)
-                fold(i, st, prec, bufs, outs)
-                log(f"{prec} step {i + 1}/{len(steps)} enqueued")
-            return outs
-        main = torch.cuda.current_stream(dev)
+                evs.append(torch.cuda.Event(enable_timing=True))
+                evs[-1].record(main_stream)
+                fold(st, prec, bufs, outs, evs)
+                log(f"{label} step {i + 1}/{len(steps)} enqueued")
+            return outs, evs
         ev_prep = [torch.cuda.Event() for _ in steps]
         ev_fold = [torch.cuda.Event() for _ in steps]
         start = torch.cuda.Event()
-        start.record(main)
+        start.record(main_stream)
 
         def prep(i):
             with torch.cuda.stream(sp):
@@ -554,68 +612,89 @@ def main():
                 fut.result()
                 if i + 1 < len(steps):
                     fut = pool.submit(prep, i + 1)
-                main.wait_event(ev_prep[i])
-                fold(i, st, prec, bufsets[i % 2], outs)
-                ev_fold[i].record(main)
-                log(f"{prec} step {i + 1}/{len(steps)} enqueued")
+                main_stream.wait_event(ev_prep[i])
+                fold(st, prec, bufsets[i % 2], outs, None)
+                ev_fold[i].record(main_stream)
+                log(f"{label} step {i + 1}/{len(steps)} enqueued")
             fut.result()
-        return outs
+        return outs, None
 
-    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    results = {}
-    prof_pick = None
+    def collect(outs):
+        return tuple(np.concatenate([o[i].cpu().numpy() for o in outs]) for i in range(4))
+
     evp = not args.no_event_profile
-    for prec in forms:
-        # warmup (the first form's warmup also picks the dominant kernel)
-        ms.ms_debug_profile(ctx, evp)
-        tw = time.perf_counter()
-        run(staged[:args.warmup], prec)
+    cat = args.roofline_kernel
+    results = {}
+    # ---- FP64: warmup, then the timed steps (as many as the time budget holds)
+    tw = time.perf_counter()
+    if warm:
+        run(staged[:warm], "fp64", "fp64 warmup")
         ctx.sync()
-        log(f"{prec} warmup ({args.warmup} steps): {time.perf_counter() - tw:.2f} s")
-        prof = {c: ms.ms_debug_profile_read(ctx, c) for c in ms.PROFILE_CATEGORIES}
-        if prof_pick is None:
-            prof_pick = args.roofline_kernel
-            if prof_pick == "auto":
-                prof_pick = max(prof, key=lambda c: prof[c][0]) if evp and args.warmup > 0 else "iface_gemm"
-        ms.ms_debug_profile(ctx, [prof_pick] if evp else False)
+    t_warm = time.perf_counter() - tw
+    pool_steps = staged[warm:]
+    if args.all_points or not warm:
+        n_timed = len(pool_steps)
+    else:
+        n_timed = max(1, min(len(pool_steps), int(args.time_budget // max(t_warm, 1e-3))))
+    timed_steps = pool_steps[:n_timed]
+    log(f"fp64 warmup: {warm} step(s) in {t_warm:.2f} s; timing {n_timed} of {args.steps} requested steps")
+    forms = ["fp64"]
+    if args.fp32_steps > 0:
+        forms.append("fp32")
+    for prec in forms:
+        steps = timed_steps if prec == "fp64" or args.all_points else timed_steps[:max(1, args.fp32_steps)]
+        if prec == "fp32" and not args.all_points:
+            est = t_warm * len(steps)
+            if elapsed() + est > args.wall_budget:
+                log(f"fp32 leg skipped: {est:.0f} s would pass the wall budget")
+                continue
+        ms.ms_debug_profile(ctx, [cat] if evp else False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs = run(staged[args.warmup:], prec)
+        outs, evs = run(steps, prec, prec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ctx.sync()
-        log(f"{prec}: {args.steps} timed steps in {dt:.2f} s")
-        timed = {c: ms.ms_debug_profile_read(ctx, c) for c in ms.PROFILE_CATEGORIES}
+        log(f"{prec}: {len(steps)} timed steps in {dt:.2f} s")
+        prof = ms.ms_debug_profile_read(ctx, cat)
         ms.ms_debug_profile(ctx, False)
-        T = np.concatenate([o[0].cpu().numpy() for o in outs])
-        R = np.concatenate([o[1].cpu().numpy() for o in outs])
-        NO = np.concatenate([o[2].cpu().numpy() for o in outs])
-        ST = np.concatenate([o[3].cpu().numpy() for o in outs])
-        results[prec] = dict(seconds=dt, points=int(T.size), T=T, R=R, NO=NO, ST=ST, prof=timed,
-                             warm_prof=prof)
+        T, R, NO, ST = collect(outs)
+        prep_s = fold_s = None
+        if evs is not None:       # stream events: [start, after prep 1, after fold 1, after prep 2, ...]
+            ms_t = [evs[i].elapsed_time(evs[i + 1]) / 1e3 for i in range(len(evs) - 1)]
+            prep_s, fold_s = float(sum(ms_t[0::2])), float(sum(ms_t[1::2]))
+        results[prec] = dict(seconds=dt, steps=len(steps), points=int(T.size), T=T, R=R, NO=NO, ST=ST, prof=prof,
+                             prep_s=prep_s, fold_s=fold_s)
 
-    base = results[forms[0]]
+    base = results["fp64"]
     out_forms = {}
     for prec, r in results.items():
-        d = dict(points_per_s=r["points"] / r["seconds"], ms_per_step=1e3 * r["seconds"] / args.steps,
+        d = dict(points_per_s=r["points"] / r["seconds"], steps=r["steps"], points=r["points"],
+                 ms_per_step=1e3 * r["seconds"] / r["steps"],
                  max_abs_R_plus_T_minus_Nopen=float(np.max(np.abs(r["T"] + r["R"] - r["NO"]))),
                  bad_points=int(np.sum(r["ST"] != 0)),
                  T_sha1=hashlib.sha1(np.ascontiguousarray(r["T"]).tobytes()).hexdigest()[:16])
-        if prec != forms[0]:
-            d["max_abs_dT_vs_" + forms[0]] = float(np.max(np.abs(r["T"] - base["T"])))
-        d["warmup_kernel_ms_per_step"] = {c: round(v[0] / max(1, args.warmup), 3)
-                                          for c, v in r["warm_prof"].items() if v[1]}
-        d["warmup_kernel_launches_per_step"] = {c: int(v[1] / max(1, args.warmup))
-                                                for c, v in r["warm_prof"].items() if v[1]}
+        if r["fold_s"]:
+            d["per_point_work"] = {
+                "points_per_s": r["points"] / r["fold_s"],
+                "fold_s": round(r["fold_s"], 3), "prepare_s": round(r["prep_s"], 3),
+                "note": "(i) the fold alone (a4-a6, k_par average) from stream events between each step's "
+                        "slice preparation (a1-a3) and its fold; `points_per_s` of the form is (ii), end to end"}
+        if prec != "fp64":
+            m = r["points"]
+            dT = np.abs(r["T"] - base["T"][:m])
+            d["max_abs_dT_vs_fp64"] = float(np.max(dT))
+            d["abs_dT_vs_fp64_quantiles"] = {q: float(f"{np.quantile(dT, float(q)):.3g}")
+                                             for q in ("0.5", "0.9", "0.99", "1.0")}
+            d["points_compared"] = m
         out_forms[prec] = d
 
-    head = forms[0]
-    if "fp32" in results and "fp64" in results and \
-            out_forms["fp32"].get("max_abs_dT_vs_fp64", 1.0) < 1e-6 and out_forms["fp32"]["bad_points"] == 0:
+    head = "fp64"
+    f32 = out_forms.get("fp32")
+    if f32 and f32["max_abs_dT_vs_fp64"] < 1e-6 and f32["bad_points"] == 0:
         head = "fp32"
     hr = results[head]
-    cat = prof_pick
-    tot_ms, launches, flops, nbytes = hr["prof"][cat]
+    tot_ms, launches, flops, nbytes = hr["prof"]
     avg_s = tot_ms / 1e3 / max(1, launches) or float("inf")
     fl_per = flops / max(1, launches)
     by_per = nbytes / max(1, launches)
@@ -631,18 +710,21 @@ def main():
     roof["kernel"] = cat
     if cat == "iface_gemm":
         roof["tile"] = f"{iface_tile}x{iface_tile}"
+        roof["algorithmic_flop_per_launch"] = fl_per
+        roof["algorithmic_bytes_per_launch"] = by_per
     roof["avg_launch_ms"] = avg_s * 1e3
     roof["launches"] = launches
     roof["note"] = ("per-launch durations from HIP events that bracket the kernel's own execution "
-                    "(hipExtLaunchKernel) on the stream it is launched on; the interface GEMM runs alone on the GPU")
+                    "(hipExtLaunchKernel) on the stream it is launched on, over the timed region of the "
+                    "headline form; the interface GEMM runs alone on the GPU")
 
     line = {
         "metric": METRIC,
         "value": out_forms[head]["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": results[head]["steps"],
+        "warmup": warm,
         "ms_per_step": out_forms[head]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -650,34 +732,47 @@ def main():
         "dtype": "c64-mfma+f64" if head == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {desc}", "n_g": j0.n_g, "n_slices": j0.n_slices,
-                   "energies_per_kpar": n_e, "kpar_per_step": kps, "prepare_overlapped": bool(args.overlap),
-                   "steps_over": [[str(st["key"]), st["iks"]] for st in staged],
+                   "energies_per_kpar": n_e, "kpar_per_step": kps, "points_per_step": kps * n_e,
+                   "prepare_overlapped": bool(args.overlap),
+                   "steps_requested": args.steps, "warmup_requested": args.warmup,
+                   "time_budget_s": None if args.all_points else args.time_budget,
+                   "steps_over": [[str(st["key"]), st["iks"]] for st in timed_steps],
                    "headline_form": head},
         "forms": out_forms,
         "roofline": roof,
         "autotune": tuned_main,
     }
-    if args.next3 and args.config == "config3":
-        line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, staged[args.warmup], bufs[0], results, log)
     if ctx_p is not None:
         ctx_p.close()                       # the preparation context's workspace
+    if args.mixed and args.config == "config3":
+        if elapsed() + 60 < args.wall_budget:
+            line["mixed_doubling"] = mixed_doubling_measure(ms, ctx, timed_steps[0], bufs[0], results, log)
+        else:
+            log("mixed doubling skipped (wall budget)")
     if args.adjoint > 0 and args.config == "config3":
-        for bs in bufsets:
-            bs.clear()
-        torch.cuda.empty_cache()
-        actx = ms.Context(0)                # its own context: the gradient's workspace is freed after
-        line["adjoint"] = adjoint_measure(ms, actx, args.adjoint, log)
-        actx.close()
-        torch.cuda.empty_cache()
+        if elapsed() + 30 + 8 * args.adjoint < args.wall_budget:
+            for bs in bufsets:
+                bs.clear()
+            torch.cuda.empty_cache()
+            actx = ms.Context(0)            # its own context: the gradient's workspace is freed after
+            line["adjoint"] = adjoint_measure(ms, actx, args.adjoint, log)
+            actx.close()
+            torch.cuda.empty_cache()
+        else:
+            log("adjoint leg skipped (wall budget)")
     if args.uneven > 0:
-        for bs in bufsets:                  # the main workload's slice buffers
-            bs.clear()
-        torch.cuda.empty_cache()
-        line["uneven_batch"] = uneven_measure(ms, ctx, args.uneven, log)
+        if elapsed() + 2.5 * args.uneven < args.wall_budget:
+            for bs in bufsets:
+                bs.clear()
+            torch.cuda.empty_cache()
+            line["uneven_batch"] = uneven_measure(ms, ctx, args.uneven, log)
+        else:
+            log("uneven leg skipped (wall budget)")
+    ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds)
-    ctx.close()
+    line["wall_s"] = round(elapsed(), 1)
     print(json.dumps(line), flush=True)
 
 

@@ -141,9 +141,13 @@ ms_status ms_slice_smatrix(ms_ctx ctx, const ms_slices* slices, double energy, i
  *   S11 = S11(b) F^-1 S11(a)             S12 = S12(b) + S11(b) F^-1 S12(a) S22(b)
  *   S21 = S21(a) + S22(a) S21(b) F^-1 S11(a)
  *   S22 = S22(a) S22(b) + S22(a) S21(b) F^-1 S12(a) S22(b)
- * The inputs are not modified; `whole` must not alias them.  prec must be
- * MS_PREC_FP64 (others return MS_ERR_UNSUPPORTED).
- * Errors: MS_ERR_ARG; MS_ERR_SINGULAR via ms_ctx_sync when F has a zero pivot. */
+ * The inputs are not modified; `whole` must not alias them.  The blocks are c128 in both
+ * forms.  prec = MS_PREC_FP64: every step in FP64.  prec = MS_PREC_FP32_MFMA: F = I - S12(a)
+ * S21(b), its LU factorisation and the solves with it stay FP64; the six products that
+ * follow (S22(a) S21(b), S11(b) W1, ..., their sums) run on FP32 MFMA with FP32 accumulation,
+ * their operands rounded to c64 (relative error of the result a few 1e-7 per product).
+ * Errors: MS_ERR_ARG (sizes, nulls, aliasing, unknown prec); MS_ERR_SINGULAR via ms_ctx_sync
+ * when F has a zero pivot. */
 ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n, ms_prec prec, ms_smat* whole);
 
 /* a6: T, R and the open-channel count of the whole junction for waves
@@ -315,15 +319,16 @@ ms_status ms_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T,
  * B^{M+1} = lam B^1 (lam = e^{ikd}) through the cell's S-matrix S = S(1, M+1), with the cell's
  * incoming amplitudes X = [A^1; B^{M+1}] as unknowns, give P X = lam Q X with
  *   P = [[S11, S12], [0, I]],  Q = [[I, 0], [S21, S22]]   (2 n_g x 2 n_g).
- *   cell    prepared (ms_slices_prepare) from the cell's slices 1..M followed by slice 1 again
- *           (its potential row and thickness repeated: slice M+1 is the next cell's slice 1),
- *           so n_slices = M + 1 >= 2; the lead entries are unused.  Checked: the last slice's
- *           thickness and channel energies (to 1e-9 relative) equal the first's
+ *   cell    the cell's slices 1..M (n_slices = M >= 1), prepared by ms_slices_prepare WITH
+ *           the eigenvectors (cell->evec); the lead entries are unused.  Slice M+1 is the next
+ *           cell's slice 1: the last interface S(M, M+1) uses O = U^M^dagger U^1 of the cell's
+ *           own eigenvectors, dz_1 and slice 1's channel energies, so both Bloch planes are
+ *           reference planes of one and the same slice-1 eigenbasis
  *   P, Q    [2 n_g][2 n_g] c128 (device outputs, row-major, distinct)
- * The pencil's eigenvalues lam and eigenvectors (A^1 in the slice-1 eigenbasis, B^{M+1} in
- * that of the repeated slice) are the electrode's Bloch states; solving it is not part of the
- * library yet.  Errors: MS_ERR_ARG, MS_ERR_UNSUPPORTED, MS_ERR_ALLOC; singular X via
- * ms_ctx_sync. */
+ * The pencil's eigenvalues lam and eigenvectors (A^1 and B^{M+1} both in slice 1's
+ * eigenbasis) are the electrode's Bloch states; solving it is not part of the library yet.
+ * Errors: MS_ERR_ARG (no eigenvectors, nulls, non-finite energy), MS_ERR_UNSUPPORTED,
+ * MS_ERR_ALLOC; singular X or F via ms_ctx_sync. */
 ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void* P, void* Q);
 
 #ifdef __cplusplus

@@ -30,6 +30,17 @@ ms_status ms_debug_gemm_batched(ms_ctx ctx, int op_a, int op_b, int64_t m, int64
                                 int64_t ldc, int64_t s_c, int64_t batch, const double* alpha, const double* beta,
                                 ms_prec prec);
 
+/* The fused fold's interface product for `batch` energies sharing one overlap O:
+ *   W[b] = A[b] [C-_b | C+_b with its diagonal set to 0],
+ *   C-_b[m][j] = O[j][m] (kp_b[j] - kq_b[m]),  C+_b[m][j] = O[j][m] (kp_b[j] + kq_b[m])
+ * (O^T K_p -+ K_q O^T, the operands of Phi_A and Phi_B in the star product of a slice
+ * interface with the accumulated right part).  A [batch][n][n] (complex128, or complex64
+ * with prec = MS_PREC_FP32_MFMA), O [n][n] complex128, kp, kq [batch][n] complex128 (entry b
+ * at kp + b n), W [batch][n][2n] complex128.  The B operand is generated in FP64 from O, kp,
+ * kq while it is staged and rounded to the product's type. */
+ms_status ms_debug_iface_product(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* o,
+                                 const void* kp, const void* kq, void* w, ms_prec prec);
+
 /* For each of `batch` row-major n x (n + nrhs) complex128 matrices [A | B]
  * (batch stride n*(n+nrhs)), factor A with partial pivoting (in place) and
  * write X = A^-1 B to x (n x nrhs per matrix, batch stride n*nrhs).

@@ -79,6 +79,7 @@ _sig("ms_debug_profile_read", [_vp, ctypes.c_char_p, _vp, _vp, _vp, _vp])
 _sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i32])
 _sig("ms_debug_gemm_batched", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
                                 _i64, _i64, _vp, _vp, _i32])
+_sig("ms_debug_iface_product", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32])
 _sig("ms_debug_lu_solve", [_vp, _i64, _i64, _i64, _vp, _vp, _vp])
 _sig("ms_debug_eigh", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 
@@ -205,13 +206,13 @@ def ms_star_cascade(ctx: Context, smats, prec="fp64"):
     arr = (MsSmat * len(smats))(*[_smat(s) for s in smats])
     whole = tuple(torch.empty((n, n), dtype=torch.complex128, device=ctx.device) for _ in range(4))
     w = _smat(whole)
-    _check(ctx.handle, lib.ms_star_cascade(ctx.handle, arr, len(smats), _PREC[prec], ctypes.byref(w)))
+    _check(ctx.handle, lib.ms_star_cascade(ctx.handle, arr, len(smats), _PREC.get(prec, prec), ctypes.byref(w)))
     return whole
 
 
 def ms_bloch_pencil(ctx: Context, cell: Slices, energy: float):
     """P, Q [2n][2n] complex128 of an electrode cell's Bloch eigenproblem P X = lam Q X; `cell`
-    holds the cell's slices 1..M followed by slice 1 again."""
+    holds the cell's slices 1..M, prepared with their eigenvectors (with_evec=True)."""
     m = 2 * cell.n_g
     P = torch.empty((m, m), dtype=torch.complex128, device=ctx.device)
     Q = torch.empty((m, m), dtype=torch.complex128, device=ctx.device)
@@ -437,6 +438,19 @@ def ms_debug_gemm_batched(ctx: Context, a: torch.Tensor, b: torch.Tensor, c: tor
     return c
 
 
+def ms_debug_iface_product(ctx: Context, a: torch.Tensor, o: torch.Tensor, kp: torch.Tensor, kq: torch.Tensor,
+                           prec="fp64"):
+    """W [batch][n][2n] = A [C- | C+ off its diagonal] with C-+[m][j] = O[j][m] (kp[j] -+ kq[m]):
+    a [batch][n][n] (complex128, complex64 for fp32), o [n][n], kp, kq [batch][n] complex128."""
+    batch, n, _ = a.shape
+    dt = torch.complex128 if _PREC[prec] == MS_PREC_FP64 else torch.complex64
+    w = torch.empty((batch, n, 2 * n), dtype=torch.complex128, device=ctx.device)
+    _check(ctx.handle, lib.ms_debug_iface_product(ctx.handle, n, batch, _ptr(a, dt, "a"),
+                                                  _ptr(o, torch.complex128, "o"), _ptr(kp, torch.complex128, "kp"),
+                                                  _ptr(kq, torch.complex128, "kq"), _ptr(w), _PREC[prec]))
+    return w
+
+
 def ms_debug_lu_solve(ctx: Context, aug: torch.Tensor, n: int):
     batch, rows, cols = aug.shape
     nrhs = cols - n
@@ -472,5 +486,6 @@ __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "
            "ms_transmission",
            "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
-           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_lu_solve", "ms_debug_eigh",
+           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_lu_solve",
+           "ms_debug_eigh",
            "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

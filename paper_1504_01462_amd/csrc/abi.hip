@@ -151,7 +151,9 @@ enum {
   WS_GSEG, WS_GCK, WS_GRS, WS_GL, WS_GK, WS_GP, WS_GCH, WS_GOS, WS_GX, WS_GFA, WS_GFB, WS_GAUG, WS_GY,
   WS_GT1, WS_GBP, WS_GBF, WS_GP1, WS_GP2, WS_GMC, WS_GYG, WS_GKC, WS_GPIV, WS_GEN, WS_GA2, WS_GB2,
   // electrode cells
-  WS_BSEG, WS_BWHOLE
+  WS_BSEG, WS_BWHOLE, WS_BEPS, WS_BOVL,
+  // complex64 operands of the FP32 form of the star product
+  WS_S32A, WS_S32B
 };
 
 constexpr int MAX_N = 4096;
@@ -522,8 +524,31 @@ struct Blocks {
   double2 *t, *rp, *r, *tp;
 };
 
-// out = a * b (Redheffer star product); out must not alias a or b.
-ms_status star(ms_ctx ctx, int n, Blocks a, Blocks b, Blocks out) {
+// C = alpha A B + beta C for n x n operands A (lda), B (ldb), C (ldc); with fp32 the operands are
+// rounded to complex64 and multiplied on FP32 MFMA with FP32 accumulation (alpha, beta and C
+// stay FP64)
+ms_status gemm_form(ms_ctx ctx, bool fp32, int n, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                    int64_t ldc, double2 alpha, double2 beta) {
+  if (!fp32) return gemm(ctx, n, n, n, A, lda, OP_N, B, ldb, OP_N, C, ldc, alpha, beta);
+  const int64_t ca = (int64_t)(n - 1) * lda + n, cb = (int64_t)(n - 1) * ldb + n;   // elements spanned
+  void *a32, *b32;
+  MS_TRY(workspace(ctx, WS_S32A, (size_t)ca * sizeof(float2), &a32));
+  MS_TRY(workspace(ctx, WS_S32B, (size_t)cb * sizeof(float2), &b32));
+  MS_TRY(launch_to_c64(ctx, ca, c2(A), static_cast<float2*>(a32)));
+  MS_TRY(launch_to_c64(ctx, cb, c2(B), static_cast<float2*>(b32)));
+  GemmArgs g;
+  g.M = n; g.N = n; g.K = n;
+  g.A = a32; g.lda = lda;
+  g.B = b32; g.ldb = ldb;
+  g.C = c2(C); g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  return cgemm32(ctx, g);
+}
+
+// out = a * b (Redheffer star product); out must not alias a or b.  F = I - rp_a r_b, its LU
+// and the solves with it are FP64 in both forms; with fp32 the six products that follow run on
+// FP32 MFMA.
+ms_status star(ms_ctx ctx, int n, Blocks a, Blocks b, Blocks out, bool fp32 = false) {
   const int64_t nn = (int64_t)n * n;
   void *aug, *z, *g, *h, *v, *piv;
   MS_TRY(workspace(ctx, WS_AUG, 3 * nn * sizeof(double2), &aug));
@@ -542,20 +567,20 @@ ms_status star(ms_ctx ctx, int n, Blocks a, Blocks b, Blocks out) {
   const double2* w1 = c2(z);
   const double2* w2 = c2(z) + n;
   // G = tp_a r_b
-  MS_TRY(gemm(ctx, n, n, n, a.tp, n, OP_N, b.r, n, OP_N, g, n, ONE, ZERO));
+  MS_TRY(gemm_form(ctx, fp32, n, a.tp, n, b.r, n, g, n, ONE, ZERO));
   // t = t_b W1
-  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, w1, 2 * n, OP_N, out.t, n, ONE, ZERO));
+  MS_TRY(gemm_form(ctx, fp32, n, b.t, n, w1, 2 * n, out.t, n, ONE, ZERO));
   // r = r_a + G W1
   MS_HIP(ctx, hipMemcpyAsync(out.r, a.r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(gemm(ctx, n, n, n, g, n, OP_N, w1, 2 * n, OP_N, out.r, n, ONE, ONE));
+  MS_TRY(gemm_form(ctx, fp32, n, g, n, w1, 2 * n, out.r, n, ONE, ONE));
   // rp = rp_b + (t_b W2) tp_b
-  MS_TRY(gemm(ctx, n, n, n, b.t, n, OP_N, w2, 2 * n, OP_N, h, n, ONE, ZERO));
+  MS_TRY(gemm_form(ctx, fp32, n, b.t, n, w2, 2 * n, h, n, ONE, ZERO));
   MS_HIP(ctx, hipMemcpyAsync(out.rp, b.rp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(gemm(ctx, n, n, n, h, n, OP_N, b.tp, n, OP_N, out.rp, n, ONE, ONE));
+  MS_TRY(gemm_form(ctx, fp32, n, h, n, b.tp, n, out.rp, n, ONE, ONE));
   // tp = (tp_a + G W2) tp_b
   MS_HIP(ctx, hipMemcpyAsync(v, a.tp, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(gemm(ctx, n, n, n, g, n, OP_N, w2, 2 * n, OP_N, v, n, ONE, ONE));
-  MS_TRY(gemm(ctx, n, n, n, v, n, OP_N, b.tp, n, OP_N, out.tp, n, ONE, ZERO));
+  MS_TRY(gemm_form(ctx, fp32, n, g, n, w2, 2 * n, v, n, ONE, ONE));
+  MS_TRY(gemm_form(ctx, fp32, n, v, n, b.tp, n, out.tp, n, ONE, ZERO));
   return MS_OK;
 }
 
@@ -1024,7 +1049,7 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
 ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec prec, ms_smat* whole) {
   if (!ctx) return MS_ERR_ARG;
   if (!s || n_mats <= 0) return fail(ctx, MS_ERR_ARG, "need at least one S-matrix");
-  if (prec != MS_PREC_FP64) return fail(ctx, MS_ERR_UNSUPPORTED, "ms_star_cascade supports MS_PREC_FP64 only");
+  if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
   const int64_t n64 = s[0].n;
   if (n64 <= 0) return fail(ctx, MS_ERR_ARG, "s[0].n must be positive");
   if (n64 > MAX_N) return fail(ctx, MS_ERR_UNSUPPORTED, "n = %lld > %d", (long long)n64, MAX_N);
@@ -1060,7 +1085,7 @@ ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec 
   int cur = 0;
   for (int64_t i = 1; i < n_mats; ++i) {
     Blocks dst = (i == n_mats - 1) ? blocks_of(*whole) : acc[cur];
-    MS_TRY(star(ctx, n, a, blocks_of(s[i]), dst));
+    MS_TRY(star(ctx, n, a, blocks_of(s[i]), dst, prec == MS_PREC_FP32_MFMA));
     a = dst;
     cur ^= 1;
   }
@@ -1071,29 +1096,13 @@ ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n_mats, ms_prec 
 ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void* P, void* Q) {
   if (!ctx) return MS_ERR_ARG;
   MS_TRY(check_slices(ctx, cell));
-  if (cell->n_slices < 2) return fail(ctx, MS_ERR_ARG, "the cell needs its M >= 1 slices and slice 1 again");
+  if (bad_ptr(cell->evec)) return fail(ctx, MS_ERR_ARG, "cell->evec (the slices' eigenvectors) is required");
   if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
   if (bad_ptr(P) || bad_ptr(Q) || P == Q) return fail(ctx, MS_ERR_ARG, "P and Q must be distinct device buffers");
   MS_HIP(ctx, hipSetDevice(ctx->device));
-  const int n = (int)cell->n_g, m = (int)cell->n_slices - 1;   // the cell's slices 1..m, then slice 1 again
+  const int n = (int)cell->n_g, m = (int)cell->n_slices;   // the cell's slices 1..m
   const int64_t nn = (int64_t)n * n;
-  {   // the last slice must repeat the first: same thickness, same channel energies (to rounding)
-    std::vector<double> e1(n), e2(n), dz(m + 1);
-    MS_HIP(ctx, hipMemcpyAsync(e1.data(), cell->eps + n, n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    MS_HIP(ctx, hipMemcpyAsync(e2.data(), cell->eps + (int64_t)(m + 1) * n, n * sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    MS_HIP(ctx, hipMemcpyAsync(dz.data(), cell->dz, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    double scale = 1.0, diff = 0.0;
-    for (int i = 0; i < n; ++i) {
-      scale = std::max(scale, std::fabs(e1[i]));
-      diff = std::max(diff, std::fabs(e1[i] - e2[i]));
-    }
-    if (dz[0] != dz[m] || !(diff <= 1e-9 * scale))
-      return fail(ctx, MS_ERR_ARG, "the cell's last slice must repeat its first (dz %g vs %g, eps differ by %g)", dz[0],
-                  dz[m], diff);
-  }
-  void *seg, *whole;
+  void *seg, *whole, *eps2, *ovl2;
   MS_TRY(workspace(ctx, WS_BSEG, (size_t)m * 4 * nn * sizeof(double2), &seg));
   MS_TRY(workspace(ctx, WS_BWHOLE, (size_t)4 * nn * sizeof(double2), &whole));
   std::vector<ms_smat> s(m);
@@ -1101,8 +1110,26 @@ ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void
     double2* b = c2(seg) + (int64_t)i * 4 * nn;
     s[i] = ms_smat{n, b, b + nn, b + 2 * nn, b + 3 * nn};
   }
-  // S(p, p+1) for p = 1..m (the last one joins slice m to the next cell's slice 1), then S(1, m+1)
-  MS_TRY(ms_slice_smatrix(ctx, cell, energy, 1, m + 1, s.data()));
+  // S(p, p+1) for p = 1..m-1 from the cell's own overlaps
+  if (m > 1) MS_TRY(ms_slice_smatrix(ctx, cell, energy, 1, m, s.data()));
+  // S(m, m+1): slice m joined to the next cell's slice 1 (thickness dz_1), through
+  // O = U^m^dagger U^1 of the cell's own eigenvectors, so both Bloch planes share slice 1's
+  // eigenbasis exactly; it is the interface 1|2 of a two-slice set (slice m, slice 1)
+  MS_TRY(workspace(ctx, WS_BEPS, (size_t)(4 * n + 2) * sizeof(double), &eps2));
+  MS_TRY(workspace(ctx, WS_BOVL, (size_t)3 * nn * sizeof(double2), &ovl2));
+  double* e2 = (double*)eps2;
+  const size_t row = n * sizeof(double);
+  MS_HIP(ctx, hipMemcpyAsync(e2, cell->eps + (int64_t)m * n, row, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(e2 + n, cell->eps + (int64_t)m * n, row, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(e2 + 2 * n, cell->eps + n, row, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(e2 + 3 * n, cell->eps + n, row, hipMemcpyDeviceToDevice, ctx->stream));
+  double* dz2 = e2 + 4 * n;   // [dz_m, dz_1]
+  MS_HIP(ctx, hipMemcpyAsync(dz2, cell->dz + (m - 1), sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(dz2 + 1, cell->dz, sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  const double2* U = c2(cell->evec);
+  MS_TRY(gemm(ctx, n, n, n, U + (int64_t)(m - 1) * nn, n, OP_C, U, n, OP_N, c2(ovl2) + nn, n, ONE, ZERO));
+  const ms_slices pair{n, 2, dz2, e2, ovl2, nullptr};
+  MS_TRY(ms_slice_smatrix(ctx, &pair, energy, 1, 2, s.data() + (m - 1)));
   double2* w = c2(whole);
   ms_smat ws{n, w, w + nn, w + 2 * nn, w + 3 * nn};
   MS_TRY(ms_star_cascade(ctx, s.data(), m, MS_PREC_FP64, &ws));
@@ -1159,7 +1186,7 @@ struct FoldGroup {          // the sets of one n_g, longest first
   ms_ctx run = nullptr;             // context (stream, workspace) the group is enqueued on
   double cost = 0.0;                // n^3 x fold steps x instances, for placing groups on streams
   double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
-  void *aop = nullptr, *oc = nullptr;
+  void* aop = nullptr;
   int32_t* piv = nullptr;
 };
 
@@ -1194,7 +1221,7 @@ FoldDims fold_dims(const FoldGroup& G, bool fp32) {
   d.sY = (int64_t)n * d.ldy;
   d.sk = (int64_t)(G.nsmax + 2) * n;
   d.asz = fp32 ? sizeof(float2) : sizeof(double2);
-  d.per_e = (size_t)(2 * d.sk) * sizeof(double2) + 2 * d.nn * d.asz + 2 * d.nn * sizeof(double2) +
+  d.per_e = (size_t)(2 * d.sk) * sizeof(double2) + d.nn * d.asz + 2 * d.nn * sizeof(double2) +
             d.sM * sizeof(double2) + d.sY * sizeof(double2) + n * sizeof(int32_t);
   return d;
 }
@@ -1301,7 +1328,7 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     const int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, (int64_t)(BATCH_BUDGET / d.per_e)));
     G.nbi = (int)std::min<int64_t>(nbi, 65535);
     nd[0] = nd[1] = (size_t)G.nbi * d.sk * sizeof(double2);
-    nd[2] = (size_t)G.nbi * 2 * d.nn * d.asz;
+    nd[2] = (size_t)G.nbi * d.nn * d.asz;
     nd[3] = (size_t)G.nbi * 2 * d.nn * sizeof(double2);
     nd[4] = (size_t)G.nbi * d.sM * sizeof(double2);
     nd[5] = (size_t)G.nbi * d.sY * sizeof(double2);
@@ -1322,12 +1349,6 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
         }
       MS_TRY(workspace(G.run, slots[i], most, &v));
     }
-    if (P.fp32) {
-      size_t most = (size_t)d.nn * sizeof(float2);
-      for (const FoldGroup& H : P.groups)
-        if (H.run == G.run) most = std::max(most, (size_t)H.n * H.n * sizeof(float2));
-      MS_TRY(workspace(G.run, WS_OC, most, &v));
-    }
     MS_TRY(lu_reserve(G.run, G.n, d.ldm, G.nbi));
   }
   for (FoldGroup& G : P.groups) {   // pass 2: take the pointers (no slot grows any more)
@@ -1346,7 +1367,6 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     G.yb = c2(v);
     MS_TRY(workspace(c, WS_PIV, 1, &v));
     G.piv = (int32_t*)v;
-    if (P.fp32) MS_TRY(workspace(c, WS_OC, 1, &G.oc));
   }
   void *chd, *end, *pmd, *v;
   MS_TRY(workspace(ctx, WS_CH, chh.size() * sizeof(int32_t), &chd));
@@ -1404,30 +1424,26 @@ ms_status enqueue_group(ms_ctx c, const FoldPlan& P, const FoldGroup& G) {
         MS_TRY(launch_prologue(c, n, act, G.yb, d.ldy, sY, kq, pq, sk, G.aop, fp32));
         for (const Seg& g : segs) {
           if (g.ns < s) break;
-          // the set's energies are contiguous, so its share is one GEMM with M = 2 n m
-          // (no per-energy row padding of the last tile); O^T is shared
+          // W = rho^T [C- | C+ off its diagonal] for the set's energies, B generated from the
+          // set's O (shared by its energies) and each energy's k of slices p and p+1
           const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
           GemmArgs gm;
-          gm.M = 2 * n * g.m; gm.N = n; gm.K = n;
-          gm.A = static_cast<char*>(G.aop) + (size_t)g.a * 2 * nn * d.asz; gm.lda = n; gm.sA = 0; gm.opA = OP_N;
+          gm.M = n; gm.N = 2 * n; gm.K = n;
+          gm.A = static_cast<char*>(G.aop) + (size_t)g.a * nn * d.asz; gm.lda = n; gm.sA = nn; gm.opA = OP_N;
           gm.B = O; gm.ldb = n; gm.sB = 0; gm.opB = OP_T;
-          gm.C = G.wg + (int64_t)g.a * 2 * nn; gm.ldc = n; gm.sC = 0;
-          gm.batch = 1;
+          gm.C = G.wg + (int64_t)g.a * 2 * nn; gm.ldc = 2 * n; gm.sC = 2 * nn;
+          gm.batch = g.m;
+          gm.kp = kp + g.a * sk; gm.kq = kq + g.a * sk; gm.sk = sk;
           gm.prof = PC_IFACE_GEMM;
-          if (fp32) {
-            MS_TRY(launch_to_c64(c, nn, O, static_cast<float2*>(G.oc)));
-            gm.B = G.oc;
-            MS_TRY(cgemm32(c, gm));
-          } else {
-            MS_TRY(zgemm(c, gm));
-          }
+          MS_TRY(fp32 ? cgemm32(c, gm) : zgemm(c, gm));
         }
       }
       for (const Seg& g : segs) {
         if (g.ns < s) break;
         const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
         MS_TRY(launch_epilogue(c, n, g.m, O, first ? nullptr : G.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
-                               kq + g.a * sk, sk, G.mm + g.a * sM, d.ldm, sM));
+                               kq + g.a * sk, pq + g.a * sk, sk, G.yb + g.a * sY, d.ldy, sY, G.mm + g.a * sM, d.ldm,
+                               sM));
         MS_TRY(launch_tcols(c, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, G.yb + g.a * sY, d.ldy, sY, n,
                             kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, G.mm + g.a * sM, d.ldm, sM));
       }

@@ -62,7 +62,7 @@ __global__ void k_scatter_results(int64_t count, const int64_t* perm, const doub
 __device__ __forceinline__ void put(double2* d, double2 v) { *d = v; }
 __device__ __forceinline__ void put(float2* d, double2 v) { *d = make_float2((float)v.x, (float)v.y); }
 
-// A_e = [rho^T ; rho^T K],  rho^T_ij = P_i k_i Y_ij P_j / k_j  (k, P of slice p+1)
+// A_e = rho^T,  rho^T_ij = P_i k_i Y_ij P_j / k_j  (k, P of slice p+1; Y = Y1 of the state)
 template <typename OutT>
 __global__ void k_prologue(int n, const double2* Y, int64_t ldy, int64_t sY, const double2* kq, const double2* pq,
                            int64_t sk, OutT* Aop) {
@@ -73,20 +73,18 @@ __global__ void k_prologue(int n, const double2* Y, int64_t ldy, int64_t sY, con
   const double2* k = kq + e * sk;
   const double2* P = pq + e * sk;
   const double2 y = Y[e * sY + (int64_t)i * ldy + j];
-  const double2 left = cmul(P[i], k[i]);
-  const double2 bot = cmul(cmul(left, y), P[j]);   // rho^T_ij k_j
-  const double2 top = cdiv(bot, k[j]);             // rho^T_ij
-  OutT* A = Aop + e * 2 * (int64_t)n * n;
-  put(A + idx, top);
-  put(A + (int64_t)n * n + idx, bot);
+  put(Aop + e * (int64_t)n * n + idx, cdiv(cmul(cmul(cmul(P[i], k[i]), y), P[j]), k[j]));
 }
 
-// M_e[:, 0:n]  = Phi_A^T = (O^T + W1) K_p + K_{p+1} O^T - W2
-// M_e[:, n:2n] = Phi_B^T = (O^T + W1) K_p - K_{p+1} O^T + W2
-// O^T read through a 32 x 32 LDS tile; W = [W1; W2] may be null (first interface).
+// With C+- = O^T K_p +- K_{p+1} O^T (elementwise: O_ji (kp_j +- kq_i)) and W = rho^T [C- | C+ off
+// its diagonal] from the interface product:
+//   M_e[:, 0:n]  = Phi_A^T = C+ + rho^T C-
+//   M_e[:, n:2n] = Phi_B^T = C- + rho^T C+   (the diagonal part rho^T_ij C+_jj added here, in FP64)
+// rho^T is formed again from Y in FP64.  O^T read through a 32 x 32 LDS tile; W may be null
+// (first interface: rho = 0).
 __global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const double2* Wg, const double2* kp,
-                                                  const double2* kq, int64_t sk, double2* M, int64_t ldm,
-                                                  int64_t sM) {
+                                                  const double2* kq, const double2* pq, int64_t sk, const double2* Y,
+                                                  int64_t ldy, int64_t sY, double2* M, int64_t ldm, int64_t sM) {
   __shared__ double2 tile[32][33];
   const int64_t e = blockIdx.z;
   const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
@@ -99,21 +97,24 @@ __global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const
   __syncthreads();
   const double2* k_p = kp + e * sk;
   const double2* k_q = kq + e * sk;
+  const double2* P = pq + e * sk;
   for (int r = ty; r < 32; r += 8) {
     const int i = bi + r, j = bj + tx;
     if (i >= n || j >= n) continue;
     const double2 ot = tile[tx][r];
-    double2 w1 = make_double2(0.0, 0.0), w2 = make_double2(0.0, 0.0);
-    if (Wg) {
-      const double2* W = Wg + e * 2 * (int64_t)n * n;
-      w1 = W[(int64_t)i * n + j];
-      w2 = W[(int64_t)(n + i) * n + j];
-    }
-    const double2 psi = cmul(cadd(ot, w1), k_p[j]);
-    const double2 dpsi = csub(cmul(k_q[i], ot), w2);
+    const double2 cp = cmul(ot, cadd(k_p[j], k_q[i]));
+    const double2 cm = cmul(ot, csub(k_p[j], k_q[i]));
     double2* Mr = M + e * sM + (int64_t)i * ldm;
-    Mr[j] = cadd(psi, dpsi);
-    Mr[n + j] = csub(psi, dpsi);
+    if (!Wg) {
+      Mr[j] = cp;
+      Mr[n + j] = cm;
+      continue;
+    }
+    const double2* W = Wg + e * 2 * (int64_t)n * n + (int64_t)i * 2 * n;
+    const double2 rho = cdiv(cmul(cmul(cmul(P[i], k_q[i]), Y[e * sY + (int64_t)i * ldy + j]), P[j]), k_q[j]);
+    const double2 cpd = cmul(O[(int64_t)j * n + j], cadd(k_p[j], k_q[j]));
+    Mr[j] = cadd(cp, W[j]);
+    Mr[n + j] = cadd(cadd(cm, W[n + j]), cmul(rho, cpd));
   }
 }
 
@@ -585,9 +586,10 @@ ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t 
 }
 
 ms_status launch_epilogue(ms_ctx ctx, int n, int n_e, const double2* O, const double2* Wg, const double2* kp,
-                          const double2* kq, int64_t sk, double2* M, int64_t ldm, int64_t sM) {
+                          const double2* kq, const double2* pq, int64_t sk, const double2* Y, int64_t ldy, int64_t sY,
+                          double2* M, int64_t ldm, int64_t sM) {
   dim3 g((n + 31) / 32, (n + 31) / 32, n_e);
-  hipLaunchKernelGGL(k_epilogue, g, dim3(256), 0, ctx->stream, n, O, Wg, kp, kq, sk, M, ldm, sM);
+  hipLaunchKernelGGL(k_epilogue, g, dim3(256), 0, ctx->stream, n, O, Wg, kp, kq, pq, sk, Y, ldy, sY, M, ldm, sM);
   return check_launch(ctx, "epilogue");
 }
 

@@ -11,6 +11,13 @@
 // owns a sub-tile (64x64 tiles with 4 waves for small problems, 128x128 tiles
 // with 8 waves otherwise).  Global->LDS staging is register double-buffered
 // (the next K-slab is fetched while the current one is used).
+//
+// The fold's interface product (ROLE 1) generates its B operand while staging it:
+//   B_b[m][j] = O[j][m] (kp_b[j] - kq_b[m])          j <  nh   (C-)
+//   B_b[m][j] = O[j'][m] (kp_b[j'] + kq_b[m]), 0 at m = j'   j = nh + j'  (C+ off its diagonal)
+// from the shared FP64 overlap O and each batch entry's wavevectors, computed in FP64 and
+// rounded to the MFMA type when stored into LDS.  A tile's columns are BN/2 columns of C-
+// and the same BN/2 columns of C+, so each O element is loaded once and staged twice.
 #include <algorithm>
 #include <cstdlib>
 #include <type_traits>
@@ -57,7 +64,16 @@ struct KParams {
   double2* C;
   int64_t ldc, sC;
   double2 alpha, beta;
+  // generated B (ROLE 1): wavevectors of batch entry b at kp + b sk, kq + b sk; N = 2 nh
+  const double2* kp;
+  const double2* kq;
+  int64_t sk;
+  int nh;
 };
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
 constexpr int BK = 16;
 
@@ -65,9 +81,10 @@ constexpr int BK = 16;
 // LDS rows are padded by one element so the transposing stores of the
 // staging pass spread over the banks.  Blocks are launched as a 1D grid whose
 // index is remapped so that consecutive logical tiles (same A row-panel, all
-// column tiles) land on the same XCD and share its L2.  ROLE does not change
-// the code: it gives the interface products of the fold (1) and the LU's
-// trailing updates (2) their own kernel names in kernel traces.
+// column tiles) land on the same XCD and share its L2.  ROLE 1 is the fold's
+// interface product with its generated B operand; otherwise ROLE does not change
+// the code: it gives the LU's trailing updates (2) their own kernel names in
+// kernel traces.
 template <typename T, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int ntm, int total) {
   typedef typename Mfma<T>::c_t CT;
@@ -93,8 +110,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   const int wave = tid >> 6;
   const int wm0 = (wave / WN) * TM, wn0 = (wave % WN) * TN;
   const int m0 = tm * BM, n0 = tn * BN;
+  constexpr bool GEN = ROLE == 1;   // generated B (opB = T semantics, FP64 source)
   const CT* A = static_cast<const CT*>(p.A) + b * p.sA;
   const CT* B = static_cast<const CT*>(p.B) + b * p.sB;
+  const double2* Bd = static_cast<const double2*>(p.B);   // generated B: the shared overlap O
   double2* C = p.C + b * p.sC;
   const bool use_beta = (p.beta.x != 0.0 || p.beta.y != 0.0);
   // FP64: alpha is applied to A as it is staged and beta C is loaded into the
@@ -109,6 +128,19 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   // consumes them afterwards: zeroes the out-of-range elements, conjugates,
   // scales by alpha and stores the split planes into LDS.
   CT ra[EA], rb[EB];
+  // generated B: each thread's B elements keep their column j across K-slabs and share one
+  // K offset (NT is a multiple of BK), so kp is loaded once and kq once per slab
+  // (generated B: tile column c < BN/2 is C- column n0h + c, c >= BN/2 is C+ column
+  // n0h + c - BN/2, with n0h = tn BN/2; a thread loads EB/2 O elements per slab)
+  constexpr int BNH = BN / 2, EBH = EB / 2;
+  const int n0h = tn * BNH;
+  double2 rbd[GEN ? EBH : 1], kpv[GEN ? EBH : 1], rkq = make_double2(0.0, 0.0);
+  const double2* kpb = GEN ? p.kp + b * p.sk : nullptr;
+  const double2* kqb = GEN ? p.kq + b * p.sk : nullptr;
+  if constexpr (GEN) {
+#pragma unroll
+    for (int e = 0; e < EBH; ++e) kpv[e] = kpb[min(n0h + (tid + NT * e) / BK, p.nh - 1)];
+  }
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
@@ -117,6 +149,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
       const int gi = min(m0 + i, p.M - 1), gk = min(k0 + k, p.K - 1);
       ra[e] = (p.opA == OP_N) ? A[(int64_t)gi * p.lda + gk] : A[(int64_t)gk * p.lda + gi];
+    }
+    if constexpr (GEN) {
+      rkq = kqb[min(k0 + tid % BK, p.K - 1)];
+#pragma unroll
+      for (int e = 0; e < EBH; ++e) {
+        const int idx = tid + NT * e;
+        const int gj = min(n0h + idx / BK, p.nh - 1), gk = min(k0 + idx % BK, p.K - 1);
+        rbd[e] = Bd[(int64_t)gj * p.ldb + gk];
+      }
+      return;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -143,6 +185,23 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       }
       As[st][0][k][i] = re;
       As[st][1][k][i] = im;
+    }
+    if constexpr (GEN) {
+#pragma unroll
+      for (int e = 0; e < EBH; ++e) {
+        const int idx = tid + NT * e;
+        const int j = idx / BK, k = idx % BK;
+        const int gj = n0h + j, gk = k0 + k;
+        const double2 vm = zmul(rbd[e], make_double2(kpv[e].x - rkq.x, kpv[e].y - rkq.y));
+        const double2 vp = zmul(rbd[e], make_double2(kpv[e].x + rkq.x, kpv[e].y + rkq.y));
+        const bool ok = gj < p.nh && gk < p.K;
+        const bool okp = ok && gk != gj;   // C+ without its diagonal
+        Bs[st][0][k][j] = ok ? (T)vm.x : (T)0;
+        Bs[st][1][k][j] = ok ? (T)vm.y : (T)0;
+        Bs[st][0][k][BNH + j] = okp ? (T)vp.x : (T)0;
+        Bs[st][1][k][BNH + j] = okp ? (T)vp.y : (T)0;
+      }
+      return;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -237,8 +296,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm0 + a * 16 + Mfma<T>::crow(lane, v);
-        const int col = n0 + wn0 + c * 16 + (lane & 15);
-        if (row < p.M && col < p.N) {
+        int col = n0 + wn0 + c * 16 + (lane & 15);
+        bool col_ok = col < p.N;
+        if constexpr (GEN) {   // tile column -> C- or C+ column
+          const int lc = wn0 + c * 16 + (lane & 15);
+          const int h = lc >= BNH ? lc - BNH : lc;
+          col_ok = n0h + h < p.nh;
+          col = (lc >= BNH ? p.nh : 0) + n0h + h;
+        }
+        if (row < p.M && col_ok) {
           if (kFold) {
             C[(int64_t)row * p.ldc + col] = make_double2((double)cr[a][c][v], (double)ci[a][c][v]);
             continue;
@@ -260,7 +326,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 
 template <typename T, int BM, int BN, int WM, int WN, int ROLE>
 ms_status launch(ms_ctx ctx, const KParams& p, int batch, const Prof& prof) {
-  const int ntn = (p.N + BN - 1) / BN, ntm = (p.M + BM - 1) / BM;
+  // generated B: a tile covers BN/2 columns of each half
+  const int ntn = ROLE == 1 ? (p.nh + BN / 2 - 1) / (BN / 2) : (p.N + BN - 1) / BN, ntm = (p.M + BM - 1) / BM;
   const int64_t total = (int64_t)ntn * ntm * batch;
   if (total > 0x7fffffff) return fail(ctx, MS_ERR_UNSUPPORTED, "gemm grid too large");
   if (prof.a)   // timed: the events bracket the kernel's execution
@@ -275,10 +342,17 @@ ms_status launch(ms_ctx ctx, const KParams& p, int batch, const Prof& prof) {
 template <typename T>
 ms_status run(ms_ctx ctx, const GemmArgs& g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return MS_OK;
+  const bool gen = g.kp != nullptr;
+  if (gen && (g.N % 2 != 0 || g.kq == nullptr || g.opB != OP_T || g.sB != 0 || g.beta.x != 0.0 || g.beta.y != 0.0 ||
+              g.alpha.x != 1.0 || g.alpha.y != 0.0 || g.opA != OP_N))
+    return fail(ctx, MS_ERR_ARG, "generated-B product: shared O^T, N = 2 nh, no alpha/beta");
   KParams p{g.M, g.N, std::max(g.K, 0), g.opA, g.opB, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha,
-            g.beta};
+            g.beta, g.kp, g.kq, g.sk, g.N / 2};
+  // algorithmic bytes: A and C per batch entry; a shared B (stride 0) once
+  const double bytes_b = gen ? 16.0 * p.K * (g.N / 2) + 2.0 * 16.0 * g.batch * (p.K + g.N / 2)
+                             : (double)(g.sB == 0 ? 1 : g.batch) * sizeof(typename Mfma<T>::c_t) * p.K * g.N;
   Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * p.K * g.batch,
-            (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K + (double)p.K * g.N) +
+            (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K) + bytes_b +
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
             true);
   // Tile edge: the tuned choice for the fold group's basis size (ms_autotune / ms_set_tiles),
@@ -302,7 +376,7 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
   const bool big = tile == 128;
   if (g.prof == PC_LU_UPDATE)
     return big ? launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof);
-  if (g.prof == PC_IFACE_GEMM)
+  if (gen)
     return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
   return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
 }

@@ -121,10 +121,18 @@ struct GemmArgs {
   double2 beta = {0.0, 0.0};
   int batch = 1;
   int prof = PC_OTHER;   // profiler category of this launch
+  // The fold's interface product generates its B operand (N = 2 nh columns) from a shared
+  // FP64 overlap O (B = O, opB = OP_T, sB = 0) and the wavevectors of batch entry b at
+  // kp + b sk (left slice), kq + b sk (right slice):
+  //   B_b[m][j] = O[j][m] (kp[j] - kq[m]),  B_b[m][nh + j] = O[j][m] (kp[j] + kq[m]) (0 at m = j)
+  const double2* kp = nullptr;
+  const double2* kq = nullptr;
+  int64_t sk = 0;
 };
-// A, B complex128; FP64 MFMA.
+// A complex128 (B complex128); FP64 MFMA.
 ms_status zgemm(ms_ctx ctx, const GemmArgs& g);
-// A, B complex64; FP32 MFMA with FP32 accumulation; C complex128.
+// A, B complex64 (a generated B: from the complex128 O, rounded when staged); FP32 MFMA
+// with FP32 accumulation; C complex128.
 ms_status cgemm32(ms_ctx ctx, const GemmArgs& g);
 
 // ---- batched LU of an augmented matrix and triangular solves (FP64) -------------------

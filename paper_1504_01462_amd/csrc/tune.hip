@@ -86,9 +86,11 @@ ms_status ms_autotune(ms_ctx ctx, int64_t n_g, int64_t n_open, int64_t batch, ms
   MS_TRY(workspace(ctx, 51, (size_t)nb * sY * sizeof(double2), &Y));
   MS_TRY(workspace(ctx, 52, (size_t)nb * n * sizeof(int32_t), &piv));
   MS_TRY(workspace(ctx, 53, (size_t)nb * sizeof(int32_t), &st));
-  MS_TRY(workspace(ctx, 54, (size_t)nb * 2 * nn * sizeof(double2), &A));
+  void* K;
+  MS_TRY(workspace(ctx, 54, (size_t)nb * nn * sizeof(double2), &A));
   MS_TRY(workspace(ctx, 55, (size_t)nn * sizeof(double2), &B));
   MS_TRY(workspace(ctx, 56, (size_t)nb * 2 * nn * sizeof(double2), &C));
+  MS_TRY(workspace(ctx, 57, (size_t)nb * 2 * n * sizeof(double2), &K));
   MS_TRY(lu_reserve(ctx, n, ncols, nb));
   hipEvent_t e0, e1;
   MS_HIP(ctx, hipEventCreate(&e0));
@@ -131,20 +133,26 @@ ms_status ms_autotune(ms_ctx ctx, int64_t n_g, int64_t n_open, int64_t batch, ms
                               static_cast<int32_t*>(st), 1);
       });
     }
-  // the interface product [W1; W2] = A O^T for nb systems stacked
+  // the interface product W = A [C- | C+] of nb systems sharing one O (B generated from O and
+  // each system's two wavevector rows)
   double if_ms[2] = {0, 0};
   for (int a = 0; a < 2 && s == MS_OK; ++a) {
     t->iface = edge[a];
     if_ms[a] = timed([&](bool setup) -> ms_status {
       if (setup) {
-        MS_TRY(fill(ctx, 2 * n * nb, n, 0, 1, 0.0, 777u, A));
+        MS_TRY(fill(ctx, n * nb, n, 0, 1, 0.0, 777u, A));
+        MS_TRY(fill(ctx, 2 * nb, n, 0, 1, 1.0, 555u, K));
         return fill(ctx, n, n, 0, 1, 0.0, 999u, B);
       }
       GemmArgs g;
-      g.M = 2 * n * nb; g.N = n; g.K = n;
-      g.A = A; g.lda = n; g.opA = OP_N;
-      g.B = B; g.ldb = n; g.opB = OP_T;
-      g.C = static_cast<double2*>(C); g.ldc = n;
+      g.M = n; g.N = 2 * n; g.K = n;
+      g.A = A; g.lda = n; g.sA = nn; g.opA = OP_N;
+      g.B = B; g.ldb = n; g.sB = 0; g.opB = OP_T;
+      g.C = static_cast<double2*>(C); g.ldc = 2 * n; g.sC = 2 * nn;
+      g.batch = nb;
+      g.kp = static_cast<const double2*>(K);
+      g.kq = static_cast<const double2*>(K) + n;
+      g.sk = 2 * n;
       g.prof = PC_IFACE_GEMM;
       return zgemm(ctx, g);
     });

@@ -1,10 +1,11 @@
 """Full-size checks at N_G = 1200, 400 slices (the benchmark workload), in the launch
 configuration bench.py times: one (gap, k_par) with its 32 energies per batch.
 
-The oracle takes about 13 minutes per point here, so its values at two sample
-points are stored (tests/golden/make_golden.py); every other point is checked
-through properties that hold at any size: current conservation R + T = N_open
-and the agreement of the FP32-MFMA form with the FP64 form."""
+The oracle takes about 13 minutes per point here, so its values at sample points
+(gaps 5.0, 6.3 and 7.5 bohr, k_par off the symmetric centre) are stored
+(tests/golden/make_golden.py, which calls only the oracle); every other point is
+checked through properties that hold at any size: current conservation
+R + T = N_open and the agreement of the FP32-MFMA form with the FP64 form."""
 import numpy as np
 import pytest
 
@@ -41,26 +42,68 @@ def test_config3_fp64_against_oracle(full):
     T, R, no, st, j = full["T"], full["R"], full["no"], full["st"], full["j"]
     assert np.all(st == 0)
     assert np.max(np.abs(T + R - no)) < 1e-9
-    for p in full["pts"]:
+    p0 = full["pts"][0]
+    same = [p for p in full["pts"] if p["junction"] == p0["junction"] and p["k_index"] == p0["k_index"]]
+    for p in same:
         i = p["e_index"]
         assert abs(j.energies[i] - p["energy"]) < 1e-15
         assert int(no[i]) == p["n_open"]
         assert abs(T[i] - p["T"]) < 1e-10, (p["energy"], T[i], p["T"])
 
 
-def test_config3_fp32_form(ms, full):
-    """FP32-MFMA interface GEMMs (FP32 accumulation), everything else FP64.  Measured
-    max |dT| over the 32 points is ~1.5e-4 (T up to 13): FP32 accumulation leaves ~1e-6
-    relative error per GEMM entry, compounded over 401 interfaces.  The 1e-6 target is
-    NOT met by this form; the bound below guards the achieved accuracy."""
+def test_config3_other_gaps_and_kpar_against_oracle(ms, full):
+    """The stored oracle points of the other (gap, k_par) groups of the benchmark workload:
+    each group's slices prepared at its own k_par, folded at the stored energies."""
+    ctx = full["ctx"]
+    p0 = full["pts"][0]
+    groups = {}
+    for p in full["pts"]:
+        if (p["junction"], p["k_index"]) != (p0["junction"], p0["k_index"]):
+            groups.setdefault((p["junction"], p["k_index"]), []).append(p)
+    assert len(groups) >= 3, "stored points cover gaps 5.0 and 7.5 and a second k_par at 6.3"
+    for (name, ik), pts in groups.items():
+        j = msgen.config3(pts[0]["meta"]["gap"], pts[0]["meta"]["registry"])
+        assert j.name == name
+        s = ms.prepare_from_inputs(ctx, msgen.junction_inputs(j, j.kpars[ik]))
+        T, R, no, st = (x.cpu().numpy() for x in ms.ms_transmission_batch(ctx, s, [p["energy"] for p in pts]))
+        ctx.sync()
+        assert np.all(st == 0)
+        for i, p in enumerate(pts):
+            assert int(no[i]) == p["n_open"], (name, ik, p["energy"])
+            assert abs(T[i] - p["T"]) < 1e-10, (name, ik, p["energy"], T[i], p["T"])
+            assert abs(R[i] - p["R"]) < 1e-10, (name, ik, p["energy"], R[i], p["R"])
+        del s
+
+
+FP32_TARGET = 1e-6
+
+
+def _config3_fp32(ms, full):
     ctx, s, j = full["ctx"], full["s"], full["j"]
-    T32, R32, no32, st32 = (x.cpu().numpy() for x in ms.ms_transmission_batch(ctx, s, j.energies, "fp32"))
-    ctx.sync()
+    if "T32" not in full:
+        T32, R32, no32, st32 = (x.cpu().numpy() for x in ms.ms_transmission_batch(ctx, s, j.energies, "fp32"))
+        ctx.sync()
+        full.update(T32=T32, R32=R32, no32=no32, st32=st32)
+    return full["T32"], full["R32"], full["no32"], full["st32"]
+
+
+@pytest.mark.xfail(strict=False, reason="FP32-MFMA form: config3 max |dT| vs FP64 may exceed the 1e-6 target "
+                                         "(see test_config3_fp32_form_guard)")
+def test_config3_fp32_form_meets_target(ms, full):
+    """The FP32-MFMA form on the 32 points of a config3 k_par: |dT| <= 1e-6 against FP64."""
+    T32 = _config3_fp32(ms, full)[0]
+    assert np.max(np.abs(T32 - full["T"])) <= FP32_TARGET
+
+
+def test_config3_fp32_form_guard(ms, full):
+    """Regression guard on the FP32-MFMA form at config3: every point valid, current conserved
+    to the form's accuracy, and |dT| against FP64 below a bound above its measured value."""
+    T32, R32, no32, st32 = _config3_fp32(ms, full)
     assert np.all(st32 == 0)
     dT = np.max(np.abs(T32 - full["T"]))
     print(f"\nconfig3 FP32-MFMA form: max |dT| vs FP64 over {T32.size} points = {dT:.3e}")
-    assert dT < 1e-3
-    assert np.max(np.abs(T32 + R32 - no32)) < 1e-3
+    assert dT < 5e-5
+    assert np.max(np.abs(T32 + R32 - no32)) < 5e-5
 
 
 def test_config3_slices_sampled_against_oracle(ms, full):
@@ -124,32 +167,94 @@ def test_uneven_instances_config4_sample(ms, full):
     assert abs(T[k] - ref["T"]) < 1e-10 and int(no[k]) == ref["n_open"]
 
 
+EPS_T = 5e-12   # bound on the change of T when one slice's eigenproblem is solved again
+
+
 def test_dT_dV_full_size_central_differences(ms, full):
-    """The adjoint workload's geometry at full size (config3 gap 6.3, k_par = 0, N_G = 1200,
-    400 slices, checkpoints every 20 planes): three slice coefficients' derivatives against
-    central differences of the batch path's T (h = 1e-5), and T itself."""
+    """The adjoint workload at full size (config3 gap 6.3, k_par = 0, N_G = 1200, 400 slices,
+    checkpoints every 20 planes): 20 seeded real parameters (Re and Im parts of V^p(Q) with
+    V(-Q) = conj V(Q) kept; 19 with Q != 0) against central differences of the GPU's own T.
+
+    Each difference re-solves only the perturbed slice (a one-slice ms_slices_prepare with its
+    eigenvectors) and replaces its eigenvalues and the two overlaps it enters, formed with the
+    library's GEMM from the neighbours' eigenvectors.  A re-solved slice changes T by up to
+    EPS_T (the eigensolver's convergence tolerance, about 3e-14 relative, carried through 401
+    interfaces), so a central difference at step h carries a rounding floor of EPS_T / h:
+    2.5e-6 absolute at the specified h = 1e-6, which is above 1e-6 of the smaller derivatives.
+    Each coefficient is therefore checked twice: (a) at h = 1e-6 within 1e-6 relative plus
+    that floor; (b) by Richardson extrapolation of the differences at h = 1e-4 and 2e-4
+    (truncation O(h^4), floor 1.5 EPS_T / 1e-4 = 7.5e-8) within 1e-6 relative plus its floor.
+    The six perturbed sets of a coefficient are folded in one ms_transmission_multi call."""
     import torch
+    import oracle as orc
     ctx = full["ctx"]
     j = msgen.config5()
     inp = msgen.junction_inputs(j, j.kpars[0])
     s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    n, ns = s.n_g, s.n_slices
     q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device="cuda")
     e = float(j.energies[8])
     g, tr, no = ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1], 20)
-    T0 = ms.ms_transmission_batch(ctx, s, [e])[0].cpu().numpy()[0]
     ctx.sync()
     g = g.cpu().numpy()
+    qi, qj, dre, dim = orc.dT_dV_real(g, inp["q_miller"])
+    eye = torch.eye(n, dtype=torch.complex128, device="cuda")
+    dz = inp["dz"]
+    steps = [1e-6, 1e-4, 2e-4]
+    # one slice set per (step, sign): the base set itself and five copies of its slice data
+    sets = [s] + [ms.Slices(n, ns, s.dz, s.eps.clone(), s.ovl.clone()) for _ in range(2 * len(steps) - 1)]
+
+    def set_slice(dst, p, vrow):
+        """dst's slice p (vq row p) re-solved from the potential row vrow."""
+        one = ms.prepare_from_inputs(ctx, dict(inp, vq=vrow[None, :].copy(), dz=dz[p:p + 1].copy()), with_evec=True)
+        u = one.evec[0]
+        left = s.evec[p - 1] if p > 0 else eye
+        right = s.evec[p + 1] if p < ns - 1 else eye
+        dst.eps[p + 1].copy_(one.eps[1])
+        ms.ms_debug_gemm(ctx, left.contiguous(), u.contiguous(), dst.ovl[p], op_a=2, op_b=0)
+        ms.ms_debug_gemm(ctx, u.contiguous(), right.contiguous(), dst.ovl[p + 1], op_a=2, op_b=0)
+
+    saved = {}
+
+    def restore(dst, p):
+        e0, o0, o1 = saved[p]
+        dst.eps[p + 1].copy_(e0)
+        dst.ovl[p].copy_(o0)
+        dst.ovl[p + 1].copy_(o1)
+
+    T0 = ms.ms_transmission_batch(ctx, s, [e])[0].cpu().numpy()[0]
+    ctx.sync()
     assert abs(tr.cpu().numpy()[0] - T0) < 1e-9
-    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
-    h = 1e-5
-    for p in (37, 200, 371):
-        vals = []
-        for sgn in (1, -1):
-            vq = inp["vq"].copy()
-            vq[p, q0] += sgn * h
-            sp = ms.prepare_from_inputs(ctx, dict(inp, vq=vq))
-            vals.append(ms.ms_transmission_batch(ctx, sp, [e])[0].cpu().numpy()[0])
-            ctx.sync()
-        fd = (vals[0] - vals[1]) / (2 * h)
-        an = 2.0 * np.real(g[p, q0])
-        assert abs(fd - an) < 1e-6 + 1e-4 * abs(an), (p, fd, an)
+    rng = np.random.default_rng(5)
+    qm = inp["q_miller"][qi]
+    low = np.where((np.abs(qm).sum(axis=1) > 0) & (np.abs(qm[:, 0]) <= 2) & (np.abs(qm[:, 1]) <= 8))[0]
+    c0 = int(np.where(np.abs(qm).sum(axis=1) == 0)[0][0])
+    picks = [(int(rng.integers(0, ns)), c0, "re")]
+    picks += [(int(rng.integers(0, ns)), int(rng.choice(low)), "re" if k % 2 else "im") for k in range(19)]
+    print(f"\nfull-size dT/dV: T = {T0:.12f}, EPS_T = {EPS_T:.0e}")
+    noise = []
+    for p, c, part in picks:
+        saved[p] = (s.eps[p + 1].clone(), s.ovl[p].clone(), s.ovl[p + 1].clone())
+        k = 0
+        for h in steps:
+            for sgn in (1, -1):
+                d = sgn * h * (1.0 if part == "re" else 1j)
+                v = inp["vq"][p].copy()
+                v[qi[c]] += d
+                if qj[c] != qi[c]:
+                    v[qj[c]] += np.conj(d)
+                set_slice(sets[k], p, v)
+                k += 1
+        Tv = ms.ms_transmission_multi(ctx, sets, np.full((len(sets), 1), e))[0].cpu().numpy()[:, 0]
+        ctx.sync()
+        for dst in sets:
+            restore(dst, p)
+        fd = [(Tv[2 * i] - Tv[2 * i + 1]) / (2 * h) for i, h in enumerate(steps)]
+        rich = (4.0 * fd[1] - fd[2]) / 3.0
+        an = dre[p, c] if part == "re" else dim[p, c]
+        noise.append(steps[0] * abs(fd[0] - rich))
+        print(f"  p={p:3d} Q={tuple(int(x) for x in inp['q_miller'][qi[c]])} {part}: adjoint={an:+.10e} "
+              f"fd(1e-6)={fd[0]:+.10e} richardson(1e-4,2e-4)={rich:+.10e} rel={abs(rich - an) / abs(an):.1e}")
+        assert abs(rich - an) <= 1e-6 * abs(an) + 1.5 * EPS_T / steps[1], (p, c, part, rich, an)
+        assert abs(fd[0] - an) <= 1e-6 * abs(an) + EPS_T / steps[0], (p, c, part, fd[0], an)
+    print(f"  T noise implied by the h = 1e-6 differences: up to {max(noise):.1e} (EPS_T = {EPS_T:.0e})")

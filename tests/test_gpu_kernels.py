@@ -62,6 +62,48 @@ def test_gemm_fp32(lib, ctx, m, n, k):
     assert err <= 6e-8 * 4 * k * 2, err
 
 
+def _iface_ref(a, o, kp, kq):
+    """W[b] = A[b] [C- | C+ with zero diagonal], C-+[m][j] = O[j][m] (kp[j] -+ kq[m]) in FP64."""
+    out = []
+    for b in range(a.shape[0]):
+        cm = o.T * (kp[b][None, :] - kq[b][:, None])
+        cp = o.T * (kp[b][None, :] + kq[b][:, None])
+        np.fill_diagonal(cp, 0.0)
+        out.append(a[b] @ np.hstack([cm, cp]))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("n,batch", [(1, 1), (7, 3), (37, 2), (64, 2), (65, 3), (130, 2), (300, 4), (1200, 2)])
+def test_iface_product_fp64(lib, ctx, n, batch):
+    """The fold's interface product with its generated B operand (ragged tile tails, both tile
+    edges: 64 for n < 128, 128 otherwise), against NumPy in FP64."""
+    rng = np.random.default_rng(n + 17 * batch)
+    a = _rand(rng, (batch, n, n))
+    o = _rand(rng, (n, n)) / np.sqrt(n)
+    kp = _rand(rng, (batch, n))
+    kq = _rand(rng, (batch, n))
+    ref = _iface_ref(a, o, kp, kq)
+    w = lib.ms_debug_iface_product(ctx, to_dev(a), to_dev(o), to_dev(kp), to_dev(kq), "fp64")
+    ctx.sync()
+    err = np.max(np.abs(w.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-14 * np.sqrt(n) + 1e-15, err
+
+
+@pytest.mark.parametrize("n,batch", [(37, 2), (130, 3), (1200, 2)])
+def test_iface_product_fp32(lib, ctx, n, batch):
+    """FP32 form: A complex64, B generated in FP64 and rounded when staged, FP32 accumulation."""
+    rng = np.random.default_rng(n + 5)
+    a = _rand(rng, (batch, n, n)).astype(np.complex64)
+    o = _rand(rng, (n, n)) / np.sqrt(n)
+    kp = _rand(rng, (batch, n))
+    kq = _rand(rng, (batch, n))
+    ref = _iface_ref(a.astype(np.complex128), o, kp, kq)
+    w = lib.ms_debug_iface_product(ctx, to_dev(a), to_dev(o), to_dev(kp), to_dev(kq), "fp32")
+    ctx.sync()
+    err = np.max(np.abs(w.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= 6e-8 * 8 * np.sqrt(n), err
+
+
 @pytest.mark.parametrize("n,nrhs,batch", [(1, 1, 2), (5, 3, 3), (16, 16, 2), (17, 13, 2), (37, 74, 3),
                                           (100, 64, 2), (128, 7, 2), (300, 313, 2), (513, 70, 1), (1030, 20, 1)])
 def test_lu_solve(lib, ctx, n, nrhs, batch):

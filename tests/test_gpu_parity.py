@@ -4,8 +4,9 @@ Tolerances (FP64 path): T within 1e-10 of the oracle, the per-slice and whole
 S-matrices within 1e-11 of the largest entry; these are the accumulated
 rounding of ~10 N^3 complex operations per interface over tens to hundreds of
 interfaces, several orders above machine epsilon and far below the 1e-10
-target on T.  The FP32-MFMA form is compared with the FP64 path on every
-point at |dT| <= 1e-6.
+target on T.  The FP32-MFMA form is held to its target |dT| <= 1e-6 against
+the FP64 path on every point (an expected failure while the form misses it,
+with the achieved accuracy guarded by a separate, named bound).
 """
 import numpy as np
 import pytest
@@ -108,6 +109,27 @@ def test_star_cascade_single_and_two(ms, ctx, c1):
 
 
 # ------------------------------------------------------------------ fused batch path -------
+@pytest.mark.parametrize("e", [0.7, 3.1])
+def test_star_cascade_fp32_form(ms, ctx, c1, e):
+    """a5 in the FP32-MFMA form: the whole S of config1's 25 interfaces (the oracle's eigendata)
+    against the FP64 cascade; F and its LU stay FP64, the other products run on FP32 MFMA, so
+    the blocks agree to the FP32 products' rounding, and T to the same order."""
+    _, inp, prep = c1
+    s = slices_from_oracle(ms, prep)
+    sm = ms.ms_slice_smatrix(ctx, s, e, 0, prep["n_slices"] + 1)
+    w64 = ms.ms_star_cascade(ctx, sm, "fp64")
+    w32 = ms.ms_star_cascade(ctx, sm, "fp32")
+    eps_l, eps_r = s.eps[0].contiguous(), s.eps[-1].contiguous()
+    t64 = _np(ms.ms_transmission(ctx, w64, e, eps_l, eps_r)[0])[0]
+    t32 = _np(ms.ms_transmission(ctx, w32, e, eps_l, eps_r)[0])[0]
+    ctx.sync()
+    for b in range(4):
+        err = rel_err(_np(w32[b]), _np(w64[b]))
+        assert err < 1e-5, (b, err)
+    print(f"\nstar cascade FP32 form, config1 E={e}: |dT| = {abs(t32 - t64):.2e}")
+    assert abs(t32 - t64) < 1e-5
+
+
 def test_batch_with_oracle_eigendata(ms, ctx, c1):
     """The fused fold alone (slice data from the oracle)."""
     j, inp, prep = c1
@@ -165,7 +187,10 @@ def test_golden_config2(ms, ctx):
             assert abs(_np(T)[i] + _np(R)[i] - p["n_open"]) < 1e-9
 
 
-def test_fp32_form_against_fp64(ms, ctx, c1):
+FP32_TARGET = 1e-6       # |dT| of the FP32-MFMA form against the FP64 path
+
+
+def _fp32_vs_fp64_config1(ms, ctx, c1):
     j, inp, _ = c1
     s = ms.prepare_from_inputs(ctx, inp)
     es = np.linspace(0.1, 4.0, 12)
@@ -173,12 +198,93 @@ def test_fp32_form_against_fp64(ms, ctx, c1):
     t32, r32, no, st = ms.ms_transmission_batch(ctx, s, es, "fp32")
     ctx.sync()
     assert np.all(_np(st) == 0)
-    # The FP32 form rounds the interface products to complex64 with FP32 accumulation
-    # (K = N terms): its error is a few 1e-7 relative per product and, unlike the FP64
-    # result, depends on the eigenvector gauge (phases and mixing inside degenerate
-    # subspaces), which the eigensolver's starting point sets.  Bound: 1e-5 absolute
-    # on T of up to 9 open channels; the FP64 path is the one held to the oracle.
-    assert np.max(np.abs(_np(t32) - t64)) < 1e-5
+    return float(np.max(np.abs(_np(t32) - t64)))
+
+
+@pytest.mark.xfail(strict=False, reason="FP32-MFMA form: measured max |dT| vs FP64 above the 1e-6 target "
+                                         "(see test_fp32_form_accuracy_guard)")
+def test_fp32_form_meets_target(ms, ctx, c1):
+    """The FP32-MFMA form against the FP64 path on 12 energies of the config1 cell (up to 9
+    open channels): |dT| <= 1e-6, the target of the form."""
+    assert _fp32_vs_fp64_config1(ms, ctx, c1) <= FP32_TARGET
+
+
+def test_fp32_form_accuracy_guard(ms, ctx, c1):
+    """Regression guard on the accuracy the FP32-MFMA form achieves on the same points (a
+    bound above its measured |dT|, not the target)."""
+    d = _fp32_vs_fp64_config1(ms, ctx, c1)
+    print(f"\nFP32-MFMA form, config1 cell, 12 energies: max |dT| vs FP64 = {d:.3e}")
+    assert d < 1e-5
+
+
+# ------------------------------------------------------------------ a7: k_par average ------
+def test_kpar_average_matches_oracle(ms, ctx):
+    """a7 (Sec. II.B, Eq. T1_d) on the device: the T and N_open table of three k_par of the
+    config1 cell from one ms_transmission_multi call, averaged by ms_kpar_average, against
+    oracle.kpar_average of the same table element by element, and against the oracle's own
+    T values averaged by the oracle."""
+    j = msgen.config1()
+    kps = [(0.0, 0.0), (0.31, 0.17), (-0.22, 0.4)]
+    inps = [msgen.junction_inputs(j, kp) for kp in kps]
+    sets = [ms.prepare_from_inputs(ctx, inp) for inp in inps]
+    es = np.linspace(0.3, 3.6, 6)
+    T, R, no, st = ms.ms_transmission_multi(ctx, sets, np.tile(es, (3, 1)), "fp64")
+    tbar, per = ms.ms_kpar_average(ctx, T, no)
+    ctx.sync()
+    assert np.all(_np(st) == 0)
+    ref_tbar, ref_per = orc.kpar_average(_np(T), _np(no))
+    assert np.max(np.abs(_np(tbar) - ref_tbar)) < 1e-14
+    assert np.max(np.abs(_np(per) - ref_per)) < 1e-14
+    t_or = np.zeros((3, es.size))
+    n_or = np.zeros((3, es.size), dtype=np.int64)
+    for k in range(3):
+        prep = orc.prepare(inps[k])
+        for i, e in enumerate(es):
+            out = orc.transmission(prep, e)
+            t_or[k, i], n_or[k, i] = out["T"], out["n_open"]
+    o_tbar, o_per = orc.kpar_average(t_or, n_or)
+    assert np.array_equal(_np(no), n_or)
+    assert np.max(np.abs(_np(tbar) - o_tbar)) < 1e-10
+    assert np.max(np.abs(_np(per) - o_per)) < 1e-10
+    assert len(set(n_or[:, -1])) > 1      # the k_par differ in their open-channel counts
+
+
+def test_kpar_average_no_open_channel(ms, ctx):
+    """Energies with no open channel at any k_par average to 0 per channel (not 0/0)."""
+    T = torch.tensor([[0.0, 0.5], [0.0, 1.5]], dtype=torch.float64, device=dev())
+    no = torch.tensor([[0, 1], [0, 2]], dtype=torch.int64, device=dev())
+    tbar, per = ms.ms_kpar_average(ctx, T, no)
+    ctx.sync()
+    assert _np(tbar).tolist() == [0.0, 1.0] and _np(per).tolist() == [0.0, 2.0 / 3.0]
+
+
+# ------------------------------------------------------------------ device-side errors -----
+def test_star_cascade_singular_F(ms, ctx):
+    """F = I - S12(a) S21(b) = 0 exactly (S12(a) = S21(b) = I): the LU of F meets a zero pivot,
+    MS_ERR_SINGULAR is recorded on the device and returned by ms_ctx_sync."""
+    n = 8
+    eye = to_dev(np.eye(n, dtype=np.complex128))
+    zero = to_dev(np.zeros((n, n), dtype=np.complex128))
+    a = (eye.clone(), eye.clone(), zero.clone(), eye.clone())
+    b = (eye.clone(), zero.clone(), eye.clone(), eye.clone())
+    ms.ms_star_cascade(ctx, [a, b], "fp64")
+    with pytest.raises(ms.MSError) as ei:
+        ctx.sync()
+    assert ei.value.status == ms.MS_ERR_SINGULAR
+    ctx.sync()                                    # the status word was cleared by the read
+
+
+def test_nonfinite_potential_is_reported(ms, ctx, c1):
+    """A NaN Fourier coefficient in one slice's V^p(Q): ms_slices_prepare records
+    MS_ERR_NONFINITE, returned by ms_ctx_sync."""
+    _, inp, _ = c1
+    vq = inp["vq"].copy()
+    vq[5, 3] = complex(np.nan, 0.0)
+    ms.prepare_from_inputs(ctx, dict(inp, vq=vq))
+    with pytest.raises(ms.MSError) as ei:
+        ctx.sync()
+    assert ei.value.status == ms.MS_ERR_NONFINITE
+    ctx.sync()
 
 
 # ------------------------------------------------------------------ edge cases -------------
@@ -241,10 +347,10 @@ def test_argument_errors(ms, ctx, c1):
     with pytest.raises(ms.MSError) as ei:
         ms.ms_transmission_batch(ctx, s, [0.5, float("nan")])
     assert ei.value.status == ms.MS_ERR_ARG
+    blocks = [tuple(to_dev(np.eye(4, dtype=complex)) for _ in range(4))]
     with pytest.raises(ms.MSError) as ei:
-        ms.ms_star_cascade(ctx, [], "fp64") if False else ms.ms_star_cascade(
-            ctx, [tuple(to_dev(np.eye(4, dtype=complex)) for _ in range(4))], "fp32")
-    assert ei.value.status == ms.MS_ERR_UNSUPPORTED
+        ms.ms_star_cascade(ctx, blocks, 7)                    # no such precision
+    assert ei.value.status == ms.MS_ERR_ARG
 
 
 def test_deterministic(ms, ctx, c1):
@@ -690,15 +796,17 @@ def test_dT_dV_batches_with_uneven_open_counts(ms, ctx):
 
 
 # ------------------------------------------------------------------ electrode cells (App. B) --
-@pytest.mark.parametrize("zonly", [False, True])
-def test_bloch_pencil_eigenvalues_match_oracle(ms, ctx, zonly):
+@pytest.mark.parametrize("zonly,m", [(False, 3), (True, 3), (False, 12)])
+def test_bloch_pencil_eigenvalues_match_oracle(ms, ctx, zonly, m):
     """The cell's S(1, M+1) and the pencil of Eq. cmp on the GPU: its eigenvalues (LAPACK on the
-    host, on the GPU's P and Q; they do not depend on the slices' eigenvector gauge) against the
-    oracle's complex bands, for a wells cell and a cell whose potential depends on z only
-    (propagating and evanescent states alike)."""
+    host, on the GPU's P and Q) against the oracle's complex bands, for a wells cell and a cell
+    whose potential depends on z only (propagating and evanescent states alike).  With M = 12
+    slices the GPU eigensolver warm-starts slices from reference slices, so slice M's and slice
+    1's eigenvectors come from different starting points: the last interface must still join
+    slice M to the cell's own slice-1 eigenbasis, or the eigenvalues move."""
     import scipy.linalg as sla
     j = msgen.config1()
-    dz = np.array([0.5, 0.6, 0.4])
+    dz = np.array([0.5, 0.6, 0.4]) if m == 3 else np.linspace(0.2, 0.35, m)
     j.dz = dz
     inp = msgen.junction_inputs(j, (0.07, -0.11), 13)
     if zonly:
@@ -707,8 +815,7 @@ def test_bloch_pencil_eigenvalues_match_oracle(ms, ctx, zonly):
         vq[:, q0] = [0.0, 0.8, -0.5]
         inp["vq"] = vq
     prep = orc.prepare(inp)
-    cell = dict(inp, vq=np.concatenate([inp["vq"], inp["vq"][:1]]), dz=np.concatenate([dz, dz[:1]]))
-    s = ms.prepare_from_inputs(ctx, cell)
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
     for e in (0.9, 1.6, 2.7):
         P, Q = ms.ms_bloch_pencil(ctx, s, e)
         ctx.sync()
@@ -724,13 +831,13 @@ def test_bloch_pencil_eigenvalues_match_oracle(ms, ctx, zonly):
 
 def test_bloch_pencil_argument_errors(ms, ctx):
     j = msgen.config1()
-    j.dz = np.array([0.5])
-    inp = msgen.junction_inputs(j, (0.07, -0.11), 9)
-    s = ms.prepare_from_inputs(ctx, inp)      # one slice: the repeated slice 1 is missing
-    with pytest.raises(ms.MSError):
-        ms.ms_bloch_pencil(ctx, s, 0.9)
     j.dz = np.array([0.5, 0.6, 0.4])
     inp = msgen.junction_inputs(j, (0.07, -0.11), 9)
-    s = ms.prepare_from_inputs(ctx, inp)      # three different slices: the last does not repeat the first
-    with pytest.raises(ms.MSError, match="repeat its first"):
+    s = ms.prepare_from_inputs(ctx, inp)      # no eigenvectors kept
+    with pytest.raises(ms.MSError) as ei:
         ms.ms_bloch_pencil(ctx, s, 0.9)
+    assert ei.value.status == ms.MS_ERR_ARG
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_bloch_pencil(ctx, s, float("inf"))
+    assert ei.value.status == ms.MS_ERR_ARG
