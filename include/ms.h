@@ -54,8 +54,10 @@ typedef enum {
 
 typedef enum {
   MS_PREC_FP64 = 0,        /* every step in FP64 (complex128)                            */
-  MS_PREC_FP32_MFMA = 1    /* star-product GEMMs on FP32 MFMA (complex64, FP32           */
-                           /* accumulation); factorisation, solves and scalings in FP64  */
+  MS_PREC_FP32_MFMA = 1    /* star-product GEMMs on FP32 MFMA (complex64 operands, FP32  */
+                           /* accumulation within each 16-deep K-slab, slabs summed in  */
+                           /* FP64); factorisation, solves, the exactly known diagonal  */
+                           /* and near-threshold terms and all scalings in FP64         */
 } ms_prec;
 
 typedef struct ms_ctx_s* ms_ctx;
@@ -144,8 +146,8 @@ ms_status ms_slice_smatrix(ms_ctx ctx, const ms_slices* slices, double energy, i
  * The inputs are not modified; `whole` must not alias them.  The blocks are c128 in both
  * forms.  prec = MS_PREC_FP64: every step in FP64.  prec = MS_PREC_FP32_MFMA: F = I - S12(a)
  * S21(b), its LU factorisation and the solves with it stay FP64; the six products that
- * follow (S22(a) S21(b), S11(b) W1, ..., their sums) run on FP32 MFMA with FP32 accumulation,
- * their operands rounded to c64 (relative error of the result a few 1e-7 per product).
+ * follow (S22(a) S21(b), S11(b) W1, ..., their sums) run on FP32 MFMA, their operands rounded
+ * to c64 (FP32 accumulation within 16-deep K-slabs, slabs summed in FP64).
  * Errors: MS_ERR_ARG (sizes, nulls, aliasing, unknown prec); MS_ERR_SINGULAR via ms_ctx_sync
  * when F has a zero pivot. */
 ms_status ms_star_cascade(ms_ctx ctx, const ms_smat* s, int64_t n, ms_prec prec, ms_smat* whole);
@@ -182,12 +184,18 @@ ms_status ms_transmission(ms_ctx ctx, const ms_smat* whole, double energy, const
 ms_status ms_mixed_doubling(ms_ctx ctx, const ms_slices* slices, double energy, double max_cond, ms_smat* whole,
                             int32_t* mixed_levels);
 
-/* a4+a5+a6 fused, batched over energies that share the slice data: the
- * interfaces are folded from the right lead to the left one; each step is
- * the star product of S(p,p+1) with the accumulated right part, written so
- * that one LU factorisation per interface and energy serves both the
- * slice matrix X and F = I - S12 S21 (exactly equal up to rounding).  No
- * S(p,p+1) is stored.
+/* a4+a5+a6 fused, batched over energies that share the slice data (Sec. II.A, Eqs. smm2 and
+ * recurrence1; App. A, Eqs. transfer, scatter and recurrence; App. C with A^0 = I,
+ * B^{N+1} = 0): the interfaces are folded from the right lead to the left one; each step is
+ * the star product of S(p,p+1) with the accumulated right part, written so that one LU
+ * factorisation per interface and energy serves both the slice matrix X and
+ * F = I - S12 S21 (exactly equal up to rounding).  No S(p,p+1) is stored.  With
+ * rho = P r P the accumulated reflection at slice p+1 and C+- = O^T K_p +- K_{p+1} O^T:
+ *   Phi_A^T = C+ + rho^T C-,   Phi_B^T = C- + rho^T C+,   r_new^T = K_p (Phi_A^-T Phi_B^T) K_p^-1
+ * (the transmitted columns ride along as right-hand sides).  The products rho^T C+- are the
+ * interface GEMM; prec = MS_PREC_FP32_MFMA runs it on FP32 MFMA, with the diagonal of C+ and
+ * the columns of rho^T whose |k_{p+1}| < 0.1 (at most 8 per interface, near a slice
+ * threshold, where rho grows like |k|^-1/2) added in FP64.
  *   energies   [n_e] f64 (host)
  *   T, R       [n_e] f64 (device outputs)
  *   n_open     [n_e] int64 (device output)
@@ -197,16 +205,36 @@ ms_status ms_transmission_batch(ms_ctx ctx, const ms_slices* slices, int64_t n_e
                                 const double* energies, ms_prec prec, double* T, double* R,
                                 int64_t* n_open, int32_t* point_status);
 
-/* ms_transmission_batch for n_k slice sets at once (e.g. several k_par of one junction),
- * n_e energies each: slices [n_k] (equal n_g and n_slices), energies [n_k][n_e] (host),
- * T, R [n_k][n_e] f64, n_open [n_k][n_e] int64, point_status [n_k][n_e] int32 (device).
- * The LU factorisations and back substitutions of all n_k * n_e points run as one batch
- * per interface, which amortises their latency-bound panel steps over more matrices.
+/* ms_transmission_batch for n_k slice sets at once (several k_par of one junction; the
+ * k_par mesh of Sec. II.B, Eq. T1_d), n_e energies each: slices [n_k] (equal n_g and
+ * n_slices), energies [n_k][n_e] (host), T, R [n_k][n_e] f64, n_open [n_k][n_e] int64,
+ * point_status [n_k][n_e] int32 (device).  The LU factorisations and back substitutions of all
+ * n_k * n_e points run as one batch per interface, which amortises their latency-bound panel
+ * steps over more matrices.
  * Errors: MS_ERR_ARG (sizes differ between sets, nulls, non-finite energies),
  * MS_ERR_UNSUPPORTED (n_k > 65535), MS_ERR_ALLOC. */
 ms_status ms_transmission_multi(ms_ctx ctx, int64_t n_k, const ms_slices* slices, int64_t n_e,
                                 const double* energies, ms_prec prec, double* T, double* R, int64_t* n_open,
                                 int32_t* point_status);
+
+/* ms_transmission_batch for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same fold, kernels and
+ * results, with every scratch buffer carved from one array of MS_NOALLOC_SCRATCH_MAX bytes
+ * that the library holds on each device it runs on (a static device array, present until the
+ * process ends).  It calls no hipMalloc, hipFree or allocating library routine, creates no
+ * stream or event (so no look-ahead LU and no event profiling), and grows no context
+ * workspace.  The energies are folded in as many sub-batches as the scratch requires; one
+ * instance (one energy of the set) needs about (2 (n_slices + 2) + 5 n_g + n_open) n_g c128
+ * plus the LU's workspace, so n_g = 300 takes about 10 per sub-batch, n_g = 1200 none.
+ * Every call on a device uses the same array and leaves its contents behind; the call sets
+ * what must start at zero itself.  Calls on one device that overlap in time (several
+ * contexts or streams, several host threads) race on the array: keep them ordered.
+ * Arguments, outputs, status per point and the other errors as ms_transmission_batch;
+ * MS_ERR_UNSUPPORTED (nothing enqueued) when one instance or the call's tables do not fit. */
+#define MS_NOALLOC_SCRATCH_MAX (128LL << 20)
+ms_status ms_transmission_batch_noalloc(ms_ctx ctx, const ms_slices* slices, int64_t n_e,
+                                        const double* energies, ms_prec prec, double* T, double* R,
+                                        int64_t* n_open, int32_t* point_status);
 
 /* Flag of ms_transmission_uneven: capture the whole fold into one hipGraph and launch it. */
 #define MS_FOLD_GRAPH 1

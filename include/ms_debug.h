@@ -17,7 +17,8 @@ extern "C" {
 /* C = alpha op(A) op(B) + beta C for one M x N x K product.  op codes:
  * 0 = none, 1 = transpose, 2 = conjugate transpose.  prec = MS_PREC_FP64:
  * A, B, C complex128.  prec = MS_PREC_FP32_MFMA: A, B complex64, C complex128
- * (FP32 MFMA products with FP32 accumulation).  alpha/beta: {re, im} host pairs. */
+ * (FP32 MFMA products, FP32 accumulation within 16-deep K-slabs summed in FP64).
+ * alpha/beta: {re, im} host pairs. */
 ms_status ms_debug_gemm(ms_ctx ctx, int op_a, int op_b, int64_t m, int64_t n, int64_t k, const void* a,
                         int64_t lda, const void* b, int64_t ldb, void* c, int64_t ldc, const double* alpha,
                         const double* beta, ms_prec prec);

@@ -60,6 +60,7 @@ _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER
 _sig("ms_bloch_pencil", [_vp, ctypes.POINTER(MsSlices), ctypes.c_double, _vp, _vp])
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
+_sig("ms_transmission_batch_noalloc", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_multi", [_vp, _i64, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_uneven", [_vp, _i64, ctypes.POINTER(MsSlices), _vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_graph_replay", [_vp])
@@ -256,6 +257,24 @@ def ms_transmission_batch(ctx: Context, slices: Slices, energies, prec="fp64"):
                                                  e.ctypes.data_as(ctypes.c_void_p), _PREC[prec],
                                                  _ptr(T), _ptr(R), _ptr(no), _ptr(st)))
     return T, R, no, st
+
+
+def ms_transmission_batch_noalloc(ctx: Context, slices: Slices, energies, T=None, R=None, n_open=None, status=None,
+                                  prec="fp64"):
+    """ms_transmission_batch without device allocation inside the library (its scratch is a
+    fixed device array); the outputs may be passed in, so the call allocates nothing at all."""
+    e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).reshape(-1))
+    n_e = e.size
+    T = torch.empty(n_e, dtype=torch.float64, device=ctx.device) if T is None else T
+    R = torch.empty(n_e, dtype=torch.float64, device=ctx.device) if R is None else R
+    n_open = torch.empty(n_e, dtype=torch.int64, device=ctx.device) if n_open is None else n_open
+    status = torch.empty(n_e, dtype=torch.int32, device=ctx.device) if status is None else status
+    _check(ctx.handle, lib.ms_transmission_batch_noalloc(ctx.handle, ctypes.byref(slices.c), n_e,
+                                                         e.ctypes.data_as(ctypes.c_void_p), _PREC[prec],
+                                                         _ptr(T, torch.float64, "T"), _ptr(R, torch.float64, "R"),
+                                                         _ptr(n_open, torch.int64, "n_open"),
+                                                         _ptr(status, torch.int32, "status")))
+    return T, R, n_open, status
 
 
 def ms_transmission_multi(ctx: Context, slices_list, energies, prec="fp64"):
@@ -484,7 +503,7 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_mixed_doubling",
            "ms_transmission",
-           "ms_transmission_batch", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
+           "ms_transmission_batch", "ms_transmission_batch_noalloc", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_lu_solve",
            "ms_debug_eigh",

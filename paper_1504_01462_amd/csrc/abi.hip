@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -15,6 +16,12 @@
 #include "ms_internal.h"
 
 static thread_local std::string g_create_error;
+
+// Scratch of the allocation-free entry point (ms_transmission_batch_noalloc): one array per
+// device, held by every process that loads the library until it ends.  Host code uses the
+// address hipGetSymbolAddress returns for the current device, never the array's name.
+constexpr size_t MS_NOALLOC_SCRATCH_BYTES = (size_t)MS_NOALLOC_SCRATCH_MAX;   // include/ms.h
+static __device__ __align__(256) unsigned char scratch[MS_NOALLOC_SCRATCH_BYTES];
 
 namespace ms {
 
@@ -45,13 +52,31 @@ ms_status check_launch(ms_ctx ctx, const char* what) {
 }
 
 ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->arena) {   // allocation-free mode: bump-allocate from the arena
+    if ((size_t)slot >= ctx->aws.size()) {
+      ctx->aws.resize(slot + 1, nullptr);
+      ctx->aws_size.resize(slot + 1, 0);
+    }
+    if (ctx->aws_size[slot] < bytes) {
+      const size_t want = (bytes + 255) & ~(size_t)255;
+      if (want > ctx->arena_size - ctx->arena_used)
+        return fail(ctx, MS_ERR_UNSUPPORTED,
+                    "the call needs more than the %zu bytes of the allocation-free scratch (slot %d, %zu bytes)",
+                    ctx->arena_size, slot, bytes);
+      ctx->aws[slot] = ctx->arena + ctx->arena_used;
+      ctx->aws_size[slot] = want;
+      ctx->arena_used += want;
+    }
+    *out = ctx->aws[slot];
+    return MS_OK;
+  }
   std::vector<void*>& ws = ctx->use_gws ? ctx->gws : ctx->ws;
   std::vector<size_t>& ws_size = ctx->use_gws ? ctx->gws_size : ctx->ws_size;
   if ((size_t)slot >= ws.size()) {
     ws.resize(slot + 1, nullptr);
     ws_size.resize(slot + 1, 0);
   }
-  if (bytes == 0) bytes = 256;
   if (ws_size[slot] < bytes) {
     if (ctx->capturing)   // the planning pass sizes every slot a captured launch uses
       return fail(ctx, MS_ERR_UNSUPPORTED, "workspace slot %d would grow inside a graph capture", slot);
@@ -83,7 +108,7 @@ static hipEvent_t take_event(ms_ctx ctx) {
 
 Prof::Prof(ms_ctx c, int category, double fl, double by, bool kernel_events)
     : ctx(c), cat(category), flops(fl), bytes(by), ext(kernel_events) {
-  if (ctx && !ctx->capturing && (ctx->prof_mask >> category & 1u)) {
+  if (ctx && !ctx->capturing && !ctx->arena && (ctx->prof_mask >> category & 1u)) {
     a = take_event(ctx);
     if (!a) return;
     if (ext) {
@@ -153,12 +178,19 @@ enum {
   // electrode cells
   WS_BSEG, WS_BWHOLE, WS_BEPS, WS_BOVL,
   // complex64 operands of the FP32 form of the star product
-  WS_S32A, WS_S32B
+  WS_S32A, WS_S32B,
+  // near-threshold columns of the FP32-MFMA fold
+  WS_SEL
 };
 
 constexpr int MAX_N = 4096;
 constexpr int64_t MAX_GRAPH_KERNELS = 96000;   // kernels one captured fold graph may hold
 constexpr size_t BATCH_BUDGET = size_t(24) << 30;   // bytes of per-energy workspace per sub-batch
+constexpr size_t ARENA_TABLES = size_t(1) << 20;     // arena bytes kept for the fold's tables
+// FP32-MFMA fold: columns of rho^T whose |k| in slice p+1 is below THRESH_K (at most THRESH_CAP
+// per instance and interface) are taken out of the FP32 product and added in FP64
+constexpr double THRESH_K = 0.1;
+constexpr int THRESH_CAP = 8;
 constexpr size_t PREP_BUDGET = size_t(8) << 30;     // bytes of eigensolver workspace per chunk
 constexpr int WARM_STRIDE = 8;                       // reference slices for the warm-started eigensolver
 
@@ -1187,7 +1219,7 @@ struct FoldGroup {          // the sets of one n_g, longest first
   double cost = 0.0;                // n^3 x fold steps x instances, for placing groups on streams
   double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
   void* aop = nullptr;
-  int32_t* piv = nullptr;
+  int32_t *piv = nullptr, *sel = nullptr;
 };
 
 struct FoldPlan {
@@ -1322,10 +1354,19 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
   // each group's scratch comes from its runner's workspace; a runner that serves several
   // groups (one after the other on its stream) is first grown to the largest need per slot,
   // so no later request moves a buffer an earlier group already holds
-  const int slots[7] = {WS_K, WS_P, WS_AOP, WS_WG, WS_M, WS_Y, WS_PIV};
+  const int slots[8] = {WS_K, WS_P, WS_AOP, WS_WG, WS_M, WS_Y, WS_PIV, WS_SEL};
+  // allocation-free mode (one group): the arena left for the per-instance scratch
+  const size_t arena_left =
+      ctx->arena ? ctx->arena_size - std::min(ctx->arena_size, ctx->arena_used + ARENA_TABLES) : 0;
+  if (ctx->arena && P.groups.size() != 1)
+    return fail(ctx, MS_ERR_UNSUPPORTED, "the allocation-free fold takes slice sets of one basis size");
   auto needs = [&](FoldGroup& G, size_t* nd) {
     const FoldDims d = fold_dims(G, P.fp32);
-    const int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, (int64_t)(BATCH_BUDGET / d.per_e)));
+    // sub-batch: the instances whose scratch fits the budget (in the allocation-free mode what
+    // is left of the arena after the tables, the LU's workspace counted per instance)
+    int64_t fit = (int64_t)(BATCH_BUDGET / d.per_e);
+    if (ctx->arena) fit = (int64_t)(arena_left / (d.per_e + lu_bytes_per_matrix(G.n, d.ldm) + 10 * 256));
+    const int64_t nbi = std::max<int64_t>(1, std::min<int64_t>(G.ni, fit));
     G.nbi = (int)std::min<int64_t>(nbi, 65535);
     nd[0] = nd[1] = (size_t)G.nbi * d.sk * sizeof(double2);
     nd[2] = (size_t)G.nbi * d.nn * d.asz;
@@ -1333,17 +1374,18 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     nd[4] = (size_t)G.nbi * d.sM * sizeof(double2);
     nd[5] = (size_t)G.nbi * d.sY * sizeof(double2);
     nd[6] = (size_t)G.nbi * G.n * sizeof(int32_t);
+    nd[7] = (size_t)G.nbi * (THRESH_CAP + 1) * sizeof(int32_t);
     return d;
   };
   for (FoldGroup& G : P.groups) {   // pass 1: grow every runner to its groups' largest needs
-    size_t nd[7];
+    size_t nd[8];
     const FoldDims d = needs(G, nd);
     void* v;
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < 8; ++i) {
       size_t most = nd[i];
       for (FoldGroup& H : P.groups)
         if (H.run == G.run) {
-          size_t nh[7];
+          size_t nh[8];
           needs(H, nh);
           most = std::max(most, nh[i]);
         }
@@ -1367,6 +1409,8 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     G.yb = c2(v);
     MS_TRY(workspace(c, WS_PIV, 1, &v));
     G.piv = (int32_t*)v;
+    MS_TRY(workspace(c, WS_SEL, 1, &v));
+    G.sel = (int32_t*)v;
   }
   void *chd, *end, *pmd, *v;
   MS_TRY(workspace(ctx, WS_CH, chh.size() * sizeof(int32_t), &chd));
@@ -1421,7 +1465,9 @@ ms_status enqueue_group(ms_ctx c, const FoldPlan& P, const FoldGroup& G) {
       const double2* pq = G.pb + (q + 1) * n;
       const bool first = (s == 0);
       if (!first) {
-        MS_TRY(launch_prologue(c, n, act, G.yb, d.ldy, sY, kq, pq, sk, G.aop, fp32));
+        if (fp32) MS_TRY(launch_thresh_select(c, n, act, kq, sk, THRESH_K, THRESH_CAP, G.sel));
+        MS_TRY(launch_prologue(c, n, act, G.yb, d.ldy, sY, kq, pq, sk, fp32 ? G.sel : nullptr, THRESH_CAP, G.aop,
+                               fp32));
         for (const Seg& g : segs) {
           if (g.ns < s) break;
           // W = rho^T [C- | C+ off its diagonal] for the set's energies, B generated from the
@@ -1442,8 +1488,9 @@ ms_status enqueue_group(ms_ctx c, const FoldPlan& P, const FoldGroup& G) {
         if (g.ns < s) break;
         const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
         MS_TRY(launch_epilogue(c, n, g.m, O, first ? nullptr : G.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
-                               kq + g.a * sk, pq + g.a * sk, sk, G.yb + g.a * sY, d.ldy, sY, G.mm + g.a * sM, d.ldm,
-                               sM));
+                               kq + g.a * sk, pq + g.a * sk, sk, G.yb + g.a * sY, d.ldy, sY,
+                               (fp32 && !first) ? G.sel + (int64_t)g.a * (THRESH_CAP + 1) : nullptr, THRESH_CAP,
+                               G.mm + g.a * sM, d.ldm, sM));
         MS_TRY(launch_tcols(c, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, G.yb + g.a * sY, d.ldy, sY, n,
                             kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, G.mm + g.a * sM, d.ldm, sM));
       }
@@ -1632,6 +1679,58 @@ ms_status ms_transmission_uneven(ms_ctx ctx, int64_t n_sets, const ms_slices* se
     return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
   MS_TRY(check_energies(ctx, total, energies));
   return fold_run(ctx, P, energies, prec, (flags & MS_FOLD_GRAPH) != 0, T, R, n_open, point_status);
+}
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// the device address of `scratch` on ctx's device (looked up once per device, with that
+// device current)
+ms_status scratch_of(ms_ctx ctx, char** out) {
+  if (ctx->device < 0 || ctx->device >= MAX_DEVICES)
+    return fail(ctx, MS_ERR_UNSUPPORTED, "device %d beyond the %d the scratch table holds", ctx->device, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[ctx->device] = p;
+  }
+  *out = static_cast<char*>(g_scratch_ptr[ctx->device]);
+  return MS_OK;
+}
+}  // namespace
+
+ms_status ms_transmission_batch_noalloc(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const double* energies,
+                                        ms_prec prec, double* T, double* R, int64_t* n_open, int32_t* point_status) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_slices(ctx, slices));
+  if (n_e < 0) return fail(ctx, MS_ERR_ARG, "n_e must be >= 0");
+  if (n_e == 0) return MS_OK;
+  if (bad_ptr(energies) || bad_ptr(T) || bad_ptr(R) || bad_ptr(n_open) || bad_ptr(point_status))
+    return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (prec != MS_PREC_FP64 && prec != MS_PREC_FP32_MFMA) return fail(ctx, MS_ERR_ARG, "unknown precision");
+  MS_TRY(check_energies(ctx, n_e, energies));
+  if (ctx->capturing) return fail(ctx, MS_ERR_UNSUPPORTED, "called inside the library's own capture");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  char* base = nullptr;
+  MS_TRY(scratch_of(ctx, &base));
+  // every call carves its slots from the start of the device's scratch
+  ctx->arena = base;
+  ctx->arena_size = MS_NOALLOC_SCRATCH_BYTES;
+  ctx->arena_used = 0;
+  ctx->aws.clear();
+  ctx->aws_size.clear();
+  FoldPlan P;
+  P.sets.push_back(FoldSet{slices, 0, n_e});
+  const ms_status st = fold_run(ctx, P, energies, prec, false, T, R, n_open, point_status);
+  ctx->arena = nullptr;
+  ctx->arena_size = ctx->arena_used = 0;
+  ctx->aws.clear();
+  ctx->aws_size.clear();
+  return st;
 }
 
 ms_status ms_graph_replay(ms_ctx ctx) {

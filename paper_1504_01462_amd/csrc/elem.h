@@ -4,13 +4,19 @@
 
 namespace ms {
 
-// A = rho^T (n x n per energy, complex64 when fp32) for the interface product
+// near-threshold columns of each instance (|kq_m| < thr, the first `cap` in index order):
+// sel [n_e][cap + 1] int32 = count, indices
+ms_status launch_thresh_select(ms_ctx ctx, int n, int n_e, const double2* kq, int64_t sk, double thr, int cap,
+                               int32_t* sel);
+// A = rho^T (n x n per energy, complex64 when fp32) for the interface product, the columns in sel
+// (may be null) left out
 ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t ldy, int64_t sY, const double2* kq,
-                          const double2* pq, int64_t sk, void* Aop, bool fp32);
-// M = [Phi_A^T | Phi_B^T] from O, the product W = rho^T [C- | C+ off its diagonal] (null: rho = 0) and Y
+                          const double2* pq, int64_t sk, const int32_t* sel, int cap, void* Aop, bool fp32);
+// M = [Phi_A^T | Phi_B^T] from O, the product W = rho^T [C- | C+ off its diagonal] (null: rho = 0),
+// Y, and the FP64 terms of the columns in sel (may be null)
 ms_status launch_epilogue(ms_ctx ctx, int n, int n_e, const double2* O, const double2* Wg, const double2* kp,
                           const double2* kq, const double2* pq, int64_t sk, const double2* Y, int64_t ldy, int64_t sY,
-                          double2* M, int64_t ldm, int64_t sM);
+                          const int32_t* sel, int cap, double2* M, int64_t ldm, int64_t sM);
 ms_status launch_tcols(ms_ctx ctx, int n, int n_o, int n_e, const int32_t* ch, const double2* Y, int64_t ldy,
                        int64_t sY, int y_off, const double2* kq, const double2* pq, int64_t sk, int first, double2* M,
                        int64_t ldm, int64_t sM);

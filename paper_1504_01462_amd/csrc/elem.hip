@@ -62,29 +62,59 @@ __global__ void k_scatter_results(int64_t count, const int64_t* perm, const doub
 __device__ __forceinline__ void put(double2* d, double2 v) { *d = v; }
 __device__ __forceinline__ void put(float2* d, double2 v) { *d = make_float2((float)v.x, (float)v.y); }
 
-// A_e = rho^T,  rho^T_ij = P_i k_i Y_ij P_j / k_j  (k, P of slice p+1; Y = Y1 of the state)
+// Near-threshold columns of the FP32-MFMA form: per instance e, the first (in index order) at
+// most `cap` indices m with |kq_m| < thr, as sel[e][0] = count, sel[e][1..count] = indices
+// (one wave per instance, ballots over 64 indices at a time, so the order is fixed).
+__global__ __launch_bounds__(64) void k_thresh_select(int n, const double2* kq, int64_t sk, double thr, int cap,
+                                                      int32_t* sel) {
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double2* k = kq + e * sk;
+  int32_t* out = sel + e * (int64_t)(cap + 1);
+  int count = 0;
+  for (int m0 = 0; m0 < n && count < cap; m0 += 64) {
+    const int m = m0 + lane;
+    const bool hit = m < n && (k[m].x * k[m].x + k[m].y * k[m].y) < thr * thr;
+    const unsigned long long mask = __ballot(hit);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (hit && count + before < cap) out[1 + count + before] = m;
+    count += __popcll(mask);
+  }
+  if (lane == 0) out[0] = min(count, cap);
+}
+
+// A_e = rho^T,  rho^T_ij = P_i k_i Y_ij P_j / k_j  (k, P of slice p+1; Y = Y1 of the state);
+// with sel (FP32 form) the selected near-threshold columns are left out (zero)
 template <typename OutT>
 __global__ void k_prologue(int n, const double2* Y, int64_t ldy, int64_t sY, const double2* kq, const double2* pq,
-                           int64_t sk, OutT* Aop) {
+                           int64_t sk, const int32_t* sel, int cap, OutT* Aop) {
   const int64_t e = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * n) return;
   const int i = (int)(idx / n), j = (int)(idx % n);
   const double2* k = kq + e * sk;
   const double2* P = pq + e * sk;
+  bool skip = false;
+  if (sel) {
+    const int32_t* se = sel + e * (int64_t)(cap + 1);
+    for (int c = 0; c < se[0]; ++c) skip = skip || se[1 + c] == j;
+  }
   const double2 y = Y[e * sY + (int64_t)i * ldy + j];
-  put(Aop + e * (int64_t)n * n + idx, cdiv(cmul(cmul(cmul(P[i], k[i]), y), P[j]), k[j]));
+  put(Aop + e * (int64_t)n * n + idx,
+      skip ? make_double2(0.0, 0.0) : cdiv(cmul(cmul(cmul(P[i], k[i]), y), P[j]), k[j]));
 }
 
 // With C+- = O^T K_p +- K_{p+1} O^T (elementwise: O_ji (kp_j +- kq_i)) and W = rho^T [C- | C+ off
 // its diagonal] from the interface product:
 //   M_e[:, 0:n]  = Phi_A^T = C+ + rho^T C-
 //   M_e[:, n:2n] = Phi_B^T = C- + rho^T C+   (the diagonal part rho^T_ij C+_jj added here, in FP64)
-// rho^T is formed again from Y in FP64.  O^T read through a 32 x 32 LDS tile; W may be null
-// (first interface: rho = 0).
+// rho^T is formed again from Y in FP64, and so are the terms of the near-threshold columns m in
+// sel (left out of the FP32 product): rho^T_im C-_mj and rho^T_im C+_mj (m != j).  O^T read
+// through a 32 x 32 LDS tile; W may be null (first interface: rho = 0).
 __global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const double2* Wg, const double2* kp,
                                                   const double2* kq, const double2* pq, int64_t sk, const double2* Y,
-                                                  int64_t ldy, int64_t sY, double2* M, int64_t ldm, int64_t sM) {
+                                                  int64_t ldy, int64_t sY, const int32_t* sel, int cap, double2* M,
+                                                  int64_t ldm, int64_t sM) {
   __shared__ double2 tile[32][33];
   const int64_t e = blockIdx.z;
   const int bi = blockIdx.y * 32, bj = blockIdx.x * 32;
@@ -98,6 +128,8 @@ __global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const
   const double2* k_p = kp + e * sk;
   const double2* k_q = kq + e * sk;
   const double2* P = pq + e * sk;
+  const int32_t* se = sel ? sel + e * (int64_t)(cap + 1) : nullptr;
+  const int nsel = se ? se[0] : 0;
   for (int r = ty; r < 32; r += 8) {
     const int i = bi + r, j = bj + tx;
     if (i >= n || j >= n) continue;
@@ -111,10 +143,20 @@ __global__ __launch_bounds__(256) void k_epilogue(int n, const double2* O, const
       continue;
     }
     const double2* W = Wg + e * 2 * (int64_t)n * n + (int64_t)i * 2 * n;
-    const double2 rho = cdiv(cmul(cmul(cmul(P[i], k_q[i]), Y[e * sY + (int64_t)i * ldy + j]), P[j]), k_q[j]);
+    const double2* Yi = Y + e * sY + (int64_t)i * ldy;
+    const double2 pk = cmul(P[i], k_q[i]);
+    const double2 rho = cdiv(cmul(cmul(pk, Yi[j]), P[j]), k_q[j]);
     const double2 cpd = cmul(O[(int64_t)j * n + j], cadd(k_p[j], k_q[j]));
-    Mr[j] = cadd(cp, W[j]);
-    Mr[n + j] = cadd(cadd(cm, W[n + j]), cmul(rho, cpd));
+    double2 wm = W[j], wp = cadd(W[n + j], cmul(rho, cpd));
+    for (int c = 0; c < nsel; ++c) {
+      const int m = se[1 + c];
+      const double2 rm = cdiv(cmul(cmul(pk, Yi[m]), P[m]), k_q[m]);
+      const double2 ojm = O[(int64_t)j * n + m];
+      wm = cadd(wm, cmul(rm, cmul(ojm, csub(k_p[j], k_q[m]))));
+      if (m != j) wp = cadd(wp, cmul(rm, cmul(ojm, cadd(k_p[j], k_q[m]))));
+    }
+    Mr[j] = cadd(cp, wm);
+    Mr[n + j] = cadd(cm, wp);
   }
 }
 
@@ -574,22 +616,29 @@ ms_status launch_scatter_results(ms_ctx ctx, int64_t count, const int64_t* perm,
   return check_launch(ctx, "scatter results");
 }
 
+ms_status launch_thresh_select(ms_ctx ctx, int n, int n_e, const double2* kq, int64_t sk, double thr, int cap,
+                               int32_t* sel) {
+  hipLaunchKernelGGL(k_thresh_select, dim3(n_e), dim3(64), 0, ctx->stream, n, kq, sk, thr, cap, sel);
+  return check_launch(ctx, "threshold select");
+}
+
 ms_status launch_prologue(ms_ctx ctx, int n, int n_e, const double2* Y, int64_t ldy, int64_t sY, const double2* kq,
-                          const double2* pq, int64_t sk, void* Aop, bool fp32) {
+                          const double2* pq, int64_t sk, const int32_t* sel, int cap, void* Aop, bool fp32) {
   if (fp32)
     hipLaunchKernelGGL((k_prologue<float2>), dim3(blocks((int64_t)n * n), n_e), dim3(256), 0, ctx->stream, n, Y, ldy,
-                       sY, kq, pq, sk, static_cast<float2*>(Aop));
+                       sY, kq, pq, sk, sel, cap, static_cast<float2*>(Aop));
   else
     hipLaunchKernelGGL((k_prologue<double2>), dim3(blocks((int64_t)n * n), n_e), dim3(256), 0, ctx->stream, n, Y,
-                       ldy, sY, kq, pq, sk, static_cast<double2*>(Aop));
+                       ldy, sY, kq, pq, sk, sel, cap, static_cast<double2*>(Aop));
   return check_launch(ctx, "prologue");
 }
 
 ms_status launch_epilogue(ms_ctx ctx, int n, int n_e, const double2* O, const double2* Wg, const double2* kp,
                           const double2* kq, const double2* pq, int64_t sk, const double2* Y, int64_t ldy, int64_t sY,
-                          double2* M, int64_t ldm, int64_t sM) {
+                          const int32_t* sel, int cap, double2* M, int64_t ldm, int64_t sM) {
   dim3 g((n + 31) / 32, (n + 31) / 32, n_e);
-  hipLaunchKernelGGL(k_epilogue, g, dim3(256), 0, ctx->stream, n, O, Wg, kp, kq, pq, sk, Y, ldy, sY, M, ldm, sM);
+  hipLaunchKernelGGL(k_epilogue, g, dim3(256), 0, ctx->stream, n, O, Wg, kp, kq, pq, sk, Y, ldy, sY, sel, cap, M, ldm,
+                     sM);
   return check_launch(ctx, "epilogue");
 }
 

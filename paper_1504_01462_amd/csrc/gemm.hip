@@ -4,8 +4,8 @@
 // Complex operands are split into real/imaginary planes when staged into LDS;
 // each 16x16x4 complex block is four real MFMAs
 //   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br
-// (v_mfma_f64_16x16x4f64 for complex128, v_mfma_f32_16x16x4f32 with FP32
-// accumulation for complex64).  Operand layouts of both: lane l holds
+// (v_mfma_f64_16x16x4f64 for complex128, v_mfma_f32_16x16x4f32 for complex64:
+// FP32 accumulation inside each K-slab of 16, the slabs summed in FP64).  Operand layouts of both: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator layouts differ
 // (see Mfma<T>::crow).  Workgroup = 4 wave64s in a 2x2 grid; each wave
 // owns a sub-tile (64x64 tiles with 4 waves for small problems, 128x128 tiles
@@ -224,6 +224,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       cr[a][c] = acc_t{0, 0, 0, 0};
       ci[a][c] = acc_t{0, 0, 0, 0};
     }
+  // FP32 MFMA: each K-slab accumulates in FP32 (four MFMA steps), and the slabs are summed in
+  // FP64, so the FP32 rounding chain of an element is 4 long instead of K / 4
+  constexpr bool kSlab64 = !kFold;
+  double sr[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4], si[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4];
+  if constexpr (kSlab64) {
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int c = 0; c < FN; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sr[a][c][v] = si[a][c][v] = 0.0;
+  }
 
   // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
   // other one; one barrier per slab
@@ -281,6 +293,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
           ci[a][c] = Mfma<T>::mac(ai[a], br[c], ci[a][c]);
         }
     }
+    if constexpr (kSlab64) {
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int c = 0; c < FN; ++c) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            sr[a][c][v] += (double)cr[a][c][v];
+            si[a][c][v] += (double)ci[a][c][v];
+          }
+          cr[a][c] = acc_t{0, 0, 0, 0};
+          ci[a][c] = acc_t{0, 0, 0, 0};
+        }
+    }
     if (k0 + BK < p.K) {
       stash(cur ^ 1, k0 + BK);              // slab k0+BK (already in registers)
       if (k0 + 2 * BK < p.K) load(k0 + 2 * BK);
@@ -309,7 +335,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
             C[(int64_t)row * p.ldc + col] = make_double2((double)cr[a][c][v], (double)ci[a][c][v]);
             continue;
           }
-          const double re = (double)cr[a][c][v], im = (double)ci[a][c][v];
+          double re, im;
+          if constexpr (kSlab64) {
+            re = sr[a][c][v];
+            im = si[a][c][v];
+          } else {
+            re = (double)cr[a][c][v];
+            im = (double)ci[a][c][v];
+          }
           double2 out;
           out.x = p.alpha.x * re - p.alpha.y * im;
           out.y = p.alpha.x * im + p.alpha.y * re;
@@ -373,12 +406,21 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
   if (tile_env == 64) tile = 64;
   if (tile == 0)
     tile = (g.prof != PC_LU_UPDATE && g.prof != PC_LU_INNER && g.M >= 128 && g.N >= 128) ? 128 : 64;
-  const bool big = tile == 128;
-  if (g.prof == PC_LU_UPDATE)
-    return big ? launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof);
-  if (gen)
-    return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
-  return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
+  // FP32 MFMA keeps FP64 sums of its K-slabs: a 128 x 128 tile would spill, so 64 x 64 always
+  if constexpr (!std::is_same<T, double>::value) {
+    if (gen) return launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
+    return g.prof == PC_LU_UPDATE ? launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof)
+                                  : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
+  } else {
+    const bool big = tile == 128;
+    if (g.prof == PC_LU_UPDATE)
+      return big ? launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof)
+                 : launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof);
+    if (gen)
+      return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof)
+                 : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
+    return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
+  }
 }
 
 }  // namespace

@@ -655,6 +655,10 @@ static size_t trsm_dinv_bytes(int n, int batch) {
   return (size_t)batch * ((n + 63) / 64) * 64 * 64 * sizeof(double2);
 }
 
+size_t lu_bytes_per_matrix(int n, int ncols) {
+  return lu_tbuf_bytes(ncols, 1) + lu_linv_bytes(1) + trsm_dinv_bytes(n, 1);
+}
+
 ms_status lu_reserve(ms_ctx ctx, int n, int ncols, int batch) {
   void* p = nullptr;
   MS_TRY(workspace(ctx, 30, lu_tbuf_bytes(ncols, batch), &p));
@@ -687,7 +691,7 @@ ms_status getrf_aug(ms_ctx ctx, double2* A, int n, int ncols, int64_t strideA, i
   ms_ctx cp = ctx;
   bool lookahead = false;
   if (const char* env = getenv("MS_LU_LOOKAHEAD"))
-    lookahead = n > OUTER && ncols > n && atoi(env) != 0 && !ctx->capturing;
+    lookahead = n > OUTER && ncols > n && atoi(env) != 0 && !ctx->capturing && !ctx->arena;
   hipEvent_t ev_panel = nullptr, ev_next = nullptr;
   if (lookahead) {
     MS_TRY(child(ctx, 0, &cp));

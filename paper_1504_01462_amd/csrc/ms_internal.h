@@ -63,6 +63,13 @@ struct ms_ctx_s {
   std::vector<void*> gws;
   std::vector<size_t> gws_size;
   bool use_gws = false;
+  // allocation-free mode: every workspace slot is carved from `arena` (a device array of
+  // arena_size bytes the library owns), bump-allocated from its start for each call; no
+  // device allocation, no event creation, no look-ahead stream
+  char* arena = nullptr;
+  size_t arena_size = 0, arena_used = 0;
+  std::vector<void*> aws;
+  std::vector<size_t> aws_size;
 };
 
 namespace ms {
@@ -100,7 +107,8 @@ ms_status hip_fail(ms_ctx ctx, hipError_t e, const char* what);
     if (_e != hipSuccess) return ms::hip_fail(ctx, _e, #expr); \
   } while (0)
 
-// workspace slot `slot` of at least `bytes` (synchronises the stream before growing)
+// workspace slot `slot` of at least `bytes` (synchronises the stream before growing; in the
+// allocation-free mode a new region of the arena instead, or MS_ERR_UNSUPPORTED past its end)
 ms_status workspace(ms_ctx ctx, int slot, size_t bytes, void** out);
 ms_status check_launch(ms_ctx ctx, const char* what);
 // internal child context i of ctx (own stream of default priority, own workspace,
@@ -179,5 +187,7 @@ ms_status launch_scatter_results(ms_ctx ctx, int64_t count, const int64_t* perm,
                                  int32_t* status);
 // workspace of getrf_aug and trsm_upper_aug for `batch` matrices, grown ahead (before a capture)
 ms_status lu_reserve(ms_ctx ctx, int n, int ncols, int batch);
+// bytes of that workspace per matrix of a batch
+size_t lu_bytes_per_matrix(int n, int ncols);
 
 }  // namespace ms
