@@ -550,6 +550,26 @@ def test_transmission_uneven_matches_batch_and_oracle(ms, ctx, graph):
             assert torch.all(st == 0)
 
 
+def test_graph_replay_after_slices_prepared_again(ms, ctx):
+    """The captured fold reads the slice data at replay: the same Slices buffers prepared again
+    from another potential (same k_par, so the same lead channels) replay to the direct call's
+    T and R on the new data."""
+    sets = _uneven_sets(ms, ctx)
+    es = [e for _, _, e in sets]
+    T, R, no, st = ms.ms_transmission_uneven(ctx, [s for _, s, _ in sets], es, "fp64", graph=True)
+    ctx.sync()
+    t_old = _np(T).copy()
+    for inp, s, _ in sets:   # 0.7 times the potential, into the same buffers
+        ms.prepare_from_inputs_into(ctx, dict(inp, vq=0.7 * inp["vq"]), s)
+    ms.ms_graph_replay(ctx)
+    ctx.sync()
+    ref = ms.ms_transmission_uneven(ctx, [s for _, s, _ in sets], es, "fp64")
+    ctx.sync()
+    assert np.max(np.abs(_np(T) - _np(ref[0]))) < 1e-12 and np.max(np.abs(_np(R) - _np(ref[1]))) < 1e-12
+    assert np.max(np.abs(_np(T) - t_old)) > 1e-3          # the new data did change T
+    assert torch.all(st == 0)
+
+
 def test_transmission_uneven_fp32_form(ms, ctx):
     sets = _uneven_sets(ms, ctx)
     args = ([s for _, s, _ in sets], [e for _, _, e in sets])
@@ -709,6 +729,8 @@ def test_transmission_autograd(ms, ctx):
     dz = torch.as_tensor(np.ascontiguousarray(inp["dz"]), device=dev)
     T = ms.Transmission.apply(vq, ctx, miller, np.asarray(inp["bvec"]).reshape(4), inp["kpar"], q, dz, e, 3)
     (3.0 * T).backward()
+    with pytest.raises(ValueError):
+        ms.Transmission.apply(vq, ctx, miller, np.asarray(inp["bvec"]).reshape(4), inp["kpar"], q, dz, [e, 1.2], 3)
     ref_T = float(_np(ms.ms_transmission_batch(ctx, s, [e])[0])[0])
     g = _np(ms.ms_dT_dV(ctx, s, e, q, inp["vq"].shape[1])[0])
     ctx.sync()
