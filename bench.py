@@ -84,7 +84,66 @@ def parse():
     ap.add_argument("--no-event-profile", action="store_true",
                     help="record no HIP events around launches (no roofline figure; for external profilers)")
     ap.add_argument("--workers", type=int, default=16, help="processes generating the seeded inputs")
+    ap.add_argument("--probe", choices=["iface64", "iface32", "lu", "eigh", "copy"],
+                    help="run one kernel at the benchmark's launch shape (for profiler counters) and exit: "
+                         "the interface product (FP64 or FP32 MFMA, n_g 1200, 32 energies), the LU solve of "
+                         "32 augmented systems, 8 slice eigenproblems, or a 1 GiB device copy (calibration)")
+    ap.add_argument("--probe-launches", type=int, default=5)
     return ap.parse_args()
+
+
+def probe(kind, launches):
+    """One kernel kind at the benchmark's launch shape, timed with stream events; one JSON line."""
+    import torch
+    import paper_1504_01462_amd as ms
+    ctx = ms.Context(0)
+    dev = ctx.device
+    g = torch.Generator(device=dev).manual_seed(1)
+    n, batch = 1200, 32
+
+    def crand(*shape, dtype=torch.complex128):
+        return torch.randn(*shape, generator=g, device=dev, dtype=dtype)
+
+    if kind.startswith("iface"):
+        dt = torch.complex128 if kind == "iface64" else torch.complex64
+        a, o = crand(batch, n, n, dtype=dt), crand(n, n) / n ** 0.5
+        kp, kq = crand(batch, n), crand(batch, n)
+        run = lambda: ms.ms_debug_iface_product(ctx, a, o, kp, kq, "fp64" if kind == "iface64" else "fp32")
+        work = {"flop": 8.0 * n * 2 * n * n * batch,
+                "bytes": batch * n * n * a.element_size() + 16.0 * n * n + 2 * 16.0 * batch * n + 16.0 * batch * 2 * n * n}
+    elif kind == "lu":
+        nrhs = n + 13
+        src = crand(batch, n, n + nrhs)
+        src[:, :, :n] += 4.0 * n ** 0.5 * torch.eye(n, device=dev, dtype=torch.complex128)
+        aug = src.clone()
+        run = lambda: (aug.copy_(src), ms.ms_debug_lu_solve(ctx, aug, n))
+        work = {"flop": 8.0 * batch * (n ** 3 / 3.0 + n * n * nrhs), "bytes": 16.0 * batch * n * (n + nrhs)}
+    elif kind == "eigh":
+        nb = 8
+        h = crand(nb, n, n)
+        h = (h + h.conj().transpose(1, 2)).contiguous()
+        shift = torch.full((nb,), 6.0 * n ** 0.5, dtype=torch.float64, device=dev)   # > the spectral radius
+        run = lambda: ms.ms_debug_eigh(ctx, h, shift)
+        work = {"flop": 8.0 * nb * 3.0 * n ** 3, "bytes": 16.0 * nb * 2 * n * n}
+    else:
+        x = torch.empty(1 << 26, dtype=torch.complex128, device=dev)
+        y = torch.empty_like(x)
+        run = lambda: y.copy_(x)
+        work = {"flop": 0.0, "bytes": 2.0 * x.numel() * 16}
+    run()
+    ctx.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        run()
+    e1.record()
+    ctx.sync()
+    torch.cuda.synchronize()
+    ms_per = e0.elapsed_time(e1) / launches
+    print(json.dumps({"probe": kind, "launches": launches, "ms_per_launch": ms_per,
+                      "tflops": work["flop"] / ms_per / 1e9 if work["flop"] else None,
+                      "gbps": work["bytes"] / ms_per / 1e6, **work}), flush=True)
+    ctx.close()
 
 
 def workload(name):
@@ -489,6 +548,9 @@ def main():
     def log(msg):
         print(f"[bench {elapsed():6.1f}s] {msg}", file=sys.stderr, flush=True)
 
+    if args.probe:
+        probe(args.probe, max(1, args.probe_launches))
+        return
     # ---- seeded inputs, generated in worker processes before this process loads the GPU
     # library or touches the GPU (the pool and its workers are gone before that)
     from concurrent.futures import ProcessPoolExecutor

@@ -329,8 +329,13 @@ ms_status ms_set_tiles(ms_ctx ctx, int64_t n_g, const ms_tiles* tiles);
 ms_status ms_autotune(ms_ctx ctx, int64_t n_g, int64_t n_open, int64_t batch, ms_tiles* chosen, double* times_ms);
 
 /* Launch the graph captured by the last ms_transmission_uneven(..., MS_FOLD_GRAPH, ...) on
- * this context again, on the context's stream: the same slice data, energies, channel
- * lists and output buffers (their contents may have changed; the sizes may not).
+ * this context again, on the context's stream.  The graph reads the slice sets' device data
+ * (eps, ovl, dz) and writes the output buffers given at capture, whose contents may have
+ * changed since (e.g. the same Slices buffers prepared again from another potential); their
+ * sizes and addresses may not.  Fixed at capture are the energies and each set's right-lead
+ * open-channel table (read from eps at the set's highest energy): a replay after changing the
+ * lead channel energies (another k_par or lead potential) folds with the captured channel
+ * columns, so capture again then.
  * Errors: MS_ERR_ARG (no graph), MS_ERR_HIP. */
 ms_status ms_graph_replay(ms_ctx ctx);
 

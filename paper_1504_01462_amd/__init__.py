@@ -346,24 +346,28 @@ def ms_dT_dV(ctx: Context, slices: Slices, energies, q_of_ij: torch.Tensor, n_q:
 
 class Transmission(torch.autograd.Function):
     """T(E, k_par) as a differentiable function of the slice potentials vq [n_slices][n_q]
-    (complex128, device).  forward: a1-a3 (with eigenvectors) and the right-cascade
-    checkpoints' run of ms_dT_dV, which also yields T; backward: the gradient it computed,
-    in PyTorch's convention for complex inputs of a real output (dL/dRe + i dL/dIm =
-    2 conj(g) dL/dT, treating every vq entry as independent).
+    (complex128, device), at one energy.  forward: a1-a3 with the eigenvectors kept, then the
+    fused fold for T (ms_transmission_batch); backward: the adjoint sweep (ms_dT_dV) on the
+    slices forward prepared, returned in PyTorch's convention for complex inputs of a real
+    output (dL/dRe + i dL/dIm = 2 conj(g) dL/dT, treating every vq entry as independent).  A
+    forward whose result is never differentiated costs one T.
 
         T = Transmission.apply(vq, ctx, miller, bvec, kpar, q_of_ij, dz, energy, checkpoint)
     """
 
     @staticmethod
     def forward(fctx, vq, ctx, miller, bvec, kpar, q_of_ij, dz, energy, checkpoint=0):
+        if np.ndim(energy) != 0:
+            raise ValueError("Transmission takes one energy (a scalar); call it once per energy")
         s = ms_slices_prepare(ctx, miller, bvec, kpar, q_of_ij, vq.detach(), dz, with_evec=True)
-        g, tr, _ = ms_dT_dV(ctx, s, energy, q_of_ij, vq.shape[1], checkpoint)
-        fctx.save_for_backward(g)
-        return tr[0].clone()
+        T = ms_transmission_batch(ctx, s, [float(energy)])[0]
+        fctx.ms = (ctx, s, q_of_ij, int(vq.shape[1]), float(energy), int(checkpoint))
+        return T[0].clone()
 
     @staticmethod
     def backward(fctx, grad_out):
-        (g,) = fctx.saved_tensors
+        ctx, s, q_of_ij, n_q, energy, checkpoint = fctx.ms
+        g, _, _ = ms_dT_dV(ctx, s, energy, q_of_ij, n_q, checkpoint)
         return (2.0 * grad_out * g.conj(),) + (None,) * 8
 
 
@@ -500,6 +504,16 @@ def prepare_from_inputs(ctx: Context, inp: dict, vlead=(0.0, 0.0), with_evec=Fal
                              with_evec)
 
 
+def prepare_from_inputs_into(ctx: Context, inp: dict, out: Slices, vlead=(0.0, 0.0)) -> Slices:
+    """prepare_from_inputs into the buffers of an existing Slices object of the same sizes."""
+    dev = ctx.device
+    miller = torch.as_tensor(np.ascontiguousarray(inp["miller"], dtype=np.int32), device=dev)
+    q = torch.as_tensor(np.ascontiguousarray(inp["q_of_ij"], dtype=np.int32), device=dev)
+    vq = torch.as_tensor(np.ascontiguousarray(inp["vq"], dtype=np.complex128), device=dev)
+    return ms_slices_prepare(ctx, miller, np.asarray(inp["bvec"]).reshape(4), inp["kpar"], q, vq, out.dz, vlead,
+                             out.evec is not None, out=out)
+
+
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_mixed_doubling",
            "ms_transmission",
@@ -507,4 +521,4 @@ __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
            "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_lu_solve",
            "ms_debug_eigh",
-           "prepare_from_inputs", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]
+           "prepare_from_inputs", "prepare_from_inputs_into", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]
