@@ -247,12 +247,13 @@ def cpu_baseline(name, budget_s):
                        f"{ns + 1} interfaces (extrapolated from the sample, not a full point)")}
 
 
-def measured_traffic(cat, flops_per_launch, form, tile=128):
+def measured_traffic(cat, flops_per_launch, form, tile):
     """HBM bytes per launch of the roofline kernel from the committed rocprofv3 counter
-    summary, or None when it covers another kernel, tile shape, launch shape or form, or
-    when the kernel source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{cat}_config3_counters.txt")
-    if form != "fp64" or not os.path.exists(path):
+    summary of that form, or None when it covers another kernel, tile shape or launch shape,
+    or when the kernel source has changed since the counters were taken."""
+    name = {"fp64": f"{cat}_config3_counters.txt", "fp32": f"{cat}32_config3_counters.txt"}.get(form)
+    path = os.path.join(ROOT, "profiles", name) if name else ""
+    if not path or not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
@@ -266,7 +267,7 @@ def measured_traffic(cat, flops_per_launch, form, tile=128):
         n = 1200
         if abs(flops_per_launch - 8.0 * 2 * n * n * n * int(kv["batch"])) > 1.0:
             return None
-        if int(kv.get("tile", "128")) != tile:
+        if int(kv.get("tile", "128")) != tile or kv.get("form", "fp64") != form:
             return None
         return float(kv["traffic_bytes"])
     except (KeyError, ValueError, OSError):
@@ -767,7 +768,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by_per / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if launches else None
-    iface_tile = (tuned_main["choice"]["iface"] if tuned_main else 0) or 128
+    # the FP32 products always use 64 x 64 tiles; FP64 the tuned (or default 128) edge
+    iface_tile = 64 if head == "fp32" else ((tuned_main["choice"]["iface"] if tuned_main else 0) or 128)
     roof["traffic"] = measured_traffic(cat, fl_per, head, iface_tile if cat == "iface_gemm" else 128)
     roof["kernel"] = cat
     if cat == "iface_gemm":

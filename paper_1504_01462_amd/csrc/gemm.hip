@@ -101,9 +101,26 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
   const int hw = blockIdx.x;
   int lid = hw;
   if ((total & 7) == 0) lid = (hw & 7) * (total >> 3) + (hw >> 3);
-  const int tn = lid % ntn;
-  const int tm = (lid / ntn) % ntm;
-  const int64_t b = lid / (ntn * ntm);
+  int tn, tm;
+  int64_t b;
+  if constexpr (ROLE == 1) {
+    // interface product: row tiles r = (batch entry, tm) of all entries share the O panels, so
+    // runs of GROUP consecutive row tiles take each column tile in turn (GROUP blocks on one
+    // XCD read the same O panel while their A panels stay in its L2)
+    constexpr int GROUP = 8;
+    const int nrow = total / ntn;
+    const int per = GROUP * ntn;
+    const int first = (lid / per) * GROUP;
+    const int gsz = min(nrow - first, GROUP);
+    const int r = first + (lid % per) % gsz;
+    tn = (lid % per) / gsz;
+    tm = r % ntm;
+    b = r / ntm;
+  } else {
+    tn = lid % ntn;
+    tm = (lid / ntn) % ntm;
+    b = lid / (ntn * ntm);
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
