@@ -364,6 +364,42 @@ ms_status ms_kpar_average(ms_ctx ctx, int64_t n_k, int64_t n_e, const double* T,
  * MS_ERR_ALLOC; singular X or F via ms_ctx_sync. */
 ms_status ms_bloch_pencil(ms_ctx ctx, const ms_slices* cell, double energy, void* P, void* Q);
 
+/* Complex band structure of an electrode cell at one energy (App. B, Eq. cmp): the 2 n_g Bloch
+ * states of the pencil P X = lam Q X of ms_bloch_pencil, by a complex QZ iteration (unitary
+ * reduction of (P, Q) to upper triangular (S, T), one workgroup per pencil): lam_k = alpha_k /
+ * beta_k, kept as pairs so that states changing by more than FP64 spans over one cell stay exact
+ * (beta_k = 0: an infinite lam), and the right eigenvectors [A^1; B^{M+1}] in the cell's slice-1
+ * eigenbasis.
+ *   cell     the cell's slices 1..M prepared with eigenvectors (as for ms_bloch_pencil)
+ *   alpha, beta [2 n_g] c128 (device outputs; beta real >= 0)
+ *   X        [2 n_g][2 n_g] c128 (device output; column k = state k, unit 2-norm)
+ * Waits for the stream (the iteration's convergence status).  Errors: MS_ERR_ARG,
+ * MS_ERR_UNSUPPORTED (n_g > 2048), MS_ERR_NOCONV (more than 30 sweeps per eigenvalue), MS_ERR_ALLOC. */
+ms_status ms_complex_bands(ms_ctx ctx, const ms_slices* cell, double energy, void* alpha, void* beta, void* X);
+
+/* Transmission between two periodic electrodes through a scattering region (App. C, Eq. trans,
+ * in the S-matrix form of Sec. II.A; the electrodes' Bloch states of App. B, Eq. cmp).  The left
+ * electrode ends with a copy of its cell's slice 1, the region's slices follow, the right
+ * electrode starts with its cell's slice 1; S = S(L1, R1) joins those two reference planes.
+ * Each electrode's 2 n_g Bloch states (ms_complex_bands) are read at the slice-1 plane where each
+ * is largest (|lam| <= 1: (A^1, S21 A^1 + S22 B^{M+1}); otherwise (S11 A^1 + S12 B^{M+1},
+ * B^{M+1}), no division by lam) and sorted by direction: propagating (||lam| - 1| < 1e-8) by the
+ * sign of their flux, evanescent by |lam| (decaying towards +z: right-going).  Per incident
+ * (right-going propagating) state of the left electrode, the 2 n_g amplitudes tau of the right
+ * electrode's right-going states and rho of the left electrode's left-going states solve
+ *   T_a tau = S11 (a_in + R_a rho) + S12 T_b tau,   b_in + R_b rho = S21 (a_in + R_a rho) + S22 T_b tau,
+ * and with the states' flux matrices J(u, v) = (a_u + b_u)^H K (a_v - b_v) + (a_u - b_u)^H K^* (a_v + b_v):
+ *   T = Re Tr[(tau_p^H J_out tau_p) J_in^-1],  R = Re Tr[(rho_p^H J_ref rho_p) J_in^-1]
+ * over the propagating transmitted and reflected states (valid for degenerate states too).
+ *   left, right   electrode cells (slices 1..M, eigenvectors kept); region: the scattering
+ *                 region's slices, eigenvectors kept; one n_g for all three (same basis)
+ *   T, R [1] f64, n_in [1] int64 (device outputs): n_in incident states, T + R = n_in
+ * Waits for the stream.  Errors: MS_ERR_ARG, MS_ERR_UNSUPPORTED (n_g > 2048, more than 24
+ * propagating states per direction), MS_ERR_THRESHOLD (not n_g states per direction: an energy
+ * at a band edge), MS_ERR_NOCONV; a singular matching system via ms_ctx_sync. */
+ms_status ms_electrode_transmission(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
+                                    const ms_slices* right, double energy, double* T, double* R, int64_t* n_in);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,13 @@ ms_status ms_debug_gemm_batched(ms_ctx ctx, int op_a, int op_b, int64_t m, int64
 ms_status ms_debug_iface_product(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* o,
                                  const void* kp, const void* kq, void* w, ms_prec prec);
 
+/* Eigenpairs of `batch` complex pencils A x = lam B x (n x n each, complex128, not modified) by
+ * the library's QZ iteration: alpha, beta [batch][n] complex128 with lam = alpha / beta (beta
+ * real >= 0; beta = 0 for an infinite eigenvalue), x [batch][n][n] right eigenvectors as unit
+ * 2-norm columns, status [batch] int32 (MS_ERR_NOCONV if the iteration did not converge). */
+ms_status ms_debug_qz(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* b, void* alpha, void* beta,
+                      void* x, int32_t* status);
+
 /* For each of `batch` row-major n x (n + nrhs) complex128 matrices [A | B]
  * (batch stride n*(n+nrhs)), factor A with partial pivoting (in place) and
  * write X = A^-1 B to x (n x nrhs per matrix, batch stride n*nrhs).

@@ -58,6 +58,9 @@ _sig("ms_slices_prepare", [_vp, _i64, _vp, _vp, _vp, _f64, _f64, _i64, _i64, _vp
 _sig("ms_slice_smatrix", [_vp, ctypes.POINTER(MsSlices), _f64, _i64, _i64, ctypes.POINTER(MsSmat)])
 _sig("ms_star_cascade", [_vp, ctypes.POINTER(MsSmat), _i64, _i32, ctypes.POINTER(MsSmat)])
 _sig("ms_bloch_pencil", [_vp, ctypes.POINTER(MsSlices), ctypes.c_double, _vp, _vp])
+_sig("ms_complex_bands", [_vp, ctypes.POINTER(MsSlices), _f64, _vp, _vp, _vp])
+_sig("ms_electrode_transmission", [_vp, ctypes.POINTER(MsSlices), ctypes.POINTER(MsSlices), ctypes.POINTER(MsSlices),
+                                   _f64, _vp, _vp, _vp])
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch_noalloc", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
@@ -81,6 +84,7 @@ _sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, 
 _sig("ms_debug_gemm_batched", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
                                 _i64, _i64, _vp, _vp, _i32])
 _sig("ms_debug_iface_product", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32])
+_sig("ms_debug_qz", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_debug_lu_solve", [_vp, _i64, _i64, _i64, _vp, _vp, _vp])
 _sig("ms_debug_eigh", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
 
@@ -220,6 +224,29 @@ def ms_bloch_pencil(ctx: Context, cell: Slices, energy: float):
     _check(ctx.handle, lib.ms_bloch_pencil(ctx.handle, ctypes.byref(cell.c), float(energy),
                                            _ptr(P, torch.complex128, "P"), _ptr(Q, torch.complex128, "Q")))
     return P, Q
+
+
+def ms_complex_bands(ctx: Context, cell: Slices, energy: float):
+    """Bloch states of an electrode cell (its slices 1..M with eigenvectors): alpha, beta [2n]
+    (lam = alpha / beta) and X [2n][2n] (columns [A^1; B^{M+1}], unit norm)."""
+    m = 2 * cell.n_g
+    al = torch.empty(m, dtype=torch.complex128, device=ctx.device)
+    be = torch.empty(m, dtype=torch.complex128, device=ctx.device)
+    X = torch.empty((m, m), dtype=torch.complex128, device=ctx.device)
+    _check(ctx.handle, lib.ms_complex_bands(ctx.handle, ctypes.byref(cell.c), float(energy), _ptr(al), _ptr(be),
+                                            _ptr(X)))
+    return al, be, X
+
+
+def ms_electrode_transmission(ctx: Context, left: Slices, region: Slices, right: Slices, energy: float):
+    """T, R, n_in between two periodic electrodes (cells with eigenvectors) through a region."""
+    T = torch.empty(1, dtype=torch.float64, device=ctx.device)
+    R = torch.empty(1, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(1, dtype=torch.int64, device=ctx.device)
+    _check(ctx.handle, lib.ms_electrode_transmission(ctx.handle, ctypes.byref(left.c), ctypes.byref(region.c),
+                                                     ctypes.byref(right.c), float(energy), _ptr(T), _ptr(R),
+                                                     _ptr(no)))
+    return T, R, no
 
 
 def ms_mixed_doubling(ctx: Context, slices: Slices, energy: float, max_cond: float = 1e6):
@@ -474,6 +501,19 @@ def ms_debug_iface_product(ctx: Context, a: torch.Tensor, o: torch.Tensor, kp: t
     return w
 
 
+def ms_debug_qz(ctx: Context, a: torch.Tensor, b: torch.Tensor):
+    """QZ eigenpairs of the pencils (a[i], b[i]) ([batch][n][n] complex128): alpha, beta [batch][n]
+    (lam = alpha / beta), x [batch][n][n] unit right eigenvectors (columns), status [batch]."""
+    batch, n, _ = a.shape
+    alpha = torch.empty((batch, n), dtype=torch.complex128, device=ctx.device)
+    beta = torch.empty((batch, n), dtype=torch.complex128, device=ctx.device)
+    x = torch.empty((batch, n, n), dtype=torch.complex128, device=ctx.device)
+    st = torch.empty(batch, dtype=torch.int32, device=ctx.device)
+    _check(ctx.handle, lib.ms_debug_qz(ctx.handle, n, batch, _ptr(a, torch.complex128, "a"),
+                                       _ptr(b, torch.complex128, "b"), _ptr(alpha), _ptr(beta), _ptr(x), _ptr(st)))
+    return alpha, beta, x, st
+
+
 def ms_debug_lu_solve(ctx: Context, aug: torch.Tensor, n: int):
     batch, rows, cols = aug.shape
     nrhs = cols - n
@@ -515,10 +555,11 @@ def prepare_from_inputs_into(ctx: Context, inp: dict, out: Slices, vlead=(0.0, 0
 
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
-           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_mixed_doubling",
+           "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_complex_bands",
+           "ms_electrode_transmission", "ms_mixed_doubling",
            "ms_transmission",
            "ms_transmission_batch", "ms_transmission_batch_noalloc", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
-           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_lu_solve",
+           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_qz", "ms_debug_lu_solve",
            "ms_debug_eigh",
            "prepare_from_inputs", "prepare_from_inputs_into", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

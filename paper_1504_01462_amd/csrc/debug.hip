@@ -3,6 +3,7 @@
 #include <cmath>
 
 #include "../../include/ms_debug.h"
+#include "elem.h"
 #include "ms_internal.h"
 
 using namespace ms;
@@ -82,6 +83,26 @@ ms_status ms_debug_iface_product(ms_ctx ctx, int64_t n, int64_t batch, const voi
   if (prec == MS_PREC_FP64) return zgemm(ctx, g);
   if (prec == MS_PREC_FP32_MFMA) return cgemm32(ctx, g);
   return fail(ctx, MS_ERR_ARG, "unknown precision");
+}
+
+ms_status ms_debug_qz(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* b, void* alpha, void* beta,
+                      void* x, int32_t* status) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!a || !b || !alpha || !beta || !x || !status) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n < 2 || batch <= 0 || n > 4096 || batch > 65535) return fail(ctx, MS_ERR_ARG, "bad sizes");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  const size_t bytes = (size_t)batch * n * n * sizeof(double2);
+  void *A, *B, *V, *Y;
+  MS_TRY(workspace(ctx, 60, bytes, &A));
+  MS_TRY(workspace(ctx, 61, bytes, &B));
+  MS_TRY(workspace(ctx, 62, bytes, &V));
+  MS_TRY(workspace(ctx, 63, bytes, &Y));
+  MS_HIP(ctx, hipMemcpyAsync(A, a, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(B, b, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  MS_TRY(launch_fill_i32(ctx, batch, status, 0));
+  return qz_eig(ctx, (int)n, (int)batch, static_cast<double2*>(A), static_cast<double2*>(B), static_cast<double2*>(V),
+                static_cast<double2*>(Y), static_cast<double2*>(alpha), static_cast<double2*>(beta),
+                static_cast<double2*>(x), status);
 }
 
 ms_status ms_debug_lu_solve(ms_ctx ctx, int64_t n, int64_t nrhs, int64_t batch, void* aug, void* x, int32_t* status) {

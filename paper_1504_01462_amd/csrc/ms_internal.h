@@ -190,4 +190,11 @@ ms_status lu_reserve(ms_ctx ctx, int n, int ncols, int batch);
 // bytes of that workspace per matrix of a batch
 size_t lu_bytes_per_matrix(int n, int ncols);
 
+// ---- generalized eigenproblem A x = lam B x (complex QZ, one workgroup per pencil) ---------
+// A, B [batch][n][n] are destroyed (S, T); V, Y scratch of the same size; alpha, beta [batch][n]
+// (lam = alpha / beta, beta real >= 0); X [batch][n][n] right eigenvectors as unit columns;
+// status [batch] (MS_ERR_NOCONV when an eigenvalue needs more than 30 n sweeps in all)
+ms_status qz_eig(ms_ctx ctx, int n, int batch, double2* A, double2* B, double2* V, double2* Y, double2* alpha,
+                 double2* beta, double2* X, int32_t* status);
+
 }  // namespace ms

@@ -161,3 +161,45 @@ def test_eigh(lib, ctx, n, batch):
         assert np.max(np.abs(eps[i] - ref)) < 1e-12 * scale
         assert np.linalg.norm(h[i] @ u[i] - u[i] * eps[i]) < 1e-12 * scale * np.sqrt(n)
         assert np.max(np.abs(u[i].conj().T @ u[i] - np.eye(n))) < 1e-12
+
+
+def _qz_check(lib, ctx, a, b, tol=1e-11):
+    """QZ eigenpairs against LAPACK (scipy.linalg.eig): residuals of every pair, and the finite
+    eigenvalues matched one to one."""
+    import scipy.linalg as sla
+    al, be, x, st = (t.cpu().numpy() for t in lib.ms_debug_qz(ctx, to_dev(a), to_dev(b)))
+    ctx.sync()
+    assert np.all(st == 0)
+    for i in range(a.shape[0]):
+        na, nb = np.linalg.norm(a[i]), np.linalg.norm(b[i])
+        res = np.linalg.norm(be[i][None, :] * (a[i] @ x[i]) - al[i][None, :] * (b[i] @ x[i]), axis=0)
+        scale = np.abs(be[i]) * na + np.abs(al[i]) * nb
+        assert np.max(res / scale) < tol, np.max(res / scale)
+        assert np.allclose(np.linalg.norm(x[i], axis=0), 1.0, atol=1e-12)
+        ref = sla.eigvals(a[i], b[i])
+        fin = np.abs(be[i]) > 1e-8 * (np.abs(al[i]) + 1e-300)
+        got = list(al[i][fin] / be[i][fin])
+        for w in ref[np.isfinite(ref) & (np.abs(ref) < 1e6)]:
+            d = [abs(g - w) / max(1.0, abs(w)) for g in got]
+            k = int(np.argmin(d))
+            assert d[k] < 1e-9, (w, got[k])
+            got.pop(k)
+    return al, be, x
+
+
+@pytest.mark.parametrize("n,batch", [(2, 3), (5, 2), (16, 2), (37, 3), (64, 2), (130, 1)])
+def test_qz_random_pencils(lib, ctx, n, batch):
+    rng = np.random.default_rng(11 + n)
+    _qz_check(lib, ctx, _rand(rng, (batch, n, n)), _rand(rng, (batch, n, n)))
+
+
+def test_qz_singular_b_infinite_eigenvalues(lib, ctx):
+    """B of rank n - 3: three infinite eigenvalues (beta = 0) deflated by chasing the zeros of
+    B's diagonal; the finite ones match LAPACK."""
+    rng = np.random.default_rng(5)
+    n = 24
+    a = _rand(rng, (2, n, n))
+    b = _rand(rng, (2, n, n - 3)) @ _rand(rng, (2, n - 3, n))
+    al, be, _ = _qz_check(lib, ctx, a, b, tol=1e-10)
+    for i in range(2):
+        assert np.sum(np.abs(be[i]) < 1e-9 * np.abs(al[i])) == 3

@@ -855,3 +855,124 @@ def test_bloch_pencil_argument_errors(ms, ctx):
     with pytest.raises(ms.MSError) as ei:
         ms.ms_bloch_pencil(ctx, s, float("inf"))
     assert ei.value.status == ms.MS_ERR_ARG
+
+
+# ------------------------------------------------------------------ electrodes on the GPU ---
+def _cell(n_g, dz, vz=None, vq=None, kpar=(0.07, -0.11)):
+    j = msgen.config1()
+    j.dz = np.asarray(dz, dtype=np.float64)
+    inp = msgen.junction_inputs(j, kpar, n_g)
+    if vz is not None:
+        q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+        v = np.zeros_like(inp["vq"])
+        v[:, q0] = vz
+        inp["vq"] = v
+    if vq is not None:
+        inp["vq"] = np.asarray(vq)
+    return inp
+
+
+@pytest.mark.parametrize("zonly,m", [(False, 3), (True, 3), (False, 12)])
+def test_complex_bands_match_oracle(ms, ctx, zonly, m):
+    """App. B on the GPU: the Bloch factors lam = alpha / beta of the library's QZ against the
+    oracle's complex bands (1e-9 relative), and every state solves the cell's pencil."""
+    dz = np.array([0.5, 0.6, 0.4]) if m == 3 else np.linspace(0.2, 0.35, m)
+    inp = _cell(13, dz, vz=[0.0, 0.8, -0.5] if zonly else None)
+    prep = orc.prepare(inp)
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    for e in (0.9, 1.6, 2.7):
+        al, be, X = (_np(t) for t in ms.ms_complex_bands(ctx, s, e))
+        P, Q = (_np(t) for t in ms.ms_bloch_pencil(ctx, s, e))
+        ctx.sync()
+        res = np.linalg.norm(be[None, :] * (P @ X) - al[None, :] * (Q @ X), axis=0)
+        assert np.max(res / (np.abs(be) * np.linalg.norm(P) + np.abs(al) * np.linalg.norm(Q))) < 1e-12
+        lam = list(al / be)
+        ref = orc.complex_bands(prep, e)["lam"]
+        for w in ref:
+            d = [abs(g - w) / abs(w) for g in lam]
+            i = int(np.argmin(d))
+            assert d[i] < 1e-9, (e, w, lam[i], d[i])
+            lam.pop(i)
+
+
+def _with_slices(inp, dz, vq):
+    return dict(inp, dz=np.asarray(dz, dtype=np.float64), vq=np.asarray(vq))
+
+
+def _electrode_case(ms, ctx, left, region, right, energies, tol=1e-10):
+    out = []
+    pl, pr, pg = orc.prepare(left), orc.prepare(right), orc.prepare(region)
+    sl, sr, sg = (ms.prepare_from_inputs(ctx, x, with_evec=True) for x in (left, right, region))
+    for e in energies:
+        T, R, no = (_np(t) for t in ms.ms_electrode_transmission(ctx, sl, sg, sr, e))
+        ctx.sync()
+        ref = orc.transmission_bands(pl, pg, pr, e)
+        assert int(no[0]) == ref["n_in"], (e, no, ref["n_in"])
+        assert abs(T[0] - ref["T"]) < tol, (e, T[0], ref["T"])
+        assert abs(R[0] - ref["R"]) < tol, (e, R[0], ref["R"])
+        out.append((float(T[0]), float(R[0]), int(no[0]), ref))
+    return out
+
+
+def test_electrode_transmission_free_electrodes(ms, ctx):
+    """Electrode cells of zero potential: T and R equal the oracle's band-electrode values and
+    the free-lead values of the same region."""
+    dz = np.array([0.5, 0.7, 0.3, 0.6])
+    inp = _cell(11, dz)
+    nq = inp["vq"].shape[1]
+    left = _with_slices(inp, [0.9], np.zeros((1, nq), dtype=np.complex128))
+    right = _with_slices(inp, [0.4, 0.35], np.zeros((2, nq), dtype=np.complex128))
+    res = _electrode_case(ms, ctx, left, inp, right, (0.45, 1.3, 2.2))
+    prep = orc.prepare(inp)
+    for (t, r, n_in, _), e in zip(res, (0.45, 1.3, 2.2)):
+        free = orc.transmission(prep, e)
+        assert n_in == free["n_open"] and abs(t - free["T"]) < 1e-10
+
+
+def test_electrode_transmission_wells_and_crystal(ms, ctx):
+    """A wells electrode on the left, a z-only crystal on the right, a random region between
+    (T, R against the oracle, T + R = n_in); and the wells crystal continued through the region
+    (T = n_in, R = 0)."""
+    dz = np.array([0.5, 0.6, 0.4])
+    inp = _cell(11, dz)
+    nq = inp["vq"].shape[1]
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    vr = np.zeros((2, nq), dtype=np.complex128)
+    vr[:, q0] = [0.3, -0.4]
+    right = _with_slices(inp, [0.45, 0.55], vr)
+    rng = np.random.default_rng(7)
+    dzs = np.array([0.3, 0.5, 0.4, 0.2, 0.6])
+    region = _with_slices(inp, dzs, inp["vq"][rng.integers(0, 3, dzs.size)] * 1.7)
+    for t, r, n_in, _ in _electrode_case(ms, ctx, inp, region, right, (0.9, 1.6, 2.4)):
+        assert abs(t + r - n_in) < 1e-9
+    order = [1, 2, 0, 1, 2, 0, 1, 2]
+    crystal = _with_slices(inp, dz[order], inp["vq"][order])
+    for t, r, n_in, _ in _electrode_case(ms, ctx, inp, crystal, inp, (0.8, 1.7)):
+        assert n_in >= 1 and abs(t - n_in) < 1e-9 and abs(r) < 1e-9
+
+
+def test_electrode_transmission_far_evanescent(ms, ctx):
+    """N_G = 137 with a 5 bohr cell: evanescent states change by far more than FP64 spans per cell
+    (infinite lam in the pencil).  The library's QZ keeps them as (alpha, beta) pairs and reads
+    each state where it is largest: T and R match the oracle, T + R = n_in."""
+    inp = _cell(137, np.full(3, 5.0 / 3))
+    rng = np.random.default_rng(3)
+    region = _with_slices(inp, [0.3, 0.5, 0.4, 0.2], inp["vq"][rng.integers(0, 3, 4)] * 1.3)
+    for t, r, n_in, _ in _electrode_case(ms, ctx, inp, region, inp, (1.3,)):
+        assert abs(t + r - n_in) < 1e-10
+
+
+def test_electrode_argument_errors(ms, ctx):
+    inp = _cell(9, [0.5, 0.6])
+    s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
+    bare = ms.prepare_from_inputs(ctx, inp)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_electrode_transmission(ctx, bare, s, s, 1.0)
+    assert ei.value.status == ms.MS_ERR_ARG
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_complex_bands(ctx, s, float("nan"))
+    assert ei.value.status == ms.MS_ERR_ARG
+    other = ms.prepare_from_inputs(ctx, _cell(13, [0.5, 0.6]), with_evec=True)
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_electrode_transmission(ctx, s, other, s, 1.0)
+    assert ei.value.status == ms.MS_ERR_ARG
