@@ -89,6 +89,14 @@ def parse():
                          "the interface product (FP64 or FP32 MFMA, n_g 1200, 32 energies), the LU solve of "
                          "32 augmented systems, 8 slice eigenproblems, or a 1 GiB device copy (calibration)")
     ap.add_argument("--probe-launches", type=int, default=5)
+    ap.add_argument("--electrode-only", type=int, default=0, metavar="N_G",
+                    help="time the periodic-electrode path at this basis size and exit: the complex bands of "
+                         "one config-3 sheet cell (one z-period, 40 slices) and the transmission from the bottom "
+                         "sheet's electrode through the config-3 junction (400 slices) into the top sheet's")
+    ap.add_argument("--electrode-bands-only", action="store_true",
+                    help="with --electrode-only: time the complex bands only")
+    ap.add_argument("--electrode-energies", type=int, default=1,
+                    help="energies (spread over the config-3 window) for --electrode-only")
     return ap.parse_args()
 
 
@@ -144,6 +152,43 @@ def probe(kind, launches):
                       "tflops": work["flop"] / ms_per / 1e9 if work["flop"] else None,
                       "gbps": work["bytes"] / ms_per / 1e6, **work}), flush=True)
     ctx.close()
+
+
+def electrode_measure(n_g, n_e, bands_only=False):
+    """Periodic electrodes (NEXT-4) at config-3 shape: per energy, the complex bands of the bottom
+    sheet's cell (one QZ of the 2 N_G pencil) and the electrode transmission bottom sheet ->
+    junction -> top sheet (two cells' bands, the region's S, the matching); one JSON line."""
+    import msgen
+    import torch
+    import paper_1504_01462_amd as ms
+    ctx = ms.Context(0)
+    jl = msgen.config3_electrode("bottom", n_g=n_g, n_slices=40)
+    jr = msgen.config3_electrode("top", n_g=n_g, n_slices=40)
+    jg = msgen.config3(6.3, "AA", n_g=n_g)
+    kp = jg.kpars[3]
+    sl, sr, sg = (ms.prepare_from_inputs(ctx, msgen.junction_inputs(j, kp), with_evec=True) for j in (jl, jr, jg))
+    ctx.sync()
+    energies = np.linspace(0.3, 0.9, n_e) if n_e > 1 else np.array([0.5])
+    rows = []
+    for e in energies:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        al, be, _ = ms.ms_complex_bands(ctx, sl, float(e))
+        ctx.sync()
+        t1 = time.perf_counter()
+        lam = (al / be).cpu().numpy()
+        rows.append(dict(energy=float(e), bands_s=round(t1 - t0, 3),
+                         propagating=int(np.sum(np.abs(np.abs(lam) - 1.0) < 1e-8))))
+        if not bands_only:
+            T, R, no = ms.ms_electrode_transmission(ctx, sl, sg, sr, float(e))
+            ctx.sync()
+            rows[-1].update(transmission_s=round(time.perf_counter() - t1, 3), T=float(T[0]), R=float(R[0]),
+                            n_in=int(no[0]))
+        print(f"[bench] electrode E={e:.3f}: {rows[-1]}", file=sys.stderr, flush=True)
+    ctx.close()
+    return dict(n_g=n_g, pencil=2 * n_g, cell_slices=40, region_slices=int(jg.dz.size), k_par=[float(x) for x in kp],
+                points=rows, note="one workgroup per pencil (complex QZ); transmission = both cells' bands + "
+                                  "the region's S-matrix + the matching solve")
 
 
 def workload(name):
@@ -551,6 +596,10 @@ def main():
 
     if args.probe:
         probe(args.probe, max(1, args.probe_launches))
+        return
+    if args.electrode_only:
+        out = electrode_measure(args.electrode_only, max(1, args.electrode_energies), args.electrode_bands_only)
+        print(json.dumps({"electrode": out, "n_gpus": 1, "data": "synthetic"}), flush=True)
         return
     # ---- seeded inputs, generated in worker processes before this process loads the GPU
     # library or touches the GPU (the pool and its workers are gone before that)

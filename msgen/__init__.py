@@ -14,10 +14,11 @@ Units: Rydberg atomic units with the kinetic operator written as -nabla^2
 from .lattice import Cell, plane_wave_basis, difference_set
 from .potential import Wells, slice_edges, vq_gaussian_wells
 from .configs import (Junction, junction_inputs, config1, config2, config3,
+                      config3_electrode,
                       config4_instances, config5, CONFIGS)
 
 __all__ = [
     "Cell", "plane_wave_basis", "difference_set", "Wells", "slice_edges",
     "vq_gaussian_wells", "Junction", "junction_inputs", "config1", "config2",
-    "config3", "config4_instances", "config5", "CONFIGS",
+    "config3", "config3_electrode", "config4_instances", "config5", "CONFIGS",
 ]

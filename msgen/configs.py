@@ -130,6 +130,24 @@ def config3(gap: float = 6.3, registry: str = "AA", n_g: int = 1200, n_slices: i
                     dict(gap=gap, registry=registry))
 
 
+def config3_electrode(side: str = "bottom", gap: float = 6.3, registry: str = "AA", n_g: int = 1200,
+                      n_slices: int = 160) -> Junction:
+    """One z-period (3 d_cc = 8.05 bohr) of a config-3 sheet continued along z: the periodic
+    electrode cell of the bottom sheet (``side="bottom"``, y = 20 - gap/2) or of the top one
+    (y = 20 + gap/2, shifted by d_cc along z for the AB registry), with the wells of the
+    neighbouring periods included so the potential is periodic.  Same transverse cell and
+    basis size as config 3."""
+    lx, ly = _A_GR, 40.0
+    period = 3.0 * _D_CC
+    cell = Cell((lx, 0.0), (0.0, ly))
+    y = ly / 2 - gap / 2 if side == "bottom" else ly / 2 + gap / 2
+    zs = _D_CC if (side == "top" and registry == "AB") else 0.0
+    centres = _zigzag_sheet(y, -period - 1e-9, 2.0 * period, zshift=zs - 6 * period)
+    return Junction(f"config3-electrode-{side}-gap{gap}-{registry}", cell, Wells(centres, 1.2, 0.6),
+                    np.full(n_slices, period / n_slices), np.linspace(0.1, 1.0, 32), np.zeros((1, 2)), n_g,
+                    dict(gap=gap, registry=registry, side=side, period=period))
+
+
 def config4_instances(n: int = 512, seed: int = 4):
     """Uneven instances from the config-2 geometry: list of dicts (junction, E, k_par index)."""
     rng = np.random.default_rng(seed)

@@ -278,3 +278,23 @@ def test_far_evanescent_states():
     crystal = orc.prepare(_with(inp, dz[order], inp["vq"][order]))
     got = orc.transmission_bands(cell, crystal, cell, 1.3)
     assert abs(got["T"] - got["n_in"]) < 1e-10 and abs(got["R"]) < 1e-10
+
+
+def test_config3_electrode_cell_is_one_period():
+    """The config-3 sheet electrode cell: its slices equal those of the sheet continued far along
+    z (every well within 8 bohr of the cell included), in its first period and in the next one,
+    and the top sheet's cell is the bottom one moved by +gap along y (a transverse phase per Q)."""
+    from msgen.configs import _zigzag_sheet
+    j = msgen.config3_electrode("bottom", n_g=61, n_slices=20)
+    per = j.meta["period"]
+    inp = msgen.junction_inputs(j, (0.0, 0.0))
+    wide = msgen.Wells(_zigzag_sheet(20.0 - 6.3 / 2, -4 * per, 6 * per, zshift=-12 * per), 1.2, 0.6)
+    two = msgen.Junction("two", j.cell, wide, np.full(40, per / 20), j.energies, j.kpars, j.n_g)
+    inp2 = msgen.junction_inputs(two, (0.0, 0.0))
+    scale = np.max(np.abs(inp["vq"]))
+    assert np.max(np.abs(inp2["vq"][:20] - inp["vq"])) < 1e-13 * scale
+    assert np.max(np.abs(inp2["vq"][20:] - inp["vq"])) < 1e-13 * scale
+    top = msgen.junction_inputs(msgen.config3_electrode("top", n_g=61, n_slices=20), (0.0, 0.0))
+    qv = np.asarray(inp["q_miller"], dtype=np.float64) @ np.asarray(inp["bvec"])
+    phase = np.exp(-1j * qv[:, 1] * 6.3)        # every well moved by +gap along y
+    assert np.max(np.abs(top["vq"] - inp["vq"] * phase[None, :])) < 1e-13 * scale
