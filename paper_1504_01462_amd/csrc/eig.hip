@@ -106,13 +106,14 @@ __device__ __forceinline__ int pair_col(int a, int I, int J, int mI, int mJ) {
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
-  __shared__ double2 G[PW][PW + 1];
+  // Gb: the pair's Gram matrix in two buffers (the inner Jacobi reads one and writes the
+  // other); the row staging of the P update reuses the same bytes afterwards
+  __shared__ __align__(16) double2 Gb[2][PW][PW + 1];
   __shared__ double2 Q[PW][PW + 1];
-  __shared__ __align__(16) double Ps[2][ROWS][PW];
-  __shared__ double rc[PW / 2], rs[PW / 2];
-  __shared__ double2 rph[PW / 2];
-  __shared__ int ra[PW / 2], rb[PW / 2];
   __shared__ int s_flag;
+  double2(*G)[PW + 1] = Gb[0];
+  double(*Ps)[ROWS][PW] = reinterpret_cast<double(*)[ROWS][PW]>(&Gb[0][0][0]);
+  static_assert(sizeof(double) * 2 * ROWS * PW <= sizeof(double2) * 2 * PW * (PW + 1), "P staging fits Gb");
 
   const int64_t b = blockIdx.y;
   // the wave index is uniform across the wave: keeping it scalar keeps the per-wave row
@@ -222,78 +223,101 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
     if (t == 0) atomicAdd(cnt + args.sweep, 1);
   }
 
-  // --- cyclic Jacobi on G (32 x 32 Hermitian), Q accumulates the rotations
+  // --- cyclic Jacobi on G (32 x 32 Hermitian), Q accumulates the rotations.  A round applies
+  //     16 disjoint rotations (circle-method pairs).  Lane l of every wave forms rotation l % 16
+  //     from the current buffer and the lanes exchange them by wave shuffles; thread t owns the
+  //     2 x 2 block of G at (row pair t / 16, column pair t % 16) and rows t / 16, t / 16 + 16
+  //     of Q in that column pair, and writes its block into the other buffer, so a round needs
+  //     one barrier.  Rows then columns, as G' = R^dagger G R:
+  //       rows:    G'_a = c G_a - s e^{i phi} G_b ;  G'_b = s e^{-i phi} G_a + c G_b
+  //       columns: X'_a = c X_a - s e^{-i phi} X_b ;  X'_b = s e^{i phi} X_a + c X_b
+  //     with e^{i phi} = G_ab / |G_ab|, t = sign(z) / (|z| + sqrt(1 + z^2)), z = (G_bb - G_aa) /
+  //     (2 |G_ab|), c = 1 / sqrt(1 + t^2), s = t c.  Q's columns drift from unitarity only by
+  //     rounding; the Newton-Schulz step below restores it.
   for (int idx = t; idx < PW * PW; idx += 256) {
     const int a = idx / PW, c = idx % PW;
     Q[a][c] = make_double2(a == c ? 1.0 : 0.0, 0.0);
   }
+  __syncthreads();   // every thread has read the pair's flag above before it is reset
+  if (t == 0) s_flag = 0;
   __syncthreads();
-  for (int sw = 0; sw < 12; ++sw) {
-    if (t == 0) s_flag = 0;
-    __syncthreads();
-    for (int r = 0; r < PW - 1; ++r) {
-      if (t < PW / 2) {
-        // circle-method pairing of 32 indices
-        const int k = t;
-        const int a = (k == 0) ? 0 : ((k - 1 + r) % (PW - 1)) + 1;
-        const int c = ((PW - 1 - k - 1 + r) % (PW - 1)) + 1;
-        const int lo = min(a, c), hi = max(a, c);
-        const double al = G[lo][lo].x, ga = G[hi][hi].x;
-        const double2 be = G[lo][hi];
-        const double mb = sqrt(be.x * be.x + be.y * be.y);
-        double cs = 1.0, sn = 0.0;
-        double2 ph = make_double2(1.0, 0.0);
-        if (mb > 1e-17 * sqrt(fabs(al * ga)) && mb > 0.0) {
-          const double zeta = (ga - al) / (2.0 * mb);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          cs = 1.0 / sqrt(1.0 + tt * tt);
-          sn = tt * cs;
-          ph = make_double2(be.x / mb, be.y / mb);
-          if (mb > 1e-15 * sqrt(fabs(al * ga))) s_flag = 1;
+  int cur = 0;
+  {
+    const int kr = t >> 4, kc = t & 15, kl = lane & 15;
+    auto ends = [](int k, int r, int* lo, int* hi) {
+      const int a = (k == 0) ? 0 : ((k - 1 + r) % (PW - 1)) + 1;
+      const int c = ((PW - 1 - k - 1 + r) % (PW - 1)) + 1;
+      *lo = min(a, c);
+      *hi = max(a, c);
+    };
+    for (int sw = 0; sw < 12; ++sw) {
+      for (int r = 0; r < PW - 1; ++r) {
+        const double2(*Gc)[PW + 1] = Gb[cur];
+        double2(*Gn)[PW + 1] = Gb[cur ^ 1];
+        // this lane's rotation kl
+        int lo, hi;
+        ends(kl, r, &lo, &hi);
+        double cs = 1.0, sn = 0.0, px = 1.0, py = 0.0;
+        {
+          const double al = Gc[lo][lo].x, ga = Gc[hi][hi].x;
+          const double2 be = Gc[lo][hi];
+          const double m2 = be.x * be.x + be.y * be.y, aga = fabs(al * ga);
+          if (m2 > 1e-34 * aga && m2 > 0.0) {
+            const double inv = rsqrt(m2);
+            const double zeta = 0.5 * (ga - al) * inv;
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            cs = rsqrt(1.0 + tt * tt);
+            sn = tt * cs;
+            px = be.x * inv;
+            py = be.y * inv;
+            if (wave == 0 && lane < 16 && m2 > 1e-30 * aga) s_flag = 1;
+          }
         }
-        ra[k] = lo;
-        rb[k] = hi;
-        rc[k] = cs;
-        rs[k] = sn;
-        rph[k] = ph;
+        // row rotation kr and column rotation kc from the lanes that formed them
+        const double rcs = __shfl(cs, kr), rsn = __shfl(sn, kr), rpx = __shfl(px, kr), rpy = __shfl(py, kr);
+        const double ccs = __shfl(cs, kc), csn = __shfl(sn, kc), cpx = __shfl(px, kc), cpy = __shfl(py, kc);
+        int rlo, rhi, clo, chi;
+        ends(kr, r, &rlo, &rhi);
+        ends(kc, r, &clo, &chi);
+        const double2 rph = make_double2(rpx, rpy), cph = make_double2(cpx, cpy);
+        const int cols[2] = {clo, chi}, rows[2] = {rlo, rhi};
+        double2 x[2][2];
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {        // row rotation of the block's two columns
+          const double2 ga = Gc[rlo][cols[v]], gb = Gc[rhi][cols[v]];
+          x[0][v] = cadd(cscale(rcs, ga), cscale(-rsn, cmul(rph, gb)));
+          x[1][v] = cadd(cscale(rsn, cmul(cconj(rph), ga)), cscale(rcs, gb));
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {        // column rotation of the rotated rows
+          const double2 xa = x[u][0], xb = x[u][1];
+          Gn[rows[u]][clo] = cadd(cscale(ccs, xa), cscale(-csn, cmul(cconj(cph), xb)));
+          Gn[rows[u]][chi] = cadd(cscale(csn, cmul(cph, xa)), cscale(ccs, xb));
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {        // Q <- Q R on rows kr, kr + 16 (in place: own elements)
+          const int q = kr + 16 * u;
+          const double2 xa = Q[q][clo], xb = Q[q][chi];
+          Q[q][clo] = cadd(cscale(ccs, xa), cscale(-csn, cmul(cconj(cph), xb)));
+          Q[q][chi] = cadd(cscale(csn, cmul(cph, xa)), cscale(ccs, xb));
+        }
+        cur ^= 1;
+        __syncthreads();
       }
+      // every thread reads the flag before thread 0 may reset it for the next sweep
+      const bool rotated = s_flag != 0;
       __syncthreads();
-      // rows: G'_a = c G_a - s e^{i phi} G_b ; G'_b = s e^{-i phi} G_a + c G_b
-      for (int idx = t; idx < (PW / 2) * PW; idx += 256) {
-        const int k = idx / PW, x = idx % PW;
-        const int a = ra[k], c = rb[k];
-        const double cs = rc[k], sn = rs[k];
-        const double2 ph = rph[k];
-        const double2 ga = G[a][x], gb = G[c][x];
-        G[a][x] = cadd(cscale(cs, ga), cscale(-sn, cmul(ph, gb)));
-        G[c][x] = cadd(cscale(sn, cmul(cconj(ph), ga)), cscale(cs, gb));
-      }
-      __syncthreads();
-      // columns of G and Q: X'_a = c X_a - s e^{-i phi} X_b ; X'_b = s e^{i phi} X_a + c X_b
-      for (int idx = t; idx < 2 * (PW / 2) * PW; idx += 256) {
-        const int which = idx / ((PW / 2) * PW);
-        const int rem = idx % ((PW / 2) * PW);
-        const int k = rem / PW, x = rem % PW;
-        const int a = ra[k], c = rb[k];
-        const double cs = rc[k], sn = rs[k];
-        const double2 ph = rph[k];
-        double2(*X)[PW + 1] = which ? Q : G;
-        const double2 xa = X[x][a], xb = X[x][c];
-        X[x][a] = cadd(cscale(cs, xa), cscale(-sn, cmul(cconj(ph), xb)));
-        X[x][c] = cadd(cscale(sn, cmul(ph, xa)), cscale(cs, xb));
-      }
+      if (!rotated) break;
+      if (t == 0) s_flag = 0;
       __syncthreads();
     }
-    // every thread reads the flag before thread 0 may reset it for the next sweep
-    const bool rotated = s_flag != 0;
-    __syncthreads();
-    if (!rotated) break;
   }
+  (void)cur;
 
   // --- Q <- Q (3 I - Q^dagger Q) / 2: one Newton-Schulz step restores unitarity to
   //     O(|Q^dagger Q - I|^2), so repeated pair updates do not drift the column norms
   {
-    double2(*Qn)[PW] = reinterpret_cast<double2(*)[PW]>(&Ps[0][0][0]);
+    double2(*Qn)[PW + 1] = Gb[1];
     for (int idx = t; idx < PW * PW; idx += 256) {      // G <- Q^dagger Q
       const int a = idx / PW, c = idx % PW;
       double2 acc = make_double2(0.0, 0.0);

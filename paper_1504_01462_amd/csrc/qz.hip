@@ -349,7 +349,6 @@ __global__ __launch_bounds__(QZ_THREADS) void k_qz(int n, double2* Aall, double2
     for (int i = n - 1; i > k; --i) y[(int64_t)i * n] = make_double2(0.0, 0.0);
     y[(int64_t)k * n] = make_double2(1.0, 0.0);
     const double small = QZ_EPS * (zabs(ak) * bnorm + zabs(bk) * anorm) + 1e-300;
-    double scale = 1.0;
     for (int i = k - 1; i >= 0; --i) {
       double2 s = make_double2(0.0, 0.0);
       for (int j = i + 1; j <= k; ++j) {
@@ -364,7 +363,6 @@ __global__ __launch_bounds__(QZ_THREADS) void k_qz(int n, double2* Aall, double2
         const double f = 1.0 / m;
         for (int j = i + 1; j <= k; ++j) y[(int64_t)j * n] = zscale(f, y[(int64_t)j * n]);
         yi = zscale(f, yi);
-        scale *= f;
       }
       y[(int64_t)i * n] = yi;
     }
