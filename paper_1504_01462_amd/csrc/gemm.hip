@@ -2,15 +2,17 @@
 //
 // C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], row-major, op in {N, T, C}.
 // Complex operands are split into real/imaginary planes when staged into LDS;
-// each 16x16x4 complex block is four real MFMAs
-//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br
+// each 16x16x4 complex block is three real MFMAs (Gauss's product)
+//   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + Ai)(Br + Bi);   Cr = P1 - P2,   Ci = P3 - P1 - P2
 // (v_mfma_f64_16x16x4f64 for complex128, v_mfma_f32_16x16x4f32 for complex64:
-// FP32 accumulation inside each K-slab of 16, the slabs summed in FP64).  Operand layouts of both: lane l holds
+// FP32 accumulation inside each K-slab of 16, the slabs combined and summed in FP64).  Three
+// products instead of four take a quarter of the matrix-core work; the imaginary part's
+// rounding error is bounded by eps sum (|Ar| + |Ai|)(|Br| + |Bi|) instead of
+// eps sum (|Ar| |Bi| + |Ai| |Br|).  Operand layouts of both: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; the accumulator layouts differ
-// (see Mfma<T>::crow).  Workgroup = 4 wave64s in a 2x2 grid; each wave
-// owns a sub-tile (64x64 tiles with 4 waves for small problems, 128x128 tiles
-// with 8 waves otherwise).  Global->LDS staging is register double-buffered
-// (the next K-slab is fetched while the current one is used).
+// (see Mfma<T>::crow).  Each wave owns a 32 x 32 sub-tile: 64 x 64 tiles with 4 waves in a
+// 2 x 2 grid, or (FP64) 128 x 64 tiles with 8 waves in a 4 x 2 grid.  Global->LDS staging is
+// register double-buffered (the next K-slab is fetched while the current one is used).
 //
 // The fold's interface product (ROLE 1) generates its B operand while staging it:
 //   B_b[m][j] = O[j][m] (kp_b[j] - kq_b[m])          j <  nh   (C-)
@@ -71,8 +73,10 @@ struct KParams {
   int nh;
 };
 
+// complex product with its two fused multiply-adds written out, so every instantiation of the
+// kernel rounds it the same way (the compiler is otherwise free to contract either product)
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 
 constexpr int BK = 16;
@@ -195,9 +199,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       const bool ok = m0 + i < p.M && k0 + k < p.K;
       T re = ok ? ra[e].x : (T)0, im = ok ? ra[e].y : (T)0;
       if (p.opA == OP_C) im = -im;
-      if (kFold && scale_a) {   // alpha op(A), staged
-        const T r2 = (T)p.alpha.x * re - (T)p.alpha.y * im;
-        im = (T)p.alpha.x * im + (T)p.alpha.y * re;
+      if (kFold && scale_a) {   // alpha op(A), staged (fused multiply-adds written out)
+        const T r2 = fma((T)p.alpha.x, re, -((T)p.alpha.y * im));
+        im = fma((T)p.alpha.x, im, (T)p.alpha.y * re);
         re = r2;
       }
       As[st][0][k][i] = re;
@@ -233,13 +237,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
     }
   };
 
-  acc_t cr[FM][FN], ci[FM][FN];
+  // Gauss's three-product form: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);
+  // Re = P1 - P2, Im = P3 - P1 - P2
+  acc_t cr[FM][FN], ci[FM][FN], c3[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
 #pragma unroll
     for (int c = 0; c < FN; ++c) {
       cr[a][c] = acc_t{0, 0, 0, 0};
       ci[a][c] = acc_t{0, 0, 0, 0};
+      c3[a][c] = acc_t{0, 0, 0, 0};
     }
   // FP32 MFMA: each K-slab accumulates in FP32 (four MFMA steps), and the slabs are summed in
   // FP64, so the FP32 rounding chain of an element is 4 long instead of K / 4
@@ -269,10 +276,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
           const int col = n0 + wn0 + c * 16 + (lane & 15);
           const double2 o = C[(int64_t)min(row, p.M - 1) * p.ldc + min(col, p.N - 1)];
           const bool ok = row < p.M && col < p.N;
-          const double re = beta_one ? o.x : p.beta.x * o.x - p.beta.y * o.y;
-          const double im = beta_one ? o.y : p.beta.x * o.y + p.beta.y * o.x;
+          const double re = beta_one ? o.x : fma(p.beta.x, o.x, -(p.beta.y * o.y));
+          const double im = beta_one ? o.y : fma(p.beta.x, o.y, p.beta.y * o.x);
           cr[a][c][v] = ok ? re : 0.0;
-          ci[a][c][v] = ok ? im : 0.0;
+          ci[a][c][v] = 0.0;
+          c3[a][c][v] = ok ? re + im : 0.0;
         }
   }
   stash(0, 0);
@@ -283,31 +291,26 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      T ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
+      T ar[FM], ai[FM], as[FM], br[FN], bi[FN], bs[FN];
 #pragma unroll
       for (int a = 0; a < FM; ++a) {
         ar[a] = As[cur][0][kr][wm0 + a * 16 + (lane & 15)];
         ai[a] = As[cur][1][kr][wm0 + a * 16 + (lane & 15)];
-        nai[a] = -ai[a];
+        as[a] = ar[a] + ai[a];
       }
 #pragma unroll
       for (int c = 0; c < FN; ++c) {
         br[c] = Bs[cur][0][kr][wn0 + c * 16 + (lane & 15)];
         bi[c] = Bs[cur][1][kr][wn0 + c * 16 + (lane & 15)];
+        bs[c] = br[c] + bi[c];
       }
 #pragma unroll
       for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int c = 0; c < FN; ++c) {
           cr[a][c] = Mfma<T>::mac(ar[a], br[c], cr[a][c]);
-          ci[a][c] = Mfma<T>::mac(ar[a], bi[c], ci[a][c]);
-        }
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int c = 0; c < FN; ++c) {
-          cr[a][c] = Mfma<T>::mac(nai[a], bi[c], cr[a][c]);
-          ci[a][c] = Mfma<T>::mac(ai[a], br[c], ci[a][c]);
+          ci[a][c] = Mfma<T>::mac(ai[a], bi[c], ci[a][c]);
+          c3[a][c] = Mfma<T>::mac(as[a], bs[c], c3[a][c]);
         }
     }
     if constexpr (kSlab64) {
@@ -317,11 +320,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
         for (int c = 0; c < FN; ++c) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            sr[a][c][v] += (double)cr[a][c][v];
-            si[a][c][v] += (double)ci[a][c][v];
+            const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
+            sr[a][c][v] += p1 - p2;
+            si[a][c][v] += p3 - p1 - p2;
           }
           cr[a][c] = acc_t{0, 0, 0, 0};
           ci[a][c] = acc_t{0, 0, 0, 0};
+          c3[a][c] = acc_t{0, 0, 0, 0};
         }
     }
     if (k0 + BK < p.K) {
@@ -349,7 +354,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
         }
         if (row < p.M && col_ok) {
           if (kFold) {
-            C[(int64_t)row * p.ldc + col] = make_double2((double)cr[a][c][v], (double)ci[a][c][v]);
+            const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
+            C[(int64_t)row * p.ldc + col] = make_double2(p1 - p2, p3 - p1 - p2);
             continue;
           }
           double re, im;
@@ -357,8 +363,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
             re = sr[a][c][v];
             im = si[a][c][v];
           } else {
-            re = (double)cr[a][c][v];
-            im = (double)ci[a][c][v];
+            const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
+            re = p1 - p2;
+            im = p3 - p1 - p2;
           }
           double2 out;
           out.x = p.alpha.x * re - p.alpha.y * im;
@@ -406,9 +413,9 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
             true);
   // Tile edge: the tuned choice for the fold group's basis size (ms_autotune / ms_set_tiles),
-  // else 64 x 64 (4 waves, two workgroups per CU) for the LU's products, which timed faster at
-  // every basis size (200-1200) and batch (3-64) tried, and for products smaller than 128 x
-  // 128, 128 x 128 (8 waves) otherwise.  Both tile shapes accumulate every element in the same
+  // else 64 x 64 (4 waves, two workgroups per CU) for the LU's products and for products
+  // smaller than 128 x 128, 128 x 64 (8 waves, one workgroup per CU) otherwise.  Every wave
+  // owns a 32 x 32 sub-tile in both shapes and every element is accumulated in the same
   // order, so the choice never changes a result.
   static const int tile_env = [] {   // MS_GEMM_TILE=64: 64 x 64 tiles everywhere
     const char* e = getenv("MS_GEMM_TILE");
@@ -423,20 +430,20 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
   if (tile_env == 64) tile = 64;
   if (tile == 0)
     tile = (g.prof != PC_LU_UPDATE && g.prof != PC_LU_INNER && g.M >= 128 && g.N >= 128) ? 128 : 64;
-  // FP32 MFMA keeps FP64 sums of its K-slabs: a 128 x 128 tile would spill, so 64 x 64 always
+  // FP32 MFMA keeps FP64 sums of its K-slabs (three per element): 64 x 64 tiles always
   if constexpr (!std::is_same<T, double>::value) {
     if (gen) return launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
     return g.prof == PC_LU_UPDATE ? launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof)
                                   : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
   } else {
-    const bool big = tile == 128;
+    const bool big = tile == 128;   // 128 x 64, 8 waves
     if (g.prof == PC_LU_UPDATE)
-      return big ? launch<T, 128, 128, 2, 4, 2>(ctx, p, g.batch, prof)
+      return big ? launch<T, 128, 64, 4, 2, 2>(ctx, p, g.batch, prof)
                  : launch<T, 64, 64, 2, 2, 2>(ctx, p, g.batch, prof);
     if (gen)
-      return big ? launch<T, 128, 128, 2, 4, 1>(ctx, p, g.batch, prof)
+      return big ? launch<T, 128, 64, 4, 2, 1>(ctx, p, g.batch, prof)
                  : launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);
-    return big ? launch<T, 128, 128, 2, 4, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
+    return big ? launch<T, 128, 64, 4, 2, 0>(ctx, p, g.batch, prof) : launch<T, 64, 64, 2, 2, 0>(ctx, p, g.batch, prof);
   }
 }
 

@@ -459,7 +459,9 @@ __global__ __launch_bounds__(64) void k_upper_block_inverse(const double2* A, in
 // The 8 waves form two halves that split the K range (alternate TR_KC chunks); within
 // a half, wave w owns 16 columns.  U chunks are staged through LDS, one buffer per
 // half, and the next chunk of U and of Y is fetched into registers while the current
-// one is multiplied.  The halves' partial sums meet in LDS.
+// one is multiplied.  The halves' partial sums meet in LDS.  Complex products take three
+// real MFMAs (Gauss): P1 = Ur Yr, P2 = Ui Yi, P3 = (Ur + Ui)(Yr + Yi), Re = P1 - P2,
+// Im = P3 - P1 - P2.
 constexpr int TR_KC = 16;
 constexpr int TR_THREADS = 512;
 __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int n, int ld, int64_t strideA,
@@ -482,9 +484,9 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
     const int r0 = ib * 64, r1 = min(n, r0 + 64);
     const int nch = (n - r1 + TR_KC - 1) / TR_KC;   // chunks of the off-diagonal product
     const int iters = (nch + 1) / 2;                 // half h takes chunks h, h+2, ...
-    d4v cr[4], ci[4];
+    d4v cr[4], ci[4], c3[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; }
+    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; c3[a] = d4v{0, 0, 0, 0}; }
     double2 up[UE], yp[TR_KC / 4];
     // loads with indices clamped into the matrices (no branch, all in flight together);
     // the out-of-range elements are zeroed when the chunk is consumed
@@ -529,18 +531,27 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
 #pragma unroll
         for (int q = 0; q < TR_KC / 4; ++q) {
           const int kl = 4 * q + (lane >> 4);
+          const double ys = yc[q].x + yc[q].y;
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
             const double ar = Us[h][0][a * 16 + (lane & 15)][kl], ai = Us[h][1][a * 16 + (lane & 15)][kl];
             cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, yc[q].x, cr[a], 0, 0, 0);
-            ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, yc[q].y, ci[a], 0, 0, 0);
-            cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, yc[q].y, cr[a], 0, 0, 0);
-            ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, yc[q].x, ci[a], 0, 0, 0);
+            ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, yc[q].y, ci[a], 0, 0, 0);
+            c3[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, ys, c3[a], 0, 0, 0);
           }
         }
       }
       __syncthreads();
     }
+    // the halves' partial sums in (re, im) form: cr <- P1 - P2, ci <- P3 - P1 - P2
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double p1 = cr[a][v], p2 = ci[a][v], p3 = c3[a][v];
+        cr[a][v] = p1 - p2;
+        ci[a][v] = p3 - p1 - p2;
+      }
     // R = Z - (partial sum of half 0) - (partial sum of half 1).  Half 0 loads its 16
     // elements of Z (clamped, all in flight together) and writes Z - S0; half 1 then
     // subtracts S1
@@ -575,20 +586,28 @@ __global__ __launch_bounds__(TR_THREADS) void k_trsm_upper(const double2* A, int
     // Y_rows = Dinv R; half h takes columns [32 h, 32 h + 32) of Dinv (read from L2)
     const double2* Di = Dinv + (b * nblk + ib) * 64 * 64;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; }
+    for (int a = 0; a < 4; ++a) { cr[a] = d4v{0, 0, 0, 0}; ci[a] = d4v{0, 0, 0, 0}; c3[a] = d4v{0, 0, 0, 0}; }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int kl = 32 * h + 4 * q + (lane >> 4);
       const double2 rr = Rs[kl][cl];
+      const double rs = rr.x + rr.y;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const double2 d = Di[(a * 16 + (lane & 15)) * 64 + kl];
         cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(d.x, rr.x, cr[a], 0, 0, 0);
-        ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(d.x, rr.y, ci[a], 0, 0, 0);
-        cr[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(-d.y, rr.y, cr[a], 0, 0, 0);
-        ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(d.y, rr.x, ci[a], 0, 0, 0);
+        ci[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(d.y, rr.y, ci[a], 0, 0, 0);
+        c3[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(d.x + d.y, rs, c3[a], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double p1 = cr[a][v], p2 = ci[a][v], p3 = c3[a][v];
+        cr[a][v] = p1 - p2;
+        ci[a][v] = p3 - p1 - p2;
+      }
     __syncthreads();   // every read of Rs done
     if (h == 1) {
 #pragma unroll

@@ -4,8 +4,9 @@
 // systems of the fold's shape (n_g x (2 n_g + n_open)) and interface-product operands,
 // times the LU factorisation + back substitution with every combination of the two tile
 // edges for the LU's trailing update and its in-panel / U12 products, and the interface
-// product with both edges, and records the fastest per role for that n_g.  The two tile
-// shapes accumulate every element in the same order, so the choice changes run time only.
+// product with both edges (64: 64 x 64 tiles, 128: 128 x 64 tiles), and records the fastest
+// per role for that n_g.  The two tile shapes accumulate every element in the same order, so
+// the choice changes run time only.
 #include <algorithm>
 #include <cmath>
 
