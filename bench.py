@@ -817,19 +817,21 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by_per / avg_s / 1e9, "peak": HBM_PEAK, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"] if launches else None
-    # the FP32 products always use 64 x 64 tiles; FP64 the tuned (or default 128) edge
-    iface_tile = 64 if head == "fp32" else ((tuned_main["choice"]["iface"] if tuned_main else 0) or 128)
+    # the FP32 products always use 64 x 64 tiles; FP64 the tuned (or default 64) edge
+    iface_tile = 64 if head == "fp32" else ((tuned_main["choice"]["iface"] if tuned_main else 0) or 64)
     roof["traffic"] = measured_traffic(cat, fl_per, head, iface_tile if cat == "iface_gemm" else 128)
     roof["kernel"] = cat
     if cat == "iface_gemm":
-        roof["tile"] = f"{iface_tile}x{iface_tile}"
+        roof["tile"] = "64x64" if iface_tile == 64 else "128x64"
         roof["algorithmic_flop_per_launch"] = fl_per
         roof["algorithmic_bytes_per_launch"] = by_per
     roof["avg_launch_ms"] = avg_s * 1e3
     roof["launches"] = launches
     roof["note"] = ("per-launch durations from HIP events that bracket the kernel's own execution "
                     "(hipExtLaunchKernel) on the stream it is launched on, over the timed region of the "
-                    "headline form; the interface GEMM runs alone on the GPU")
+                    "headline form; the interface GEMM runs alone on the GPU; algorithmic flops are "
+                    "8 M N K per complex product (the kernel issues three real MFMA products per "
+                    "complex one, 6 M N K)")
 
     line = {
         "metric": METRIC,

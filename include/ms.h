@@ -306,8 +306,7 @@ ms_status ms_dT_dV(ms_ctx ctx, const ms_slices* slices, int64_t n_e, const doubl
 
 /* Tile edges of the fold's complex GEMMs for one basis size: 64 (64 x 64 tiles, 4 waves) or
  * 128 (128 x 64 tiles, 8 waves; FP64 products only, the FP32-MFMA form always takes 64); 0 =
- * the default rule (64 for the LU's products, 128 for the interface product when it is at
- * least 128 x 128, else 64).  Roles: the interface product (Sec. II, the
+ * the default (64).  Roles: the interface product (Sec. II, the
  * star product with the accumulated right part), the LU's rank-128 trailing update, and its
  * in-panel and U12 products.  Both shapes accumulate every element in the same order, so the
  * edges change run time only, never a result. */

@@ -413,10 +413,10 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
                 (double)g.batch * 16.0 * g.M * g.N * ((g.beta.x != 0.0 || g.beta.y != 0.0) ? 2 : 1),
             true);
   // Tile edge: the tuned choice for the fold group's basis size (ms_autotune / ms_set_tiles),
-  // else 64 x 64 (4 waves, two workgroups per CU) for the LU's products and for products
-  // smaller than 128 x 128, 128 x 64 (8 waves, one workgroup per CU) otherwise.  Every wave
-  // owns a 32 x 32 sub-tile in both shapes and every element is accumulated in the same
-  // order, so the choice never changes a result.
+  // else 64 x 64 (4 waves, two workgroups per CU), which timed faster than 128 x 64 (8 waves,
+  // one workgroup per CU) for every role at N_G = 1200.  Every wave owns a 32 x 32 sub-tile in
+  // both shapes and every element is accumulated in the same order, so the choice never
+  // changes a result.
   static const int tile_env = [] {   // MS_GEMM_TILE=64: 64 x 64 tiles everywhere
     const char* e = getenv("MS_GEMM_TILE");
     return e ? atoi(e) : 0;
@@ -428,8 +428,7 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
         tile = g.prof == PC_IFACE_GEMM ? t.iface
                                        : (g.prof == PC_LU_UPDATE ? t.lu_update : (g.prof == PC_LU_INNER ? t.lu_inner : 0));
   if (tile_env == 64) tile = 64;
-  if (tile == 0)
-    tile = (g.prof != PC_LU_UPDATE && g.prof != PC_LU_INNER && g.M >= 128 && g.N >= 128) ? 128 : 64;
+  if (tile == 0) tile = 64;
   // FP32 MFMA keeps FP64 sums of its K-slabs (three per element): 64 x 64 tiles always
   if constexpr (!std::is_same<T, double>::value) {
     if (gen) return launch<T, 64, 64, 2, 2, 1>(ctx, p, g.batch, prof);

@@ -75,8 +75,8 @@ def _iface_ref(a, o, kp, kq):
 
 @pytest.mark.parametrize("n,batch", [(1, 1), (7, 3), (37, 2), (64, 2), (65, 3), (130, 2), (300, 4), (1200, 2)])
 def test_iface_product_fp64(lib, ctx, n, batch):
-    """The fold's interface product with its generated B operand (ragged tile tails, both tile
-    edges: 64 for n < 128, 128 otherwise), against NumPy in FP64."""
+    """The fold's interface product with its generated B operand (ragged tile tails), against
+    NumPy in FP64."""
     rng = np.random.default_rng(n + 17 * batch)
     a = _rand(rng, (batch, n, n))
     o = _rand(rng, (n, n)) / np.sqrt(n)

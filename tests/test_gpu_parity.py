@@ -660,6 +660,25 @@ def test_tile_choice_and_autotune_do_not_change_results(ms, ctx):
     assert ei.value.status == ms.MS_ERR_ARG
 
 
+def test_tile_shapes_bit_identical_at_ragged_size(ms, ctx):
+    """The fold at N_G = 130 (ragged tails for 64 x 64 and 128 x 64 tiles alike): T and R of the
+    FP64 form are bit-identical with either tile edge for every GEMM role."""
+    j = msgen.config1()
+    inp = msgen.junction_inputs(j, (0.03, -0.02), n_g=130)
+    s = ms.prepare_from_inputs(ctx, inp)
+    es = np.linspace(0.3, 0.9, 6)
+    out = []
+    try:
+        for tiles in ((64, 64, 64), (128, 128, 128)):
+            ms.ms_set_tiles(ctx, 130, *tiles)
+            T, R = (_np(x) for x in ms.ms_transmission_batch(ctx, s, es, "fp64")[:2])
+            ctx.sync()
+            out.append((T, R))
+    finally:
+        ms.ms_set_tiles(ctx, 130)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 # ------------------------------------------------------------------ dT/dV -----------------
 def _grad_case(ms, ctx, n_g, ns, kpar):
     j = msgen.config1()
