@@ -507,6 +507,10 @@ def uneven_measure(ms, ctx, count, log, replays=2, prep_streams=3, chunk_bytes=6
         "max_abs_R_plus_T_minus_Nopen_fp64": float(np.max(np.abs(res_T["fp64"] + res_R64 - res_no64))),
         "bad_points": bad,
     }
+    res["worst_dT"] = [dict(instance=int(i), n_g=int(inst[i]["junction"].n_g), slices=len(inst[i]["junction"].dz),
+                            energy=round(float(inst[i]["energy"]), 4), n_open=int(res_no64[i]),
+                            T=round(float(res_T["fp64"][i]), 6), dT=float(f"{dT[i]:.3g}"))
+                       for i in np.argsort(-dT)[:3]]
     if count <= 32:
         res["abs_dT_fp32_vs_fp64"] = [float(f"{v:.3g}") for v in dT]
     else:
