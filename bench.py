@@ -170,7 +170,8 @@ def electrode_measure(n_g, n_e, bands_only=False):
     ctx.sync()
     energies = np.linspace(0.3, 0.9, n_e) if n_e > 1 else np.array([0.5])
     rows = []
-    for e in energies:
+    # one energy at a time: all of them for the bands alone, else the first (compared with the batch)
+    for e in (energies if bands_only else energies[:1]):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         al, be, _ = ms.ms_complex_bands(ctx, sl, float(e))
@@ -185,10 +186,24 @@ def electrode_measure(n_g, n_e, bands_only=False):
             rows[-1].update(transmission_s=round(time.perf_counter() - t1, 3), T=float(T[0]), R=float(R[0]),
                             n_in=int(no[0]))
         print(f"[bench] electrode E={e:.3f}: {rows[-1]}", file=sys.stderr, flush=True)
+    batch = None
+    if n_e > 1 and not bands_only:   # all energies in one call: both cells' pencils in one QZ launch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, R, no = ms.ms_electrode_transmission_batch(ctx, sl, sg, sr, energies)
+        ctx.sync()
+        tb = time.perf_counter() - t0
+        Th = T.cpu().numpy()
+        batch = dict(energies=int(n_e), seconds=round(tb, 3), seconds_per_energy=round(tb / n_e, 3),
+                     single_call_seconds=rows[0]["transmission_s"], T=[float(x) for x in Th],
+                     n_in=[int(x) for x in no.cpu().numpy()],
+                     abs_T_minus_single_call_first_energy=float(abs(Th[0] - rows[0]["T"])))
+        print(f"[bench] electrode batch of {n_e}: {tb:.2f} s", file=sys.stderr, flush=True)
     ctx.close()
     return dict(n_g=n_g, pencil=2 * n_g, cell_slices=40, region_slices=int(jg.dz.size), k_par=[float(x) for x in kp],
-                points=rows, note="one workgroup per pencil (complex QZ); transmission = both cells' bands + "
-                                  "the region's S-matrix + the matching solve")
+                points=rows, batch=batch,
+                note="one workgroup per pencil (complex QZ); transmission = both cells' bands + the region's "
+                     "S-matrix + the matching solve; batch = all energies in one call")
 
 
 def workload(name):

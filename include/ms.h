@@ -400,6 +400,16 @@ ms_status ms_complex_bands(ms_ctx ctx, const ms_slices* cell, double energy, voi
 ms_status ms_electrode_transmission(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
                                     const ms_slices* right, double energy, double* T, double* R, int64_t* n_in);
 
+/* ms_electrode_transmission at n_e energies (host array energies [n_e], 1 <= n_e <= 32768):
+ * T, R [n_e] f64 and n_in [n_e] int64 device outputs.  Both electrodes' pencils at every energy
+ * are solved in one QZ launch (one workgroup per pencil, 2 n_e pencils; in chunks of at most
+ * 48 GiB of pencil buffers), then each energy is matched as in the single call, whose results
+ * it reproduces bit for bit.  Waits for the stream.  Errors: as ms_electrode_transmission; the
+ * first energy that fails names its index in the error text. */
+ms_status ms_electrode_transmission_batch(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
+                                          const ms_slices* right, int64_t n_e, const double* energies, double* T,
+                                          double* R, int64_t* n_in);
+
 #ifdef __cplusplus
 }
 #endif

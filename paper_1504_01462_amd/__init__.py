@@ -61,6 +61,8 @@ _sig("ms_bloch_pencil", [_vp, ctypes.POINTER(MsSlices), ctypes.c_double, _vp, _v
 _sig("ms_complex_bands", [_vp, ctypes.POINTER(MsSlices), _f64, _vp, _vp, _vp])
 _sig("ms_electrode_transmission", [_vp, ctypes.POINTER(MsSlices), ctypes.POINTER(MsSlices), ctypes.POINTER(MsSlices),
                                    _f64, _vp, _vp, _vp])
+_sig("ms_electrode_transmission_batch", [_vp, ctypes.POINTER(MsSlices), ctypes.POINTER(MsSlices),
+                                         ctypes.POINTER(MsSlices), _i64, _vp, _vp, _vp, _vp])
 _sig("ms_transmission", [_vp, ctypes.POINTER(MsSmat), _f64, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
 _sig("ms_transmission_batch_noalloc", [_vp, ctypes.POINTER(MsSlices), _i64, _vp, _i32, _vp, _vp, _vp, _vp])
@@ -246,6 +248,20 @@ def ms_electrode_transmission(ctx: Context, left: Slices, region: Slices, right:
     _check(ctx.handle, lib.ms_electrode_transmission(ctx.handle, ctypes.byref(left.c), ctypes.byref(region.c),
                                                      ctypes.byref(right.c), float(energy), _ptr(T), _ptr(R),
                                                      _ptr(no)))
+    return T, R, no
+
+
+def ms_electrode_transmission_batch(ctx: Context, left: Slices, region: Slices, right: Slices, energies):
+    """T, R, n_in [n_e] between two periodic electrodes through a region at several energies
+    (both electrodes' Bloch pencils of all energies in one QZ launch)."""
+    e = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).reshape(-1))
+    T = torch.empty(e.size, dtype=torch.float64, device=ctx.device)
+    R = torch.empty(e.size, dtype=torch.float64, device=ctx.device)
+    no = torch.empty(e.size, dtype=torch.int64, device=ctx.device)
+    _check(ctx.handle, lib.ms_electrode_transmission_batch(ctx.handle, ctypes.byref(left.c), ctypes.byref(region.c),
+                                                           ctypes.byref(right.c), e.size,
+                                                           e.ctypes.data_as(ctypes.c_void_p), _ptr(T), _ptr(R),
+                                                           _ptr(no)))
     return T, R, no
 
 
@@ -556,7 +572,7 @@ def prepare_from_inputs_into(ctx: Context, inp: dict, out: Slices, vlead=(0.0, 0
 
 __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "ms_status_str",
            "ms_slices_prepare", "ms_slice_smatrix", "ms_star_cascade", "ms_bloch_pencil", "ms_complex_bands",
-           "ms_electrode_transmission", "ms_mixed_doubling",
+           "ms_electrode_transmission", "ms_electrode_transmission_batch", "ms_mixed_doubling",
            "ms_transmission",
            "ms_transmission_batch", "ms_transmission_batch_noalloc", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",

@@ -12,13 +12,16 @@
 namespace ms {
 namespace {
 
-// workspace slots of this file; a cell's own buffers (P, Q, alpha, beta, X, a|b) take the six
-// slots from WE_ONE, WE_RIGHT or WE_LEFT
+// workspace slots of this file, above every slot the fold, the cell pencil (ms_bloch_pencil)
+// and the star products take, since those run between a request here and its use
 enum {
-  WE_QA = 70, WE_QB, WE_QV, WE_QY, WE_G, WE_FL, WE_ST,
-  WE_SEG, WE_WHOLE, WE_EPS2, WE_OVL2, WE_IDX, WE_M, WE_Y, WE_PIV, WE_TMP, WE_EN, WE_ZERO,
-  WE_ONE = 100, WE_RIGHT = 110, WE_LEFT = 120
+  WE_SEG = 200, WE_WHOLE, WE_EPS2, WE_OVL2, WE_IDX, WE_M, WE_Y, WE_PIV, WE_TMP, WE_EN,
+  // the band stage: the batch's pencils (P, Q), their QZ copies and transforms, (alpha, beta),
+  // X, one G, the states' (a | b), fluxes and QZ status words
+  WB_P = 220, WB_Q, WB_QA, WB_QB, WB_QV, WB_QY, WB_AL, WB_BE, WB_X, WB_G, WB_AB, WB_FL, WB_ST
 };
+// device bytes the band stage may take for the pencils of one QZ launch
+constexpr size_t BANDS_BUDGET = size_t(48) << 30;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -197,69 +200,91 @@ ms_status check_cell(ms_ctx ctx, const ms_slices* s, const char* name) {
 }
 
 struct Bands {
-  double2 *al, *be, *X, *P, *Q, *a, *b;
+  const double2 *al, *be, *X, *a, *b;
   std::vector<double2> alh, beh;
   std::vector<double> flux;
 };
 
-// the 2n Bloch states of a cell at `energy`: alpha, beta, X (QZ), and a, b at their planes;
-// slots base + {P, Q, ..}
-ms_status cell_bands(ms_ctx ctx, const ms_slices* cell, double energy, int base, Bands* out) {
-  const int n = (int)cell->n_g, m = 2 * n;
+// The 2n Bloch states of `count` (cell, energy) pairs: each pencil (Eq. cmp) is built with the
+// fold's kernels, the pencils' QZ runs as one batch (one workgroup per pencil), then each
+// pencil's states are read at their planes (a, b) and their fluxes formed.  Pencils are taken
+// in chunks whose eight 2n x 2n buffers fit BANDS_BUDGET; out[k].a, .b stay valid until the next
+// call, out[k].al, .be, .X only for the last chunk (count 1: always).
+ms_status bands_batch(ms_ctx ctx, int count, const ms_slices* const* cells, const double* energies,
+                      std::vector<Bands>& out) {
+  const int n = (int)cells[0]->n_g, m = 2 * n;
   const int64_t mm = (int64_t)m * m;
   const size_t big = (size_t)mm * sizeof(double2);
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(count, (int64_t)(BANDS_BUDGET / (8 * big))));
   void *P, *Q, *QA, *QB, *QV, *QY, *al, *be, *X, *G, *ab, *fl, *st;
-  MS_TRY(workspace(ctx, base + 0, big, &P));
-  MS_TRY(workspace(ctx, base + 1, big, &Q));
-  MS_TRY(workspace(ctx, WE_QA, big, &QA));
-  MS_TRY(workspace(ctx, WE_QB, big, &QB));
-  MS_TRY(workspace(ctx, WE_QV, big, &QV));
-  MS_TRY(workspace(ctx, WE_QY, big, &QY));
-  MS_TRY(workspace(ctx, base + 2, (size_t)m * sizeof(double2), &al));
-  MS_TRY(workspace(ctx, base + 3, (size_t)m * sizeof(double2), &be));
-  MS_TRY(workspace(ctx, base + 4, big, &X));
-  MS_TRY(workspace(ctx, WE_G, big, &G));
-  MS_TRY(workspace(ctx, base + 5, (size_t)2 * n * m * sizeof(double2), &ab));
-  MS_TRY(workspace(ctx, WE_FL, (size_t)m * sizeof(double), &fl));
-  MS_TRY(workspace(ctx, WE_ST, sizeof(int32_t), &st));
-  MS_TRY(ms_bloch_pencil(ctx, cell, energy, P, Q));
-  MS_HIP(ctx, hipMemcpyAsync(QA, P, big, hipMemcpyDeviceToDevice, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(QB, Q, big, hipMemcpyDeviceToDevice, ctx->stream));
-  MS_TRY(launch_fill_i32(ctx, 1, (int32_t*)st, 0));
-  MS_TRY(qz_eig(ctx, m, 1, (double2*)QA, (double2*)QB, (double2*)QV, (double2*)QY, (double2*)al, (double2*)be,
-                (double2*)X, (int32_t*)st));
-  // G = [(P X)_top ; (Q X)_bot]
-  GemmArgs g;
-  g.M = n; g.N = m; g.K = m;
-  g.A = P; g.lda = m; g.B = X; g.ldb = m; g.C = (double2*)G; g.ldc = m;
-  MS_TRY(zgemm(ctx, g));
-  g.A = (double2*)Q + (int64_t)n * m; g.C = (double2*)G + (int64_t)n * m;
-  MS_TRY(zgemm(ctx, g));
-  double2* a = (double2*)ab;
-  double2* b = a + (int64_t)n * m;
-  hipLaunchKernelGGL(k_modes_select, dim3((unsigned)((n * (int64_t)m + 255) / 256)), dim3(256), 0, ctx->stream, n,
-                     (const double2*)X, (const double2*)G, (const double2*)al, (const double2*)be, a, b);
-  MS_TRY(check_launch(ctx, "modes select"));
-  hipLaunchKernelGGL(k_mode_flux, dim3(m), dim3(256), 0, ctx->stream, n, energy, cell->eps + n, (const double2*)a,
-                     (const double2*)b, (double*)fl);
-  MS_TRY(check_launch(ctx, "mode flux"));
-  out->al = (double2*)al;
-  out->be = (double2*)be;
-  out->X = (double2*)X;
-  out->P = (double2*)P;
-  out->Q = (double2*)Q;
-  out->a = a;
-  out->b = b;
-  out->alh.resize(m);
-  out->beh.resize(m);
-  out->flux.resize(m);
-  int32_t sth = 0;
-  MS_HIP(ctx, hipMemcpyAsync(out->alh.data(), al, m * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(out->beh.data(), be, m * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(out->flux.data(), fl, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(&sth, st, sizeof sth, hipMemcpyDeviceToHost, ctx->stream));
+  MS_TRY(workspace(ctx, WB_AB, (size_t)count * 2 * n * m * sizeof(double2), &ab));
+  MS_TRY(workspace(ctx, WB_FL, (size_t)count * m * sizeof(double), &fl));
+  MS_TRY(workspace(ctx, WB_ST, (size_t)count * sizeof(int32_t), &st));
+  std::vector<int32_t> sth(count, 0);
+  out.assign(count, Bands{});
+  for (int c0 = 0; c0 < count; c0 += chunk) {
+    const int cn = std::min(chunk, count - c0);
+    // the pencils first: ms_bloch_pencil takes slots of its own, none of WB_*
+    MS_TRY(workspace(ctx, WB_P, cn * big, &P));
+    MS_TRY(workspace(ctx, WB_Q, cn * big, &Q));
+    for (int k = 0; k < cn; ++k)
+      MS_TRY(ms_bloch_pencil(ctx, cells[c0 + k], energies[c0 + k], (double2*)P + k * mm, (double2*)Q + k * mm));
+    MS_TRY(workspace(ctx, WB_QA, cn * big, &QA));
+    MS_TRY(workspace(ctx, WB_QB, cn * big, &QB));
+    MS_TRY(workspace(ctx, WB_QV, cn * big, &QV));
+    MS_TRY(workspace(ctx, WB_QY, cn * big, &QY));
+    MS_TRY(workspace(ctx, WB_AL, (size_t)cn * m * sizeof(double2), &al));
+    MS_TRY(workspace(ctx, WB_BE, (size_t)cn * m * sizeof(double2), &be));
+    MS_TRY(workspace(ctx, WB_X, cn * big, &X));
+    MS_TRY(workspace(ctx, WB_G, big, &G));
+    MS_HIP(ctx, hipMemcpyAsync(QA, P, cn * big, hipMemcpyDeviceToDevice, ctx->stream));
+    MS_HIP(ctx, hipMemcpyAsync(QB, Q, cn * big, hipMemcpyDeviceToDevice, ctx->stream));
+    int32_t* stc = (int32_t*)st + c0;
+    MS_TRY(launch_fill_i32(ctx, cn, stc, 0));
+    MS_TRY(qz_eig(ctx, m, cn, (double2*)QA, (double2*)QB, (double2*)QV, (double2*)QY, (double2*)al, (double2*)be,
+                  (double2*)X, stc));
+    for (int k = 0; k < cn; ++k) {
+      const int c = c0 + k;
+      const double2* Xk = (const double2*)X + k * mm;
+      const double2* alk = (const double2*)al + (int64_t)k * m;
+      const double2* bek = (const double2*)be + (int64_t)k * m;
+      // G = [(P X)_top ; (Q X)_bot]
+      GemmArgs g;
+      g.M = n; g.N = m; g.K = m;
+      g.A = (double2*)P + k * mm; g.lda = m; g.B = Xk; g.ldb = m; g.C = (double2*)G; g.ldc = m;
+      MS_TRY(zgemm(ctx, g));
+      g.A = (double2*)Q + k * mm + (int64_t)n * m; g.C = (double2*)G + (int64_t)n * m;
+      MS_TRY(zgemm(ctx, g));
+      double2* a = (double2*)ab + (int64_t)c * 2 * n * m;
+      double2* b = a + (int64_t)n * m;
+      double* flc = (double*)fl + (int64_t)c * m;
+      hipLaunchKernelGGL(k_modes_select, dim3((unsigned)((n * (int64_t)m + 255) / 256)), dim3(256), 0, ctx->stream, n,
+                         Xk, (const double2*)G, alk, bek, a, b);
+      MS_TRY(check_launch(ctx, "modes select"));
+      hipLaunchKernelGGL(k_mode_flux, dim3(m), dim3(256), 0, ctx->stream, n, energies[c], cells[c]->eps + n,
+                         (const double2*)a, (const double2*)b, flc);
+      MS_TRY(check_launch(ctx, "mode flux"));
+      Bands& o = out[c];
+      o.al = alk;
+      o.be = bek;
+      o.X = Xk;
+      o.a = a;
+      o.b = b;
+      o.alh.resize(m);
+      o.beh.resize(m);
+      MS_HIP(ctx, hipMemcpyAsync(o.alh.data(), alk, m * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+      MS_HIP(ctx, hipMemcpyAsync(o.beh.data(), bek, m * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    }
+  }
+  std::vector<double> flh((size_t)count * m);
+  MS_HIP(ctx, hipMemcpyAsync(flh.data(), fl, flh.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(sth.data(), st, count * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
   MS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (sth != 0) return fail(ctx, (ms_status)sth, "QZ of the cell's Bloch pencil did not converge");
+  for (int c = 0; c < count; ++c) {
+    if (sth[c] != 0)
+      return fail(ctx, (ms_status)sth[c], "QZ of the Bloch pencil at energy %g did not converge", energies[c]);
+    out[c].flux.assign(flh.begin() + (int64_t)c * m, flh.begin() + (int64_t)(c + 1) * m);
+  }
   return MS_OK;
 }
 
@@ -312,45 +337,13 @@ ms_status cross_interface(ms_ctx ctx, int n, const double* eps_u, const double* 
   return ms_slice_smatrix(ctx, &pair, energy, 1, 2, out);
 }
 
-}  // namespace
-}  // namespace ms
-
-using namespace ms;
-
-extern "C" {
-
-ms_status ms_complex_bands(ms_ctx ctx, const ms_slices* cell, double energy, void* alpha, void* beta, void* X) {
-  if (!ctx) return MS_ERR_ARG;
-  MS_TRY(check_cell(ctx, cell, "cell"));
-  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
-  if (!alpha || !beta || !X) return fail(ctx, MS_ERR_ARG, "NULL output pointer");
-  MS_HIP(ctx, hipSetDevice(ctx->device));
-  Bands bd;
-  MS_TRY(cell_bands(ctx, cell, energy, WE_ONE, &bd));
-  const int m = 2 * (int)cell->n_g;
-  MS_HIP(ctx, hipMemcpyAsync(alpha, bd.al, m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(beta, bd.be, m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  MS_HIP(ctx, hipMemcpyAsync(X, bd.X, (size_t)m * m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
-  return MS_OK;
-}
-
-ms_status ms_electrode_transmission(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
-                                    const ms_slices* right, double energy, double* T, double* R, int64_t* n_in) {
-  if (!ctx) return MS_ERR_ARG;
-  MS_TRY(check_cell(ctx, left, "left"));
-  MS_TRY(check_cell(ctx, region, "region"));
-  MS_TRY(check_cell(ctx, right, "right"));
-  if (left->n_g != region->n_g || right->n_g != region->n_g)
-    return fail(ctx, MS_ERR_ARG, "the electrodes and the region need the same basis size");
-  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
-  if (!T || !R || !n_in) return fail(ctx, MS_ERR_ARG, "NULL output pointer");
-  MS_HIP(ctx, hipSetDevice(ctx->device));
+// Eq. trans at one energy from both electrodes' Bloch states (bl, br): the region's S between
+// the electrodes' slice-1 planes, the states sorted by direction, the matching solve, and T, R
+// written to the device scalars T, R (left as they are without incident states)
+ms_status match_one(ms_ctx ctx, const ms_slices* left, const ms_slices* region, const ms_slices* right, double energy,
+                    const Bands& bl, const Bands& br, double* T, double* R, int64_t* nin_out) {
   const int n = (int)region->n_g, m = 2 * n, ns = (int)region->n_slices;
   const int64_t nn = (int64_t)n * n;
-  // 1. Bloch states of both electrodes (the right one's slots first: the left's use the same scratch)
-  Bands bl, br;
-  MS_TRY(cell_bands(ctx, right, energy, WE_RIGHT, &br));
-  MS_TRY(cell_bands(ctx, left, energy, WE_LEFT, &bl));
   Dirs dl, dr;
   MS_TRY(directions(ctx, bl, n, "left electrode", &dl));
   MS_TRY(directions(ctx, br, n, "right electrode", &dr));
@@ -454,27 +447,98 @@ ms_status ms_electrode_transmission(ms_ctx ctx, const ms_slices* left, const ms_
     MS_TRY(getrf_aug(ctx, Mm, m, lm, (int64_t)m * lm, 1, (int32_t*)piv, ctx->d_status, 0));
     MS_TRY(trsm_upper_aug(ctx, Mm, m, lm, (int64_t)m * lm, 1, (double2*)Y, nin, (int64_t)m * nin, ctx->d_status, 0));
   }
-  // 5. T and R
-  {
-    void* en;
-    MS_TRY(workspace(ctx, WE_EN, sizeof(int64_t), &en));
-    const int64_t v = nin;
-    MS_TRY(upload(ctx, en, &v, sizeof v));
-    MS_HIP(ctx, hipMemcpyAsync(n_in, en, sizeof v, hipMemcpyDeviceToDevice, ctx->stream));
-  }
-  if (nin == 0) {
-    const double zero[2] = {0.0, 0.0};
-    void* z;
-    MS_TRY(workspace(ctx, WE_ZERO, sizeof zero, &z));
-    MS_TRY(upload(ctx, z, zero, sizeof zero));
-    MS_HIP(ctx, hipMemcpyAsync(T, z, sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    MS_HIP(ctx, hipMemcpyAsync(R, z, sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    return MS_OK;
-  }
+  // 5. T and R (zeroed by the caller: nothing to do without incident states)
+  *nin_out = nin;
+  if (nin == 0) return MS_OK;
   hipLaunchKernelGGL(k_electrode_T, dim3(1), dim3(256), 0, ctx->stream, n, nin, nt, nr, id + 2 * n + nin, energy,
                      left->eps + n, right->eps + n, (const double2*)SA, (const double2*)SB, ld, (const double2*)Y, nin,
                      T, R);
   return check_launch(ctx, "electrode T");
+}
+
+// checks shared by the entry points; energies on the host
+ms_status check_electrodes(ms_ctx ctx, const ms_slices* left, const ms_slices* region, const ms_slices* right,
+                           int64_t n_e, const double* energies) {
+  MS_TRY(check_cell(ctx, left, "left"));
+  MS_TRY(check_cell(ctx, region, "region"));
+  MS_TRY(check_cell(ctx, right, "right"));
+  if (left->n_g != region->n_g || right->n_g != region->n_g)
+    return fail(ctx, MS_ERR_ARG, "the electrodes and the region need the same basis size");
+  if (n_e < 1 || n_e > 32768) return fail(ctx, MS_ERR_ARG, "n_e must be in [1, 32768]");
+  if (!energies) return fail(ctx, MS_ERR_ARG, "energies is NULL");
+  for (int64_t e = 0; e < n_e; ++e)
+    if (!std::isfinite(energies[e])) return fail(ctx, MS_ERR_ARG, "energy %lld is not finite", (long long)e);
+  return MS_OK;
+}
+
+// both electrodes' bands at every energy in one batch, then the matching energy by energy
+ms_status electrode_batch(ms_ctx ctx, const ms_slices* left, const ms_slices* region, const ms_slices* right,
+                          int64_t n_e, const double* energies, double* T, double* R, int64_t* n_in) {
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  MS_HIP(ctx, hipMemsetAsync(T, 0, n_e * sizeof(double), ctx->stream));
+  MS_HIP(ctx, hipMemsetAsync(R, 0, n_e * sizeof(double), ctx->stream));
+  std::vector<const ms_slices*> cells;
+  std::vector<double> ens;
+  for (int side = 0; side < 2; ++side)
+    for (int64_t e = 0; e < n_e; ++e) {
+      cells.push_back(side == 0 ? right : left);
+      ens.push_back(energies[e]);
+    }
+  std::vector<Bands> bands;
+  MS_TRY(bands_batch(ctx, (int)cells.size(), cells.data(), ens.data(), bands));
+  std::vector<int64_t> nin(n_e, 0);
+  for (int64_t e = 0; e < n_e; ++e) {
+    const ms_status st = match_one(ctx, left, region, right, energies[e], bands[n_e + e], bands[e], T + e, R + e,
+                                   &nin[e]);
+    if (st != MS_OK) {
+      ctx->last_error = "energy " + std::to_string((long long)e) + ": " + ctx->last_error;
+      return st;
+    }
+  }
+  void* en;
+  MS_TRY(workspace(ctx, WE_EN, n_e * sizeof(int64_t), &en));
+  MS_TRY(upload(ctx, en, nin.data(), n_e * sizeof(int64_t)));
+  MS_HIP(ctx, hipMemcpyAsync(n_in, en, n_e * sizeof(int64_t), hipMemcpyDeviceToDevice, ctx->stream));
+  return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+ms_status ms_complex_bands(ms_ctx ctx, const ms_slices* cell, double energy, void* alpha, void* beta, void* X) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_cell(ctx, cell, "cell"));
+  if (!std::isfinite(energy)) return fail(ctx, MS_ERR_ARG, "energy must be finite");
+  if (!alpha || !beta || !X) return fail(ctx, MS_ERR_ARG, "NULL output pointer");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  std::vector<Bands> bd;
+  MS_TRY(bands_batch(ctx, 1, &cell, &energy, bd));
+  const int m = 2 * (int)cell->n_g;
+  MS_HIP(ctx, hipMemcpyAsync(alpha, bd[0].al, m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(beta, bd[0].be, m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  MS_HIP(ctx, hipMemcpyAsync(X, bd[0].X, (size_t)m * m * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream));
+  return MS_OK;
+}
+
+ms_status ms_electrode_transmission(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
+                                    const ms_slices* right, double energy, double* T, double* R, int64_t* n_in) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_electrodes(ctx, left, region, right, 1, &energy));
+  if (!T || !R || !n_in) return fail(ctx, MS_ERR_ARG, "NULL output pointer");
+  return electrode_batch(ctx, left, region, right, 1, &energy, T, R, n_in);
+}
+
+ms_status ms_electrode_transmission_batch(ms_ctx ctx, const ms_slices* left, const ms_slices* region,
+                                          const ms_slices* right, int64_t n_e, const double* energies, double* T,
+                                          double* R, int64_t* n_in) {
+  if (!ctx) return MS_ERR_ARG;
+  MS_TRY(check_electrodes(ctx, left, region, right, n_e, energies));
+  if (!T || !R || !n_in) return fail(ctx, MS_ERR_ARG, "NULL output pointer");
+  return electrode_batch(ctx, left, region, right, n_e, energies, T, R, n_in);
 }
 
 }  // extern "C"

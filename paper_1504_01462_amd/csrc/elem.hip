@@ -178,13 +178,39 @@ __global__ void k_tcols(int n, int n_o, const int32_t* ch, const double2* Y, int
   M[e * sM + (int64_t)i * ldm + 2 * n + c] = cmul(pq[e * sk + i], v);
 }
 
+// Sums (and a minimum, a count) over the 256 threads of a workgroup: butterfly shuffles inside
+// each wave, then the four wave results in a fixed order, so the result is the same every run.
+struct TRPart {
+  double t, r, m;
+  int o;
+};
+__device__ __forceinline__ TRPart block_reduce_tr(TRPart v, TRPart* wave_part) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.t += __shfl_xor(v.t, off, 64);
+    v.r += __shfl_xor(v.r, off, 64);
+    v.m = fmin(v.m, __shfl_xor(v.m, off, 64));
+    v.o += __shfl_xor(v.o, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) wave_part[wave] = v;
+  __syncthreads();
+  TRPart s = wave_part[0];
+  for (int w = 1; w < 4; ++w) {
+    s.t += wave_part[w].t;
+    s.r += wave_part[w].r;
+    s.m = fmin(s.m, wave_part[w].m);
+    s.o += wave_part[w].o;
+  }
+  return s;
+}
+
 // T, R, N_open of the fused path from the final state (Y1 = K^-1 r^T K, Y2 = (2K)^-1 t^T)
 __global__ __launch_bounds__(256) void k_batch_T(int n, int n_o, const int32_t* ch, const double* energies,
                                                  const double* eps_l, const double* eps_r, const double2* Y,
                                                  int64_t ldy, int64_t sY, double* T, double* R, int64_t* n_open,
                                                  int32_t* status) {
-  __shared__ double st[256], sr[256], sm[256];
-  __shared__ int so[256];
+  __shared__ TRPart wp[4];
   const int64_t e = blockIdx.x;
   const int t = threadIdx.x;
   const double E = energies[e];
@@ -209,24 +235,14 @@ __global__ __launch_bounds__(256) void k_batch_T(int n, int n_o, const int32_t* 
       rr += (ka / kb) * cabs2(Yb[(int64_t)a * ldy + b]);
     }
   }
-  st[t] = tt; sr[t] = rr; sm[t] = mind; so[t] = no;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) {
-      st[t] += st[t + o];
-      sr[t] += sr[t + o];
-      sm[t] = fmin(sm[t], sm[t + o]);
-      so[t] += so[t + o];
-    }
-    __syncthreads();
-  }
+  const TRPart sum = block_reduce_tr(TRPart{tt, rr, mind, no}, wp);
   if (t == 0) {
-    T[e] = st[0];
-    R[e] = sr[0];
-    n_open[e] = so[0];
+    T[e] = sum.t;
+    R[e] = sum.r;
+    n_open[e] = sum.o;
     int32_t code = 0;
-    if (sm[0] < 1e-10) code = MS_ERR_THRESHOLD;
-    else if (!isfinite(st[0]) || !isfinite(sr[0])) code = MS_ERR_NONFINITE;
+    if (sum.m < 1e-10) code = MS_ERR_THRESHOLD;
+    else if (!isfinite(sum.t) || !isfinite(sum.r)) code = MS_ERR_NONFINITE;
     if (code) atomicCAS(status + e, 0, code);
   }
 }
@@ -235,8 +251,7 @@ __global__ __launch_bounds__(256) void k_batch_T(int n, int n_o, const int32_t* 
 __global__ __launch_bounds__(256) void k_whole_T(int n, double E, const double2* t, const double2* r,
                                                  const double* eps_l, const double* eps_r, double* T, double* R,
                                                  int64_t* n_open, int32_t* status) {
-  __shared__ double st[256], sr[256], sm[256];
-  __shared__ int so[256];
+  __shared__ TRPart wp[4];
   const int tid = threadIdx.x;
   double tt = 0.0, rr = 0.0, mind = 1e300;
   int no = 0;
@@ -252,23 +267,13 @@ __global__ __launch_bounds__(256) void k_whole_T(int n, double E, const double2*
       if (eps_l[i] < E) rr += (sqrt(E - eps_l[i]) / kj) * cabs2(r[idx]);
     }
   }
-  st[tid] = tt; sr[tid] = rr; sm[tid] = mind; so[tid] = no;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      st[tid] += st[tid + o];
-      sr[tid] += sr[tid + o];
-      sm[tid] = fmin(sm[tid], sm[tid + o]);
-      so[tid] += so[tid + o];
-    }
-    __syncthreads();
-  }
+  const TRPart sum = block_reduce_tr(TRPart{tt, rr, mind, no}, wp);
   if (tid == 0) {
-    T[0] = st[0];
-    R[0] = sr[0];
-    n_open[0] = so[0];
-    if (sm[0] < 1e-10) atomicCAS(status, 0, (int32_t)MS_ERR_THRESHOLD);
-    else if (!isfinite(st[0]) || !isfinite(sr[0])) atomicCAS(status, 0, (int32_t)MS_ERR_NONFINITE);
+    T[0] = sum.t;
+    R[0] = sum.r;
+    n_open[0] = sum.o;
+    if (sum.m < 1e-10) atomicCAS(status, 0, (int32_t)MS_ERR_THRESHOLD);
+    else if (!isfinite(sum.t) || !isfinite(sum.r)) atomicCAS(status, 0, (int32_t)MS_ERR_NONFINITE);
   }
 }
 

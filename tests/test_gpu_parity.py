@@ -981,6 +981,34 @@ def test_electrode_transmission_far_evanescent(ms, ctx):
         assert abs(t + r - n_in) < 1e-10
 
 
+def test_electrode_transmission_batch(ms, ctx):
+    """Several energies in one call (both electrodes' pencils in one QZ launch): T, R, n_in equal
+    the single-energy calls bit for bit and the oracle to 1e-10; an energy at a band edge or a
+    non-finite energy is reported with its index."""
+    dz = np.array([0.5, 0.6, 0.4])
+    inp = _cell(11, dz)
+    nq = inp["vq"].shape[1]
+    q0 = int(np.where((inp["q_miller"] == 0).all(axis=1))[0][0])
+    vr = np.zeros((2, nq), dtype=np.complex128)
+    vr[:, q0] = [0.3, -0.4]
+    right = _with_slices(inp, [0.45, 0.55], vr)
+    rng = np.random.default_rng(11)
+    dzs = np.array([0.3, 0.5, 0.4, 0.2])
+    region = _with_slices(inp, dzs, inp["vq"][rng.integers(0, 3, dzs.size)] * 1.5)
+    sl, sr, sg = (ms.prepare_from_inputs(ctx, x, with_evec=True) for x in (inp, right, region))
+    es = np.array([0.9, 1.6, 2.4, 1.25])
+    T, R, no = (_np(x) for x in ms.ms_electrode_transmission_batch(ctx, sl, sg, sr, es))
+    pl, pr, pg = orc.prepare(inp), orc.prepare(right), orc.prepare(region)
+    for i, e in enumerate(es):
+        t1, r1, n1 = (_np(x) for x in ms.ms_electrode_transmission(ctx, sl, sg, sr, e))
+        assert T[i] == t1[0] and R[i] == r1[0] and no[i] == n1[0], (e, T[i], t1[0])
+        ref = orc.transmission_bands(pl, pg, pr, e)
+        assert int(no[i]) == ref["n_in"] and abs(T[i] - ref["T"]) < 1e-10 and abs(R[i] - ref["R"]) < 1e-10
+    with pytest.raises(ms.MSError) as ei:
+        ms.ms_electrode_transmission_batch(ctx, sl, sg, sr, [1.0, float("nan")])
+    assert ei.value.status == ms.MS_ERR_ARG and "energy 1" in str(ei.value)
+
+
 def test_electrode_argument_errors(ms, ctx):
     inp = _cell(9, [0.5, 0.6])
     s = ms.prepare_from_inputs(ctx, inp, with_evec=True)
