@@ -103,6 +103,13 @@ struct JacobiArgs {
   int max_sweeps;
   int sweep;
   double tol;              // relative off-diagonal tolerance
+  // skip record: stamp (sweep x rounds + round) at which each column block was last rotated,
+  // [batch][nblk], and at which each pair was last found orthogonal, [batch][rounds x per]
+  // (-1: never); a pair whose blocks have not been rotated since it was found orthogonal has
+  // the same Gram matrix and is skipped without reading its columns
+  int32_t* bmod;
+  int32_t* pconv;
+  int nblk, npairs, round, per;
 };
 
 __device__ __forceinline__ int pair_col(int a, int I, int J, int mI, int mJ) {
@@ -134,6 +141,13 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   const int mJ = (J < args.nb_real) ? min(BW, n - J * BW) : 0;
   if (mI + mJ == 0) return;
   double2* W = args.W + b * (int64_t)n * n;
+  const int stamp = args.sweep * (args.nblk - 1) + args.round;
+  int32_t* bmod = args.bmod + b * args.nblk;
+  int32_t* pconv = args.pconv + b * args.npairs + args.round * args.per + blockIdx.x;
+  {
+    const int cst = *pconv;
+    if (cst >= 0 && bmod[I] < cst && bmod[J] < cst) return;   // unchanged since found orthogonal
+  }
 
   // Columns of the pair are read with indices clamped into this workgroup's own columns
   // (padding lanes read a real column of the pair and discard it), so every load is
@@ -225,8 +239,16 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
     }
     if (rot) s_flag = 1;
     __syncthreads();
-    if (s_flag == 0) return;
-    if (t == 0) atomicAdd(cnt + args.sweep, 1);
+    if (s_flag == 0) {
+      if (t == 0) *pconv = stamp;
+      return;
+    }
+    if (t == 0) {
+      atomicAdd(cnt + args.sweep, 1);
+      *pconv = -1;
+      bmod[I] = stamp;   // written before the rotated columns, read only by later launches
+      bmod[J] = stamp;
+    }
   }
 
   // --- cyclic Jacobi on G (32 x 32 Hermitian), Q accumulates the rotations.  A round applies
@@ -555,23 +577,33 @@ ms_status jacobi_eigh(ms_ctx ctx, int n, int nb, double2* W, const double2* H, d
   const size_t pbytes = pairs.size() * sizeof(int2);
   const bool have = ctx->ws.size() > 10 && ctx->ws[10] && ctx->jacobi_n == n;
   MS_TRY(workspace(ctx, 10, pbytes, &wsp));
-  MS_TRY(workspace(ctx, 11, (size_t)nb * max_sweeps * sizeof(int32_t), &wsc));
+  MS_TRY(workspace(ctx, 11, (size_t)nb * (max_sweeps + nblk + (size_t)rounds * per) * sizeof(int32_t), &wsc));
   if (!have || wsp != ctx->jacobi_pairs) {   // the schedule depends on n only: upload once
     MS_TRY(upload(ctx, wsp, pairs.data(), pbytes));
     ctx->jacobi_n = n;
     ctx->jacobi_pairs = wsp;
   }
-  MS_HIP(ctx, hipMemsetAsync(wsc, 0, (size_t)nb * max_sweeps * sizeof(int32_t), ctx->stream));
+  // [counters: nb x max_sweeps][block stamps: nb x nblk][pair stamps: nb x rounds x per]
+  int32_t* cnt0 = static_cast<int32_t*>(wsc);
+  const int64_t nrec = (int64_t)nb * (nblk + (int64_t)rounds * per);
+  MS_TRY(launch_fill_i32(ctx, (int64_t)nb * max_sweeps, cnt0, 0));
+  MS_TRY(launch_fill_i32(ctx, nrec, cnt0 + (int64_t)nb * max_sweeps, -1));
   JacobiArgs a;
   a.W = W;
   a.n = n;
   a.nb_real = nb_real;
-  a.counter = static_cast<int32_t*>(wsc);
+  a.counter = cnt0;
   a.max_sweeps = max_sweeps;
   a.tol = std::max(1e-14, 4.0 * 2.220446049250313e-16 * std::sqrt((double)n));
+  a.bmod = cnt0 + (int64_t)nb * max_sweeps;
+  a.pconv = a.bmod + (int64_t)nb * nblk;
+  a.nblk = nblk;
+  a.npairs = rounds * per;
+  a.per = per;
   for (int s = 0; s < max_sweeps; ++s) {
     a.sweep = s;
     for (int r = 0; r < rounds; ++r) {
+      a.round = r;
       a.pairs = static_cast<const int2*>(wsp) + (size_t)r * per;
       Prof prof(ctx, PC_JACOBI, 2.0 * 8.0 * PW * PW * (double)n * per * nb, 3.0 * 16.0 * PW * (double)n * per * nb);
       hipLaunchKernelGGL(k_jacobi_round, dim3(per, nb), dim3(256), 0, ctx->stream, a);
