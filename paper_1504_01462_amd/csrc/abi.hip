@@ -166,7 +166,7 @@ namespace {
 
 // workspace slots
 enum {
-  WS_KIN = 0, WS_SHIFT, WS_W, WS_U, WS_MISC, WS_K, WS_P, WS_AOP, WS_WG, WS_M,
+  WS_KIN = 0, WS_SHIFT, WS_W, WS_U, WS_MISC, WS_K, WS_P, WS_AOP, WS_M = 9,
   WS_JPAIRS = 10, WS_JCOUNT = 11,
   WS_Y = 12, WS_PIV, WS_CH, WS_EN, WS_OC, WS_AUG, WS_XC, WS_YC, WS_Z, WS_S4,
   WS_ACC0, WS_ACC1, WS_G, WS_H, WS_V, WS_UREF, WS_PREP_V,
@@ -1217,7 +1217,7 @@ struct FoldGroup {          // the sets of one n_g, longest first
   int64_t ch0 = 0;                  // channel table [sets][n_oc] at ch0 of the channel buffer
   ms_ctx run = nullptr;             // context (stream, workspace) the group is enqueued on
   double cost = 0.0;                // n^3 x fold steps x instances, for placing groups on streams
-  double2 *kb = nullptr, *pb = nullptr, *wg = nullptr, *mm = nullptr, *yb = nullptr;
+  double2 *kb = nullptr, *pb = nullptr, *mm = nullptr, *yb = nullptr;
   void* aop = nullptr;
   int32_t *piv = nullptr, *sel = nullptr;
 };
@@ -1253,8 +1253,8 @@ FoldDims fold_dims(const FoldGroup& G, bool fp32) {
   d.sY = (int64_t)n * d.ldy;
   d.sk = (int64_t)(G.nsmax + 2) * n;
   d.asz = fp32 ? sizeof(float2) : sizeof(double2);
-  d.per_e = (size_t)(2 * d.sk) * sizeof(double2) + d.nn * d.asz + 2 * d.nn * sizeof(double2) +
-            d.sM * sizeof(double2) + d.sY * sizeof(double2) + n * sizeof(int32_t);
+  d.per_e = (size_t)(2 * d.sk) * sizeof(double2) + d.nn * d.asz + d.sM * sizeof(double2) +
+            d.sY * sizeof(double2) + n * sizeof(int32_t);
   return d;
 }
 
@@ -1354,7 +1354,7 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
   // each group's scratch comes from its runner's workspace; a runner that serves several
   // groups (one after the other on its stream) is first grown to the largest need per slot,
   // so no later request moves a buffer an earlier group already holds
-  const int slots[8] = {WS_K, WS_P, WS_AOP, WS_WG, WS_M, WS_Y, WS_PIV, WS_SEL};
+  const int slots[7] = {WS_K, WS_P, WS_AOP, WS_M, WS_Y, WS_PIV, WS_SEL};
   // allocation-free mode (one group): the arena left for the per-instance scratch
   const size_t arena_left =
       ctx->arena ? ctx->arena_size - std::min(ctx->arena_size, ctx->arena_used + ARENA_TABLES) : 0;
@@ -1370,22 +1370,21 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     G.nbi = (int)std::min<int64_t>(nbi, 65535);
     nd[0] = nd[1] = (size_t)G.nbi * d.sk * sizeof(double2);
     nd[2] = (size_t)G.nbi * d.nn * d.asz;
-    nd[3] = (size_t)G.nbi * 2 * d.nn * sizeof(double2);
-    nd[4] = (size_t)G.nbi * d.sM * sizeof(double2);
-    nd[5] = (size_t)G.nbi * d.sY * sizeof(double2);
-    nd[6] = (size_t)G.nbi * G.n * sizeof(int32_t);
-    nd[7] = (size_t)G.nbi * (THRESH_CAP + 1) * sizeof(int32_t);
+    nd[3] = (size_t)G.nbi * d.sM * sizeof(double2);
+    nd[4] = (size_t)G.nbi * d.sY * sizeof(double2);
+    nd[5] = (size_t)G.nbi * G.n * sizeof(int32_t);
+    nd[6] = (size_t)G.nbi * (THRESH_CAP + 1) * sizeof(int32_t);
     return d;
   };
   for (FoldGroup& G : P.groups) {   // pass 1: grow every runner to its groups' largest needs
-    size_t nd[8];
+    size_t nd[7];
     const FoldDims d = needs(G, nd);
     void* v;
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 7; ++i) {
       size_t most = nd[i];
       for (FoldGroup& H : P.groups)
         if (H.run == G.run) {
-          size_t nh[8];
+          size_t nh[7];
           needs(H, nh);
           most = std::max(most, nh[i]);
         }
@@ -1401,8 +1400,6 @@ ms_status fold_plan(ms_ctx ctx, const double* energies, ms_prec prec, FoldPlan& 
     MS_TRY(workspace(c, WS_P, 1, &v));
     G.pb = c2(v);
     MS_TRY(workspace(c, WS_AOP, 1, &G.aop));
-    MS_TRY(workspace(c, WS_WG, 1, &v));
-    G.wg = c2(v);
     MS_TRY(workspace(c, WS_M, 1, &v));
     G.mm = c2(v);
     MS_TRY(workspace(c, WS_Y, 1, &v));
@@ -1477,20 +1474,25 @@ ms_status enqueue_group(ms_ctx c, const FoldPlan& P, const FoldGroup& G) {
           gm.M = n; gm.N = 2 * n; gm.K = n;
           gm.A = static_cast<char*>(G.aop) + (size_t)g.a * nn * d.asz; gm.lda = n; gm.sA = nn; gm.opA = OP_N;
           gm.B = O; gm.ldb = n; gm.sB = 0; gm.opB = OP_T;
-          gm.C = G.wg + (int64_t)g.a * 2 * nn; gm.ldc = 2 * n; gm.sC = 2 * nn;
+          // the product's epilogue writes [Phi_A^T | Phi_B^T] straight into the augmented matrix
+          gm.C = G.mm + g.a * sM; gm.ldc = d.ldm; gm.sC = sM;
           gm.batch = g.m;
           gm.kp = kp + g.a * sk; gm.kq = kq + g.a * sk; gm.sk = sk;
+          gm.ey = G.yb + g.a * sY; gm.eldy = d.ldy; gm.esy = sY;
+          gm.epq = pq + g.a * sk;
+          gm.esel = fp32 ? G.sel + (int64_t)g.a * (THRESH_CAP + 1) : nullptr;
+          gm.ecap = THRESH_CAP;
           gm.prof = PC_IFACE_GEMM;
           MS_TRY(fp32 ? cgemm32(c, gm) : zgemm(c, gm));
         }
       }
       for (const Seg& g : segs) {
         if (g.ns < s) break;
-        const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
-        MS_TRY(launch_epilogue(c, n, g.m, O, first ? nullptr : G.wg + (int64_t)g.a * 2 * nn, kp + g.a * sk,
-                               kq + g.a * sk, pq + g.a * sk, sk, G.yb + g.a * sY, d.ldy, sY,
-                               (fp32 && !first) ? G.sel + (int64_t)g.a * (THRESH_CAP + 1) : nullptr, THRESH_CAP,
-                               G.mm + g.a * sM, d.ldm, sM));
+        if (first) {   // no product at the first interface: C+- alone
+          const double2* O = c2(P.sets[G.sets[g.j]].sl->ovl) + (int64_t)(g.ns - s) * nn;
+          MS_TRY(launch_epilogue(c, n, g.m, O, nullptr, kp + g.a * sk, kq + g.a * sk, pq + g.a * sk, sk,
+                                 G.yb + g.a * sY, d.ldy, sY, nullptr, THRESH_CAP, G.mm + g.a * sM, d.ldm, sM));
+        }
         MS_TRY(launch_tcols(c, n, n_o, g.m, P.ch + G.ch0 + (int64_t)g.j * G.n_oc, G.yb + g.a * sY, d.ldy, sY, n,
                             kq + g.a * sk, pq + g.a * sk, sk, first ? 1 : 0, G.mm + g.a * sM, d.ldm, sM));
       }

@@ -71,12 +71,24 @@ struct KParams {
   const double2* kq;
   int64_t sk;
   int nh;
+  // fused fold epilogue (generated B only; ey null: plain W)
+  const double2* ey;
+  int64_t eldy, esy;
+  const double2* epq;
+  const int32_t* esel;
+  int ecap;
 };
 
 // complex product with its two fused multiply-adds written out, so every instantiation of the
 // kernel rounds it the same way (the compiler is otherwise free to contract either product)
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {   // fused multiply-adds written out
+  const double d = fma(b.x, b.x, b.y * b.y);
+  return make_double2(fma(a.x, b.x, a.y * b.y) / d, fma(a.y, b.x, -(a.x * b.y)) / d);
 }
 
 constexpr int BK = 16;
@@ -353,6 +365,48 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
           col = (lc >= BNH ? p.nh : 0) + n0h + h;
         }
         if (row < p.M && col_ok) {
+          if constexpr (GEN) {
+            if (p.ey) {   // the fold's augmented-matrix columns (see GemmArgs)
+              double wr, wi;
+              if constexpr (kSlab64) {
+                wr = sr[a][c][v];
+                wi = si[a][c][v];
+              } else {
+                const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
+                wr = p1 - p2;
+                wi = p3 - p1 - p2;
+              }
+              const int lc = wn0 + c * 16 + (lane & 15);
+              const bool plus = lc >= BNH;       // W+ column (Phi_B^T), else W- (Phi_A^T)
+              const int j = n0h + (plus ? lc - BNH : lc), i = row;
+              const double2 kpj = kpb[j], kqi = kqb[i];
+              const double2 ot = Bd[(int64_t)j * p.ldb + i];
+              const double2* Yb = p.ey + b * p.esy + (int64_t)i * p.eldy;
+              const double2* Pb = p.epq + b * p.sk;
+              const double2 pk = zmul(Pb[i], kqi);
+              double2 out = make_double2(wr, wi);
+              if (!plus) {
+                out = zadd(out, zmul(ot, zadd(kpj, kqi)));
+              } else {
+                out = zadd(out, zmul(ot, zsub(kpj, kqi)));
+                const double2 rho = zdiv(zmul(zmul(pk, Yb[j]), Pb[j]), kqb[j]);
+                out = zadd(out, zmul(rho, zmul(Bd[(int64_t)j * p.ldb + j], zadd(kpj, kqb[j]))));
+              }
+              if (p.esel) {
+                const int32_t* se = p.esel + b * (int64_t)(p.ecap + 1);
+                const int nsel = se[0];
+                for (int q = 0; q < nsel; ++q) {
+                  const int m = se[1 + q];
+                  if (plus && m == j) continue;
+                  const double2 rm = zdiv(zmul(zmul(pk, Yb[m]), Pb[m]), kqb[m]);
+                  const double2 ojm = Bd[(int64_t)j * p.ldb + m];
+                  out = zadd(out, zmul(rm, zmul(ojm, plus ? zadd(kpj, kqb[m]) : zsub(kpj, kqb[m]))));
+                }
+              }
+              C[(int64_t)row * p.ldc + col] = out;
+              continue;
+            }
+          }
           if (kFold) {
             const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
             C[(int64_t)row * p.ldc + col] = make_double2(p1 - p2, p3 - p1 - p2);
@@ -404,7 +458,7 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
               g.alpha.x != 1.0 || g.alpha.y != 0.0 || g.opA != OP_N))
     return fail(ctx, MS_ERR_ARG, "generated-B product: shared O^T, N = 2 nh, no alpha/beta");
   KParams p{g.M, g.N, std::max(g.K, 0), g.opA, g.opB, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha,
-            g.beta, g.kp, g.kq, g.sk, g.N / 2};
+            g.beta, g.kp, g.kq, g.sk, g.N / 2, gen ? g.ey : nullptr, g.eldy, g.esy, g.epq, g.esel, g.ecap};
   // algorithmic bytes: A and C per batch entry; a shared B (stride 0) once
   const double bytes_b = gen ? 16.0 * p.K * (g.N / 2) + 2.0 * 16.0 * g.batch * (p.K + g.N / 2)
                              : (double)(g.sB == 0 ? 1 : g.batch) * sizeof(typename Mfma<T>::c_t) * p.K * g.N;

@@ -136,6 +136,18 @@ struct GemmArgs {
   const double2* kp = nullptr;
   const double2* kq = nullptr;
   int64_t sk = 0;
+  // Optional epilogue of the interface product (ey != nullptr): instead of W = rho^T [C- | C+],
+  // C receives the fold's augmented-matrix columns [Phi_A^T | Phi_B^T]:
+  //   C[i][j]      = C+_ij + W-_ij + sum_sel rho^T_im O_jm (kp_j - kq_m)
+  //   C[i][nh + j] = C-_ij + W+_ij + rho^T_ij C+_jj + sum_sel, m != j rho^T_im O_jm (kp_j + kq_m)
+  // with C+-_ij = O_ji (kp_j +- kq_i) and rho^T_im = P_i kq_i Y_im P_m / kq_m from the state Y
+  // (ey + b esy, row stride eldy) and the propagators P (epq + b sk); sel (esel + b (ecap + 1):
+  // count, then columns) lists the columns rho^T was staged without (null: none)
+  const double2* ey = nullptr;
+  int64_t eldy = 0, esy = 0;
+  const double2* epq = nullptr;
+  const int32_t* esel = nullptr;
+  int ecap = 0;
 };
 // A complex128 (B complex128); FP64 MFMA.
 ms_status zgemm(ms_ctx ctx, const GemmArgs& g);

@@ -67,11 +67,23 @@ def test_noalloc_sub_batches_inside_the_scratch(ms):
     ctx.close()
 
 
-def test_noalloc_rejects_what_does_not_fit(ms):
-    """One instance at N_G = 1200 needs more than the scratch: MS_ERR_UNSUPPORTED, outputs
-    untouched; the next call on the context works."""
+def test_noalloc_full_basis_size(ms):
+    """One instance at N_G = 1200 (about 104 MB of scratch) fits: the same T, R, N_open as the
+    allocating entry point."""
     ctx = ms.Context(0)
     j = msgen.config3(6.3, "AA", n_slices=2)
+    j.dz = np.full(2, 0.05)
+    s = ms.prepare_from_inputs(ctx, msgen.junction_inputs(j, j.kpars[3]))
+    ref, got = _both(ms, ctx, s, [0.5])
+    _same(ref, got)
+    ctx.close()
+
+
+def test_noalloc_rejects_what_does_not_fit(ms):
+    """One instance at N_G = 1500 needs more than the scratch (about 158 MB): MS_ERR_UNSUPPORTED,
+    outputs untouched; the next call on the context works."""
+    ctx = ms.Context(0)
+    j = msgen.config3(6.3, "AA", n_g=1500, n_slices=2)
     j.dz = np.full(2, 0.05)
     s = ms.prepare_from_inputs(ctx, msgen.junction_inputs(j, j.kpars[3]))
     T = torch.full((1,), -1.0, dtype=torch.float64, device=dev())
