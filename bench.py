@@ -86,7 +86,8 @@ def parse():
     ap.add_argument("--workers", type=int, default=16, help="processes generating the seeded inputs")
     ap.add_argument("--probe", choices=["iface64", "iface32", "lu", "eigh", "copy"],
                     help="run one kernel at the benchmark's launch shape (for profiler counters) and exit: "
-                         "the interface product (FP64 or FP32 MFMA, n_g 1200, 32 energies), the LU solve of "
+                         "the interface product with the fold's fused epilogue (FP64 or FP32 MFMA, n_g 1200, 32 "
+                         "energies), the LU solve of "
                          "32 augmented systems, 8 slice eigenproblems, or a 1 GiB device copy (calibration)")
     ap.add_argument("--probe-launches", type=int, default=5)
     ap.add_argument("--electrode-only", type=int, default=0, metavar="N_G",
@@ -112,13 +113,15 @@ def probe(kind, launches):
     def crand(*shape, dtype=torch.complex128):
         return torch.randn(*shape, generator=g, device=dev, dtype=dtype)
 
-    if kind.startswith("iface"):
+    if kind.startswith("iface"):   # as the fold launches it: the fused epilogue reads Y and P
         dt = torch.complex128 if kind == "iface64" else torch.complex64
         a, o = crand(batch, n, n, dtype=dt), crand(n, n) / n ** 0.5
-        kp, kq = crand(batch, n), crand(batch, n)
-        run = lambda: ms.ms_debug_iface_product(ctx, a, o, kp, kq, "fp64" if kind == "iface64" else "fp32")
+        kp, kq = crand(batch, n), crand(batch, n) + 1.5
+        y, pq = crand(batch, n, n), crand(batch, n)
+        run = lambda: ms.ms_debug_iface_fused(ctx, a, o, kp, kq, y, pq, "fp64" if kind == "iface64" else "fp32")
         work = {"flop": 8.0 * n * 2 * n * n * batch,
-                "bytes": batch * n * n * a.element_size() + 16.0 * n * n + 2 * 16.0 * batch * n + 16.0 * batch * 2 * n * n}
+                "bytes": batch * n * n * a.element_size() + 16.0 * n * n + 2 * 16.0 * batch * n + 16.0 * batch * 2 * n * n
+                         + 16.0 * batch * n * n}
     elif kind == "lu":
         nrhs = n + 13
         src = crand(batch, n, n + nrhs)

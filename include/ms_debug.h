@@ -42,6 +42,14 @@ ms_status ms_debug_gemm_batched(ms_ctx ctx, int op_a, int op_b, int64_t m, int64
 ms_status ms_debug_iface_product(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* o,
                                  const void* kp, const void* kq, void* w, ms_prec prec);
 
+/* The same product with the fold's fused epilogue: m [batch][n][2n] c128 receives
+ *   m[i][j]     = C+_ij + (A C-)_ij,
+ *   m[i][n + j] = C-_ij + (A C+')_ij + rho_ij C+_jj,   rho_ij = pq_i kq_i y_ij pq_j / kq_j,
+ * with C+-_ij = O_ji (kp_j +- kq_i), C+' = C+ without its diagonal; y [batch][n][n] c128,
+ * pq [batch][n] c128. */
+ms_status ms_debug_iface_fused(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* o, const void* kp,
+                               const void* kq, const void* y, const void* pq, void* m, ms_prec prec);
+
 /* Eigenpairs of `batch` complex pencils A x = lam B x (n x n each, complex128, not modified) by
  * the library's QZ iteration: alpha, beta [batch][n] complex128 with lam = alpha / beta (beta
  * real >= 0; beta = 0 for an infinite eigenvalue), x [batch][n][n] right eigenvectors as unit

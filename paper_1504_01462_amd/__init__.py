@@ -86,6 +86,7 @@ _sig("ms_debug_gemm", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, 
 _sig("ms_debug_gemm_batched", [_vp, _i32, _i32, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _vp, _i64,
                                 _i64, _i64, _vp, _vp, _i32])
 _sig("ms_debug_iface_product", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _i32])
+_sig("ms_debug_iface_fused", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32])
 _sig("ms_debug_qz", [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ms_debug_lu_solve", [_vp, _i64, _i64, _i64, _vp, _vp, _vp])
 _sig("ms_debug_eigh", [_vp, _i64, _i64, _vp, _vp, _vp, _vp])
@@ -504,6 +505,19 @@ def ms_debug_gemm_batched(ctx: Context, a: torch.Tensor, b: torch.Tensor, c: tor
     return c
 
 
+def ms_debug_iface_fused(ctx: Context, a: torch.Tensor, o: torch.Tensor, kp: torch.Tensor, kq: torch.Tensor,
+                         y: torch.Tensor, pq: torch.Tensor, prec="fp64"):
+    """The interface product with the fold's fused epilogue: m [batch][n][2n] (see ms_debug.h)."""
+    batch, n, _ = a.shape
+    dt = torch.complex128 if _PREC[prec] == MS_PREC_FP64 else torch.complex64
+    m = torch.empty((batch, n, 2 * n), dtype=torch.complex128, device=ctx.device)
+    _check(ctx.handle, lib.ms_debug_iface_fused(ctx.handle, n, batch, _ptr(a, dt, "a"), _ptr(o, torch.complex128, "o"),
+                                                _ptr(kp, torch.complex128, "kp"), _ptr(kq, torch.complex128, "kq"),
+                                                _ptr(y, torch.complex128, "y"), _ptr(pq, torch.complex128, "pq"),
+                                                _ptr(m), _PREC[prec]))
+    return m
+
+
 def ms_debug_iface_product(ctx: Context, a: torch.Tensor, o: torch.Tensor, kp: torch.Tensor, kq: torch.Tensor,
                            prec="fp64"):
     """W [batch][n][2n] = A [C- | C+ off its diagonal] with C-+[m][j] = O[j][m] (kp[j] -+ kq[m]):
@@ -576,6 +590,6 @@ __all__ = ["lib", "LIB_PATH", "MSError", "Context", "Slices", "ms_ctx_create", "
            "ms_transmission",
            "ms_transmission_batch", "ms_transmission_batch_noalloc", "ms_transmission_multi", "ms_transmission_uneven", "ms_graph_replay",
            "MS_FOLD_GRAPH", "ms_dT_dV", "Transmission", "ms_set_tiles", "ms_autotune", "ms_kpar_average", "ms_debug_profile", "ms_debug_profile_read",
-           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_qz", "ms_debug_lu_solve",
+           "PROFILE_CATEGORIES", "ms_debug_gemm", "ms_debug_gemm_batched", "ms_debug_iface_product", "ms_debug_iface_fused", "ms_debug_qz", "ms_debug_lu_solve",
            "ms_debug_eigh",
            "prepare_from_inputs", "prepare_from_inputs_into", "MS_PREC_FP64", "MS_PREC_FP32_MFMA"]

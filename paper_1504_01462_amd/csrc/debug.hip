@@ -85,6 +85,31 @@ ms_status ms_debug_iface_product(ms_ctx ctx, int64_t n, int64_t batch, const voi
   return fail(ctx, MS_ERR_ARG, "unknown precision");
 }
 
+ms_status ms_debug_iface_fused(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* o, const void* kp,
+                               const void* kq, const void* y, const void* pq, void* m, ms_prec prec) {
+  if (!ctx) return MS_ERR_ARG;
+  if (!a || !o || !kp || !kq || !y || !pq || !m) return fail(ctx, MS_ERR_ARG, "NULL pointer argument");
+  if (n <= 0 || batch <= 0 || n > 4096 || batch > 65535) return fail(ctx, MS_ERR_ARG, "bad sizes");
+  MS_HIP(ctx, hipSetDevice(ctx->device));
+  GemmArgs g;
+  g.M = (int)n; g.N = 2 * (int)n; g.K = (int)n;
+  g.A = a; g.lda = n; g.sA = n * n; g.opA = OP_N;
+  g.B = o; g.ldb = n; g.sB = 0; g.opB = OP_T;
+  g.C = static_cast<double2*>(m); g.ldc = 2 * n; g.sC = 2 * n * n;
+  g.batch = (int)batch;
+  g.kp = static_cast<const double2*>(kp);
+  g.kq = static_cast<const double2*>(kq);
+  g.sk = n;
+  g.ey = static_cast<const double2*>(y);
+  g.eldy = n;
+  g.esy = n * n;
+  g.epq = static_cast<const double2*>(pq);
+  g.prof = PC_IFACE_GEMM;
+  if (prec == MS_PREC_FP64) return zgemm(ctx, g);
+  if (prec == MS_PREC_FP32_MFMA) return cgemm32(ctx, g);
+  return fail(ctx, MS_ERR_ARG, "unknown precision");
+}
+
 ms_status ms_debug_qz(ms_ctx ctx, int64_t n, int64_t batch, const void* a, const void* b, void* alpha, void* beta,
                       void* x, int32_t* status) {
   if (!ctx) return MS_ERR_ARG;

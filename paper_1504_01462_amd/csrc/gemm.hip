@@ -459,8 +459,10 @@ ms_status run(ms_ctx ctx, const GemmArgs& g) {
     return fail(ctx, MS_ERR_ARG, "generated-B product: shared O^T, N = 2 nh, no alpha/beta");
   KParams p{g.M, g.N, std::max(g.K, 0), g.opA, g.opB, g.A, g.lda, g.sA, g.B, g.ldb, g.sB, g.C, g.ldc, g.sC, g.alpha,
             g.beta, g.kp, g.kq, g.sk, g.N / 2, gen ? g.ey : nullptr, g.eldy, g.esy, g.epq, g.esel, g.ecap};
-  // algorithmic bytes: A and C per batch entry; a shared B (stride 0) once
-  const double bytes_b = gen ? 16.0 * p.K * (g.N / 2) + 2.0 * 16.0 * g.batch * (p.K + g.N / 2)
+  // algorithmic bytes: A and C per batch entry; a shared B (stride 0) once; the fused fold
+  // epilogue also reads each entry's state Y (M x K)
+  const double bytes_b = gen ? 16.0 * p.K * (g.N / 2) + 2.0 * 16.0 * g.batch * (p.K + g.N / 2) +
+                                   (g.ey ? 16.0 * g.batch * (double)g.M * p.K : 0.0)
                              : (double)(g.sB == 0 ? 1 : g.batch) * sizeof(typename Mfma<T>::c_t) * p.K * g.N;
   Prof prof(ctx, g.prof, 8.0 * g.M * (double)g.N * p.K * g.batch,
             (double)g.batch * sizeof(typename Mfma<T>::c_t) * ((double)g.M * p.K) + bytes_b +

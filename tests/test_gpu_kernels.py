@@ -89,6 +89,35 @@ def test_iface_product_fp64(lib, ctx, n, batch):
     assert err <= 1e-14 * np.sqrt(n) + 1e-15, err
 
 
+@pytest.mark.parametrize("n,batch,prec", [(7, 2, "fp64"), (65, 3, "fp64"), (300, 2, "fp64"), (130, 2, "fp32")])
+def test_iface_fused_epilogue(lib, ctx, n, batch, prec):
+    """The interface product with the fold's epilogue fused into its tile epilogue:
+    [C+ + A C- | C- + A C+' + rho_ij C+_jj] against NumPy (rho_ij = P_i kq_i Y_ij P_j / kq_j)."""
+    rng = np.random.default_rng(n + 3 * batch)
+    a = _rand(rng, (batch, n, n))
+    o = _rand(rng, (n, n)) / np.sqrt(n)
+    kp = _rand(rng, (batch, n))
+    kq = _rand(rng, (batch, n)) + 1.5
+    y = _rand(rng, (batch, n, n))
+    pq = np.exp(1j * _rand(rng, (batch, n)))
+    if prec == "fp32":
+        a = a.astype(np.complex64)
+    ref = []
+    for b in range(batch):
+        cm = o.T * (kp[b][None, :] - kq[b][:, None])
+        cp = o.T * (kp[b][None, :] + kq[b][:, None])
+        cpo = cp.copy()
+        np.fill_diagonal(cpo, 0.0)
+        rho = (pq[b] * kq[b])[:, None] * y[b] * (pq[b] / kq[b])[None, :]
+        ab = a[b].astype(np.complex128)
+        ref.append(np.hstack([cp + ab @ cm, cm + ab @ cpo + rho * np.diag(cp)[None, :]]))
+    ref = np.stack(ref)
+    m = lib.ms_debug_iface_fused(ctx, to_dev(a), to_dev(o), to_dev(kp), to_dev(kq), to_dev(y), to_dev(pq), prec)
+    ctx.sync()
+    err = np.max(np.abs(m.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err <= (1e-14 * np.sqrt(n) + 1e-15 if prec == "fp64" else 6e-8 * 8 * np.sqrt(n)), err
+
+
 @pytest.mark.parametrize("n,batch", [(37, 2), (130, 3), (1200, 2)])
 def test_iface_product_fp32(lib, ctx, n, batch):
     """FP32 form: A complex64, B generated in FP64 and rounded when staged, FP32 accumulation."""
