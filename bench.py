@@ -5,10 +5,11 @@ Workload (default): the side-contact overlap junction -- rectangular 4.65 x 40
 bohr cell, two graphene-like Gaussian-well sheets overlapping 15 bohr along
 the transport direction, N_G = 1200 plane waves, 400 slices of 0.05 bohr,
 free-electron leads, 32 energies at each of 8 k_par for 3 vacuum gaps (768
-points).  One step = four k_par of one gap (128 points): slice Hamiltonians,
+points).  One step = the eight k_par of one gap (256 points): slice Hamiltonians,
 eigenpairs and overlaps (E-independent) of each, the fused slice-S /
-star-product fold of all 128 points in one batch, T and R per point, and the
-k_par average.  Successive steps walk through the 6 (gap, k_par quartet) groups.
+star-product fold of all 256 points in one batch, T and R per point, and the
+k_par average.  Successive steps walk through the 3 gaps (`--kpar-per-step 4`:
+the 6 (gap, k_par quartet) groups of 128 points).
 Inputs are seeded and synthetic, generated once per distinct (gap, k_par) in
 worker processes before the GPU is touched, and resident in HBM before timing.
 
@@ -65,7 +66,7 @@ def parse():
                     help="every (gap, k_par pair) group once, in both forms, without time budget")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kpar-per-step", type=int, default=4,
+    ap.add_argument("--kpar-per-step", type=int, default=8,
                     help="k_par values of one junction folded together in one batch per step")
     ap.add_argument("--mixed", action="store_true",
                     help="also time the paper's mixed-recurrence doubling (ms_mixed_doubling) at one point")

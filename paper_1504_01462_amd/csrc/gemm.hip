@@ -5,7 +5,7 @@
 // each 16x16x4 complex block is three real MFMAs (Gauss's product)
 //   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + Ai)(Br + Bi);   Cr = P1 - P2,   Ci = P3 - P1 - P2
 // (v_mfma_f64_16x16x4f64 for complex128, v_mfma_f32_16x16x4f32 for complex64:
-// FP32 accumulation inside each K-slab of 16, the slabs combined and summed in FP64).  Three
+// FP32 accumulation inside each K-slab of 16, each product's slabs summed in FP64).  Three
 // products instead of four take a quarter of the matrix-core work; the imaginary part's
 // rounding error is bounded by eps sum (|Ar| + |Ai|)(|Br| + |Bi|) instead of
 // eps sum (|Ar| |Bi| + |Ai| |Br|).  Operand layouts of both: lane l holds
@@ -174,7 +174,26 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 #pragma unroll
     for (int e = 0; e < EBH; ++e) kpv[e] = kpb[min(n0h + (tid + NT * e) / BK, p.nh - 1)];
   }
+  // generated B (op(A) = A): every thread's A and O elements keep their rows across K-slabs
+  // and share one K offset (tid mod BK), so the row addresses are formed once, here
+  const CT* arow[GEN ? EA : 1];
+  const double2* brow[GEN ? EBH : 1];
+  if constexpr (GEN) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) arow[e] = A + (int64_t)min(m0 + (tid + NT * e) / BK, p.M - 1) * p.lda;
+#pragma unroll
+    for (int e = 0; e < EBH; ++e) brow[e] = Bd + (int64_t)min(n0h + (tid + NT * e) / BK, p.nh - 1) * p.ldb;
+  }
   auto load = [&](int k0) {
+    if constexpr (GEN) {
+      const int gk = min(k0 + tid % BK, p.K - 1);
+#pragma unroll
+      for (int e = 0; e < EA; ++e) ra[e] = arow[e][gk];
+      rkq = kqb[gk];
+#pragma unroll
+      for (int e = 0; e < EBH; ++e) rbd[e] = brow[e][gk];
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
@@ -182,16 +201,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
       const int gi = min(m0 + i, p.M - 1), gk = min(k0 + k, p.K - 1);
       ra[e] = (p.opA == OP_N) ? A[(int64_t)gi * p.lda + gk] : A[(int64_t)gk * p.lda + gi];
-    }
-    if constexpr (GEN) {
-      rkq = kqb[min(k0 + tid % BK, p.K - 1)];
-#pragma unroll
-      for (int e = 0; e < EBH; ++e) {
-        const int idx = tid + NT * e;
-        const int gj = min(n0h + idx / BK, p.nh - 1), gk = min(k0 + idx % BK, p.K - 1);
-        rbd[e] = Bd[(int64_t)gj * p.ldb + gk];
-      }
-      return;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -203,14 +212,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
     }
   };
   auto stash = [&](int st, int k0) {
+    const bool aN = GEN || p.opA == OP_N;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       const int idx = tid + NT * e;
       int i, k;
-      if (p.opA == OP_N) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
+      if (aN) { i = idx / BK; k = idx % BK; } else { k = idx / BM; i = idx % BM; }
       const bool ok = m0 + i < p.M && k0 + k < p.K;
       T re = ok ? ra[e].x : (T)0, im = ok ? ra[e].y : (T)0;
-      if (p.opA == OP_C) im = -im;
+      if (!GEN && p.opA == OP_C) im = -im;
       if (kFold && scale_a) {   // alpha op(A), staged (fused multiply-adds written out)
         const T r2 = fma((T)p.alpha.x, re, -((T)p.alpha.y * im));
         im = fma((T)p.alpha.x, im, (T)p.alpha.y * re);
@@ -260,17 +270,20 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
       ci[a][c] = acc_t{0, 0, 0, 0};
       c3[a][c] = acc_t{0, 0, 0, 0};
     }
-  // FP32 MFMA: each K-slab accumulates in FP32 (four MFMA steps), and the slabs are summed in
-  // FP64, so the FP32 rounding chain of an element is 4 long instead of K / 4
+  // FP32 MFMA: each K-slab accumulates in FP32 (four MFMA steps), and the slabs of each of the
+  // three products are summed in FP64 (sr, si, s3: P1, P2, P3), so the FP32 rounding chain of
+  // an element is 4 long instead of K / 4; the products are combined once, after the K loop
+  // (three sums take two FP64 operations per element and slab fewer than two combined ones)
   constexpr bool kSlab64 = !kFold;
-  double sr[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4], si[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4];
+  double sr[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4], si[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4],
+      s3[kSlab64 ? FM : 1][kSlab64 ? FN : 1][4];
   if constexpr (kSlab64) {
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int c = 0; c < FN; ++c)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sr[a][c][v] = si[a][c][v] = 0.0;
+        for (int v = 0; v < 4; ++v) sr[a][c][v] = si[a][c][v] = s3[a][c][v] = 0.0;
   }
 
   // two LDS stages: compute on stage `cur` while the next K-slab is stored into the
@@ -333,8 +346,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
-            sr[a][c][v] += p1 - p2;
-            si[a][c][v] += p3 - p1 - p2;
+            sr[a][c][v] += p1;
+            si[a][c][v] += p2;
+            s3[a][c][v] += p3;
           }
           cr[a][c] = acc_t{0, 0, 0, 0};
           ci[a][c] = acc_t{0, 0, 0, 0};
@@ -369,8 +383,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
             if (p.ey) {   // the fold's augmented-matrix columns (see GemmArgs)
               double wr, wi;
               if constexpr (kSlab64) {
-                wr = sr[a][c][v];
-                wi = si[a][c][v];
+                wr = sr[a][c][v] - si[a][c][v];
+                wi = s3[a][c][v] - sr[a][c][v] - si[a][c][v];
               } else {
                 const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
                 wr = p1 - p2;
@@ -414,8 +428,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(KParams p, int ntn, int n
           }
           double re, im;
           if constexpr (kSlab64) {
-            re = sr[a][c][v];
-            im = si[a][c][v];
+            re = sr[a][c][v] - si[a][c][v];
+            im = s3[a][c][v] - sr[a][c][v] - si[a][c][v];
           } else {
             const double p1 = (double)cr[a][c][v], p2 = (double)ci[a][c][v], p3 = (double)c3[a][c][v];
             re = p1 - p2;
