@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="config3", choices=["config1", "config2", "config3"])
-    ap.add_argument("--time-budget", type=float, default=200.0,
+    ap.add_argument("--time-budget", type=float, default=150.0,
                     help="seconds of the timed FP64 leg: fewer than --steps are timed when they would not fit")
     ap.add_argument("--wall-budget", type=float, default=450.0,
                     help="seconds from start after which optional legs are skipped")

@@ -185,7 +185,9 @@ enum {
 
 constexpr int MAX_N = 4096;
 constexpr int64_t MAX_GRAPH_KERNELS = 96000;   // kernels one captured fold graph may hold
-constexpr size_t BATCH_BUDGET = size_t(24) << 30;   // bytes of per-energy workspace per sub-batch
+// bytes of per-energy workspace per sub-batch: 256 instances at N_G = 1200 (108 MB each in
+// FP64, 96 MB in FP32) fold in one sub-batch
+constexpr size_t BATCH_BUDGET = size_t(32) << 30;
 constexpr size_t ARENA_TABLES = size_t(1) << 20;     // arena bytes kept for the fold's tables
 // FP32-MFMA fold: columns of rho^T whose |k| in slice p+1 is below THRESH_K (at most THRESH_CAP
 // per instance and interface) are taken out of the FP32 product and added in FP64
