@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
   // --- Gram G = P^dagger P: each wave takes a quarter of the rows for all three blocks
   {
     d4_t g00r = {0, 0, 0, 0}, g00i = {0, 0, 0, 0}, g01r = {0, 0, 0, 0}, g01i = {0, 0, 0, 0},
-         g11r = {0, 0, 0, 0}, g11i = {0, 0, 0, 0};
+         g11r = {0, 0, 0, 0}, g11i = {0, 0, 0, 0}, g003 = {0, 0, 0, 0}, g013 = {0, 0, 0, 0}, g113 = {0, 0, 0, 0};
     const int c = lane & 15;
     const bool okI = c < mI, okJ = c < mJ;
     const int colI = okI ? I * BW + c : own0;
@@ -183,19 +183,19 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
         const bool okk = k0 + 4 * s + (lane >> 4) < kend;
         const double2 pi = (okk && okI) ? xi[s] : make_double2(0.0, 0.0);
         const double2 pj = (okk && okJ) ? xj[s] : make_double2(0.0, 0.0);
-        // A = conj(P_X)^T (16 x 4), B = P_Y (4 x 16): lane holds element (c, k) of both
+        // A = conj(P_X)^T (16 x 4), B = P_Y (4 x 16): lane holds element (c, k) of both.  Three
+        // real products per block (Gauss): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi) with
+        // Ar = Re P_X, Ai = -Im P_X; Re G = P1 - P2, Im G = P3 - P1 - P2 (combined in the reduction)
+        const double di = pi.x - pi.y, sj = pj.x + pj.y, si = pi.x + pi.y;
         g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.x, g00r, 0, 0, 0);
-        g00r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pi.y, g00r, 0, 0, 0);
-        g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pi.y, g00i, 0, 0, 0);
-        g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pi.x, g00i, 0, 0, 0);
+        g00i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pi.y, g00i, 0, 0, 0);
+        g003 = __builtin_amdgcn_mfma_f64_16x16x4f64(di, si, g003, 0, 0, 0);
         g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.x, g01r, 0, 0, 0);
-        g01r = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.y, pj.y, g01r, 0, 0, 0);
-        g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(pi.x, pj.y, g01i, 0, 0, 0);
-        g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pj.x, g01i, 0, 0, 0);
+        g01i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi.y, pj.y, g01i, 0, 0, 0);
+        g013 = __builtin_amdgcn_mfma_f64_16x16x4f64(di, sj, g013, 0, 0, 0);
         g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.x, g11r, 0, 0, 0);
-        g11r = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.y, pj.y, g11r, 0, 0, 0);
-        g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x, pj.y, g11i, 0, 0, 0);
-        g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj.y, pj.x, g11i, 0, 0, 0);
+        g11i = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj.y, pj.y, g11i, 0, 0, 0);
+        g113 = __builtin_amdgcn_mfma_f64_16x16x4f64(pj.x - pj.y, sj, g113, 0, 0, 0);
       }
 #pragma unroll
       for (int s = 0; s < GS; ++s) {
@@ -211,9 +211,9 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = (lane >> 4) + 4 * v, j = lane & 15;   // f64 MFMA accumulator layout
-          G[i][j] = cadd(G[i][j], make_double2(g00r[v], g00i[v]));
-          G[i][BW + j] = cadd(G[i][BW + j], make_double2(g01r[v], g01i[v]));
-          G[BW + i][BW + j] = cadd(G[BW + i][BW + j], make_double2(g11r[v], g11i[v]));
+          G[i][j] = cadd(G[i][j], make_double2(g00r[v] - g00i[v], g003[v] - g00r[v] - g00i[v]));
+          G[i][BW + j] = cadd(G[i][BW + j], make_double2(g01r[v] - g01i[v], g013[v] - g01r[v] - g01i[v]));
+          G[BW + i][BW + j] = cadd(G[BW + i][BW + j], make_double2(g11r[v] - g11i[v], g113[v] - g11r[v] - g11i[v]));
         }
       }
       __syncthreads();
@@ -397,30 +397,31 @@ __global__ __launch_bounds__(256) void k_jacobi_round(JacobiArgs args) {
     }
     __syncthreads();
     if (r0 + ROWS < n) pload(r0 + ROWS);
-    d4_t cr0 = {0, 0, 0, 0}, ci0 = {0, 0, 0, 0}, cr1 = {0, 0, 0, 0}, ci1 = {0, 0, 0, 0};
+    // three real products per complex block: P1 = Pr Qr, P2 = Pi Qi, P3 = (Pr + Pi)(Qr + Qi)
+    d4_t a0 = {0, 0, 0, 0}, b0 = {0, 0, 0, 0}, c0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0},
+         c1 = {0, 0, 0, 0};
     const int rr = wave * 16;
 #pragma unroll
     for (int kk = 0; kk < PW; kk += 4) {
       const int k = kk + (lane >> 4);
       const double ar = Ps[0][rr + (lane & 15)][k], ai = Ps[1][rr + (lane & 15)][k];
       const double2 q0 = Q[k][lane & 15], q1 = Q[k][16 + (lane & 15)];
-      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q0.x, cr0, 0, 0, 0);
-      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q0.y, ci0, 0, 0, 0);
-      cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q1.x, cr1, 0, 0, 0);
-      ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q1.y, ci1, 0, 0, 0);
-      cr0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, q0.y, cr0, 0, 0, 0);
-      ci0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q0.x, ci0, 0, 0, 0);
-      cr1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, q1.y, cr1, 0, 0, 0);
-      ci1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q1.x, ci1, 0, 0, 0);
+      const double as = ar + ai;
+      a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q0.x, a0, 0, 0, 0);
+      b0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q0.y, b0, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(as, q0.x + q0.y, c0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, q1.x, a1, 0, 0, 0);
+      b1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, q1.y, b1, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(as, q1.x + q1.y, c1, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = r0 + rr + (lane >> 4) + 4 * v;
       if (row < n) {
-        const int c0 = pair_col(lane & 15, I, J, mI, mJ);
-        const int c1 = pair_col(16 + (lane & 15), I, J, mI, mJ);
-        if (c0 >= 0) W[(int64_t)row * n + c0] = make_double2(cr0[v], ci0[v]);
-        if (c1 >= 0) W[(int64_t)row * n + c1] = make_double2(cr1[v], ci1[v]);
+        const int col0 = pair_col(lane & 15, I, J, mI, mJ);
+        const int col1 = pair_col(16 + (lane & 15), I, J, mI, mJ);
+        if (col0 >= 0) W[(int64_t)row * n + col0] = make_double2(a0[v] - b0[v], c0[v] - a0[v] - b0[v]);
+        if (col1 >= 0) W[(int64_t)row * n + col1] = make_double2(a1[v] - b1[v], c1[v] - a1[v] - b1[v]);
       }
     }
     __syncthreads();
